@@ -1,0 +1,205 @@
+/*
+ * otgs.h - C ABI of the MI355X (gfx950) library for regularised discrete
+ * optimal transport with a group-sparse regulariser (squared L2 plus group
+ * lasso, one group per source class label).
+ *
+ * The problem (paper: Ida et al., AAAI 2023, Sec. 2): labelled source
+ * samples x_i (i < n_src, label y_i), unlabelled target samples x_j
+ * (j < n_tgt), cost c_ij = ||x_i - x_j||^2 (Sec. 2.1), marginals a, b, and
+ *     min_{T in U(a,b)} <T,C> + sum_j Psi(t_j),
+ *     Psi(t) = gamma (||t||^2 / 2 + mu sum_l ||t_[l]||)          (Eqs. 2-3).
+ * The library works on the smooth relaxed dual (Eq. 4)
+ *     D(alpha, beta) = a.alpha + b.beta - sum_j psi(alpha + beta_j 1 - c_j)
+ * whose gradient blocks are the group soft threshold of Eq. 5:
+ *     grad psi(f)_[l] = [1 - mu gamma / z_lj]_+ [f_[l]]_+ / gamma,
+ *     z_lj = ||[f_[l]]_+||.
+ * Note on names: the paper calls the source count m and the target count n;
+ * this header says n_src and n_tgt.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller, unless the
+ *     comment says "host".  The library never frees caller memory.
+ *   - All work is enqueued on the caller's HIP stream `stream` (a
+ *     hipStream_t passed as void*; NULL is the default stream) and is
+ *     asynchronous unless stated otherwise.
+ *   - Arrays indexed by sample are in the caller's order.  For a handle with
+ *     several instances ("batch"), per-sample arrays are the concatenation
+ *     of the instances in order (instance k starts at the sum of the sizes
+ *     of instances 0..k-1); per-instance scalars are arrays of length
+ *     `count`.
+ *   - Floating point: float32 storage and arithmetic, float64 for the dual
+ *     objective accumulation and the L-BFGS dot products.
+ *   - Return value: OT_GS_OK (0), a negative error code, or a positive
+ *     warning.  On error nothing has been enqueued unless the code is
+ *     OT_GS_EDEVICE.  ot_gs_last_error() gives a message (thread-local).
+ *     No C++ exception crosses this interface.
+ */
+#ifndef OTGS_H
+#define OTGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define OT_GS_OK              0
+#define OT_GS_EINVAL         -1   /* invalid argument (sizes, gamma, mu, labels, NULL) */
+#define OT_GS_ESHAPE         -2   /* inconsistent sizes between arguments            */
+#define OT_GS_EDEVICE        -3   /* a HIP runtime call failed                        */
+#define OT_GS_ENUMERIC       -4   /* NaN or Inf met in an input or the objective      */
+#define OT_GS_ENOMEM         -5   /* device allocation failed                         */
+#define OT_GS_NOT_CONVERGED   1   /* solve stopped at max_iter                        */
+#define OT_GS_LINESEARCH      2   /* solve stopped: line search found no step         */
+
+/* evaluation modes of ot_gs_dual_grad */
+#define OT_GS_DENSE      0  /* every (group, target) block evaluated ("origin")         */
+#define OT_GS_SCREENED   1  /* Algorithm 2: blocks in the set N evaluated directly,
+                               others skipped when the upper bound of Eq. 6 shows
+                               they are zero; needs a snapshot (see SNAPSHOT)          */
+#define OT_GS_SNAPSHOT   2  /* dense evaluation that also records the snapshot
+                               (alpha~, beta~, z~_lj, o~_lj) of Defs. 1-2 at this
+                               point; the set N is first rebuilt from the lower bound
+                               of Eq. 7 against the previous snapshot (Algorithm 1)   */
+
+/* cost providers */
+#define OT_GS_COST_GIVEN       0  /* caller passes C [n_src x n_tgt] row-major        */
+#define OT_GS_COST_MATERIALIZE 1  /* C = ||x_i - x_j||^2 built once from features    */
+#define OT_GS_COST_ONTHEFLY    2  /* C tiles recomputed from features in every
+                                     evaluation on FP32 matrix cores; never stored   */
+
+typedef struct ot_gs_handle ot_gs_handle;
+
+/* One OT instance.  All pointers are device pointers (caller-owned; they
+ * need to stay valid only during ot_gs_create, which copies what it keeps). */
+typedef struct {
+    int n_src;             /* >= 1 labelled source samples (rows)                  */
+    int n_tgt;             /* >= 1 target samples (columns)                        */
+    int dim;               /* feature dimension (features only)                    */
+    int n_groups;          /* labels lie in [0, n_groups); empty labels allowed    */
+    const int32_t *labels; /* [n_src]                                              */
+    int cost_mode;         /* OT_GS_COST_*                                         */
+    const float *cost;     /* [n_src * n_tgt] row-major, C >= 0 (COST_GIVEN)       */
+    const float *x_src;    /* [n_src * dim] row-major (COST_MATERIALIZE/ONTHEFLY)  */
+    const float *x_tgt;    /* [n_tgt * dim] row-major                              */
+    float cost_scale;      /* C is multiplied by this; 0 = 1 / max_ij C_ij         */
+    const float *a;        /* [n_src] source marginal, NULL = 1/n_src              */
+    const float *b;        /* [n_tgt] target marginal, NULL = 1/n_tgt              */
+    float gamma;           /* > 0                                                   */
+    float mu;              /* >= 0                                                  */
+} ot_gs_problem;
+
+/* Screening and timing counters, cumulative since create / last reset. */
+typedef struct {
+    long long evals;            /* gradient evaluations                               */
+    long long pairs_total;      /* (group, target) blocks covered, summed over evals  */
+    long long pairs_in_N;       /* blocks evaluated because they were in N   (s_i)    */
+    long long pairs_checked;    /* blocks outside N whose upper bound was tested (s_n)*/
+    long long pairs_unskipped;  /* tested blocks that could not be skipped   (s_u)    */
+    long long refreshes;        /* snapshot refreshes                        (s_r)    */
+    long long tiles_total;      /* (group, 64-target) tiles covered                   */
+    long long tiles_computed;   /* tiles actually streamed through the gradient kernel*/
+} ot_gs_stats;
+
+/* ------------------------------------------------------------ handle life */
+
+/* Builds the device layout of `count` instances: groups of rows by label (a
+ * stable counting sort), target columns clustered by nearest source class,
+ * the cost in that layout (or the features for COST_ONTHEFLY), marginals.
+ * Synchronises `stream` before returning.  Errors: OT_GS_EINVAL for
+ * n_src/n_tgt < 1, n_groups < 1 or > 16384, gamma <= 0, mu < 0, a label
+ * outside [0, n_groups), missing cost or features for the chosen mode;
+ * OT_GS_ENUMERIC if the cost or the scale is not finite or max C is 0 with
+ * cost_scale == 0; OT_GS_ENOMEM, OT_GS_EDEVICE. */
+int ot_gs_create(const ot_gs_problem *probs /* host [count] */, int count,
+                 ot_gs_handle **out /* host */, void *stream);
+
+void ot_gs_destroy(ot_gs_handle *h);
+
+/* ------------------------------------------------------------ hot path */
+
+/* One evaluation of the dual objective (Eq. 4) and its gradient (the ascent
+ * direction): grad_alpha = a - T 1, grad_beta = b - T^T 1 with
+ * T = [grad psi(alpha + beta_j 1 - c_j)]_j (Eq. 5), for every instance.
+ * alpha [sum n_src], beta [sum n_tgt] in; grad_alpha, grad_beta out (same
+ * shapes, may be NULL); obj out [count] float64 (device, may be NULL).
+ * mode: OT_GS_DENSE, OT_GS_SCREENED or OT_GS_SNAPSHOT.  SCREENED results are
+ * bit-identical to DENSE at the same point (Theorem 2); SCREENED before any
+ * SNAPSHOT uses the zero snapshot (valid for alpha~ = beta~ = 0 since C >= 0).
+ * Errors: OT_GS_EINVAL (NULL alpha/beta, bad mode), OT_GS_EDEVICE. */
+int ot_gs_dual_grad(ot_gs_handle *h, const float *alpha, const float *beta,
+                    float *grad_alpha, float *grad_beta, double *obj, int mode,
+                    void *stream);
+
+/* Solver options (host struct). */
+typedef struct {
+    int max_iter;         /* accepted L-BFGS iterations (default 200)                */
+    int hist;             /* L-BFGS history, 1..32 (default 10)                      */
+    int refresh;          /* r of Algorithm 1: snapshot / N refresh period (10)      */
+    int use_screen;       /* 1: Algorithms 1-2, 0: dense evaluations ("origin")      */
+    int use_lower;        /* 1: build N from the lower bound, 0: never (ablation)    */
+    int max_ls;           /* evaluations per line search (default 40)                */
+    int init_user;        /* 1: start from alpha_io/beta_io, 0: from zero            */
+    double c1, c2;        /* strong-Wolfe constants (1e-4, 0.9)                      */
+    double gtol;          /* stop when ||grad||_inf <= gtol (default 0: run max_iter)*/
+    double *obj_trace;    /* optional DEVICE [count * (max_iter + 1)] float64: D after
+                             each accepted iteration (k = 0 is the starting point)    */
+} ot_gs_options;
+
+/* Fills `o` with the defaults listed above. */
+void ot_gs_default_options(ot_gs_options *o);
+
+/* Per-instance result (host struct). */
+typedef struct {
+    int iters, evals, status;   /* status: OT_GS_OK converged, NOT_CONVERGED, LINESEARCH */
+    double obj;                 /* final D                                               */
+    double gnorm_inf;           /* final ||grad D||_inf                                  */
+} ot_gs_info;
+
+/* Maximises D by L-BFGS with every evaluation on the device (Algorithm 1
+ * when use_screen = 1).  alpha_io [sum n_src], beta_io [sum n_tgt]: start
+ * point if init_user, final point on return.  info: host [count] or NULL.
+ * Synchronises the stream before returning.  Returns OT_GS_OK or the worst
+ * per-instance status (OT_GS_NOT_CONVERGED, OT_GS_LINESEARCH), or an error. */
+int ot_gs_solve(ot_gs_handle *h, const ot_gs_options *opts, float *alpha_io,
+                float *beta_io, ot_gs_info *info, void *stream);
+
+/* Plan recovery t_j = grad psi(alpha + beta_j 1 - c_j) (Sec. 2.3) into a
+ * dense row-major T, instance k at offset sum_{k'<k} n_src n_tgt, caller
+ * order.  Errors as ot_gs_dual_grad. */
+int ot_gs_plan(ot_gs_handle *h, const float *alpha, const float *beta, float *T,
+               void *stream);
+
+/* ------------------------------------------------------------ utilities */
+
+/* rho parameterisation of the experiments (Sec. 5.2):
+ * gamma (1-rho)/2 ||t||^2 + gamma rho sum ||t_[l]||  ==  Eq. 3 with
+ * gamma' = gamma (1 - rho), mu' = rho / (1 - rho).  OT_GS_EINVAL unless
+ * 0 <= rho < 1 and gamma > 0. */
+int ot_gs_rho_to_mu(double gamma, double rho, double *gamma_out, double *mu_out);
+
+/* Copies the cumulative counters (host out) after synchronising `stream`;
+ * reset != 0 zeroes them afterwards. */
+int ot_gs_get_stats(ot_gs_handle *h, ot_gs_stats *out, int reset, void *stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of kernel `which` (0: gradient tiles, 1: screen, 2: reduce,
+ * 3: L-BFGS); enable != 0 turns it on.  ot_gs_kernel_time synchronises and
+ * returns the summed milliseconds and launch count since enabling. */
+int ot_gs_kernel_timing(ot_gs_handle *h, int enable);
+int ot_gs_kernel_time(ot_gs_handle *h, int which, double *ms, long long *launches);
+
+/* Size facts of instance k (host out, any may be NULL): groups that are
+ * nonempty, padded target count of the internal layout, tiles. */
+int ot_gs_layout_info(ot_gs_handle *h, int k, int *n_groups_nonempty,
+                      int *n_tgt_padded, int *n_tiles);
+
+const char *ot_gs_last_error(void);
+const char *ot_gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OTGS_H */

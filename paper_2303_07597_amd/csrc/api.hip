@@ -1,0 +1,873 @@
+// Host side of libotgs: the handle, its device layout, and the C ABI of
+// include/otgs.h.  All device work is enqueued on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "otgs_internal.h"
+#include "../../include/otgs.h"
+
+namespace otgs {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess)                                                           \
+      return fail(OT_GS_EDEVICE, "%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                              \
+  } while (0)
+
+#define LAUNCHCHK()                                                                 \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess)                                                           \
+      return fail(OT_GS_EDEVICE, "kernel launch failed: %s (%s:%d)",               \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                       \
+  } while (0)
+
+static inline long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+struct InstHost {
+  InstDev d;
+  int cost_mode;
+  std::vector<int> g_size, g_start, g_chunk0;
+  int n_chunk_rows;
+};
+
+// kernel ids of the timing facility
+enum { KT_GRAD = 0, KT_SCREEN, KT_REDUCE, KT_LBFGS, KT_NUM };
+
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KT_NUM];
+  double ms[KT_NUM] = {0, 0, 0, 0};
+  long long n[KT_NUM] = {0, 0, 0, 0};
+};
+
+}  // namespace otgs
+
+using namespace otgs;
+
+struct ot_gs_handle {
+  int count = 0;
+  std::vector<InstHost> inst;
+  std::vector<void*> allocs;
+  // totals
+  long long tot_rows = 0, tot_cols = 0, tot_cols_pad = 0, tot_groups = 0, tot_pairs = 0,
+            tot_tiles = 0, tot_c = 0, tot_r = 0, tot_chunk = 0;
+  int n_main = 0, n_sg = 0, n_sc = 0;
+  int dev = 0, n_cu = 256;
+  // device arrays
+  InstDev* d_inst = nullptr;
+  int *perm_row = nullptr, *row_grp = nullptr, *perm_col = nullptr;
+  int *g_start = nullptr, *g_size = nullptr, *g_chunk0 = nullptr, *grp_inst = nullptr;
+  float* C = nullptr;
+  float *a_int = nullptr, *b_int = nullptr;
+  int *a_uniform = nullptr, *b_uniform = nullptr;
+  float *alpha = nullptr, *beta = nullptr, *ga = nullptr, *gb = nullptr;
+  float *alpha_s = nullptr, *beta_s = nullptr, *zsnap = nullptr, *osnap = nullptr;
+  float *rowpart = nullptr, *colsum = nullptr, *part = nullptr, *kappa = nullptr;
+  float* excess = nullptr;
+  double* obj = nullptr;
+  GroupStats* gstats = nullptr;
+  uint8_t *inN = nullptr, *tile_on = nullptr;
+  TileDesc *tiles_all = nullptr, *list_main = nullptr, *list_sg = nullptr, *list_sc = nullptr;
+  TileDesc *dyn_main = nullptr, *dyn_sg = nullptr, *dyn_sc = nullptr;
+  int* counts_static = nullptr;  // [3]
+  int* counts_dyn = nullptr;     // [3]
+  long long* counters = nullptr;
+  int* err = nullptr;
+  long long* t_off = nullptr;    // plan offsets
+  Timing timing;
+  bool has_snapshot = false;
+
+  template <class T>
+  int alloc(T** p, size_t n) {
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(OT_GS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back(q);
+    *p = (T*)q;
+    return OT_GS_OK;
+  }
+  ~ot_gs_handle() {
+    for (void* p : allocs) (void)hipFree(p);
+    for (auto& v : timing.ev)
+      for (auto& e : v) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
+};
+
+#define TRY(x)                 \
+  do {                         \
+    int rc_ = (x);             \
+    if (rc_ != OT_GS_OK) return rc_; \
+  } while (0)
+
+// ------------------------------------------------------------ timing helpers
+
+static int tbegin(ot_gs_handle* h, int which, hipStream_t s, hipEvent_t* ev) {
+  if (!h->timing.on) return OT_GS_OK;
+  HIPCHK(hipEventCreate(ev));
+  HIPCHK(hipEventRecord(*ev, s));
+  (void)which;
+  return OT_GS_OK;
+}
+static int tend(ot_gs_handle* h, int which, hipStream_t s, hipEvent_t ev0) {
+  if (!h->timing.on) return OT_GS_OK;
+  hipEvent_t ev1;
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev1, s));
+  h->timing.ev[which].push_back({ev0, ev1});
+  return OT_GS_OK;
+}
+
+// ------------------------------------------------------------ create
+
+static int sync_err(ot_gs_handle* h, hipStream_t s, int* out) {
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(out, h->err, sizeof(int), hipMemcpyDeviceToHost));
+  return OT_GS_OK;
+}
+
+static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out, hipStream_t s) {
+  if (!probs || !out || count < 1) return fail(OT_GS_EINVAL, "create: bad arguments");
+  for (int k = 0; k < count; ++k) {
+    const ot_gs_problem& p = probs[k];
+    if (p.n_src < 1 || p.n_tgt < 1) return fail(OT_GS_EINVAL, "instance %d: n_src and n_tgt must be >= 1", k);
+    if (p.n_groups < 1 || p.n_groups > MAX_GROUPS)
+      return fail(OT_GS_EINVAL, "instance %d: n_groups must lie in [1, %d]", k, MAX_GROUPS);
+    if (!p.labels) return fail(OT_GS_EINVAL, "instance %d: labels is NULL", k);
+    if (!(p.gamma > 0.f) || !std::isfinite(p.gamma)) return fail(OT_GS_EINVAL, "instance %d: gamma must be > 0", k);
+    if (!(p.mu >= 0.f) || !std::isfinite(p.mu)) return fail(OT_GS_EINVAL, "instance %d: mu must be >= 0", k);
+    if (!std::isfinite(p.cost_scale) || p.cost_scale < 0.f)
+      return fail(OT_GS_ENUMERIC, "instance %d: cost_scale must be finite and >= 0", k);
+    if (p.cost_mode == OT_GS_COST_GIVEN) {
+      if (!p.cost) return fail(OT_GS_EINVAL, "instance %d: COST_GIVEN needs cost", k);
+    } else if (p.cost_mode == OT_GS_COST_MATERIALIZE) {
+      if (!p.x_src || !p.x_tgt || p.dim < 1)
+        return fail(OT_GS_EINVAL, "instance %d: COST_MATERIALIZE needs x_src, x_tgt and dim >= 1", k);
+    } else if (p.cost_mode == OT_GS_COST_ONTHEFLY) {
+      return fail(OT_GS_EINVAL, "instance %d: COST_ONTHEFLY is not available in this build", k);
+    } else {
+      return fail(OT_GS_EINVAL, "instance %d: unknown cost_mode %d", k, p.cost_mode);
+    }
+  }
+  auto* h = new ot_gs_handle();
+  std::unique_ptr<ot_gs_handle> guard(h);
+  h->count = count;
+  h->inst.resize(count);
+  HIPCHK(hipGetDevice(&h->dev));
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->dev));
+    h->n_cu = prop.multiProcessorCount;
+  }
+
+  // ---- offsets independent of the group layout
+  long long lab_tot = 0;
+  std::vector<long long> lab_off(count);
+  int maxL = 1;
+  for (int k = 0; k < count; ++k) {
+    const ot_gs_problem& p = probs[k];
+    InstDev& d = h->inst[k].d;
+    std::memset(&d, 0, sizeof d);
+    d.ns = p.n_src;
+    d.nt = p.n_tgt;
+    d.nt_pad = (int)ceil_div(p.n_tgt, TJ) * TJ;
+    d.njb = d.nt_pad / TJ;
+    d.L = p.n_groups;
+    d.row_off = (int)h->tot_rows;
+    d.scol_off = (int)h->tot_cols;
+    d.col_off = (int)h->tot_cols_pad;
+    d.gamma = p.gamma;
+    d.mu = p.mu;
+    d.thr = (float)((double)p.mu * (double)p.gamma);
+    h->inst[k].cost_mode = p.cost_mode;
+    lab_off[k] = lab_tot;
+    lab_tot += p.n_groups;
+    maxL = std::max(maxL, p.n_groups);
+    h->tot_rows += p.n_src;
+    h->tot_cols += p.n_tgt;
+    h->tot_cols_pad += d.nt_pad;
+    if (h->tot_rows > 2000000000LL || h->tot_cols_pad > 2000000000LL)
+      return fail(OT_GS_EINVAL, "total sizes exceed the 32-bit index range");
+  }
+  TRY(h->alloc(&h->err, 1));
+  HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
+
+  // ---- group layout of the rows: histogram, host prefix sums, stable scatter
+  int *labels = nullptr, *cnt = nullptr, *start = nullptr, *keymap = nullptr;
+  SegDesc* segs = nullptr;
+  TRY(h->alloc(&labels, h->tot_rows));
+  TRY(h->alloc(&cnt, lab_tot));
+  TRY(h->alloc(&start, lab_tot));
+  TRY(h->alloc(&keymap, lab_tot));
+  TRY(h->alloc(&segs, count));
+  TRY(h->alloc(&h->perm_row, h->tot_rows));
+  TRY(h->alloc(&h->row_grp, h->tot_rows));
+  std::vector<SegDesc> hseg(count);
+  for (int k = 0; k < count; ++k) {
+    const InstDev& d = h->inst[k].d;
+    HIPCHK(hipMemcpyAsync(labels + d.row_off, probs[k].labels, sizeof(int) * d.ns,
+                          hipMemcpyDeviceToDevice, s));
+    hseg[k] = SegDesc{d.ns, d.L, d.row_off, (int)lab_off[k], d.row_off, 0, 0, 0};
+  }
+  HIPCHK(hipMemcpyAsync(segs, hseg.data(), sizeof(SegDesc) * count, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_histogram, dim3(count), dim3(256), sizeof(int) * maxL, s, segs, labels, cnt, h->err);
+  LAUNCHCHK();
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
+  if (herr & 1) return fail(OT_GS_EINVAL, "a label lies outside [0, n_groups)");
+  std::vector<int> hcnt(lab_tot), hstart(lab_tot), hkey(lab_tot);
+  HIPCHK(hipMemcpy(hcnt.data(), cnt, sizeof(int) * lab_tot, hipMemcpyDeviceToHost));
+  for (int k = 0; k < count; ++k) {
+    InstHost& ih = h->inst[k];
+    int acc = 0, ge = 0;
+    for (int l = 0; l < ih.d.L; ++l) {
+      const int c = hcnt[lab_off[k] + l];
+      hstart[lab_off[k] + l] = acc;
+      hkey[lab_off[k] + l] = c > 0 ? ge : -1;
+      if (c > 0) {
+        ih.g_start.push_back(acc);
+        ih.g_size.push_back(c);
+        ++ge;
+      }
+      acc += c;
+    }
+    ih.d.Le = ge;
+  }
+  HIPCHK(hipMemcpyAsync(start, hstart.data(), sizeof(int) * lab_tot, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(keymap, hkey.data(), sizeof(int) * lab_tot, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_stable_scatter, dim3(count), dim3(WAVE), sizeof(int) * maxL, s, segs, labels,
+                     start, keymap, h->perm_row, h->row_grp);
+  LAUNCHCHK();
+
+  // ---- offsets that depend on the groups
+  for (int k = 0; k < count; ++k) {
+    InstHost& ih = h->inst[k];
+    InstDev& d = ih.d;
+    d.grp_off = (int)h->tot_groups;
+    d.pair_off = (int)h->tot_pairs;
+    d.tile_off = (int)h->tot_tiles;
+    d.c_off = h->tot_c;
+    d.r_off = h->tot_r;
+    d.chunk_off = h->tot_chunk;
+    ih.n_chunk_rows = 0;
+    for (int g = 0; g < d.Le; ++g) {
+      if (ih.g_size[g] > CHUNK) {
+        ih.g_chunk0.push_back(ih.n_chunk_rows);
+        ih.n_chunk_rows += (int)ceil_div(ih.g_size[g], CHUNK);
+      } else {
+        ih.g_chunk0.push_back(-1);
+      }
+    }
+    h->tot_groups += d.Le;
+    h->tot_pairs += (long long)d.Le * d.nt_pad;
+    h->tot_tiles += (long long)d.Le * d.njb;
+    h->tot_c += (long long)d.ns * d.nt_pad;
+    h->tot_r += (long long)d.njb * d.ns;
+    h->tot_chunk += (long long)ih.n_chunk_rows * d.nt_pad;
+    if (h->tot_pairs > 2000000000LL || h->tot_tiles > 2000000000LL)
+      return fail(OT_GS_EINVAL, "total pair count exceeds the 32-bit index range");
+  }
+  {
+    std::vector<int> gs, gn, gc, gi;
+    for (int k = 0; k < count; ++k) {
+      const InstHost& ih = h->inst[k];
+      gs.insert(gs.end(), ih.g_start.begin(), ih.g_start.end());
+      gn.insert(gn.end(), ih.g_size.begin(), ih.g_size.end());
+      gc.insert(gc.end(), ih.g_chunk0.begin(), ih.g_chunk0.end());
+      gi.insert(gi.end(), ih.d.Le, k);
+    }
+    TRY(h->alloc(&h->g_start, gs.size()));
+    TRY(h->alloc(&h->g_size, gs.size()));
+    TRY(h->alloc(&h->g_chunk0, gs.size()));
+    TRY(h->alloc(&h->grp_inst, gs.size()));
+    HIPCHK(hipMemcpyAsync(h->g_start, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->g_size, gn.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->g_chunk0, gc.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->grp_inst, gi.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // ---- cost in the caller's order (given or built from features)
+  std::vector<const float*> hcost(count);
+  std::vector<float*> temps;
+  for (int k = 0; k < count; ++k) {
+    const ot_gs_problem& p = probs[k];
+    if (p.cost_mode == OT_GS_COST_GIVEN) {
+      hcost[k] = p.cost;
+    } else {
+      float* tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, sizeof(float) * (size_t)p.n_src * p.n_tgt));
+      temps.push_back(tmp);
+      dim3 grid((unsigned)ceil_div(p.n_tgt, 64), (unsigned)ceil_div(p.n_src, 64));
+      hipLaunchKernelGGL(k_cost_features, grid, dim3(256), 0, s, p.x_src, p.x_tgt, p.n_src, p.n_tgt,
+                         p.dim, tmp);
+      LAUNCHCHK();
+      hcost[k] = tmp;
+    }
+  }
+  struct TempFree {
+    std::vector<float*>& v;
+    ~TempFree() {
+      for (float* p : v) (void)hipFree(p);
+    }
+  } tfree{temps};
+  const float** d_costs = nullptr;
+  long long* d_sizes = nullptr;
+  unsigned int* d_max = nullptr;
+  float* d_scale = nullptr;
+  TRY(h->alloc(&d_costs, count));
+  TRY(h->alloc(&d_sizes, count));
+  TRY(h->alloc(&d_max, count));
+  TRY(h->alloc(&d_scale, count));
+  std::vector<long long> hsizes(count);
+  long long maxsize = 1;
+  for (int k = 0; k < count; ++k) {
+    hsizes[k] = (long long)probs[k].n_src * probs[k].n_tgt;
+    maxsize = std::max(maxsize, hsizes[k]);
+  }
+  HIPCHK(hipMemcpyAsync(d_costs, hcost.data(), sizeof(float*) * count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_sizes, hsizes.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(d_max, 0, sizeof(unsigned int) * count, s));
+  {
+    dim3 grid((unsigned)std::min<long long>(ceil_div(maxsize, 256 * 8), 2048), count);
+    hipLaunchKernelGGL(k_cost_max, grid, dim3(256), 0, s, d_costs, d_sizes, d_max, h->err);
+    LAUNCHCHK();
+  }
+  TRY(sync_err(h, s, &herr));
+  if (herr & 2) return fail(OT_GS_ENUMERIC, "the cost has a negative, NaN or Inf entry");
+  std::vector<unsigned int> hmax(count);
+  std::vector<float> hscale(count);
+  HIPCHK(hipMemcpy(hmax.data(), d_max, sizeof(unsigned int) * count, hipMemcpyDeviceToHost));
+  for (int k = 0; k < count; ++k) {
+    float cmax;
+    std::memcpy(&cmax, &hmax[k], sizeof cmax);
+    float sc = probs[k].cost_scale;
+    if (sc == 0.f) {
+      if (!(cmax > 0.f)) return fail(OT_GS_ENUMERIC, "instance %d: max C is 0, cannot normalise", k);
+      sc = (float)(1.0 / (double)cmax);
+    }
+    hscale[k] = sc;
+    const float cm = cmax * sc;   // rounding is monotone: max of the scaled cost
+    if (!std::isfinite(cm)) return fail(OT_GS_ENUMERIC, "instance %d: scaled cost overflows", k);
+    h->inst[k].d.cmax = cm;
+  }
+  HIPCHK(hipMemcpyAsync(d_scale, hscale.data(), sizeof(float) * count, hipMemcpyHostToDevice, s));
+
+  // ---- instance descriptors
+  TRY(h->alloc(&h->d_inst, count));
+  {
+    std::vector<InstDev> hd(count);
+    for (int k = 0; k < count; ++k) hd[k] = h->inst[k].d;
+    HIPCHK(hipMemcpyAsync(h->d_inst, hd.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
+  }
+
+  // ---- column clustering: nearest source class, then a stable sort by it
+  int* colkey = nullptr;
+  int *ccnt = nullptr, *cstart = nullptr;
+  SegDesc* csegs = nullptr;
+  TRY(h->alloc(&colkey, h->tot_cols));
+  TRY(h->alloc(&ccnt, std::max<long long>(h->tot_groups, 1)));
+  TRY(h->alloc(&cstart, std::max<long long>(h->tot_groups, 1)));
+  TRY(h->alloc(&csegs, count));
+  TRY(h->alloc(&h->perm_col, h->tot_cols_pad));
+  HIPCHK(hipMemsetAsync(h->perm_col, 0xff, sizeof(int) * h->tot_cols_pad, s));
+  {
+    int maxnt = 1;
+    for (int k = 0; k < count; ++k) maxnt = std::max(maxnt, probs[k].n_tgt);
+    hipLaunchKernelGGL(k_col_assign, dim3((unsigned)ceil_div(maxnt, 256), count), dim3(256), 0, s,
+                       h->d_inst, d_costs, h->perm_row, h->row_grp, colkey);
+    LAUNCHCHK();
+  }
+  std::vector<SegDesc> cseg(count);
+  int maxLe = 1;
+  for (int k = 0; k < count; ++k) {
+    const InstDev& d = h->inst[k].d;
+    cseg[k] = SegDesc{d.nt, d.Le, d.scol_off, d.grp_off, d.col_off, 0, 0, 0};
+    maxLe = std::max(maxLe, d.Le);
+  }
+  HIPCHK(hipMemcpyAsync(csegs, cseg.data(), sizeof(SegDesc) * count, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_histogram, dim3(count), dim3(256), sizeof(int) * maxLe, s, csegs, colkey, ccnt, h->err);
+  LAUNCHCHK();
+  TRY(sync_err(h, s, &herr));
+  if (herr) return fail(OT_GS_EDEVICE, "column clustering produced an invalid key");
+  {
+    std::vector<int> hc(std::max<long long>(h->tot_groups, 1)), hs(hc.size());
+    HIPCHK(hipMemcpy(hc.data(), ccnt, sizeof(int) * h->tot_groups, hipMemcpyDeviceToHost));
+    for (int k = 0; k < count; ++k) {
+      const InstDev& d = h->inst[k].d;
+      int acc = 0;
+      for (int g = 0; g < d.Le; ++g) {
+        hs[d.grp_off + g] = acc;
+        acc += hc[d.grp_off + g];
+      }
+    }
+    HIPCHK(hipMemcpyAsync(cstart, hs.data(), sizeof(int) * h->tot_groups, hipMemcpyHostToDevice, s));
+  }
+  hipLaunchKernelGGL(k_stable_scatter, dim3(count), dim3(WAVE), sizeof(int) * maxLe, s, csegs, colkey,
+                     cstart, (const int*)nullptr, h->perm_col, (int*)nullptr);
+  LAUNCHCHK();
+
+  // ---- internal cost
+  // the gradient kernel may read up to CHUNK rows past a group (masked), so
+  // the pool carries CHUNK zero rows of the widest instance at its end
+  {
+    long long maxntp = 64;
+    for (int k = 0; k < count; ++k) maxntp = std::max<long long>(maxntp, h->inst[k].d.nt_pad);
+    const long long pad = (long long)CHUNK * maxntp;
+    TRY(h->alloc(&h->C, h->tot_c + pad));
+    HIPCHK(hipMemsetAsync(h->C + h->tot_c, 0, sizeof(float) * pad, s));
+  }
+  {
+    int maxns = 1, maxntp = 64;
+    for (int k = 0; k < count; ++k) {
+      maxns = std::max(maxns, h->inst[k].d.ns);
+      maxntp = std::max(maxntp, h->inst[k].d.nt_pad);
+    }
+    dim3 grid((unsigned)std::min<long long>(ceil_div(maxntp, 256), 64), (unsigned)std::min(maxns, 65535), count);
+    hipLaunchKernelGGL(k_relayout_cost, grid, dim3(256), 0, s, h->d_inst, d_costs, d_scale, h->perm_row,
+                       h->perm_col, h->C);
+    LAUNCHCHK();
+  }
+
+  // ---- marginals
+  TRY(h->alloc(&h->a_int, h->tot_rows));
+  TRY(h->alloc(&h->b_int, h->tot_cols_pad));
+  TRY(h->alloc(&h->a_uniform, count));
+  TRY(h->alloc(&h->b_uniform, count));
+  {
+    const float** da = nullptr;
+    const float** db = nullptr;
+    TRY(h->alloc(&da, count));
+    TRY(h->alloc(&db, count));
+    std::vector<const float*> ha(count), hb(count);
+    std::vector<int> ua(count), ub(count);
+    int maxn = 1;
+    for (int k = 0; k < count; ++k) {
+      ha[k] = probs[k].a;
+      hb[k] = probs[k].b;
+      ua[k] = probs[k].a == nullptr;
+      ub[k] = probs[k].b == nullptr;
+      maxn = std::max(maxn, std::max(h->inst[k].d.ns, h->inst[k].d.nt_pad));
+    }
+    HIPCHK(hipMemcpyAsync(da, ha.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(db, hb.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->a_uniform, ua.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->b_uniform, ub.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_marginals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), count),
+                       dim3(256), 0, s, h->d_inst, da, db, h->perm_row, h->perm_col, h->a_int, h->b_int);
+    LAUNCHCHK();
+  }
+
+  // ---- work lists (static for dense evaluations, dynamic for screened ones)
+  {
+    std::vector<TileDesc> all, mainl, sg, sc;
+    for (int k = 0; k < count; ++k) {
+      const InstHost& ih = h->inst[k];
+      for (int g = 0; g < ih.d.Le; ++g) {
+        const int n = ih.g_size[g];
+        const bool split = n > CHUNK;
+        const int nch = (int)ceil_div(n, CHUNK);
+        for (int jb = 0; jb < ih.d.njb; ++jb) {
+          TileDesc t{k, g, jb, split ? -nch : row_class(n)};
+          all.push_back(t);
+          if (!split) {
+            mainl.push_back(t);
+          } else {
+            sg.push_back(TileDesc{k, g, jb, 0});
+            for (int c = 0; c < nch; ++c) sc.push_back(TileDesc{k, g, jb, c});
+          }
+        }
+      }
+    }
+    h->n_main = (int)mainl.size();
+    h->n_sg = (int)sg.size();
+    h->n_sc = (int)sc.size();
+    TRY(h->alloc(&h->tiles_all, all.size()));
+    TRY(h->alloc(&h->list_main, mainl.size()));
+    TRY(h->alloc(&h->list_sg, sg.size()));
+    TRY(h->alloc(&h->list_sc, sc.size()));
+    TRY(h->alloc(&h->dyn_main, mainl.size()));
+    TRY(h->alloc(&h->dyn_sg, sg.size()));
+    TRY(h->alloc(&h->dyn_sc, sc.size()));
+    auto up = [&](TileDesc* dst, const std::vector<TileDesc>& v) -> int {
+      if (!v.empty())
+        HIPCHK(hipMemcpyAsync(dst, v.data(), sizeof(TileDesc) * v.size(), hipMemcpyHostToDevice, s));
+      return OT_GS_OK;
+    };
+    TRY(up(h->tiles_all, all));
+    TRY(up(h->list_main, mainl));
+    TRY(up(h->list_sg, sg));
+    TRY(up(h->list_sc, sc));
+    TRY(h->alloc(&h->counts_static, 3));
+    TRY(h->alloc(&h->counts_dyn, 3));
+    int hc[3] = {h->n_main, h->n_sg, h->n_sc};
+    HIPCHK(hipMemcpyAsync(h->counts_static, hc, sizeof hc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->counts_dyn, 0, sizeof(int) * 3, s));
+  }
+
+  // ---- evaluation state
+  TRY(h->alloc(&h->alpha, h->tot_rows));
+  TRY(h->alloc(&h->beta, h->tot_cols_pad));
+  TRY(h->alloc(&h->ga, h->tot_rows));
+  TRY(h->alloc(&h->gb, h->tot_cols_pad));
+  TRY(h->alloc(&h->alpha_s, h->tot_rows));
+  TRY(h->alloc(&h->beta_s, h->tot_cols_pad));
+  TRY(h->alloc(&h->zsnap, h->tot_pairs));
+  TRY(h->alloc(&h->osnap, h->tot_pairs));
+  TRY(h->alloc(&h->colsum, h->tot_pairs));
+  TRY(h->alloc(&h->kappa, h->tot_pairs));
+  TRY(h->alloc(&h->inN, h->tot_pairs));
+  TRY(h->alloc(&h->rowpart, h->tot_r));
+  TRY(h->alloc(&h->excess, h->tot_pairs));
+  TRY(h->alloc(&h->tile_on, h->tot_tiles));
+  TRY(h->alloc(&h->part, 3 * std::max<long long>(h->tot_chunk, 1)));
+  TRY(h->alloc(&h->gstats, std::max<long long>(h->tot_groups, 1)));
+  TRY(h->alloc(&h->obj, count));
+  TRY(h->alloc(&h->counters, CNT_NUM));
+  TRY(h->alloc(&h->t_off, count));
+  HIPCHK(hipMemsetAsync(h->alpha_s, 0, sizeof(float) * h->tot_rows, s));
+  HIPCHK(hipMemsetAsync(h->beta_s, 0, sizeof(float) * h->tot_cols_pad, s));
+  HIPCHK(hipMemsetAsync(h->zsnap, 0, sizeof(float) * h->tot_pairs, s));
+  HIPCHK(hipMemsetAsync(h->osnap, 0, sizeof(float) * h->tot_pairs, s));
+  HIPCHK(hipMemsetAsync(h->inN, 0, h->tot_pairs, s));
+  HIPCHK(hipMemsetAsync(h->counters, 0, sizeof(long long) * CNT_NUM, s));
+  {
+    std::vector<long long> to(count);
+    long long acc = 0;
+    for (int k = 0; k < count; ++k) {
+      to[k] = acc;
+      acc += (long long)probs[k].n_src * probs[k].n_tgt;
+    }
+    HIPCHK(hipMemcpyAsync(h->t_off, to.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
+  }
+  TRY(sync_err(h, s, &herr));
+  if (herr) return fail(OT_GS_EDEVICE, "setup kernels reported error flags %d", herr);
+  *out = guard.release();
+  return OT_GS_OK;
+}
+
+// ------------------------------------------------------------ evaluation
+
+static GradArgs grad_args(ot_gs_handle* h, int snapshot) {
+  GradArgs A;
+  std::memset(&A, 0, sizeof A);
+  A.inst = h->d_inst;
+  A.g_start = h->g_start;
+  A.g_size = h->g_size;
+  A.g_chunk0 = h->g_chunk0;
+  A.C = h->C;
+  A.alpha = h->alpha;
+  A.beta = h->beta;
+  A.rowpart = h->rowpart;
+  A.colsum = h->colsum;
+  A.excess = h->excess;
+  A.zsnap = h->zsnap;
+  A.osnap = h->osnap;
+  A.part = h->part;
+  A.part_stride = std::max<long long>(h->tot_chunk, 1);
+  A.kappa = h->kappa;
+  A.snapshot = snapshot;
+  return A;
+}
+
+static ScreenArgs screen_args(ot_gs_handle* h, int mode) {
+  ScreenArgs S;
+  std::memset(&S, 0, sizeof S);
+  S.inst = h->d_inst;
+  S.g_start = h->g_start;
+  S.g_size = h->g_size;
+  S.grp_inst = h->grp_inst;
+  S.tiles_all = h->tiles_all;
+  S.n_tiles_all = (int)h->tot_tiles;
+  S.alpha = h->alpha;
+  S.beta = h->beta;
+  S.alpha_s = h->alpha_s;
+  S.beta_s = h->beta_s;
+  S.zsnap = h->zsnap;
+  S.osnap = h->osnap;
+  S.gstats = h->gstats;
+  S.inN = h->inN;
+  S.tile_on = h->tile_on;
+  S.list_main = h->dyn_main;
+  S.list_sg = h->dyn_sg;
+  S.list_sc = h->dyn_sc;
+  S.counts = h->counts_dyn;
+  S.counters = h->counters;
+  S.mode = mode;
+  return S;
+}
+
+static int grid_for(ot_gs_handle* h, int n) {
+  // enough workgroups to fill the chip twice, never more than the list
+  return std::max(1, std::min(n, 2 * h->n_cu));
+}
+
+// Evaluates the dual and its gradient at the internal (alpha, beta) of the
+// handle.  mode: OT_GS_DENSE, OT_GS_SCREENED, OT_GS_SNAPSHOT.  Writes the
+// internal-order gradient (h->ga, h->gb), the objective (h->obj) and, when
+// given, caller-order gradients.
+static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hipStream_t s,
+                    bool write_kappa = false) {
+  const bool screened = mode == OT_GS_SCREENED;
+  const bool snapshot = mode == OT_GS_SNAPSHOT;
+  hipEvent_t e0 = nullptr;
+  // screen (or extraction before a snapshot)
+  if (screened || snapshot) {
+    TRY(tbegin(h, KT_SCREEN, s, &e0));
+    ScreenArgs S = screen_args(h, screened ? 1 : 2);
+    if (h->tot_groups > 0) {
+      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, 4)), dim3(256), 0, s, S);
+      LAUNCHCHK();
+    }
+    TRY(tend(h, KT_SCREEN, s, e0));
+  }
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_EVALS, 1LL);
+  if (snapshot) hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_REFRESH, 1LL);
+  if (!screened) {
+    // dense evaluation covers every pair and tile
+    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_TOTAL, h->tot_tiles);
+    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_COMPUTED, h->tot_tiles);
+  }
+  // gradient tiles
+  TRY(tbegin(h, KT_GRAD, s, &e0));
+  GradArgs A = grad_args(h, snapshot ? 1 : 0);
+  A.write_kappa = write_kappa ? 1 : 0;
+  const int* cnt = screened ? h->counts_dyn : h->counts_static;
+  if (h->n_main > 0) {
+    A.list = screened ? h->dyn_main : h->list_main;
+    A.count = cnt + 0;
+    hipLaunchKernelGGL(k_grad_tiles<0>, dim3(grid_for(h, h->n_main)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+  }
+  if (h->n_sg > 0) {
+    A.list = screened ? h->dyn_sc : h->list_sc;
+    A.count = cnt + 2;
+    hipLaunchKernelGGL(k_grad_tiles<1>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+    A.list = screened ? h->dyn_sg : h->list_sg;
+    A.count = cnt + 1;
+    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
+    LAUNCHCHK();
+    A.list = screened ? h->dyn_sc : h->list_sc;
+    A.count = cnt + 2;
+    hipLaunchKernelGGL(k_grad_tiles<2>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+  }
+  TRY(tend(h, KT_GRAD, s, e0));
+  // assembly
+  TRY(tbegin(h, KT_REDUCE, s, &e0));
+  ReduceArgs R;
+  std::memset(&R, 0, sizeof R);
+  R.inst = h->d_inst;
+  R.row_grp = h->row_grp;
+  R.perm_row = h->perm_row;
+  R.perm_col = h->perm_col;
+  R.rowpart = h->rowpart;
+  R.colsum = h->colsum;
+  R.excess = h->excess;
+  R.tile_on = screened ? h->tile_on : nullptr;
+  R.a_int = h->a_int;
+  R.b_int = h->b_int;
+  R.alpha = h->alpha;
+  R.beta = h->beta;
+  R.ga_int = h->ga;
+  R.gb_int = h->gb;
+  R.ga_out = ga_out;
+  R.gb_out = gb_out;
+  R.obj = h->obj;
+  R.a_uniform = h->a_uniform;
+  R.b_uniform = h->b_uniform;
+  R.err = h->err;
+  int maxns = 1, maxntp = 64;
+  for (auto& ih : h->inst) {
+    maxns = std::max(maxns, ih.d.ns);
+    maxntp = std::max(maxntp, ih.d.nt_pad);
+  }
+  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)std::min<long long>(ceil_div(maxns, 256), 1024), h->count),
+                     dim3(256), 0, s, R);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)std::min<long long>(ceil_div(maxntp, 256), 1024), h->count),
+                     dim3(256), 0, s, R);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_objective, dim3(h->count), dim3(1024), 0, s, R);
+  LAUNCHCHK();
+  TRY(tend(h, KT_REDUCE, s, e0));
+  if (snapshot) {
+    hipLaunchKernelGGL(k_copy2, dim3(256), dim3(256), 0, s, h->alpha, h->alpha_s, h->tot_rows, h->beta,
+                       h->beta_s, h->tot_cols_pad);
+    LAUNCHCHK();
+    h->has_snapshot = true;
+  }
+  return OT_GS_OK;
+}
+
+static int gather(ot_gs_handle* h, const float* alpha, const float* beta, hipStream_t s) {
+  int maxn = 1;
+  for (auto& ih : h->inst) maxn = std::max(maxn, std::max(ih.d.ns, ih.d.nt_pad));
+  hipLaunchKernelGGL(k_gather_duals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), h->count),
+                     dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, alpha, beta, h->alpha, h->beta,
+                     h->err);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+// ------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int ot_gs_create(const ot_gs_problem* probs, int count, ot_gs_handle** out, void* stream) {
+  try {
+    return create_impl(probs, count, out, (hipStream_t)stream);
+  } catch (...) {
+    return fail(OT_GS_ENOMEM, "create: host allocation failed");
+  }
+}
+
+void ot_gs_destroy(ot_gs_handle* h) { delete h; }
+
+int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, float* grad_alpha,
+                    float* grad_beta, double* obj, int mode, void* stream) {
+  if (!h || !alpha || !beta) return fail(OT_GS_EINVAL, "dual_grad: NULL argument");
+  if (mode != OT_GS_DENSE && mode != OT_GS_SCREENED && mode != OT_GS_SNAPSHOT)
+    return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", mode);
+  hipStream_t s = (hipStream_t)stream;
+  TRY(gather(h, alpha, beta, s));
+  TRY(evaluate(h, mode, grad_alpha, grad_beta, s));
+  if (obj) HIPCHK(hipMemcpyAsync(obj, h->obj, sizeof(double) * h->count, hipMemcpyDeviceToDevice, s));
+  return OT_GS_OK;
+}
+
+int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T, void* stream) {
+  if (!h || !alpha || !beta || !T) return fail(OT_GS_EINVAL, "plan: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  TRY(gather(h, alpha, beta, s));
+  TRY(evaluate(h, OT_GS_DENSE, nullptr, nullptr, s, true));
+  int maxns = 1, maxnt = 1;
+  for (auto& ih : h->inst) {
+    maxns = std::max(maxns, ih.d.ns);
+    maxnt = std::max(maxnt, ih.d.nt);
+  }
+  dim3 grid((unsigned)std::min<long long>(ceil_div(maxnt, 256), 16), (unsigned)std::min(maxns, 4096), h->count);
+  hipLaunchKernelGGL(k_plan_dense, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
+                     h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+int ot_gs_rho_to_mu(double gamma, double rho, double* gamma_out, double* mu_out) {
+  if (!(gamma > 0) || !(rho >= 0 && rho < 1)) return fail(OT_GS_EINVAL, "rho must lie in [0,1), gamma > 0");
+  if (gamma_out) *gamma_out = gamma * (1 - rho);
+  if (mu_out) *mu_out = rho / (1 - rho);
+  return OT_GS_OK;
+}
+
+int ot_gs_get_stats(ot_gs_handle* h, ot_gs_stats* out, int reset, void* stream) {
+  if (!h || !out) return fail(OT_GS_EINVAL, "get_stats: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  long long c[CNT_NUM];
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(c, h->counters, sizeof c, hipMemcpyDeviceToHost));
+  out->evals = c[CNT_EVALS];
+  out->pairs_total = c[CNT_PAIRS_TOTAL];
+  out->pairs_in_N = c[CNT_PAIRS_N];
+  out->pairs_checked = c[CNT_PAIRS_CHECKED];
+  out->pairs_unskipped = c[CNT_PAIRS_UNSKIPPED];
+  out->refreshes = c[CNT_REFRESH];
+  out->tiles_total = c[CNT_TILES_TOTAL];
+  out->tiles_computed = c[CNT_TILES_COMPUTED];
+  if (reset) HIPCHK(hipMemset(h->counters, 0, sizeof c));
+  return OT_GS_OK;
+}
+
+int ot_gs_kernel_timing(ot_gs_handle* h, int enable) {
+  if (!h) return fail(OT_GS_EINVAL, "kernel_timing: NULL handle");
+  h->timing.on = enable != 0;
+  return OT_GS_OK;
+}
+
+int ot_gs_kernel_time(ot_gs_handle* h, int which, double* ms, long long* launches) {
+  if (!h || which < 0 || which >= KT_NUM) return fail(OT_GS_EINVAL, "kernel_time: bad arguments");
+  auto& v = h->timing.ev[which];
+  for (auto& e : v) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e.first, e.second));
+    h->timing.ms[which] += t;
+    h->timing.n[which] += 1;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  v.clear();
+  if (ms) *ms = h->timing.ms[which];
+  if (launches) *launches = h->timing.n[which];
+  h->timing.ms[which] = 0;
+  h->timing.n[which] = 0;
+  return OT_GS_OK;
+}
+
+int ot_gs_layout_info(ot_gs_handle* h, int k, int* n_groups_nonempty, int* n_tgt_padded, int* n_tiles) {
+  if (!h || k < 0 || k >= h->count) return fail(OT_GS_EINVAL, "layout_info: bad arguments");
+  const InstDev& d = h->inst[k].d;
+  if (n_groups_nonempty) *n_groups_nonempty = d.Le;
+  if (n_tgt_padded) *n_tgt_padded = d.nt_pad;
+  if (n_tiles) *n_tiles = d.Le * d.njb;
+  return OT_GS_OK;
+}
+
+const char* ot_gs_last_error(void) { return g_err.c_str(); }
+
+const char* ot_gs_version(void) { return "otgs 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+extern "C" {
+
+int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* alpha_io, float* beta_io,
+                ot_gs_info* info, void* stream) {
+  (void)h; (void)opts; (void)alpha_io; (void)beta_io; (void)info; (void)stream;
+  return fail(OT_GS_EINVAL, "solve: not available yet");
+}
+
+void ot_gs_default_options(ot_gs_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->max_iter = 200;
+  o->hist = 10;
+  o->refresh = 10;
+  o->use_screen = 1;
+  o->use_lower = 1;
+  o->max_ls = 40;
+  o->init_user = 0;
+  o->c1 = 1e-4;
+  o->c2 = 0.9;
+  o->gtol = 0.0;
+  o->obj_trace = nullptr;
+}
+
+}  // extern "C"

@@ -1,0 +1,443 @@
+// The hot path: fused dual-gradient tiles, the fixed-order reductions that
+// assemble grad_alpha = a - T 1, grad_beta = b - T^T 1 and the objective of
+// the smooth relaxed dual (Eq. 4).
+//
+// Gradient tile (group l, 64 target columns j, one column per lane): every
+// lane streams the cost column segment of all rows of the group, forms
+// f = (alpha_i + beta_j) - c_ij and p = max(f, 0) in registers, accumulates
+// z^2 = sum p^2 and s1 = sum p; the 16 wavefronts combine their partial
+// sums through LDS in a fixed order; then
+//     kappa = (z - mu gamma) / (gamma z)   if z > mu gamma, else 0
+// is the group soft threshold of Eq. 5 (T_ij = kappa p_ij), the column sum of
+// the block is kappa s1, the block's share of psi is (z - mu gamma)^2/(2 gamma)
+// and the row sums sum_j kappa_j p_ij are wavefront reductions over lanes.
+// Groups up to 512 rows keep p in registers (R rows per lane, R in
+// {1,...,32}); larger groups are cut in chunks of 512 rows: one pass writes
+// per-chunk column sums, a combine step forms kappa, a second pass re-reads
+// the chunk and forms the row sums.
+// Every reduction has a fixed order and there are no floating-point atomics,
+// so a tile gives bit-identical results whichever mode requested it; skipped
+// tiles contribute exact zeros, hence screened == dense bit for bit.
+#include "otgs_internal.h"
+
+namespace otgs {
+
+struct GradArgs {
+  const InstDev* inst;
+  const int* g_start;
+  const int* g_size;
+  const int* g_chunk0;    // first chunk row of a split group (-1: not split)
+  const TileDesc* list;   // work list
+  const int* count;       // number of entries (device)
+  const float* C;
+  const float* alpha;     // internal order
+  const float* beta;      // internal order, padded
+  float* rowpart;
+  float* colsum;
+  float* excess;          // [z - mu gamma]_+ per pair (objective: excess^2/(2 gamma))
+  float* zsnap;           // snapshot outputs (snapshot != 0)
+  float* osnap;
+  float* part;            // split chunks: [3][chunk pair] column partial sums
+  long long part_stride;  // elements per partial kind
+  float* kappa;           // split groups: kappa per pair
+  int snapshot;
+  int write_kappa;        // also store kappa per pair (plan recovery)
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over the 16 lanes of each lane row (DPP row shifts); lane 15 of every
+// row ends with the row's total.  Fixed order: deterministic.
+__device__ __forceinline__ float row16_sum(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, false));
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, false));
+  return x;
+}
+
+// Row sums of a register tile: v[k] holds row k's value in every lane; the
+// sum over the 64 lanes of each row is formed with a transposed butterfly:
+// a permlane32 swap pairs row i with row i + RP/2 (lower lanes keep row i,
+// upper lanes row i + RP/2), a permlane16 swap pairs rows i and i + RP/4 the
+// same way, and DPP row shifts finish within 16 lanes.  Afterwards lane
+// 16 q + 15 holds the total of row i + q RP/4 in x[i].
+template <int RP>
+__device__ __forceinline__ void transposed_row_sums(float (&v)[RP], float (&x)[RP / 4]) {
+  constexpr int H = RP / 2, Q = RP / 4;
+  float w[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + H]),
+                                                    false, false);
+    w[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[i]), __float_as_uint(w[i + Q]),
+                                                    false, false);
+    x[i] = row16_sum(__uint_as_float(r[0]) + __uint_as_float(r[1]));
+  }
+}
+
+// PHASE 0: whole group; 1: split chunk, column partials; 2: split chunk, rows.
+// R rows per lane: row k of wavefront w is r0 + w + NW k (NW R >= rows).
+template <int R, int PHASE>
+__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
+                                          float (*red)[NW][TJ]) {
+  const InstDev I = A.inst[d.inst];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gs = A.g_start[I.grp_off + d.grp];
+  const int gn = A.g_size[I.grp_off + d.grp];
+  int r0 = gs, r1 = gs + gn;
+  if (PHASE != 0) {
+    r0 = gs + d.aux * CHUNK;
+    r1 = min(r0 + CHUNK, r1);
+  }
+  const int col = d.jb * TJ + lane;
+  const bool colok = col < I.nt;
+  const float bj = A.beta[I.col_off + col];
+  const bool snap = A.snapshot != 0 && PHASE != 2;
+  const int rw = r0 + w;
+  // rows of this wavefront inside the tile (wave-uniform)
+  const int nk = rw < r1 ? min(R, (r1 - rw + NW - 1) / NW) : 0;
+  // alpha of row k sits in lane k
+  const float av = (lane < nk) ? A.alpha[I.row_off + rw + NW * lane] : 0.f;
+  // Raw buffer loads: scalar descriptor at this wavefront's first row, one
+  // per-lane byte offset (the column) and a scalar offset per row.  Rows past
+  // the tile re-read the last valid row (a cache hit) and are masked below.
+  const float* Cw = A.C + I.c_off + (size_t)rw * I.nt_pad + (size_t)d.jb * TJ;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
+  const int stride_b = __builtin_amdgcn_readfirstlane(NW * I.nt_pad * 4);
+  const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
+
+  float p[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    p[k] = __uint_as_float(
+        __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float ak = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), k));
+    const float f = (ak + bj) - p[k];
+    const bool ok = (k < nk) && colok;
+    const float pk = ok ? fmaxf(f, 0.f) : 0.f;
+    if (PHASE != 2) {
+      z2 = fmaf(pk, pk, z2);
+      s1 += pk;
+      if (snap) {
+        const float nkv = ok ? fminf(f, 0.f) : 0.f;
+        o2 = fmaf(nkv, nkv, o2);
+      }
+    }
+    p[k] = pk;
+  }
+
+  float kap = 0.f;
+  if (PHASE != 2) {
+    red[0][w][lane] = z2;
+    red[1][w][lane] = s1;
+    if (snap) red[2][w][lane] = o2;
+    __syncthreads();
+    float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+#pragma unroll 4
+    for (int v = 0; v < NW; ++v) {
+      Z2 += red[0][v][lane];
+      S1 += red[1][v][lane];
+    }
+    if (snap) {
+#pragma unroll 4
+      for (int v = 0; v < NW; ++v) O2 += red[2][v][lane];
+    }
+    if (PHASE == 1) {
+      // column partial sums of chunk `aux` of a split group
+      if (w == 0) {
+        const long long q = I.chunk_off +
+                            (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
+        A.part[q] = Z2;
+        A.part[q + A.part_stride] = S1;
+        A.part[q + 2 * A.part_stride] = O2;
+      }
+      return;
+    }
+    const float z = sqrtf(Z2);
+    float num = 0.f;
+    if (z > I.thr) {
+      num = z - I.thr;
+      kap = num / (I.gamma * z);
+    }
+    if (w == 0) {
+      const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+      A.colsum[pr] = kap * S1;
+      A.excess[pr] = num;
+      if (A.write_kappa) A.kappa[pr] = kap;
+      if (snap) {
+        A.zsnap[pr] = z;
+        A.osnap[pr] = sqrtf(O2);
+      }
+    }
+  } else {
+    kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
+  }
+
+  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + rw;
+  if (__ballot(kap > 0.f) == 0ull) {
+    // every block of the tile is zero: its row sums are exact zeros
+    if (lane < nk) rp[NW * lane] = 0.f;
+    return;
+  }
+  constexpr int RP = R < 4 ? 4 : (R + 3) / 4 * 4;
+  constexpr int Q = RP / 4;
+  float v[RP];
+#pragma unroll
+  for (int k = 0; k < RP; ++k) v[k] = (k < R) ? kap * p[(k < R) ? k : 0] : 0.f;
+  float x[Q];
+  transposed_row_sums<RP>(v, x);
+  if ((lane & 15) == 15) {
+    const int q = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int k = i + q * Q;
+      if (k < nk) rp[NW * k] = x[i];
+    }
+  }
+}
+
+template <int PHASE>
+__global__ void __launch_bounds__(BLOCK) k_grad_tiles(GradArgs A) {
+  __shared__ float red[3][NW][TJ];
+  const int n = *A.count;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TileDesc d = A.list[t];
+    if (PHASE == 0) {
+      switch (d.aux) {
+#define OTGS_CASE(r) \
+  case r:            \
+    grad_tile<r, 0>(A, d, red); \
+    break;
+        OTGS_CASE(1) OTGS_CASE(2) OTGS_CASE(3) OTGS_CASE(4) OTGS_CASE(5) OTGS_CASE(6)
+        OTGS_CASE(7) OTGS_CASE(8) OTGS_CASE(9) OTGS_CASE(10) OTGS_CASE(11) OTGS_CASE(12)
+        OTGS_CASE(13) OTGS_CASE(14) OTGS_CASE(15) OTGS_CASE(16) OTGS_CASE(17) OTGS_CASE(18)
+        OTGS_CASE(19) OTGS_CASE(20) OTGS_CASE(21) OTGS_CASE(22) OTGS_CASE(23) OTGS_CASE(24)
+        OTGS_CASE(25) OTGS_CASE(26) OTGS_CASE(27) OTGS_CASE(28) OTGS_CASE(29) OTGS_CASE(30)
+        OTGS_CASE(31)
+#undef OTGS_CASE
+        default: grad_tile<32, 0>(A, d, red); break;
+      }
+    } else {
+      grad_tile<RMAX, PHASE>(A, d, red);
+    }
+    __syncthreads();
+  }
+}
+
+
+// Split groups: combine the chunk partials of every listed (group, column
+// block) in chunk order and finalise kappa, the column sums, the objective
+// share and the snapshot, exactly as the single-pass tile does.  One
+// wavefront per entry (blockDim 64); entries are group tiles (aux unused).
+__global__ void __launch_bounds__(WAVE) k_split_combine(GradArgs A) {
+  const int n = *A.count;
+  const int lane = threadIdx.x;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TileDesc d = A.list[t];
+    const InstDev I = A.inst[d.inst];
+    const int gn = A.g_size[I.grp_off + d.grp];
+    const int nch = (gn + CHUNK - 1) / CHUNK;
+    const int col = d.jb * TJ + lane;
+    const long long q0 =
+        I.chunk_off + (long long)A.g_chunk0[I.grp_off + d.grp] * I.nt_pad + col;
+    float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      const long long q = q0 + (long long)c * I.nt_pad;
+      Z2 += A.part[q];
+      S1 += A.part[q + A.part_stride];
+      O2 += A.part[q + 2 * A.part_stride];
+    }
+    const float z = sqrtf(Z2);
+    float num = 0.f, kap = 0.f;
+    if (z > I.thr) {
+      num = z - I.thr;
+      kap = num / (I.gamma * z);
+    }
+    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+    A.kappa[pr] = kap;
+    A.colsum[pr] = kap * S1;
+    A.excess[pr] = num;
+    if (A.snapshot) {
+      A.zsnap[pr] = z;
+      A.osnap[pr] = sqrtf(O2);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- assembly
+
+struct ReduceArgs {
+  const InstDev* inst;
+  const int* row_grp;
+  const int* perm_row;
+  const int* perm_col;
+  const float* rowpart;
+  const float* colsum;
+  const float* excess;
+  const uint8_t* tile_on;   // NULL: every tile was evaluated (dense)
+  const float* a_int;
+  const float* b_int;
+  const float* alpha;       // internal order
+  const float* beta;
+  float* ga_int;            // internal-order gradients (may be NULL)
+  float* gb_int;
+  float* ga_out;            // caller-order gradients (may be NULL)
+  float* gb_out;
+  double* obj;              // [count]
+  const int* a_uniform;     // per instance flags
+  const int* b_uniform;
+  int* err;
+};
+
+// grad_alpha_r = a_r - sum over column blocks of the row partials, in block
+// order, counting only evaluated tiles.  grid.x rows / 256, grid.y instance.
+__global__ void __launch_bounds__(256) k_reduce_rows(ReduceArgs A) {
+  const InstDev I = A.inst[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
+    const int g = A.row_grp[I.row_off + r];
+    const float* rp = A.rowpart + I.r_off + r;
+    const uint8_t* on = A.tile_on ? A.tile_on + I.tile_off + (size_t)g * I.njb : nullptr;
+    float s = 0.f;
+    for (int jb = 0; jb < I.njb; ++jb)
+      if (!on || on[jb]) s += rp[(size_t)jb * I.ns];
+    const float gval = A.a_int[I.row_off + r] - s;
+    if (A.ga_int) A.ga_int[I.row_off + r] = gval;
+    if (A.ga_out) A.ga_out[I.row_off + A.perm_row[I.row_off + r]] = gval;
+  }
+}
+
+// grad_beta_c = b_c - sum over groups of the column sums, in group order.
+__global__ void __launch_bounds__(256) k_reduce_cols(ReduceArgs A) {
+  const InstDev I = A.inst[blockIdx.y];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
+    const int jb = c / TJ;
+    float s = 0.f;
+    for (int g = 0; g < I.Le; ++g) {
+      if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + jb]) continue;
+      s += A.colsum[(size_t)I.pair_off + (size_t)g * I.nt_pad + c];
+    }
+    const float gval = (c < I.nt) ? A.b_int[I.col_off + c] - s : 0.f;
+    if (A.gb_int) A.gb_int[I.col_off + c] = gval;
+    if (A.gb_out && c < I.nt) A.gb_out[I.scol_off + A.perm_col[I.col_off + c]] = gval;
+  }
+}
+
+// D = a.alpha + b.beta - sum psi, float64, fixed-order block reduction; one
+// block of 1024 threads per instance.  Uniform marginals use 1/n in float64.
+__global__ void __launch_bounds__(1024) k_objective(ReduceArgs A) {
+  __shared__ double red[1024];
+  const int k = blockIdx.x;
+  const InstDev I = A.inst[k];
+  const double ua = 1.0 / (double)I.ns, ub = 1.0 / (double)I.nt;
+  const bool au = A.a_uniform[k] != 0, bu = A.b_uniform[k] != 0;
+  double s = 0.0;
+  for (int r = threadIdx.x; r < I.ns; r += blockDim.x)
+    s += (au ? ua : (double)A.a_int[I.row_off + r]) * (double)A.alpha[I.row_off + r];
+  for (int c = threadIdx.x; c < I.nt; c += blockDim.x)
+    s += (bu ? ub : (double)A.b_int[I.col_off + c]) * (double)A.beta[I.col_off + c];
+  // psi terms: sum over evaluated pairs of excess^2 / (2 gamma)
+  double ps = 0.0;
+  const long long npair = (long long)I.Le * I.nt_pad;
+  for (long long q = threadIdx.x; q < npair; q += blockDim.x) {
+    const int g = (int)(q / I.nt_pad), c = (int)(q % I.nt_pad);
+    if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + c / TJ]) continue;
+    const double e = A.excess[(size_t)I.pair_off + q];
+    ps += e * e;
+  }
+  s -= ps * (0.5 / (double)I.gamma);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double D = red[0];
+    if (!isfinite(D)) atomicOr(A.err, 4);
+    if (A.obj) A.obj[k] = D;
+  }
+}
+
+// caller-order (alpha, beta) -> internal order; padding columns get 0.
+// Flags non-finite inputs.  grid.y instance.
+__global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict__ inst,
+                                                      const int* __restrict__ perm_row,
+                                                      const int* __restrict__ perm_col,
+                                                      const float* __restrict__ alpha,
+                                                      const float* __restrict__ beta,
+                                                      float* __restrict__ al_int,
+                                                      float* __restrict__ be_int,
+                                                      int* __restrict__ err) {
+  const InstDev I = inst[blockIdx.y];
+  bool bad = false;
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
+    const float v = alpha[I.row_off + perm_row[I.row_off + r]];
+    bad |= !isfinite(v);
+    al_int[I.row_off + r] = v;
+  }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (c < I.nt) v = beta[I.scol_off + perm_col[I.col_off + c]];
+    bad |= !isfinite(v);
+    be_int[I.col_off + c] = v;
+  }
+  if (bad) atomicOr(err, 8);
+}
+
+// internal order -> caller order
+__global__ void __launch_bounds__(256) k_scatter_duals(const InstDev* __restrict__ inst,
+                                                       const int* __restrict__ perm_row,
+                                                       const int* __restrict__ perm_col,
+                                                       const float* __restrict__ al_int,
+                                                       const float* __restrict__ be_int,
+                                                       float* __restrict__ alpha,
+                                                       float* __restrict__ beta) {
+  const InstDev I = inst[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x)
+    alpha[I.row_off + perm_row[I.row_off + r]] = al_int[I.row_off + r];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt; c += gridDim.x * blockDim.x)
+    beta[I.scol_off + perm_col[I.col_off + c]] = be_int[I.col_off + c];
+}
+
+// Dense plan in the caller's order (Sec. 2.3): T[i][j] = kappa_lj max(f_ij, 0)
+// with kappa_lj written per pair by a preceding dense evaluation.
+// grid.x columns / 256, grid.y rows (strided), grid.z instance.
+__global__ void __launch_bounds__(256) k_plan_dense(const InstDev* __restrict__ inst,
+                                                    const int* __restrict__ perm_row,
+                                                    const int* __restrict__ perm_col,
+                                                    const int* __restrict__ row_grp,
+                                                    const float* __restrict__ C,
+                                                    const float* __restrict__ alpha,
+                                                    const float* __restrict__ beta,
+                                                    const float* __restrict__ kappa,
+                                                    const long long* __restrict__ t_off,
+                                                    float* __restrict__ T) {
+  const InstDev I = inst[blockIdx.z];
+  for (int r = blockIdx.y; r < I.ns; r += gridDim.y) {
+    const int g = row_grp[I.row_off + r];
+    const float a = alpha[I.row_off + r];
+    float* trow = T + t_off[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
+    const float* crow = C + I.c_off + (size_t)r * I.nt_pad;
+    const float* krow = kappa + I.pair_off + (size_t)g * I.nt_pad;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt; c += gridDim.x * blockDim.x) {
+      const float f = (a + beta[I.col_off + c]) - crow[c];
+      trow[perm_col[I.col_off + c]] = krow[c] * fmaxf(f, 0.f);
+    }
+  }
+}
+
+}  // namespace otgs

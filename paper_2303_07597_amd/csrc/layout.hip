@@ -1,0 +1,191 @@
+// Setup kernels: group layout of the source rows (stable counting sort by
+// label), clustering of the target columns by nearest source class, the cost
+// in the internal layout, marginals.  All run once per handle.
+#include "otgs_internal.h"
+
+namespace otgs {
+
+// ---------------------------------------------------------------- sorting
+
+// Histogram of integer keys in [0, K) of each segment; one block per segment.
+__global__ void k_histogram(const SegDesc* __restrict__ segs, const int* __restrict__ keys,
+                            int* __restrict__ counts, int* __restrict__ err) {
+  extern __shared__ int h[];
+  const SegDesc s = segs[blockIdx.x];
+  for (int l = threadIdx.x; l < s.K; l += blockDim.x) h[l] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < s.n; i += blockDim.x) {
+    const int key = keys[s.key_off + i];
+    if (key < 0 || key >= s.K) {
+      atomicOr(err, 1);
+      continue;
+    }
+    atomicAdd(&h[key], 1);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < s.K; l += blockDim.x) counts[s.kt_off + l] = h[l];
+}
+
+// Stable scatter: position of element i = start[key] + number of earlier
+// elements with the same key.  One wavefront per segment walks the keys in
+// order, 64 at a time; lanes holding equal keys are found with ballots over
+// the key bits.  out_perm[pos] = i, out_key[pos] = keymap[key].
+__global__ void __launch_bounds__(WAVE) k_stable_scatter(
+    const SegDesc* __restrict__ segs, const int* __restrict__ keys,
+    const int* __restrict__ start, const int* __restrict__ keymap,
+    int* __restrict__ out_perm, int* __restrict__ out_key) {
+  extern __shared__ int cur[];
+  const SegDesc s = segs[blockIdx.x];
+  const int lane = threadIdx.x;
+  for (int l = lane; l < s.K; l += WAVE) cur[l] = start[s.kt_off + l];
+  __syncthreads();
+  int nbits = 1;
+  while ((1 << nbits) < s.K) ++nbits;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int base = 0; base < s.n; base += WAVE) {
+    const int i = base + lane;
+    const bool v = i < s.n;
+    const int key = v ? keys[s.key_off + i] : 0;
+    unsigned long long peers = __ballot(v);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (key >> b) & 1;
+      const unsigned long long m = __ballot(v && bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & below);
+    int pos = 0;
+    if (v) {
+      pos = cur[key] + rank;
+      out_perm[s.out_off + pos] = i;
+      if (out_key) out_key[s.out_off + pos] = keymap ? keymap[s.kt_off + key] : key;
+    }
+    __syncthreads();
+    if (v && rank == 0) cur[key] += __popcll(peers);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- cost
+
+// max over a nonnegative float array, per instance (grid.y); flags negative,
+// NaN or Inf values.  Result as float bits through an integer atomic max,
+// which orders nonnegative floats correctly and is order independent.
+__global__ void k_cost_max(const float* const* __restrict__ costs, const long long* __restrict__ sizes,
+                           unsigned int* __restrict__ maxbits, int* __restrict__ err) {
+  const int k = blockIdx.y;
+  const float* c = costs[k];
+  const long long n = sizes[k];
+  float m = 0.f;
+  bool bad = false;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float x = c[i];
+    bad |= !(x >= 0.f) || isinf(x);
+    m = fmaxf(m, x);
+  }
+  if (bad) atomicOr(err, 2);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(&maxbits[k], __float_as_uint(m));
+}
+
+// Squared Euclidean cost from features in the caller's order (materialised
+// provider): c_ij = sum_k (x_ik - y_jk)^2, float32, 16x16 threads per 64x64
+// block with both feature tiles staged in LDS.
+__global__ void __launch_bounds__(256) k_cost_features(const float* __restrict__ xs,
+                                                       const float* __restrict__ xt, int ns,
+                                                       int nt, int d, float* __restrict__ C) {
+  constexpr int TB = 64, KB = 32;
+  __shared__ float sx[KB][TB + 1];
+  __shared__ float sy[KB][TB + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < d; k0 += KB) {
+    for (int e = threadIdx.x; e < TB * KB; e += 256) {
+      const int rr = e / KB, kk = e % KB;
+      const int gi = i0 + rr, gj = j0 + rr, gk = k0 + kk;
+      sx[kk][rr] = (gi < ns && gk < d) ? xs[(size_t)gi * d + gk] : 0.f;
+      sy[kk][rr] = (gj < nt && gk < d) ? xt[(size_t)gj * d + gk] : 0.f;
+    }
+    __syncthreads();
+    const int kmax = min(KB, d - k0);
+    for (int kk = 0; kk < kmax; ++kk) {
+      float xv[4], yv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = sx[kk][ty + 16 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) yv[u] = sy[kk][tx + 16 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float t = xv[u] - yv[v];
+          acc[u][v] = fmaf(t, t, acc[u][v]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
+      if (gi < ns && gj < nt) C[(size_t)gi * nt + gj] = acc[u][v];
+    }
+}
+
+// For every target column j (grid.x) of instance k (grid.y): the nonempty
+// group holding the source row of least cost (first such group on ties).
+__global__ void k_col_assign(const InstDev* __restrict__ inst, const float* const* __restrict__ costs,
+                             const int* __restrict__ perm_row, const int* __restrict__ row_grp,
+                             int* __restrict__ colkey) {
+  const InstDev I = inst[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= I.nt) return;
+  const float* c = costs[blockIdx.y];
+  float best = INFINITY;
+  int bg = 0;
+  for (int r = 0; r < I.ns; ++r) {
+    const float v = c[(size_t)perm_row[I.row_off + r] * I.nt + j];
+    const int g = row_grp[I.row_off + r];
+    if (v < best) {
+      best = v;
+      bg = g;
+    }
+  }
+  colkey[I.scol_off + j] = bg;
+}
+
+// Internal cost: C_int[r][c] = fl32(C[perm_row[r]][perm_col[c]] * scale), 0 on
+// padding columns.  grid.x: columns / 256, grid.y: rows, grid.z: instance.
+__global__ void k_relayout_cost(const InstDev* __restrict__ inst, const float* const* __restrict__ costs,
+                                const float* __restrict__ scales, const int* __restrict__ perm_row,
+                                const int* __restrict__ perm_col, float* __restrict__ Cint) {
+  const InstDev I = inst[blockIdx.z];
+  const int r = blockIdx.y;
+  if (r >= I.ns) return;
+  const float s = scales[blockIdx.z];
+  const float* src = costs[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
+  float* dst = Cint + I.c_off + (size_t)r * I.nt_pad;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (c < I.nt) v = src[perm_col[I.col_off + c]] * s;
+    dst[c] = v;
+  }
+}
+
+// Marginals in the internal order (float32); uniform ones are 1/n.
+__global__ void k_marginals(const InstDev* __restrict__ inst, const float* const* __restrict__ a_src,
+                            const float* const* __restrict__ b_src, const int* __restrict__ perm_row,
+                            const int* __restrict__ perm_col, float* __restrict__ a_int,
+                            float* __restrict__ b_int) {
+  const InstDev I = inst[blockIdx.y];
+  const float* a = a_src[blockIdx.y];
+  const float* b = b_src[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x)
+    a_int[I.row_off + r] = a ? a[perm_row[I.row_off + r]] : 1.0f / (float)I.ns;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x)
+    b_int[I.col_off + c] = (c < I.nt) ? (b ? b[perm_col[I.col_off + c]] : 1.0f / (float)I.nt) : 0.f;
+}
+
+}  // namespace otgs

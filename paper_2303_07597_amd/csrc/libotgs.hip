@@ -1,0 +1,6 @@
+// Single translation unit of libotgs (kernels and host code), compiled by
+// hipcc for gfx950 into a shared library with the C ABI of include/otgs.h.
+#include "layout.hip"
+#include "grad.hip"
+#include "screen.hip"
+#include "api.hip"

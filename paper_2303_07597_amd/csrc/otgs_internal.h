@@ -1,0 +1,81 @@
+// Internal declarations shared by the HIP translation units of libotgs.
+// Device layout (all arrays packed over the instances of a handle):
+//   rows    - source rows sorted by label (stable), instance k at row_off;
+//             perm_row maps an internal row to the caller's row.
+//   columns - target columns clustered by nearest source class (stable),
+//             padded to a multiple of TJ, instance k at col_off; perm_col
+//             maps an internal column to the caller's column (-1 = pad).
+//   groups  - nonempty label groups, instance k at grp_off: first internal
+//             row and size.
+//   pairs   - (group, padded column) arrays, [Le x nt_pad] at pair_off.
+//   tiles   - (group, block of TJ columns), [Le x njb] at tile_off.
+//   cost    - C in the internal layout, [ns x nt_pad] at c_off.
+//   rowpart - row partial sums of T per column block, [njb x ns] at r_off.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace otgs {
+
+constexpr int WAVE = 64;
+constexpr int TJ = 64;                 // target columns per tile (one per lane)
+constexpr int NW = 16;                 // waves per gradient workgroup
+constexpr int BLOCK = NW * WAVE;       // 1024 threads
+constexpr int RMAX = 32;               // rows per thread in the largest class
+constexpr int CHUNK = NW * RMAX;       // 512: largest group handled in one pass
+constexpr int NCLASS = 32;             // row classes R = 1..32 rows per lane
+constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
+
+struct InstDev {
+  int ns, nt, nt_pad, njb;
+  int L;          // label range
+  int Le;         // nonempty groups
+  int row_off;    // packed row arrays (also the caller's row offset)
+  int col_off;    // packed padded column arrays
+  int scol_off;   // caller's packed column offset
+  int grp_off;    // packed group arrays
+  int pair_off;   // packed pair arrays
+  int tile_off;   // packed tile arrays
+  int pad0;
+  long long chunk_off;  // split-chunk partial table offset (floats)
+  long long c_off;  // cost pool offset (floats)
+  long long r_off;  // row-partial pool offset (floats)
+  float gamma, mu, thr;  // thr = fl32(mu * gamma)
+  float cmax;            // max of the internal (scaled) cost
+};
+
+// A segment of keys for the stable counting sort: n keys in [0, K) at
+// key_off, key tables (counts / starts) at kt_off, output at out_off.
+struct SegDesc {
+  int n, K, key_off, kt_off, out_off, pad0, pad1, pad2;
+};
+
+// A unit of work of the gradient kernel: (instance, group, column block)
+// plus the row class (whole-group tiles) or the chunk index (split groups).
+struct TileDesc {
+  int inst, grp, jb, aux;
+};
+
+// Per-group statistics of the change since the snapshot, in float64.
+struct GroupStats {
+  double up;        // || [alpha - alpha~]_+ ||  over the group
+  double dn;        // || [alpha - alpha~]_- ||
+  double all;       // || alpha - alpha~ ||
+  double amax;      // max |alpha_i| over the group (current point)
+  double amax_s;    // max |alpha~_i| over the group (snapshot)
+  double pad[3];
+};
+
+// Device-side counters (int64, integer atomics only).
+enum Counter {
+  CNT_EVALS = 0, CNT_PAIRS_TOTAL, CNT_PAIRS_N, CNT_PAIRS_CHECKED, CNT_PAIRS_UNSKIPPED,
+  CNT_REFRESH, CNT_TILES_TOTAL, CNT_TILES_COMPUTED, CNT_NUM
+};
+
+// pair state written by the screen / extraction kernels
+enum PairFlag : uint8_t { PAIR_SKIP = 0, PAIR_CHECK = 1, PAIR_IN_N = 2 };
+
+// rows per lane of a whole-group tile: smallest R with NW R >= rows
+__host__ __device__ inline int row_class(int rows) { return rows <= NW ? 1 : (rows + NW - 1) / NW; }
+
+}  // namespace otgs

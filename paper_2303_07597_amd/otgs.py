@@ -1,0 +1,233 @@
+"""ctypes binding of libotgs (include/otgs.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libotgs.so``.  Device arrays are torch tensors on the GPU; the
+binding passes their data pointers and the current HIP stream.  Importing
+this module on a machine where the library was not built raises
+``OSError`` - there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotgs.so")
+
+OT_GS_OK = 0
+OT_GS_EINVAL = -1
+OT_GS_ESHAPE = -2
+OT_GS_EDEVICE = -3
+OT_GS_ENUMERIC = -4
+OT_GS_ENOMEM = -5
+OT_GS_NOT_CONVERGED = 1
+OT_GS_LINESEARCH = 2
+
+OT_GS_DENSE = 0
+OT_GS_SCREENED = 1
+OT_GS_SNAPSHOT = 2
+
+OT_GS_COST_GIVEN = 0
+OT_GS_COST_MATERIALIZE = 1
+OT_GS_COST_ONTHEFLY = 2
+
+KERNEL_GRAD, KERNEL_SCREEN, KERNEL_REDUCE, KERNEL_LBFGS = 0, 1, 2, 3
+
+
+class ot_gs_problem(ct.Structure):
+    _fields_ = [("n_src", ct.c_int), ("n_tgt", ct.c_int), ("dim", ct.c_int), ("n_groups", ct.c_int),
+                ("labels", ct.c_void_p), ("cost_mode", ct.c_int), ("cost", ct.c_void_p),
+                ("x_src", ct.c_void_p), ("x_tgt", ct.c_void_p), ("cost_scale", ct.c_float),
+                ("a", ct.c_void_p), ("b", ct.c_void_p), ("gamma", ct.c_float), ("mu", ct.c_float)]
+
+
+class ot_gs_stats(ct.Structure):
+    _fields_ = [(n, ct.c_longlong) for n in ("evals", "pairs_total", "pairs_in_N", "pairs_checked",
+                                             "pairs_unskipped", "refreshes", "tiles_total",
+                                             "tiles_computed")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class ot_gs_options(ct.Structure):
+    _fields_ = [("max_iter", ct.c_int), ("hist", ct.c_int), ("refresh", ct.c_int),
+                ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
+                ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
+                ("gtol", ct.c_double), ("obj_trace", ct.c_void_p)]
+
+
+class ot_gs_info(ct.Structure):
+    _fields_ = [("iters", ct.c_int), ("evals", ct.c_int), ("status", ct.c_int),
+                ("obj", ct.c_double), ("gnorm_inf", ct.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} is missing: build it with `python -m paper_2303_07597_amd.build` "
+                      "(there is no CPU fallback)")
+    lib = ct.CDLL(LIB_PATH)
+    vp, i, d = ct.c_void_p, ct.c_int, ct.c_double
+    lib.ot_gs_create.argtypes = [ct.POINTER(ot_gs_problem), i, ct.POINTER(vp), vp]
+    lib.ot_gs_destroy.argtypes = [vp]
+    lib.ot_gs_destroy.restype = None
+    lib.ot_gs_dual_grad.argtypes = [vp, vp, vp, vp, vp, vp, i, vp]
+    lib.ot_gs_solve.argtypes = [vp, ct.POINTER(ot_gs_options), vp, vp, ct.POINTER(ot_gs_info), vp]
+    lib.ot_gs_default_options.argtypes = [ct.POINTER(ot_gs_options)]
+    lib.ot_gs_default_options.restype = None
+    lib.ot_gs_plan.argtypes = [vp, vp, vp, vp, vp]
+    lib.ot_gs_rho_to_mu.argtypes = [d, d, ct.POINTER(d), ct.POINTER(d)]
+    lib.ot_gs_get_stats.argtypes = [vp, ct.POINTER(ot_gs_stats), i, vp]
+    lib.ot_gs_kernel_timing.argtypes = [vp, i]
+    lib.ot_gs_kernel_time.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(ct.c_longlong)]
+    lib.ot_gs_layout_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
+    lib.ot_gs_last_error.restype = ct.c_char_p
+    lib.ot_gs_version.restype = ct.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+class OTGSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"otgs error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc < 0:
+        raise OTGSError(rc, lib().ot_gs_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensors only")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensors only")
+    return ct.c_void_p(t.data_ptr())
+
+
+def ot_gs_version():
+    return lib().ot_gs_version().decode()
+
+
+def ot_gs_rho_to_mu(gamma, rho):
+    g, m = ct.c_double(), ct.c_double()
+    _check(lib().ot_gs_rho_to_mu(gamma, rho, ct.byref(g), ct.byref(m)))
+    return g.value, m.value
+
+
+class Handle:
+    """Owner of an ``ot_gs_handle``.  ``problems`` is a list of dicts with keys
+    labels (int32 cuda), n_groups, gamma, mu and either cost (float32 cuda
+    [n_src, n_tgt]) or x_src / x_tgt (float32 cuda) with cost_mode; optional
+    a, b, cost_scale.  Tensors are referenced only during creation."""
+
+    def __init__(self, problems, stream=None):
+        if isinstance(problems, dict):
+            problems = [problems]
+        n = len(problems)
+        arr = (ot_gs_problem * n)()
+        self.n_src, self.n_tgt = [], []
+        for k, p in enumerate(problems):
+            labels = p["labels"]
+            mode = p.get("cost_mode", OT_GS_COST_GIVEN if p.get("cost") is not None else OT_GS_COST_MATERIALIZE)
+            ns = int(labels.numel())
+            if p.get("cost") is not None:
+                nt = int(p["cost"].shape[1])
+            else:
+                nt = int(p["x_tgt"].shape[0])
+            dim = int(p["x_src"].shape[1]) if p.get("x_src") is not None else 0
+            arr[k] = ot_gs_problem(ns, nt, dim, int(p["n_groups"]), _ptr(labels), mode,
+                                   _ptr(p.get("cost")), _ptr(p.get("x_src")), _ptr(p.get("x_tgt")),
+                                   float(p.get("cost_scale", 0.0)), _ptr(p.get("a")), _ptr(p.get("b")),
+                                   float(p["gamma"]), float(p["mu"]))
+            self.n_src.append(ns)
+            self.n_tgt.append(nt)
+        h = ct.c_void_p()
+        _check(lib().ot_gs_create(arr, n, ct.byref(h), _stream(stream)))
+        self.h = h
+        self.count = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ot_gs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- calls
+    def dual_grad(self, alpha, beta, grad_alpha=None, grad_beta=None, obj=None,
+                  mode=OT_GS_DENSE, stream=None):
+        _check(lib().ot_gs_dual_grad(self.h, _ptr(alpha), _ptr(beta), _ptr(grad_alpha),
+                                     _ptr(grad_beta), _ptr(obj), int(mode), _stream(stream)))
+
+    def solve(self, alpha=None, beta=None, stream=None, obj_trace=None, **opts):
+        o = ot_gs_options()
+        lib().ot_gs_default_options(ct.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        if obj_trace is not None:
+            o.obj_trace = _ptr(obj_trace).value
+        dev = torch.device("cuda")
+        if alpha is None:
+            alpha = torch.zeros(sum(self.n_src), dtype=torch.float32, device=dev)
+        if beta is None:
+            beta = torch.zeros(sum(self.n_tgt), dtype=torch.float32, device=dev)
+        info = (ot_gs_info * self.count)()
+        rc = _check(lib().ot_gs_solve(self.h, ct.byref(o), _ptr(alpha), _ptr(beta), info, _stream(stream)))
+        return alpha, beta, [x.as_dict() for x in info], rc
+
+    def plan(self, alpha, beta, T, stream=None):
+        _check(lib().ot_gs_plan(self.h, _ptr(alpha), _ptr(beta), _ptr(T), _stream(stream)))
+
+    def stats(self, reset=False, stream=None):
+        st = ot_gs_stats()
+        _check(lib().ot_gs_get_stats(self.h, ct.byref(st), int(reset), _stream(stream)))
+        return st.as_dict()
+
+    def kernel_timing(self, enable=True):
+        _check(lib().ot_gs_kernel_timing(self.h, int(enable)))
+
+    def kernel_time(self, which):
+        ms, n = ct.c_double(), ct.c_longlong()
+        _check(lib().ot_gs_kernel_time(self.h, int(which), ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
+
+    def layout_info(self, k=0):
+        g, tp, nt = ct.c_int(), ct.c_int(), ct.c_int()
+        _check(lib().ot_gs_layout_info(self.h, k, ct.byref(g), ct.byref(tp), ct.byref(nt)))
+        return dict(n_groups_nonempty=g.value, n_tgt_padded=tp.value, n_tiles=nt.value)
+
+
+EXPORTED = [
+    "ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_default_options",
+    "ot_gs_plan", "ot_gs_rho_to_mu", "ot_gs_get_stats", "ot_gs_kernel_timing", "ot_gs_kernel_time",
+    "ot_gs_layout_info", "ot_gs_last_error", "ot_gs_version",
+]
