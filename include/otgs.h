@@ -146,6 +146,8 @@ typedef struct {
     double gtol;          /* stop when ||grad||_inf <= gtol (default 0: run max_iter)*/
     double *obj_trace;    /* optional DEVICE [count * (max_iter + 1)] float64: D after
                              each accepted iteration (k = 0 is the starting point)    */
+    long long *time_trace;/* optional DEVICE [count * (max_iter + 1)]: device clock
+                             (wall_clock64, 100 MHz) at each accepted iteration        */
 } ot_gs_options;
 
 /* Fills `o` with the defaults listed above. */

@@ -95,6 +95,21 @@ struct ot_gs_handle {
   long long* counters = nullptr;
   int* err = nullptr;
   long long* t_off = nullptr;    // plan offsets
+  int* inst_mode = nullptr;      // EvalMode per instance (device)
+  long long tot_pairs_valid = 0; // sum of Le * nt
+  int max_ns = 1, max_ntp = 64;
+  // solver buffers (allocated by the first solve)
+  struct Solver {
+    int hist = 0, maxb = 0, ndot = 0;
+    long long vtot = 0;
+    long long* voff = nullptr;
+    float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr;
+    LbState* st = nullptr;
+    double* part = nullptr;
+    int* n_active = nullptr;
+    int* h_active = nullptr;  // pinned host
+    std::vector<void*> mem;
+  } sol;
   Timing timing;
   bool has_snapshot = false;
 
@@ -108,7 +123,13 @@ struct ot_gs_handle {
     *p = (T*)q;
     return OT_GS_OK;
   }
+  void free_solver() {
+    for (void* p : sol.mem) (void)hipFree(p);
+    if (sol.h_active) (void)hipHostFree(sol.h_active);
+    sol = Solver();
+  }
   ~ot_gs_handle() {
+    free_solver();
     for (void* p : allocs) (void)hipFree(p);
     for (auto& v : timing.ev)
       for (auto& e : v) {
@@ -530,6 +551,13 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   }
 
   // ---- evaluation state
+  for (int k = 0; k < count; ++k) {
+    h->max_ns = std::max(h->max_ns, h->inst[k].d.ns);
+    h->max_ntp = std::max(h->max_ntp, h->inst[k].d.nt_pad);
+    h->tot_pairs_valid += (long long)h->inst[k].d.Le * h->inst[k].d.nt;
+  }
+  TRY(h->alloc(&h->inst_mode, count));
+  HIPCHK(hipMemsetAsync(h->inst_mode, 0, sizeof(int) * count, s));
   TRY(h->alloc(&h->alpha, h->tot_rows));
   TRY(h->alloc(&h->beta, h->tot_cols_pad));
   TRY(h->alloc(&h->ga, h->tot_rows));
@@ -572,7 +600,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
 
 // ------------------------------------------------------------ evaluation
 
-static GradArgs grad_args(ot_gs_handle* h, int snapshot) {
+static GradArgs grad_args(ot_gs_handle* h) {
   GradArgs A;
   std::memset(&A, 0, sizeof A);
   A.inst = h->d_inst;
@@ -590,11 +618,11 @@ static GradArgs grad_args(ot_gs_handle* h, int snapshot) {
   A.part = h->part;
   A.part_stride = std::max<long long>(h->tot_chunk, 1);
   A.kappa = h->kappa;
-  A.snapshot = snapshot;
+  A.inst_mode = h->inst_mode;
   return A;
 }
 
-static ScreenArgs screen_args(ot_gs_handle* h, int mode) {
+static ScreenArgs screen_args(ot_gs_handle* h, int use_lower) {
   ScreenArgs S;
   std::memset(&S, 0, sizeof S);
   S.inst = h->d_inst;
@@ -617,7 +645,8 @@ static ScreenArgs screen_args(ot_gs_handle* h, int mode) {
   S.list_sc = h->dyn_sc;
   S.counts = h->counts_dyn;
   S.counters = h->counters;
-  S.mode = mode;
+  S.inst_mode = h->inst_mode;
+  S.use_lower = use_lower;
   return S;
 }
 
@@ -626,62 +655,7 @@ static int grid_for(ot_gs_handle* h, int n) {
   return std::max(1, std::min(n, 2 * h->n_cu));
 }
 
-// Evaluates the dual and its gradient at the internal (alpha, beta) of the
-// handle.  mode: OT_GS_DENSE, OT_GS_SCREENED, OT_GS_SNAPSHOT.  Writes the
-// internal-order gradient (h->ga, h->gb), the objective (h->obj) and, when
-// given, caller-order gradients.
-static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hipStream_t s,
-                    bool write_kappa = false) {
-  const bool screened = mode == OT_GS_SCREENED;
-  const bool snapshot = mode == OT_GS_SNAPSHOT;
-  hipEvent_t e0 = nullptr;
-  // screen (or extraction before a snapshot)
-  if (screened || snapshot) {
-    TRY(tbegin(h, KT_SCREEN, s, &e0));
-    ScreenArgs S = screen_args(h, screened ? 1 : 2);
-    if (h->tot_groups > 0) {
-      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
-      LAUNCHCHK();
-      hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, 4)), dim3(256), 0, s, S);
-      LAUNCHCHK();
-    }
-    TRY(tend(h, KT_SCREEN, s, e0));
-  }
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_EVALS, 1LL);
-  if (snapshot) hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_REFRESH, 1LL);
-  if (!screened) {
-    // dense evaluation covers every pair and tile
-    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_TOTAL, h->tot_tiles);
-    hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_COMPUTED, h->tot_tiles);
-  }
-  // gradient tiles
-  TRY(tbegin(h, KT_GRAD, s, &e0));
-  GradArgs A = grad_args(h, snapshot ? 1 : 0);
-  A.write_kappa = write_kappa ? 1 : 0;
-  const int* cnt = screened ? h->counts_dyn : h->counts_static;
-  if (h->n_main > 0) {
-    A.list = screened ? h->dyn_main : h->list_main;
-    A.count = cnt + 0;
-    hipLaunchKernelGGL(k_grad_tiles<0>, dim3(grid_for(h, h->n_main)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-  }
-  if (h->n_sg > 0) {
-    A.list = screened ? h->dyn_sc : h->list_sc;
-    A.count = cnt + 2;
-    hipLaunchKernelGGL(k_grad_tiles<1>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-    A.list = screened ? h->dyn_sg : h->list_sg;
-    A.count = cnt + 1;
-    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
-    LAUNCHCHK();
-    A.list = screened ? h->dyn_sc : h->list_sc;
-    A.count = cnt + 2;
-    hipLaunchKernelGGL(k_grad_tiles<2>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-  }
-  TRY(tend(h, KT_GRAD, s, e0));
-  // assembly
-  TRY(tbegin(h, KT_REDUCE, s, &e0));
+static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, float* gb_out) {
   ReduceArgs R;
   std::memset(&R, 0, sizeof R);
   R.inst = h->d_inst;
@@ -691,7 +665,7 @@ static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hip
   R.rowpart = h->rowpart;
   R.colsum = h->colsum;
   R.excess = h->excess;
-  R.tile_on = screened ? h->tile_on : nullptr;
+  R.tile_on = dynamic ? h->tile_on : nullptr;
   R.a_int = h->a_int;
   R.b_int = h->b_int;
   R.alpha = h->alpha;
@@ -704,32 +678,95 @@ static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hip
   R.a_uniform = h->a_uniform;
   R.b_uniform = h->b_uniform;
   R.err = h->err;
-  int maxns = 1, maxntp = 64;
-  for (auto& ih : h->inst) {
-    maxns = std::max(maxns, ih.d.ns);
-    maxntp = std::max(maxntp, ih.d.nt_pad);
+  return R;
+}
+
+// Gradient tiles over the static (every tile) or dynamic (screen output)
+// work lists, then the fixed-order assembly.
+static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, float* gb_out,
+                                hipStream_t s, bool write_kappa) {
+  hipEvent_t e0 = nullptr;
+  TRY(tbegin(h, KT_GRAD, s, &e0));
+  GradArgs A = grad_args(h);
+  A.write_kappa = write_kappa ? 1 : 0;
+  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
+  if (h->n_main > 0) {
+    A.list = dynamic ? h->dyn_main : h->list_main;
+    A.count = cnt + 0;
+    hipLaunchKernelGGL(k_grad_tiles<0>, dim3(grid_for(h, h->n_main)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
   }
-  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)std::min<long long>(ceil_div(maxns, 256), 1024), h->count),
+  if (h->n_sg > 0) {
+    A.list = dynamic ? h->dyn_sc : h->list_sc;
+    A.count = cnt + 2;
+    hipLaunchKernelGGL(k_grad_tiles<1>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+    A.list = dynamic ? h->dyn_sg : h->list_sg;
+    A.count = cnt + 1;
+    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
+    LAUNCHCHK();
+    A.list = dynamic ? h->dyn_sc : h->list_sc;
+    A.count = cnt + 2;
+    hipLaunchKernelGGL(k_grad_tiles<2>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+  }
+  TRY(tend(h, KT_GRAD, s, e0));
+  TRY(tbegin(h, KT_REDUCE, s, &e0));
+  ReduceArgs R = reduce_args(h, dynamic, ga_out, gb_out);
+  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns, 256), 1024), h->count),
                      dim3(256), 0, s, R);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)std::min<long long>(ceil_div(maxntp, 256), 1024), h->count),
+  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 1024), h->count),
                      dim3(256), 0, s, R);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_objective, dim3(h->count), dim3(1024), 0, s, R);
   LAUNCHCHK();
   TRY(tend(h, KT_REDUCE, s, e0));
-  if (snapshot) {
-    hipLaunchKernelGGL(k_copy2, dim3(256), dim3(256), 0, s, h->alpha, h->alpha_s, h->tot_rows, h->beta,
-                       h->beta_s, h->tot_cols_pad);
-    LAUNCHCHK();
-    h->has_snapshot = true;
-  }
   return OT_GS_OK;
 }
 
+// Evaluation with the mode of every instance read on the device: screen
+// (bounds, extraction at refreshes, work lists), tiles, assembly, snapshot.
+static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float* ga_out,
+                            float* gb_out, bool write_kappa = false) {
+  hipEvent_t e0 = nullptr;
+  TRY(tbegin(h, KT_SCREEN, s, &e0));
+  ScreenArgs S = screen_args(h, use_lower);
+  if (h->tot_groups > 0) {
+    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, 4)), dim3(256), 0, s, S);
+    LAUNCHCHK();
+  }
+  TRY(tend(h, KT_SCREEN, s, e0));
+  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa));
+  hipLaunchKernelGGL(k_snapshot_copy, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns + h->max_ntp, 256), 256), h->count),
+                     dim3(256), 0, s, h->d_inst, h->inst_mode, h->alpha, h->alpha_s, h->beta, h->beta_s);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+// Host-directed evaluation of every instance in one mode (OT_GS_DENSE uses the
+// static work lists and needs no screen pass).
+static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hipStream_t s,
+                    bool write_kappa = false) {
+  hipLaunchKernelGGL(k_fill_mode, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, mode);
+  LAUNCHCHK();
+  if (mode != OT_GS_DENSE) {
+    TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa));
+    if (mode == OT_GS_SNAPSHOT) h->has_snapshot = true;
+    return OT_GS_OK;
+  }
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_EVALS, (long long)h->count);
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_PAIRS_TOTAL, h->tot_pairs_valid);
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_TOTAL, h->tot_tiles);
+  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_COMPUTED, h->tot_tiles);
+  LAUNCHCHK();
+  return run_tiles_and_reduce(h, false, ga_out, gb_out, s, write_kappa);
+}
+
 static int gather(ot_gs_handle* h, const float* alpha, const float* beta, hipStream_t s) {
-  int maxn = 1;
-  for (auto& ih : h->inst) maxn = std::max(maxn, std::max(ih.d.ns, ih.d.nt_pad));
+  const long long maxn = std::max<long long>(h->max_ns, h->max_ntp);
   hipLaunchKernelGGL(k_gather_duals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), h->count),
                      dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, alpha, beta, h->alpha, h->beta,
                      h->err);
@@ -768,12 +805,7 @@ int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T,
   hipStream_t s = (hipStream_t)stream;
   TRY(gather(h, alpha, beta, s));
   TRY(evaluate(h, OT_GS_DENSE, nullptr, nullptr, s, true));
-  int maxns = 1, maxnt = 1;
-  for (auto& ih : h->inst) {
-    maxns = std::max(maxns, ih.d.ns);
-    maxnt = std::max(maxnt, ih.d.nt);
-  }
-  dim3 grid((unsigned)std::min<long long>(ceil_div(maxnt, 256), 16), (unsigned)std::min(maxns, 4096), h->count);
+  dim3 grid((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 16), (unsigned)std::min(h->max_ns, 4096), h->count);
   hipLaunchKernelGGL(k_plan_dense, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
                      h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
   LAUNCHCHK();
@@ -848,12 +880,6 @@ const char* ot_gs_version(void) { return "otgs 0.1 (gfx950)"; }
 
 extern "C" {
 
-int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* alpha_io, float* beta_io,
-                ot_gs_info* info, void* stream) {
-  (void)h; (void)opts; (void)alpha_io; (void)beta_io; (void)info; (void)stream;
-  return fail(OT_GS_EINVAL, "solve: not available yet");
-}
-
 void ot_gs_default_options(ot_gs_options* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
@@ -871,3 +897,159 @@ void ot_gs_default_options(ot_gs_options* o) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ solver
+
+static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
+  auto& V = h->sol;
+  if (V.hist == hist && V.X) return OT_GS_OK;
+  HIPCHK(hipStreamSynchronize(s));
+  h->free_solver();
+  std::vector<long long> voff(h->count);
+  long long acc = 0;
+  int maxb = 1;
+  for (int k = 0; k < h->count; ++k) {
+    voff[k] = acc;
+    const long long n = (long long)h->inst[k].d.ns + h->inst[k].d.nt_pad;
+    acc += n;
+    maxb = std::max<int>(maxb, (int)ceil_div(n, LB_VB));
+  }
+  V.hist = hist;
+  V.vtot = acc;
+  V.maxb = maxb;
+  V.ndot = 5 + 3 * hist;
+  auto al = [&](void** p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return fail(OT_GS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    V.mem.push_back(*p);
+    return OT_GS_OK;
+  };
+  TRY(al((void**)&V.voff, sizeof(long long) * h->count));
+  TRY(al((void**)&V.X, sizeof(float) * acc));
+  TRY(al((void**)&V.G, sizeof(float) * acc));
+  TRY(al((void**)&V.Dv, sizeof(float) * acc));
+  TRY(al((void**)&V.S, sizeof(float) * acc * hist));
+  TRY(al((void**)&V.Y, sizeof(float) * acc * hist));
+  TRY(al((void**)&V.st, sizeof(LbState) * h->count));
+  TRY(al((void**)&V.part, sizeof(double) * (size_t)h->count * maxb * V.ndot));
+  TRY(al((void**)&V.n_active, sizeof(int)));
+  HIPCHK(hipHostMalloc((void**)&V.h_active, sizeof(int), hipHostMallocDefault));
+  HIPCHK(hipMemcpyAsync(V.voff, voff.data(), sizeof(long long) * h->count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(V.st, 0, sizeof(LbState) * h->count, s));
+  HIPCHK(hipMemsetAsync(V.S, 0, sizeof(float) * acc * hist, s));
+  HIPCHK(hipMemsetAsync(V.Y, 0, sizeof(float) * acc * hist, s));
+  return OT_GS_OK;
+}
+
+static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
+  LbArgs A;
+  std::memset(&A, 0, sizeof A);
+  auto& V = h->sol;
+  A.inst = h->d_inst;
+  A.P = P;
+  A.st = V.st;
+  A.inst_mode = h->inst_mode;
+  A.n_active = V.n_active;
+  A.voff = V.voff;
+  A.X = V.X;
+  A.G = V.G;
+  A.Dv = V.Dv;
+  A.S = V.S;
+  A.Y = V.Y;
+  A.vtot = V.vtot;
+  A.alpha = h->alpha;
+  A.beta = h->beta;
+  A.ga = h->ga;
+  A.gb = h->gb;
+  A.obj = h->obj;
+  A.part = V.part;
+  A.maxb = V.maxb;
+  A.ndot = V.ndot;
+  return A;
+}
+
+// One function evaluation of every live instance and one step of its solver.
+static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, hipStream_t s) {
+  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr));
+  hipEvent_t e0 = nullptr;
+  TRY(tbegin(h, KT_LBFGS, s, &e0));
+  const long long maxv = h->max_ns + h->max_ntp;
+  hipLaunchKernelGGL(k_lbfgs_dots, dim3(h->sol.maxb, h->count), dim3(LB_BLOCK), 0, s, A);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                     dim3(256), 0, s, A);
+  LAUNCHCHK();
+  TRY(tend(h, KT_LBFGS, s, e0));
+  return OT_GS_OK;
+}
+
+extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* alpha_io,
+                           float* beta_io, ot_gs_info* info, void* stream) {
+  if (!h || !opts || !alpha_io || !beta_io) return fail(OT_GS_EINVAL, "solve: NULL argument");
+  const ot_gs_options& o = *opts;
+  if (o.hist < 1 || o.hist > HMAX) return fail(OT_GS_EINVAL, "solve: hist must lie in [1, %d]", HMAX);
+  if (o.max_iter < 0 || o.refresh < 1 || o.max_ls < 1)
+    return fail(OT_GS_EINVAL, "solve: max_iter >= 0, refresh >= 1, max_ls >= 1 required");
+  if (!(o.c1 > 0 && o.c1 < o.c2 && o.c2 < 1)) return fail(OT_GS_EINVAL, "solve: need 0 < c1 < c2 < 1");
+  hipStream_t s = (hipStream_t)stream;
+  TRY(ensure_solver(h, o.hist, s));
+  LbParams P;
+  std::memset(&P, 0, sizeof P);
+  P.hist = o.hist;
+  P.max_iter = o.max_iter;
+  P.max_ls = o.max_ls;
+  P.refresh = o.refresh;
+  P.use_screen = o.use_screen ? 1 : 0;
+  P.use_lower = o.use_lower ? 1 : 0;
+  P.c1 = o.c1;
+  P.c2 = o.c2;
+  P.gtol = o.gtol;
+  P.obj_trace = o.obj_trace;
+  P.time_trace = o.time_trace;
+  LbArgs A = lb_args(h, P);
+  if (o.init_user) TRY(gather(h, alpha_io, beta_io, s));
+  const long long maxv = h->max_ns + h->max_ntp;
+  hipLaunchKernelGGL(k_lbfgs_init, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                     dim3(256), 0, s, A, o.init_user ? 1 : 0, h->alpha_s, h->beta_s, h->zsnap, h->osnap,
+                     h->inN, P.use_screen);
+  LAUNCHCHK();
+  h->has_snapshot = P.use_screen != 0;
+  // upper bound on evaluations: the first one plus max_ls per iteration
+  const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;
+  const int check_every = 16;
+  for (long long step = 0; step < max_steps; ++step) {
+    TRY(solver_step(h, A, P.use_lower, s));
+    if ((step + 1) % check_every == 0 || step + 1 == max_steps) {
+      HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (*h->sol.h_active == 0) break;
+    }
+  }
+  // final points: X of every instance, back in the caller's order
+  hipLaunchKernelGGL(k_lbfgs_export, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                     dim3(256), 0, s, A);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scatter_duals, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 1024), h->count),
+                     dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->alpha, h->beta, alpha_io, beta_io);
+  LAUNCHCHK();
+  std::vector<LbState> hs(h->count);
+  HIPCHK(hipMemcpyAsync(hs.data(), h->sol.st, sizeof(LbState) * h->count, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int worst = OT_GS_OK;
+  for (int k = 0; k < h->count; ++k) {
+    int st = OT_GS_NOT_CONVERGED;
+    if (hs[k].status == LB_CONVERGED) st = OT_GS_OK;
+    else if (hs[k].status == LB_LSFAIL) st = OT_GS_LINESEARCH;
+    worst = std::max(worst, st);
+    if (info) {
+      info[k].iters = hs[k].iter;
+      info[k].evals = hs[k].evals;
+      info[k].status = st;
+      info[k].obj = -hs[k].f;
+      info[k].gnorm_inf = hs[k].gmax;
+    }
+  }
+  return worst;
+}

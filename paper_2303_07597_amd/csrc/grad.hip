@@ -40,7 +40,7 @@ struct GradArgs {
   float* part;            // split chunks: [3][chunk pair] column partial sums
   long long part_stride;  // elements per partial kind
   float* kappa;           // split groups: kappa per pair
-  int snapshot;
+  const int* inst_mode;   // EM_SNAPSHOT: also record z~ and o~
   int write_kappa;        // also store kappa per pair (plan recovery)
 };
 
@@ -102,7 +102,7 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
   const int col = d.jb * TJ + lane;
   const bool colok = col < I.nt;
   const float bj = A.beta[I.col_off + col];
-  const bool snap = A.snapshot != 0 && PHASE != 2;
+  const bool snap = A.inst_mode[d.inst] == EM_SNAPSHOT && PHASE != 2;
   const int rw = r0 + w;
   // rows of this wavefront inside the tile (wave-uniform)
   const int nk = rw < r1 ? min(R, (r1 - rw + NW - 1) / NW) : 0;
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(WAVE) k_split_combine(GradArgs A) {
     A.kappa[pr] = kap;
     A.colsum[pr] = kap * S1;
     A.excess[pr] = num;
-    if (A.snapshot) {
+    if (A.inst_mode[d.inst] == EM_SNAPSHOT) {
       A.zsnap[pr] = z;
       A.osnap[pr] = sqrtf(O2);
     }

@@ -3,4 +3,5 @@
 #include "layout.hip"
 #include "grad.hip"
 #include "screen.hip"
+#include "lbfgs.hip"
 #include "api.hip"

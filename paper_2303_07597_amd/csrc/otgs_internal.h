@@ -72,6 +72,9 @@ enum Counter {
   CNT_REFRESH, CNT_TILES_TOTAL, CNT_TILES_COMPUTED, CNT_NUM
 };
 
+// per-instance evaluation mode, read on the device
+enum EvalMode { EM_DENSE = 0, EM_SCREEN = 1, EM_SNAPSHOT = 2, EM_SKIP = 3 };
+
 // pair state written by the screen / extraction kernels
 enum PairFlag : uint8_t { PAIR_SKIP = 0, PAIR_CHECK = 1, PAIR_IN_N = 2 };
 

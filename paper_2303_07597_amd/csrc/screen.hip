@@ -48,7 +48,8 @@ struct ScreenArgs {
   TileDesc* list_sc;         // split chunk tiles
   int* counts;               // [3]: main, split groups, split chunks
   long long* counters;
-  int mode;                  // 1 screen, 2 extract
+  const int* inst_mode;      // EvalMode per instance
+  int use_lower;             // build N at snapshot refreshes
 };
 
 // Per-group float64 statistics of alpha - alpha~ (and max |alpha|, |alpha~|);
@@ -91,7 +92,11 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
     s.amax_s = sm[3][0];
     s.pad[0] = s.pad[1] = s.pad[2] = 0;
     A.gstats[gidx] = s;
-    (void)ge;
+    if (ge == 0) {
+      const int m = A.inst_mode[k];
+      if (m != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
+      if (m == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
+    }
     if (gidx == 0) {
       A.counts[0] = 0;
       A.counts[1] = 0;
@@ -123,16 +128,22 @@ __global__ void __launch_bounds__(256) k_screen_pairs(ScreenArgs A) {
   const double sg = sqrt((double)g);
   const double thr = (double)I.thr;
 
-  if (A.mode == 2) {
-    if (valid) {
+  const int mode = A.inst_mode[d.inst];
+  if (mode == EM_SKIP) {
+    if (lane == 0) A.tile_on[(size_t)I.tile_off + (size_t)d.grp * I.njb + d.jb] = 0;
+    return;
+  }
+  if (mode == EM_SNAPSHOT && valid) {
+    // Algorithm 1: rebuild N from the lower bound against the old snapshot
+    uint8_t f = PAIR_SKIP;
+    if (A.use_lower) {
       const double zt = A.zsnap[pr], ot = A.osnap[pr];
       const double kt = sqrt(zt * zt + ot * ot);
       const double zlow = kt - S.all - sg * fabs(db) - ot - S.dn - sg * (db < 0 ? -db : 0.0);
-      A.inN[pr] = (zlow > thr) ? PAIR_IN_N : PAIR_SKIP;
+      if (zlow > thr) f = PAIR_IN_N;
     }
-    return;
+    A.inN[pr] = f;
   }
-
   const double u = 5.9604644775390625e-08;
   const int nch = (g + CHUNK - 1) / CHUNK;
   const double nop = (double)g + 17.0 * nch + 16.0;
@@ -142,8 +153,10 @@ __global__ void __launch_bounds__(256) k_screen_pairs(ScreenArgs A) {
   const double del_c = 2.01 * u * (S.amax + fabs(b) + cm);
   bool inN = false, checked = false, compute = false;
   if (valid) {
-    inN = A.inN[pr] == PAIR_IN_N;
-    if (inN) {
+    if (mode != EM_SCREEN) {
+      compute = true;               // dense evaluation (also at a snapshot)
+    } else if (A.inN[pr] == PAIR_IN_N) {
+      inN = true;
       compute = true;
     } else {
       checked = true;
@@ -189,14 +202,24 @@ __global__ void __launch_bounds__(256) k_screen_pairs(ScreenArgs A) {
   }
 }
 
-// alpha~ <- alpha, beta~ <- beta (internal order, all instances)
-__global__ void k_copy2(const float* __restrict__ a, float* __restrict__ as, long long na,
-                        const float* __restrict__ b, float* __restrict__ bs, long long nb) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < na + nb;
-       i += (long long)gridDim.x * blockDim.x) {
-    if (i < na) as[i] = a[i];
-    else bs[i - na] = b[i - na];
+// alpha~ <- alpha, beta~ <- beta for the instances evaluated at a snapshot;
+// grid (blocks, count)
+__global__ void k_snapshot_copy(const InstDev* __restrict__ inst, const int* __restrict__ inst_mode,
+                                const float* __restrict__ a, float* __restrict__ as,
+                                const float* __restrict__ b, float* __restrict__ bs) {
+  const int k = blockIdx.y;
+  if (inst_mode[k] != EM_SNAPSHOT) return;
+  const InstDev I = inst[k];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.ns + I.nt_pad; e += gridDim.x * blockDim.x) {
+    if (e < I.ns) as[I.row_off + e] = a[I.row_off + e];
+    else bs[I.col_off + e - I.ns] = b[I.col_off + e - I.ns];
   }
+}
+
+// every instance gets the same evaluation mode
+__global__ void k_fill_mode(int* inst_mode, int count, int mode) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x)
+    inst_mode[k] = mode;
 }
 
 // integer counter update from the device (no host round trip)

@@ -56,7 +56,7 @@ class ot_gs_options(ct.Structure):
     _fields_ = [("max_iter", ct.c_int), ("hist", ct.c_int), ("refresh", ct.c_int),
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
                 ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
-                ("gtol", ct.c_double), ("obj_trace", ct.c_void_p)]
+                ("gtol", ct.c_double), ("obj_trace", ct.c_void_p), ("time_trace", ct.c_void_p)]
 
 
 class ot_gs_info(ct.Structure):
@@ -188,13 +188,15 @@ class Handle:
         _check(lib().ot_gs_dual_grad(self.h, _ptr(alpha), _ptr(beta), _ptr(grad_alpha),
                                      _ptr(grad_beta), _ptr(obj), int(mode), _stream(stream)))
 
-    def solve(self, alpha=None, beta=None, stream=None, obj_trace=None, **opts):
+    def solve(self, alpha=None, beta=None, stream=None, obj_trace=None, time_trace=None, **opts):
         o = ot_gs_options()
         lib().ot_gs_default_options(ct.byref(o))
         for k, v in opts.items():
             setattr(o, k, v)
         if obj_trace is not None:
             o.obj_trace = _ptr(obj_trace).value
+        if time_trace is not None:
+            o.time_trace = _ptr(time_trace).value
         dev = torch.device("cuda")
         if alpha is None:
             alpha = torch.zeros(sum(self.n_src), dtype=torch.float32, device=dev)
