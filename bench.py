@@ -1,0 +1,215 @@
+"""Benchmark: dual-gradient throughput and time to tolerance on one MI355X.
+
+Workload: 4096 labelled source samples x 4096 target samples, d = 64, ten
+Gaussian-blob classes (410 or 409 samples each), target = the blobs under a
+random rotation plus a shift, cost = squared Euclidean distance built on the
+GPU and normalised by its maximum, uniform marginals, gamma = 0.1, mu = 0.1
+(--mu changes it).  Inputs are synthetic and seeded.
+
+A "step" is one evaluation of the dual objective and its gradient over the
+whole instance (dense: every (class, target) block), at the point an L-BFGS
+run reaches after 200 iterations.  value = n_src * n_tgt * steps / time.
+Also reported: the screened evaluation at the same point after a snapshot,
+and time to 1e-6 relative objective of full dense and screened solves.
+
+--gpus N > 1 exits with a message: this benchmark uses one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(HERE, "profiles", "grad_tiles_blobs4096_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mu", type=float, default=0.1)
+    ap.add_argument("--solve-iters", type=int, default=400)
+    ap.add_argument("--ref-iters", type=int, default=3000)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--skip-solve", action="store_true", help="omit the time-to-tolerance solves")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (traffic counter calibration)")
+    return ap.parse_args()
+
+
+def grad_source_hash():
+    h = hashlib.sha256()
+    for f in ("grad.hip", "otgs_internal.h"):
+        with open(os.path.join(HERE, "paper_2303_07597_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(ns, nt, L, tj=64):
+    """Bytes one dense gradient-tile launch must move at minimum: the cost
+    once (4 B per entry), alpha and beta once, the row partials (one float per
+    row and 64-column block), column sums and excess per (class, target)."""
+    njb = -(-nt // tj)
+    return 4 * ns * nt + 4 * (ns + nt) + 4 * ns * njb + 8 * L * nt
+
+
+def cpu_baseline(inst, alpha, beta, budget_s=12.0):
+    """The FP64 oracle's dense evaluation, single thread, on the same
+    instance and point; as many evaluations as fit in ~budget_s."""
+    import oracle
+    C, _ = oracle.cost_normalized(inst["xs"], inst["xt"])
+    P = oracle.Problem(C, inst["labels"], inst["n_groups"], inst["gamma"], inst["mu"])
+    a64, b64 = alpha.astype(np.float64), beta.astype(np.float64)
+    oracle.dual_grad(P, a64, b64)           # warm (page in C)
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.dual_grad(P, a64, b64)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 200:
+            break
+    return dict(value=P.ns * P.nt * n / el, unit="entries/s", cores=1, kind="oracle",
+                sample=f"{n} dense FP64 evaluations of the full {P.ns}x{P.nt} instance, single thread, "
+                       f"{el:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (every box here has "
+              "one GPU; see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    import paper_2303_07597_amd.otgs as O
+
+    dev = torch.device("cuda")
+    inst = synth.blobs(seed=2, n_src=4096, n_tgt=4096, d=64, n_groups=10, gamma=0.1, mu=args.mu)
+    ns, nt, L = inst["xs"].shape[0], inst["xt"].shape[0], inst["n_groups"]
+    h = O.Handle([dict(labels=torch.from_numpy(inst["labels"]).to(dev), n_groups=L,
+                       gamma=inst["gamma"], mu=inst["mu"],
+                       x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
+                       cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0)])
+
+    # point of measurement: 200 L-BFGS iterations from zero (dense solve)
+    a_pt, b_pt, info, _ = h.solve(max_iter=200, use_screen=0)
+    torch.cuda.synchronize()
+
+    ga = torch.empty_like(a_pt)
+    gb = torch.empty_like(b_pt)
+    obj = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def dense():
+        h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
+
+    for _ in range(args.warmup):
+        dense()
+    torch.cuda.synchronize()
+    h.kernel_timing(True)
+    h.kernel_time(O.KERNEL_GRAD)          # clear
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dense()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.kernel_timing(False)
+    grad_ms, grad_n = h.kernel_time(O.KERNEL_GRAD)
+    ms_step = 1e3 * el / args.steps
+    value = ns * nt * args.steps / el
+    grad_avg_s = grad_ms * 1e-3 / max(grad_n, 1)
+    alg_bytes = algorithmic_bytes(ns, nt, L)
+    achieved = alg_bytes / grad_avg_s / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == grad_source_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    # screened evaluation at the same point after a snapshot there
+    h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_SNAPSHOT)
+    h.stats(reset=True)
+    for _ in range(args.warmup):
+        h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_SCREENED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_SCREENED)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    st = h.stats(reset=True)
+    screened = dict(entries_per_s=ns * nt * args.steps / el_s, ms_per_eval=1e3 * el_s / args.steps,
+                    tiles_computed_frac=st["tiles_computed"] / max(st["tiles_total"], 1),
+                    pairs_skipped_frac=1 - (st["pairs_unskipped"] + st["pairs_in_N"]) / max(st["pairs_total"], 1))
+
+    solves = None
+    if not args.skip_solve:
+        M = args.ref_iters
+        tr = torch.full((M + 1,), float("nan"), dtype=torch.float64, device=dev)
+        h.solve(max_iter=M, use_screen=0, obj_trace=tr)
+        torch.cuda.synchronize()
+        dstar = float(np.nanmax(tr.cpu().numpy()))
+        out = {}
+        for name, scr in (("dense", 0), ("screened", 1)):
+            K = args.solve_iters
+            otr = torch.full((K + 1,), float("nan"), dtype=torch.float64, device=dev)
+            ttr = torch.zeros(K + 1, dtype=torch.int64, device=dev)
+            torch.cuda.synchronize()
+            h.stats(reset=True)
+            t0 = time.perf_counter()
+            _, _, inf, _ = h.solve(max_iter=K, use_screen=scr, obj_trace=otr, time_trace=ttr)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            s2 = h.stats(reset=True)
+            o_ = otr.cpu().numpy()
+            t_ = ttr.cpu().numpy().astype(np.float64) / 100e6     # device clock, 100 MHz
+            rel = (dstar - o_) / abs(dstar)
+            hit = np.nonzero(rel <= 1e-6)[0]
+            out[name] = dict(wall_s=wall, iters=inf[0]["iters"], evals=inf[0]["evals"],
+                             final_rel_gap=float(rel[inf[0]["iters"]]),
+                             time_to_1e6_s=float(t_[hit[0]] - t_[0]) if hit.size else None,
+                             iters_to_1e6=int(hit[0]) if hit.size else None,
+                             tiles_computed_frac=s2["tiles_computed"] / max(s2["tiles_total"], 1))
+        ttd, tts = out["dense"]["time_to_1e6_s"], out["screened"]["time_to_1e6_s"]
+        solves = dict(d_star=dstar, ref_iters=M, **out,
+                      speedup_time_to_1e6=(ttd / tts) if (ttd and tts) else None)
+
+    if args.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.skip_cpu:
+        cpu = cpu_baseline(inst, a_pt.cpu().numpy(), b_pt.cpu().numpy())
+
+    line = dict(
+        metric="dual-grad entries/s (dense, float32) + time-to-1e-6 rel obj (screened vs dense)",
+        value=value, unit="entries/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
+        config=dict(workload="blobs n_src=n_tgt=4096 d=64 classes=10 gamma=0.1 mu=%g" % args.mu,
+                    point="after 200 dense L-BFGS iterations from zero", parallelism="single GPU"),
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      kernel="k_grad_tiles<0>", algorithmic_bytes_per_launch=alg_bytes,
+                      avg_launch_us=grad_avg_s * 1e6, launches=grad_n),
+        cpu_baseline=cpu,
+        screened_eval=screened,
+        solves=solves,
+    )
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

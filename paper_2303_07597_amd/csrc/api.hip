@@ -98,6 +98,8 @@ struct ot_gs_handle {
   int* inst_mode = nullptr;      // EvalMode per instance (device)
   long long tot_pairs_valid = 0; // sum of Le * nt
   int max_ns = 1, max_ntp = 64;
+  int n_asm = 1;                 // assembly blocks per instance
+  double* obj_part = nullptr;    // [count][n_asm]
   // solver buffers (allocated by the first solve)
   struct Solver {
     int hist = 0, maxb = 0, ndot = 0;
@@ -105,6 +107,7 @@ struct ot_gs_handle {
     long long* voff = nullptr;
     float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr;
     LbState* st = nullptr;
+    double* gram = nullptr;
     double* part = nullptr;
     int* n_active = nullptr;
     int* h_active = nullptr;  // pinned host
@@ -556,6 +559,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     h->max_ntp = std::max(h->max_ntp, h->inst[k].d.nt_pad);
     h->tot_pairs_valid += (long long)h->inst[k].d.Le * h->inst[k].d.nt;
   }
+  h->n_asm = asm_row_blocks(h->max_ns) + asm_col_blocks(h->max_ntp);
+  TRY(h->alloc(&h->obj_part, (size_t)count * h->n_asm));
   TRY(h->alloc(&h->inst_mode, count));
   HIPCHK(hipMemsetAsync(h->inst_mode, 0, sizeof(int) * count, s));
   TRY(h->alloc(&h->alpha, h->tot_rows));
@@ -675,6 +680,9 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   R.ga_out = ga_out;
   R.gb_out = gb_out;
   R.obj = h->obj;
+  R.obj_part = h->obj_part;
+  R.obj_stride = h->n_asm;
+  R.max_ns = h->max_ns;
   R.a_uniform = h->a_uniform;
   R.b_uniform = h->b_uniform;
   R.err = h->err;
@@ -684,7 +692,7 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
 // Gradient tiles over the static (every tile) or dynamic (screen output)
 // work lists, then the fixed-order assembly.
 static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, float* gb_out,
-                                hipStream_t s, bool write_kappa) {
+                                hipStream_t s, bool write_kappa, bool finalize = true) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_GRAD, s, &e0));
   GradArgs A = grad_args(h);
@@ -713,14 +721,12 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
   TRY(tend(h, KT_GRAD, s, e0));
   TRY(tbegin(h, KT_REDUCE, s, &e0));
   ReduceArgs R = reduce_args(h, dynamic, ga_out, gb_out);
-  hipLaunchKernelGGL(k_reduce_rows, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns, 256), 1024), h->count),
-                     dim3(256), 0, s, R);
+  hipLaunchKernelGGL(k_assemble, dim3(h->n_asm, h->count), dim3(ASM_BLOCK), 0, s, R);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 1024), h->count),
-                     dim3(256), 0, s, R);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_objective, dim3(h->count), dim3(1024), 0, s, R);
-  LAUNCHCHK();
+  if (finalize) {
+    hipLaunchKernelGGL(k_obj_finalize, dim3(h->count), dim3(64), 0, s, R);
+    LAUNCHCHK();
+  }
   TRY(tend(h, KT_REDUCE, s, e0));
   return OT_GS_OK;
 }
@@ -728,18 +734,23 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
 // Evaluation with the mode of every instance read on the device: screen
 // (bounds, extraction at refreshes, work lists), tiles, assembly, snapshot.
 static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float* ga_out,
-                            float* gb_out, bool write_kappa = false) {
+                            float* gb_out, bool write_kappa = false, bool finalize = true,
+                            bool snapshot_copy = true, bool group_stats = true) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_SCREEN, s, &e0));
   ScreenArgs S = screen_args(h, use_lower);
   if (h->tot_groups > 0) {
-    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
-    LAUNCHCHK();
-    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, 4)), dim3(256), 0, s, S);
+    if (group_stats) {
+      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+      LAUNCHCHK();
+    }
+    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TILES)),
+                       dim3(SCREEN_TILES * 64), 0, s, S);
     LAUNCHCHK();
   }
   TRY(tend(h, KT_SCREEN, s, e0));
-  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa));
+  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa, finalize));
+  if (!snapshot_copy) return OT_GS_OK;
   hipLaunchKernelGGL(k_snapshot_copy, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns + h->max_ntp, 256), 256), h->count),
                      dim3(256), 0, s, h->d_inst, h->inst_mode, h->alpha, h->alpha_s, h->beta, h->beta_s);
   LAUNCHCHK();
@@ -750,18 +761,14 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
 // static work lists and needs no screen pass).
 static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hipStream_t s,
                     bool write_kappa = false) {
-  hipLaunchKernelGGL(k_fill_mode, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, mode);
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, mode, h->counters,
+                     h->tot_pairs_valid, h->tot_tiles);
   LAUNCHCHK();
   if (mode != OT_GS_DENSE) {
     TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa));
     if (mode == OT_GS_SNAPSHOT) h->has_snapshot = true;
     return OT_GS_OK;
   }
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_EVALS, (long long)h->count);
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_PAIRS_TOTAL, h->tot_pairs_valid);
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_TOTAL, h->tot_tiles);
-  hipLaunchKernelGGL(k_count_add, dim3(1), dim3(64), 0, s, h->counters, (int)CNT_TILES_COMPUTED, h->tot_tiles);
-  LAUNCHCHK();
   return run_tiles_and_reduce(h, false, ga_out, gb_out, s, write_kappa);
 }
 
@@ -931,6 +938,7 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   TRY(al((void**)&V.S, sizeof(float) * acc * hist));
   TRY(al((void**)&V.Y, sizeof(float) * acc * hist));
   TRY(al((void**)&V.st, sizeof(LbState) * h->count));
+  TRY(al((void**)&V.gram, sizeof(double) * 2 * hist * hist * h->count));
   TRY(al((void**)&V.part, sizeof(double) * (size_t)h->count * maxb * V.ndot));
   TRY(al((void**)&V.n_active, sizeof(int)));
   HIPCHK(hipHostMalloc((void**)&V.h_active, sizeof(int), hipHostMallocDefault));
@@ -965,16 +973,23 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.part = V.part;
   A.maxb = V.maxb;
   A.ndot = V.ndot;
+  A.obj_part = h->obj_part;
+  A.obj_stride = h->n_asm;
+  A.obj_out = h->obj;
+  A.gram = V.gram;
+  A.alpha_s = h->alpha_s;
+  A.beta_s = h->beta_s;
   return A;
 }
 
 // One function evaluation of every live instance and one step of its solver.
 static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, hipStream_t s) {
-  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr));
+  // the control kernel finalises D and the update kernel records snapshots
+  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false));
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
-  hipLaunchKernelGGL(k_lbfgs_dots, dim3(h->sol.maxb, h->count), dim3(LB_BLOCK), 0, s, A);
+  hipLaunchKernelGGL(k_lbfgs_dots, dim3(h->sol.maxb, h->count, 1 + h->sol.hist), dim3(LB_BLOCK), 0, s, A);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();

@@ -298,77 +298,119 @@ struct ReduceArgs {
   float* ga_out;            // caller-order gradients (may be NULL)
   float* gb_out;
   double* obj;              // [count]
+  double* obj_part;         // [count][obj_stride] assembly partials of D
+  long long obj_stride;
+  int max_ns;               // largest n_src over the instances (grid layout)
   const int* a_uniform;     // per instance flags
   const int* b_uniform;
   int* err;
 };
 
-// grad_alpha_r = a_r - sum over column blocks of the row partials, in block
-// order, counting only evaluated tiles.  grid.x rows / 256, grid.y instance.
-__global__ void __launch_bounds__(256) k_reduce_rows(ReduceArgs A) {
-  const InstDev I = A.inst[blockIdx.y];
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
-    const int g = A.row_grp[I.row_off + r];
-    const float* rp = A.rowpart + I.r_off + r;
-    const uint8_t* on = A.tile_on ? A.tile_on + I.tile_off + (size_t)g * I.njb : nullptr;
-    float s = 0.f;
-    for (int jb = 0; jb < I.njb; ++jb)
-      if (!on || on[jb]) s += rp[(size_t)jb * I.ns];
-    const float gval = A.a_int[I.row_off + r] - s;
-    if (A.ga_int) A.ga_int[I.row_off + r] = gval;
-    if (A.ga_out) A.ga_out[I.row_off + A.perm_row[I.row_off + r]] = gval;
-  }
-}
+constexpr int ASM_BLOCK = 256;
+constexpr int ASM_LPR = 8;                      // lanes per row
+constexpr int ASM_ROWS = ASM_BLOCK / ASM_LPR;   // rows per assembly block
 
-// grad_beta_c = b_c - sum over groups of the column sums, in group order.
-__global__ void __launch_bounds__(256) k_reduce_cols(ReduceArgs A) {
-  const InstDev I = A.inst[blockIdx.y];
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
-    const int jb = c / TJ;
+// Blocks of the assembly kernel per instance: row blocks, then column blocks.
+__host__ __device__ inline int asm_row_blocks(int ns) { return (ns + ASM_ROWS - 1) / ASM_ROWS; }
+__host__ __device__ inline int asm_col_blocks(int ntp) { return (ntp + ASM_BLOCK - 1) / ASM_BLOCK; }
+
+// Assembly, grid (max row blocks + max column blocks, count):
+//  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 lanes per row
+//                  take jb = q mod 8 in order, then a fixed xor tree), and the
+//                  block's float64 share of a.alpha;
+//  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order and
+//                  the block's share of b.beta - sum_l excess_lc^2 / (2 gamma).
+// Only evaluated tiles are summed (skipped ones are exact zeros).  Each
+// block writes one float64 partial of D; k_obj_finalize (or the solver's
+// control kernel) adds them in block order.
+__global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
+  __shared__ double red[ASM_BLOCK / 64];
+  const int k = blockIdx.y;
+  const InstDev I = A.inst[k];
+  // per-instance layout of the partials (rows, then columns), so that an
+  // instance's objective does not depend on the other instances of a batch
+  const int nbr = asm_row_blocks(I.ns);
+  const int nbc = asm_col_blocks(I.nt_pad);
+  const int b = blockIdx.x;
+  if (b >= nbr + nbc) return;
+  double part = 0.0;
+  if (b < nbr) {
+    const int r = b * ASM_ROWS + threadIdx.x / ASM_LPR;
+    const int q = threadIdx.x % ASM_LPR;
     float s = 0.f;
-    for (int g = 0; g < I.Le; ++g) {
-      if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + jb]) continue;
-      s += A.colsum[(size_t)I.pair_off + (size_t)g * I.nt_pad + c];
+    if (r < I.ns) {
+      const int g = A.row_grp[I.row_off + r];
+      const float* rp = A.rowpart + I.r_off + r;
+      const uint8_t* on = A.tile_on ? A.tile_on + I.tile_off + (size_t)g * I.njb : nullptr;
+      for (int jb = q; jb < I.njb; jb += ASM_LPR) {
+        const float v = rp[(size_t)jb * I.ns];
+        s += (!on || on[jb]) ? v : 0.f;   // skipped tiles: exact zeros (stale data ignored)
+      }
     }
-    const float gval = (c < I.nt) ? A.b_int[I.col_off + c] - s : 0.f;
-    if (A.gb_int) A.gb_int[I.col_off + c] = gval;
-    if (A.gb_out && c < I.nt) A.gb_out[I.scol_off + A.perm_col[I.col_off + c]] = gval;
+    // fixed-order combine of the lanes of a row (xor tree over 8 lanes)
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (q == 0 && r < I.ns) {
+      const float gval = A.a_int[I.row_off + r] - s;
+      if (A.ga_int) A.ga_int[I.row_off + r] = gval;
+      if (A.ga_out) A.ga_out[I.row_off + A.perm_row[I.row_off + r]] = gval;
+      const double av = A.a_uniform[k] ? 1.0 / (double)I.ns : (double)A.a_int[I.row_off + r];
+      part = av * (double)A.alpha[I.row_off + r];
+    }
+  } else {
+    const int c = (b - nbr) * ASM_BLOCK + threadIdx.x;
+    if (c < I.nt_pad) {
+      const int jb = c / TJ;
+      float s = 0.f;
+      double e2 = 0.0;
+      for (int g = 0; g < I.Le; ++g) {
+        if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + jb]) continue;
+        const size_t pr = (size_t)I.pair_off + (size_t)g * I.nt_pad + c;
+        s += A.colsum[pr];
+        const double e = A.excess[pr];
+        e2 += e * e;
+      }
+      const float gval = (c < I.nt) ? A.b_int[I.col_off + c] - s : 0.f;
+      if (A.gb_int) A.gb_int[I.col_off + c] = gval;
+      if (A.gb_out && c < I.nt) A.gb_out[I.scol_off + A.perm_col[I.col_off + c]] = gval;
+      if (c < I.nt) {
+        const double bv = A.b_uniform[k] ? 1.0 / (double)I.nt : (double)A.b_int[I.col_off + c];
+        part = bv * (double)A.beta[I.col_off + c] - e2 * (0.5 / (double)I.gamma);
+      }
+    }
+  }
+  // fixed-order block sum
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < ASM_BLOCK / 64; ++w) t += red[w];
+    A.obj_part[(size_t)k * A.obj_stride + b] = t;
   }
 }
 
-// D = a.alpha + b.beta - sum psi, float64, fixed-order block reduction; one
-// block of 1024 threads per instance.  Uniform marginals use 1/n in float64.
-__global__ void __launch_bounds__(1024) k_objective(ReduceArgs A) {
-  __shared__ double red[1024];
+// D of every instance: sum of the assembly partials in block order (one
+// wavefront per instance: strided partial sums, then a fixed xor tree).
+__device__ __forceinline__ double obj_from_parts(const double* parts, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s += parts[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  return s;
+}
+
+__global__ void __launch_bounds__(64) k_obj_finalize(ReduceArgs A) {
   const int k = blockIdx.x;
   const InstDev I = A.inst[k];
-  const double ua = 1.0 / (double)I.ns, ub = 1.0 / (double)I.nt;
-  const bool au = A.a_uniform[k] != 0, bu = A.b_uniform[k] != 0;
-  double s = 0.0;
-  for (int r = threadIdx.x; r < I.ns; r += blockDim.x)
-    s += (au ? ua : (double)A.a_int[I.row_off + r]) * (double)A.alpha[I.row_off + r];
-  for (int c = threadIdx.x; c < I.nt; c += blockDim.x)
-    s += (bu ? ub : (double)A.b_int[I.col_off + c]) * (double)A.beta[I.col_off + c];
-  // psi terms: sum over evaluated pairs of excess^2 / (2 gamma)
-  double ps = 0.0;
-  const long long npair = (long long)I.Le * I.nt_pad;
-  for (long long q = threadIdx.x; q < npair; q += blockDim.x) {
-    const int g = (int)(q / I.nt_pad), c = (int)(q % I.nt_pad);
-    if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + c / TJ]) continue;
-    const double e = A.excess[(size_t)I.pair_off + q];
-    ps += e * e;
-  }
-  s -= ps * (0.5 / (double)I.gamma);
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
+  const int nparts = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
+  const double D = obj_from_parts(A.obj_part + (size_t)k * A.obj_stride, nparts);
   if (threadIdx.x == 0) {
-    const double D = red[0];
     if (!isfinite(D)) atomicOr(A.err, 4);
-    if (A.obj) A.obj[k] = D;
+    A.obj[k] = D;
   }
 }
 
@@ -396,6 +438,21 @@ __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict_
     be_int[I.col_off + c] = v;
   }
   if (bad) atomicOr(err, 8);
+}
+
+// Host-directed evaluation prologue: every instance gets `mode`; for dense
+// evaluations the counters are advanced here (screened ones count in the
+// screen pass).
+__global__ void k_prologue(int* inst_mode, int count, int mode, long long* counters,
+                           long long pairs_valid, long long tiles) {
+  for (int k = threadIdx.x; k < count; k += blockDim.x) inst_mode[k] = mode;
+  if (threadIdx.x == 0 && mode == EM_DENSE) {
+    unsigned long long* C = (unsigned long long*)counters;
+    atomicAdd(&C[CNT_EVALS], (unsigned long long)count);
+    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)pairs_valid);
+    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)tiles);
+    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)tiles);
+  }
 }
 
 // internal order -> caller order

@@ -22,9 +22,10 @@
 namespace otgs {
 
 constexpr int HMAX = 32;
-constexpr int LB_BLOCK = 256;
+constexpr int LB_BLOCK = 64;
 constexpr int LB_PER_THREAD = 8;
 constexpr int LB_VB = LB_BLOCK * LB_PER_THREAD;   // vector elements per dots block
+constexpr int LB_STAGE = 2048;                     // doubles of LDS staging in ctrl
 
 enum LbStatus { LB_RUNNING = 0, LB_CONVERGED = 1, LB_LSFAIL = 2, LB_MAXITER = 3 };
 
@@ -39,16 +40,28 @@ struct LbState {
   int status, phase, iter, evals, nls, zoom;
   int count, head;            // history ring
   int accept, push, slot, newdir;
-  int since_refresh, pad0;
+  int since_refresh, mode_eval;   // mode_eval: mode of the evaluation just done
+  int pad1, pad2;
   double f, gtd0, gmax;
   double t, t_prev, f_prev, dp_prev;
   double t_lo, f_lo, dp_lo, t_hi, f_hi, dp_hi;
   double t_acc, t_next;
   double GG, cg;
   double SG[HMAX], YG[HMAX], rho[HMAX];
-  double SY[HMAX][HMAX], YY[HMAX][HMAX];
   double cs[HMAX], cy[HMAX];
+  double pad3;
 };
+// The Gram matrices s_i.y_j and y_i.y_j of an instance live next to the state
+// as [2][hist][hist] float64 (row-major, stride hist); the control kernel
+// keeps them in LDS during a step.
+struct LbGram {
+  double* SY;   // SY[i * hist + j] = s_i . y_j
+  double* YY;   // YY[i * hist + j] = y_i . y_j
+  int h;
+  __device__ __forceinline__ double& sy(int i, int j) { return SY[i * h + j]; }
+  __device__ __forceinline__ double& yy(int i, int j) { return YY[i * h + j]; }
+};
+static_assert(sizeof(LbState) % 16 == 0, "LbState is copied as int4");
 
 struct LbArgs {
   const InstDev* inst;
@@ -72,34 +85,23 @@ struct LbArgs {
   double* part;  // [count][maxb][ndot]
   int maxb;
   int ndot;
+  const double* obj_part;   // assembly partials of D, [count][obj_stride]
+  long long obj_stride;
+  double* obj_out;          // D of every instance (also written by ctrl)
+  double* gram;             // [count][2][hist][hist]
+  float* alpha_s;           // snapshot point, written at snapshot evaluations
+  float* beta_s;
 };
 
 __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }
 
 // dot slots: 0 Gt.d, 1 Gt.Gt, 2 Gt.G, 3 d.d, 4 max|Gt| (as a double),
 // 5 + 3i: Gt.s_i, 6 + 3i: Gt.y_i, 7 + 3i: d.y_i
-__device__ __forceinline__ double block_sum_d(double v, double* red) {
+
+__device__ __forceinline__ double wave_sum_dd(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
-}
-
-__device__ __forceinline__ float block_max_f(float v, float* red) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  float s = 0.f;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmaxf(s, red[i]);
-  return s;
+  return v;
 }
 
 // element e of instance k: trial gradient of F (= -grad D)
@@ -107,64 +109,84 @@ __device__ __forceinline__ float lb_gt(const LbArgs& A, const InstDev& I, int e)
   return e < I.ns ? -A.ga[I.row_off + e] : -A.gb[I.col_off + (e - I.ns)];
 }
 
-// grid (maxb, count), block LB_BLOCK
+// grid (maxb, count, 1 + hist), one wavefront per block, LB_PER_THREAD
+// elements per lane.  blockIdx.z = 0 forms the five base dots, z = 1 + i the
+// three dots of history slot i, so every block issues all its loads at once.
+// Each lane writes its partials into an LDS row; lane j then adds column j
+// over the 64 rows in order: one float64 partial per block and dot.
 __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
-  __shared__ double red_d[LB_BLOCK / 64];
-  __shared__ float red_f[LB_BLOCK / 64];
-  const int k = blockIdx.y, b = blockIdx.x;
+  __shared__ double rows[64][6];
+  const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
+  const int lane = threadIdx.x;
   const InstDev I = A.inst[k];
   const LbState& S = A.st[k];
-  if (b == 0 && k == 0 && threadIdx.x == 0) *A.n_active = 0;
+  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
   const int n = I.ns + I.nt_pad;
+  if (b * LB_VB >= n) return;           // beyond this instance: ctrl reads no such partial
   const long long v0 = A.voff[k];
+  const bool run = S.status == LB_RUNNING;
+  const int cnt = (run && S.phase != 0) ? S.count : 0;
+  const int slot = z - 1;
   double* out = A.part + ((size_t)k * A.maxb + b) * A.ndot;
-  const bool live = S.status == LB_RUNNING && S.phase != 0;
-  float gt[LB_PER_THREAD], gv[LB_PER_THREAD], dv[LB_PER_THREAD];
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  float gm = 0.f;
+  if (z > 0 && slot >= cnt) {
+    if (slot < A.P.hist && lane < 3) out[5 + 3 * slot + lane] = 0.0;
+    return;
+  }
+  float gt[LB_PER_THREAD], v1[LB_PER_THREAD], v2[LB_PER_THREAD];
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
-    const int e = b * LB_VB + q * LB_BLOCK + threadIdx.x;
-    gt[q] = gv[q] = dv[q] = 0.f;
-    if (e < n && S.status == LB_RUNNING) {
-      gt[q] = lb_gt(A, I, e);
-      gv[q] = A.G[v0 + e];
-      dv[q] = A.Dv[v0 + e];
+    const int e = b * LB_VB + q * LB_BLOCK + lane;
+    const bool ok = e < n && run;
+    gt[q] = ok ? lb_gt(A, I, e) : 0.f;
+    if (z == 0) {
+      v1[q] = ok ? A.G[v0 + e] : 0.f;    // G
+      v2[q] = ok ? A.Dv[v0 + e] : 0.f;   // d
+    } else {
+      v1[q] = ok ? A.S[(size_t)slot * A.vtot + v0 + e] : 0.f;
+      v2[q] = ok ? A.Y[(size_t)slot * A.vtot + v0 + e] : 0.f;
     }
-    a0 += (double)gt[q] * dv[q];
-    a1 += (double)gt[q] * gt[q];
-    a2 += (double)gt[q] * gv[q];
-    a3 += (double)dv[q] * dv[q];
-    gm = fmaxf(gm, fabsf(gt[q]));
   }
-  double r;
-  r = block_sum_d(a0, red_d); if (threadIdx.x == 0) out[0] = r;
-  r = block_sum_d(a1, red_d); if (threadIdx.x == 0) out[1] = r;
-  r = block_sum_d(a2, red_d); if (threadIdx.x == 0) out[2] = r;
-  r = block_sum_d(a3, red_d); if (threadIdx.x == 0) out[3] = r;
-  const float m = block_max_f(gm, red_f);
-  if (threadIdx.x == 0) out[4] = (double)m;
-  // history dots (only valid ring slots are read)
-  for (int i = 0; i < A.P.hist; ++i) {
-    double s0 = 0, s1 = 0, s2 = 0;
-    const bool valid = live && S.count > 0 && (i < S.count);
-    if (valid) {
-      const float* Si = A.S + (size_t)i * A.vtot + v0;
-      const float* Yi = A.Y + (size_t)i * A.vtot + v0;
+  if (z == 0) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    float gm = 0.f;
 #pragma unroll
-      for (int q = 0; q < LB_PER_THREAD; ++q) {
-        const int e = b * LB_VB + q * LB_BLOCK + threadIdx.x;
-        if (e < n) {
-          const double sv = Si[e], yv = Yi[e];
-          s0 += (double)gt[q] * sv;
-          s1 += (double)gt[q] * yv;
-          s2 += (double)dv[q] * yv;
-        }
-      }
+    for (int q = 0; q < LB_PER_THREAD; ++q) {
+      a0 += (double)gt[q] * v2[q];
+      a1 += (double)gt[q] * gt[q];
+      a2 += (double)gt[q] * v1[q];
+      a3 += (double)v2[q] * v2[q];
+      gm = fmaxf(gm, fabsf(gt[q]));
     }
-    r = block_sum_d(s0, red_d); if (threadIdx.x == 0) out[5 + 3 * i] = r;
-    r = block_sum_d(s1, red_d); if (threadIdx.x == 0) out[6 + 3 * i] = r;
-    r = block_sum_d(s2, red_d); if (threadIdx.x == 0) out[7 + 3 * i] = r;
+    rows[lane][0] = a0;
+    rows[lane][1] = a1;
+    rows[lane][2] = a2;
+    rows[lane][3] = a3;
+    rows[lane][4] = (double)gm;
+  } else {
+    // d is needed for d.y_i
+    double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int q = 0; q < LB_PER_THREAD; ++q) {
+      const int e = b * LB_VB + q * LB_BLOCK + lane;
+      const float dv = (e < n && run) ? A.Dv[v0 + e] : 0.f;
+      s0 += (double)gt[q] * v1[q];
+      s1 += (double)gt[q] * v2[q];
+      s2 += (double)dv * v2[q];
+    }
+    rows[lane][0] = s0;
+    rows[lane][1] = s1;
+    rows[lane][2] = s2;
+  }
+  __syncthreads();
+  const int nd = z == 0 ? 5 : 3;
+  if (lane < nd) {
+    double t = 0.0;
+    if (z == 0 && lane == 4) {
+      for (int r = 0; r < 64; ++r) t = fmax(t, rows[r][lane]);
+    } else {
+      for (int r = 0; r < 64; ++r) t += rows[r][lane];
+    }
+    out[(z == 0 ? 0 : 5 + 3 * slot) + lane] = t;
   }
 }
 
@@ -190,49 +212,56 @@ __device__ __forceinline__ int lb_slot(const LbState& S, int hist, int j) {
   return (S.head - S.count + j + hist) % hist;
 }
 
-// Two-loop recursion on coefficients; d = -H G.  Returns d.G.
-__device__ double lb_direction(LbState& S, int hist) {
+// Two-loop recursion on coefficients; d = -H G.  Returns d.G.  Run by all 64
+// lanes of the control wavefront: lane i keeps the coefficients of pair slot
+// i in registers and every inner product over the slots is a fixed-order
+// wavefront reduction; the state S (LDS) is read by all lanes, written with
+// identical values.
+__device__ double lb_direction(LbState& S, LbGram& G, int hist) {
+  const int lane = threadIdx.x & 63;
   const int m = S.count;
-  double cy[HMAX], cs[HMAX], al[HMAX];
-  for (int i = 0; i < hist; ++i) cy[i] = cs[i] = al[i] = 0.0;
+  const bool mine = lane < hist;
+  double cy = 0.0, cs = 0.0, al = 0.0;
   // q = G + sum cy_i y_i
   for (int j = m - 1; j >= 0; --j) {
     const int sj = lb_slot(S, hist, j);
-    double sq = S.SG[sj];
-    for (int i = 0; i < hist; ++i) sq += cy[i] * S.SY[sj][i];
-    al[sj] = S.rho[sj] * sq;
-    cy[sj] -= al[sj];
+    const double sq = S.SG[sj] + wave_sum_dd(mine ? cy * G.sy(sj, lane) : 0.0);
+    const double a = S.rho[sj] * sq;
+    if (lane == sj) {
+      al = a;
+      cy -= a;
+    }
   }
   double cg = 1.0;
   if (m > 0) {
     const int sn = lb_slot(S, hist, m - 1);
-    const double g0 = S.SY[sn][sn] / S.YY[sn][sn];
+    const double g0 = G.sy(sn, sn) / G.yy(sn, sn);
     cg = g0;
-    for (int i = 0; i < hist; ++i) cy[i] *= g0;
+    cy *= g0;
   }
   for (int j = 0; j < m; ++j) {
     const int sj = lb_slot(S, hist, j);
-    double yr = cg * S.YG[sj];
-    for (int i = 0; i < hist; ++i) yr += cy[i] * S.YY[sj][i] + cs[i] * S.SY[i][sj];
+    const double yr =
+        cg * S.YG[sj] + wave_sum_dd(mine ? cy * G.yy(sj, lane) + cs * G.sy(lane, sj) : 0.0);
     const double be = S.rho[sj] * yr;
-    cs[sj] += al[sj] - be;
+    if (lane == sj) cs += al - be;
   }
+  const double dG = -cg * S.GG + wave_sum_dd(mine ? -cs * S.SG[lane] - cy * S.YG[lane] : 0.0);
   S.cg = -cg;
-  double dG = -cg * S.GG;
-  for (int i = 0; i < hist; ++i) {
-    S.cs[i] = -cs[i];
-    S.cy[i] = -cy[i];
-    dG += S.cs[i] * S.SG[i] + S.cy[i] * S.YG[i];
+  if (mine) {
+    S.cs[lane] = -cs;
+    S.cy[lane] = -cy;
   }
   return dG;
 }
 
-__device__ void lb_new_direction(LbState& S, const LbParams& P) {
-  double gtd = lb_direction(S, P.hist);
+__device__ void lb_new_direction(LbState& S, LbGram& G, const LbParams& P) {
+  const int lane = threadIdx.x & 63;
+  double gtd = lb_direction(S, G, P.hist);
   if (!(gtd < 0.0)) {  // not a descent direction: restart from steepest descent
     S.count = 0;
     S.head = 0;
-    for (int i = 0; i < P.hist; ++i) S.cs[i] = S.cy[i] = 0.0;
+    if (lane < P.hist) S.cs[lane] = S.cy[lane] = 0.0;
     S.cg = -1.0;
     gtd = -S.GG;
   }
@@ -247,42 +276,27 @@ __device__ void lb_new_direction(LbState& S, const LbParams& P) {
   S.newdir = 1;
 }
 
-// one wavefront per instance
-__global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
-  __shared__ double dots[5 + 3 * HMAX];
-  const int k = blockIdx.x;
-  const InstDev I = A.inst[k];
-  LbState& S = A.st[k];
-  const int nb = (I.ns + I.nt_pad + LB_VB - 1) / LB_VB;
-  for (int j = threadIdx.x; j < A.ndot; j += 64) {
-    const double* p = A.part + (size_t)k * A.maxb * A.ndot + j;
-    double s = 0.0;
-    if (j == 4) {
-      for (int b = 0; b < nb; ++b) s = fmax(s, p[(size_t)b * A.ndot]);
-    } else {
-      for (int b = 0; b < nb; ++b) s += p[(size_t)b * A.ndot];
-    }
-    dots[j] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
+__device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, const double* dots,
+                              double D) {
   const LbParams& P = A.P;
   S.accept = 0;
   S.push = 0;
   S.newdir = 0;
+  const bool l0 = (threadIdx.x & 63) == 0;
+  S.mode_eval = A.inst_mode[k];
+  __builtin_amdgcn_wave_barrier();
   if (S.status != LB_RUNNING) {
-    A.inst_mode[k] = EM_SKIP;
+    if (l0) A.inst_mode[k] = EM_SKIP;
     S.t_next = 0.0;
     return;
   }
-  const double D = A.obj[k];
   const double ft = -D;
   const double Gtd = dots[0], GtGt = dots[1], GtG = dots[2], dd = dots[3];
   S.evals++;
   const size_t tr = (size_t)k * (P.max_iter + 1);
   if (!isfinite(D) || !isfinite(GtGt)) {
     S.status = LB_LSFAIL;
-    A.inst_mode[k] = EM_SKIP;
+    if (l0) A.inst_mode[k] = EM_SKIP;
     S.t_next = 0.0;
     return;
   }
@@ -295,21 +309,23 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
     S.gmax = dots[4];
     S.count = 0;
     S.head = 0;
-    if (P.obj_trace) P.obj_trace[tr] = D;
-    if (P.time_trace) P.time_trace[tr] = wall_clock64();
+    if (P.obj_trace && l0) P.obj_trace[tr] = D;
+    if (P.time_trace && l0) P.time_trace[tr] = wall_clock64();
     if (S.gmax <= P.gtol) {
       S.status = LB_CONVERGED;
     } else if (P.max_iter <= 0) {
       S.status = LB_MAXITER;
     }
     if (S.status != LB_RUNNING) {
-      A.inst_mode[k] = EM_SKIP;
+      if (l0) A.inst_mode[k] = EM_SKIP;
       S.t_next = 0.0;
       return;
     }
-    lb_new_direction(S, P);
-    A.inst_mode[k] = P.use_screen ? EM_SCREEN : EM_DENSE;
-    atomicAdd(A.n_active, 1);
+    lb_new_direction(S, G, P);
+    if (l0) {
+      A.inst_mode[k] = P.use_screen ? EM_SCREEN : EM_DENSE;
+      atomicAdd(A.n_active, 1);
+    }
     return;
   }
   // strong-Wolfe line search on phi(t) = F(X + t d)
@@ -348,13 +364,13 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   if (!ok) {
     if (S.nls >= P.max_ls) {
       S.status = LB_LSFAIL;
-      A.inst_mode[k] = EM_SKIP;
+      if (l0) A.inst_mode[k] = EM_SKIP;
       S.t_next = 0.0;
       return;
     }
     if (S.zoom) S.t = lb_cubic(S.t_lo, S.f_lo, S.dp_lo, S.t_hi, S.f_hi, S.dp_hi);
     S.t_next = S.t;
-    atomicAdd(A.n_active, 1);
+    if (l0) atomicAdd(A.n_active, 1);
     // the next trial of the same line search keeps the current mode
     return;
   }
@@ -367,58 +383,147 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   const double sy = t * (Gtd - S.gtd0);
   const double ss = t * t * dd;
   const double yy = GtGt - 2.0 * GtG + S.GG;
-  double SGn[HMAX], YGn[HMAX];
-  for (int i = 0; i < h; ++i) {
-    SGn[i] = dots[5 + 3 * i];
-    YGn[i] = dots[6 + 3 * i];
-  }
+  const int lane = threadIdx.x & 63;
+  double SGn = lane < h ? dots[5 + 3 * lane] : 0.0;   // lane i: s_i . G_new
+  double YGn = lane < h ? dots[6 + 3 * lane] : 0.0;   // lane i: y_i . G_new
   if (sy > 1e-10 * sqrt(ss * yy) && yy > 0.0) {
     const int sl = S.head;
-    // pairs that stay: every valid slot except the one being overwritten
-    for (int j = 0; j < S.count; ++j) {
-      const int i = lb_slot(S, h, j);
-      if (i == sl) continue;
-      S.SY[sl][i] = t * dots[7 + 3 * i];            // s_new . y_i
-      S.SY[i][sl] = dots[5 + 3 * i] - S.SG[i];       // s_i . y_new
-      const double yyi = dots[6 + 3 * i] - S.YG[i];  // y_new . y_i
-      S.YY[sl][i] = yyi;
-      S.YY[i][sl] = yyi;
+    // lane i updates the Gram entries between the new pair and pair i
+    // (every valid slot except the one being overwritten)
+    bool valid = false;
+    for (int j = 0; j < S.count; ++j) valid |= (lb_slot(S, h, j) == lane);
+    const double old_sg = lane < h ? S.SG[lane] : 0.0, old_yg = lane < h ? S.YG[lane] : 0.0;
+    if (lane < h && valid && lane != sl) {
+      G.sy(sl, lane) = t * dots[7 + 3 * lane];            // s_new . y_i
+      G.sy(lane, sl) = dots[5 + 3 * lane] - old_sg;        // s_i . y_new
+      const double yyi = dots[6 + 3 * lane] - old_yg;      // y_new . y_i
+      G.yy(sl, lane) = yyi;
+      G.yy(lane, sl) = yyi;
     }
-    S.SY[sl][sl] = sy;
-    S.YY[sl][sl] = yy;
+    G.sy(sl, sl) = sy;
+    G.yy(sl, sl) = yy;
     S.rho[sl] = 1.0 / sy;
-    SGn[sl] = t * Gtd;
-    YGn[sl] = GtGt - GtG;
+    if (lane == sl) {
+      SGn = t * Gtd;
+      YGn = GtGt - GtG;
+    }
     S.push = 1;
     S.slot = sl;
     S.head = (S.head + 1) % h;
     if (S.count < h) S.count++;
   }
-  for (int i = 0; i < h; ++i) {
-    S.SG[i] = SGn[i];
-    S.YG[i] = YGn[i];
+  if (lane < h) {
+    S.SG[lane] = SGn;
+    S.YG[lane] = YGn;
   }
   S.GG = GtGt;
   S.gmax = dots[4];
-  if (P.obj_trace) P.obj_trace[tr + S.iter] = D;
-  if (P.time_trace) P.time_trace[tr + S.iter] = wall_clock64();
+  if (P.obj_trace && l0) P.obj_trace[tr + S.iter] = D;
+  if (P.time_trace && l0) P.time_trace[tr + S.iter] = wall_clock64();
   if (S.gmax <= P.gtol) S.status = LB_CONVERGED;
   else if (S.iter >= P.max_iter) S.status = LB_MAXITER;
   if (S.status != LB_RUNNING) {
-    A.inst_mode[k] = EM_SKIP;
+    if (l0) A.inst_mode[k] = EM_SKIP;
     S.t_next = 0.0;
     return;
   }
-  lb_new_direction(S, P);
+  lb_new_direction(S, G, P);
   int mode = P.use_screen ? EM_SCREEN : EM_DENSE;
   if (P.use_screen && ++S.since_refresh >= P.refresh) {
     S.since_refresh = 0;
     mode = EM_SNAPSHOT;
   }
-  A.inst_mode[k] = mode;
-  atomicAdd(A.n_active, 1);
+  if (l0) {
+    A.inst_mode[k] = mode;
+    atomicAdd(A.n_active, 1);
+  }
 }
 
+// one wavefront per instance; the state lives in LDS during the step
+__global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
+  __shared__ double dots[5 + 3 * HMAX];
+  __shared__ LbState S;
+  __shared__ double gram_s[2 * HMAX * HMAX];
+  __shared__ double stage[LB_STAGE];   // chunk of the dot partials
+  const int k = blockIdx.x;
+  const InstDev I = A.inst[k];
+  const int h = A.P.hist;
+  double* gram_g = A.gram + (size_t)k * 2 * h * h;
+  {
+    // state (int4 words) and the two Gram matrices: every load is issued
+    // before any LDS store
+    constexpr int NV = (int)(sizeof(LbState) / 16);
+    static_assert(NV <= 2 * 64, "state copy assumes at most two int4 per lane");
+    const int4* src = (const int4*)&A.st[k];
+    int4* dst = (int4*)&S;
+    const int i0 = threadIdx.x, i1 = threadIdx.x + 64;
+    const int4 w0 = src[i0];
+    const int4 w1 = i1 < NV ? src[i1] : int4{0, 0, 0, 0};
+    const int ng = 2 * h * h;
+    double g[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int q = u * 64 + threadIdx.x;
+      g[u] = q < ng ? gram_g[q] : 0.0;
+    }
+    dst[i0] = w0;
+    if (i1 < NV) dst[i1] = w1;
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int q = u * 64 + threadIdx.x;
+      if (q < ng) gram_s[q] = g[u];
+    }
+  }
+  LbGram G{gram_s, gram_s + h * h, h};
+  // dot partials [nb][ndot] staged through LDS in chunks of whole blocks,
+  // then summed per dot in block order
+  const int nb = (I.ns + I.nt_pad + LB_VB - 1) / LB_VB;
+  const int per_chunk = max(1, LB_STAGE / A.ndot);
+  double acc = 0.0;   // lane j: dot j (j < ndot <= 5 + 3 HMAX <= 101 handled below)
+  double acc2 = 0.0;  // lane j: dot j + 64
+  for (int b0 = 0; b0 < nb; b0 += per_chunk) {
+    const int nbc = min(per_chunk, nb - b0);
+    const double* src = A.part + ((size_t)k * A.maxb + b0) * A.ndot;
+    const int tot = nbc * A.ndot;
+    for (int base = 0; base < tot; base += 64 * 8) {
+      double tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * 64 + threadIdx.x;
+        tmp[u] = i < tot ? src[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * 64 + threadIdx.x;
+        if (i < tot) stage[i] = tmp[u];
+      }
+    }
+    __syncthreads();
+    const int j = threadIdx.x;
+    if (j < A.ndot) {
+      for (int b = 0; b < nbc; ++b)
+        acc = (j == 4) ? fmax(acc, stage[b * A.ndot + j]) : acc + stage[b * A.ndot + j];
+    }
+    if (j + 64 < A.ndot) {
+      for (int b = 0; b < nbc; ++b) acc2 += stage[b * A.ndot + j + 64];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < A.ndot) dots[threadIdx.x] = acc;
+  if (threadIdx.x + 64 < A.ndot) dots[threadIdx.x + 64] = acc2;
+  const double Dobj = obj_from_parts(A.obj_part + (size_t)k * A.obj_stride,
+                                     asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad));
+  __syncthreads();
+  if (threadIdx.x == 0) A.obj_out[k] = Dobj;
+  lb_ctrl_logic(A, k, S, G, dots, Dobj);
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
+  {
+    const int4* src = (const int4*)&S;
+    int4* dst = (int4*)&A.st[k];
+    for (int i = threadIdx.x; i < (int)(sizeof(LbState) / 16); i += 64) dst[i] = src[i];
+  }
+}
 // grid (vector blocks, count); accept, push, new direction, next trial point
 __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const int k = blockIdx.y;
@@ -427,8 +532,14 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const int n = I.ns + I.nt_pad;
   const long long v0 = A.voff[k];
   const int h = A.P.hist;
+  const bool snap = S.mode_eval == EM_SNAPSHOT;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     float* tp = e < I.ns ? &A.alpha[I.row_off + e] : &A.beta[I.col_off + (e - I.ns)];
+    if (snap) {
+      // the point just evaluated densely becomes the snapshot (alpha~, beta~)
+      if (e < I.ns) A.alpha_s[I.row_off + e] = *tp;
+      else A.beta_s[I.col_off + (e - I.ns)] = *tp;
+    }
     float x = A.X[v0 + e];
     if (S.accept) {
       const float gt = lb_gt(A, I, e);
@@ -441,8 +552,11 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
       A.G[v0 + e] = gt;
     }
     if (S.newdir) {
+      // d = cg G + sum over ring slots (in age order) of cs_i s_i + cy_i y_i
       double d = S.cg * (double)A.G[v0 + e];
-      for (int j = 0; j < S.count; ++j) {
+      const int cnt = S.count;
+#pragma unroll 8
+      for (int j = 0; j < cnt; ++j) {
         const int i = lb_slot(S, h, j);
         d += S.cs[i] * (double)A.S[(size_t)i * A.vtot + v0 + e] +
              S.cy[i] * (double)A.Y[(size_t)i * A.vtot + v0 + e];
@@ -484,8 +598,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     S.t_next = 0.0;
     S.GG = 0.0;
     for (int i = 0; i < HMAX; ++i) S.SG[i] = S.YG[i] = S.rho[i] = S.cs[i] = S.cy[i] = 0.0;
-    for (int i = 0; i < HMAX; ++i)
-      for (int j = 0; j < HMAX; ++j) S.SY[i][j] = S.YY[i][j] = 0.0;
+    for (int q = 0; q < 2 * A.P.hist * A.P.hist; ++q) A.gram[(size_t)k * 2 * A.P.hist * A.P.hist + q] = 0.0;
     // zero start: the zero snapshot is exact (z~ = 0 since C >= 0); a user
     // start is evaluated densely and taken as the first snapshot
     A.inst_mode[k] = !use_screen ? EM_DENSE : (init_user ? EM_SNAPSHOT : EM_SCREEN);

@@ -63,7 +63,8 @@ struct GroupStats {
   double all;       // || alpha - alpha~ ||
   double amax;      // max |alpha_i| over the group (current point)
   double amax_s;    // max |alpha~_i| over the group (snapshot)
-  double pad[3];
+  double sg;        // sqrt(g_l)
+  double fa, fb;    // rounding factors of the safe upper bound (see screen.hip)
 };
 
 // Device-side counters (int64, integer atomics only).

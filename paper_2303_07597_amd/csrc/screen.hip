@@ -90,7 +90,14 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
     s.all = sqrt(sm[0][0] + sm[1][0]);
     s.amax = sm[2][0];
     s.amax_s = sm[3][0];
-    s.pad[0] = s.pad[1] = s.pad[2] = 0;
+    // per-group constants of the rounding-safe upper bound
+    const double u = 5.9604644775390625e-08;
+    const int nch = (n + CHUNK - 1) / CHUNK;
+    const double nop = (double)n + 17.0 * nch + 16.0;
+    const double gam = nop * u / (1.0 - nop * u);
+    s.sg = sqrt((double)n);
+    s.fa = (1.0 + 2.0 * u) * sqrt(1.0 + gam) * (1.0 + 1e-9);
+    s.fb = 1.0 / ((1.0 - 2.0 * u) * sqrt(1.0 - gam));
     A.gstats[gidx] = s;
     if (ge == 0) {
       const int m = A.inst_mode[k];
@@ -105,98 +112,124 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
   }
 }
 
-__device__ __forceinline__ long long wave_popc(bool b) { return __popcll(__ballot(b)); }
+constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
 
-// One wavefront per group tile (4 per block), one lane per target column.
-// mode 1 (screen): classify every pair (in N / bound tested / skipped), mark
-// the tile when any pair must be evaluated and append it to the work lists.
-// mode 2 (extract): rebuild N from the lower bound; no lists.
-__global__ void __launch_bounds__(256) k_screen_pairs(ScreenArgs A) {
+// One wavefront per group tile (SCREEN_TILES per block), one lane per target
+// column.  SCREEN: classify every pair (in N / bound tested / skipped), mark
+// the tile when any pair must be evaluated.  SNAPSHOT: rebuild N from the
+// lower bound, then evaluate densely.  DENSE: every tile.  SKIP: nothing.
+// Active tiles are appended to the work lists; counters and list positions
+// are aggregated per block so each block issues one atomic per quantity.
+__global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A) {
+  __shared__ int s_cnt[SCREEN_TILES][8];   // valid, inN, checked, unskipped, main, split,
+                                           // chunks of an active split tile, tile counted
+  __shared__ int s_base[3];
   const int lane = threadIdx.x & (WAVE - 1);
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= A.n_tiles_all) return;
-  const TileDesc d = A.tiles_all[t];
-  const InstDev I = A.inst[d.inst];
-  const int gidx = I.grp_off + d.grp;
-  const GroupStats S = A.gstats[gidx];
-  const int g = A.g_size[gidx];
-  const int col = d.jb * TJ + lane;
-  const bool valid = col < I.nt;
-  const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
-  const double b = A.beta[I.col_off + col], bs = A.beta_s[I.col_off + col];
-  const double db = b - bs;
-  const double sg = sqrt((double)g);
-  const double thr = (double)I.thr;
-
-  const int mode = A.inst_mode[d.inst];
-  if (mode == EM_SKIP) {
-    if (lane == 0) A.tile_on[(size_t)I.tile_off + (size_t)d.grp * I.njb + d.jb] = 0;
-    return;
-  }
-  if (mode == EM_SNAPSHOT && valid) {
-    // Algorithm 1: rebuild N from the lower bound against the old snapshot
-    uint8_t f = PAIR_SKIP;
-    if (A.use_lower) {
-      const double zt = A.zsnap[pr], ot = A.osnap[pr];
-      const double kt = sqrt(zt * zt + ot * ot);
-      const double zlow = kt - S.all - sg * fabs(db) - ot - S.dn - sg * (db < 0 ? -db : 0.0);
-      if (zlow > thr) f = PAIR_IN_N;
-    }
-    A.inN[pr] = f;
-  }
-  const double u = 5.9604644775390625e-08;
-  const int nch = (g + CHUNK - 1) / CHUNK;
-  const double nop = (double)g + 17.0 * nch + 16.0;
-  const double gam = nop * u / (1.0 - nop * u);
-  const double cm = (double)I.cmax;
-  const double del_s = 2.01 * u * (S.amax_s + fabs(bs) + cm);
-  const double del_c = 2.01 * u * (S.amax + fabs(b) + cm);
-  bool inN = false, checked = false, compute = false;
-  if (valid) {
-    if (mode != EM_SCREEN) {
-      compute = true;               // dense evaluation (also at a snapshot)
-    } else if (A.inN[pr] == PAIR_IN_N) {
-      inN = true;
-      compute = true;
-    } else {
-      checked = true;
-      const double zt = A.zsnap[pr];
-      const double ub = (1.0 + 2.0 * u) * sqrt(1.0 + gam) *
-                        (zt / ((1.0 - 2.0 * u) * sqrt(1.0 - gam)) + sg * (del_s + del_c) + S.up +
-                         sg * (db > 0 ? db : 0.0)) *
-                        (1.0 + 1e-9);
-      compute = !(ub <= thr);
-    }
-  }
-  const unsigned long long on = __ballot(compute);
-  const long long c_valid = wave_popc(valid), c_in = wave_popc(inN), c_chk = wave_popc(checked),
-                  c_uns = wave_popc(checked && compute);
-  if (lane == 0) {
-    const size_t tix = (size_t)I.tile_off + (size_t)d.grp * I.njb + d.jb;
-    A.tile_on[tix] = on ? 1 : 0;
-    atomicAdd((unsigned long long*)&A.counters[CNT_PAIRS_TOTAL], (unsigned long long)c_valid);
-    if (c_in) atomicAdd((unsigned long long*)&A.counters[CNT_PAIRS_N], (unsigned long long)c_in);
-    if (c_chk)
-      atomicAdd((unsigned long long*)&A.counters[CNT_PAIRS_CHECKED], (unsigned long long)c_chk);
-    if (c_uns)
-      atomicAdd((unsigned long long*)&A.counters[CNT_PAIRS_UNSKIPPED], (unsigned long long)c_uns);
-    atomicAdd((unsigned long long*)&A.counters[CNT_TILES_TOTAL], 1ull);
-    if (on) {
-      atomicAdd((unsigned long long*)&A.counters[CNT_TILES_COMPUTED], 1ull);
-      if (d.aux >= 0) {
-        const int pos = atomicAdd(&A.counts[0], 1);
-        A.list_main[pos] = d;
-      } else {
-        const int pos = atomicAdd(&A.counts[1], 1);
-        TileDesc e = d;
-        e.aux = 0;
-        A.list_sg[pos] = e;
-        const int n = -d.aux;
-        const int pc = atomicAdd(&A.counts[2], n);
-        for (int c = 0; c < n; ++c) {
-          e.aux = c;
-          A.list_sc[pc + c] = e;
+  const int wv = threadIdx.x >> 6;
+  const int t = blockIdx.x * SCREEN_TILES + wv;
+  const bool tile_ok = t < A.n_tiles_all;
+  TileDesc d = tile_ok ? A.tiles_all[t] : TileDesc{0, 0, 0, 0};
+  int c_valid = 0, c_in = 0, c_chk = 0, c_uns = 0;
+  bool on = false;
+  if (tile_ok) {
+    const InstDev I = A.inst[d.inst];
+    const int mode = A.inst_mode[d.inst];
+    const int gidx = I.grp_off + d.grp;
+    const int col = d.jb * TJ + lane;
+    const bool valid = col < I.nt && mode != EM_SKIP;
+    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+    bool inN = false, checked = false, compute = false;
+    if (valid) {
+      const GroupStats S = A.gstats[gidx];
+      const double b = A.beta[I.col_off + col], bs = A.beta_s[I.col_off + col];
+      const double db = b - bs;
+      const double sg = S.sg;
+      const double thr = (double)I.thr;
+      if (mode == EM_SNAPSHOT) {
+        // Algorithm 1: rebuild N from the lower bound against the old snapshot
+        uint8_t f = PAIR_SKIP;
+        if (A.use_lower) {
+          const double zt = A.zsnap[pr], ot = A.osnap[pr];
+          const double kt = sqrt(zt * zt + ot * ot);
+          const double zlow = kt - S.all - sg * fabs(db) - ot - S.dn - sg * (db < 0 ? -db : 0.0);
+          if (zlow > thr) f = PAIR_IN_N;
         }
+        A.inN[pr] = f;
+        compute = true;
+      } else if (mode == EM_DENSE) {
+        compute = true;
+      } else if (A.inN[pr] == PAIR_IN_N) {
+        inN = true;
+        compute = true;
+      } else {
+        const double u2 = 2.01 * 5.9604644775390625e-08;
+        checked = true;
+        const double zt = A.zsnap[pr];
+        const double ub = S.fa * (zt * S.fb +
+                                  S.sg * (u2 * (S.amax_s + S.amax + 2.0 * (double)I.cmax +
+                                                fabs(bs) + fabs(b)) + (db > 0 ? db : 0.0)) +
+                                  S.up);
+        compute = !(ub <= thr);
+      }
+    }
+    on = __ballot(compute) != 0ull;
+    c_valid = __popcll(__ballot(valid));
+    c_in = __popcll(__ballot(inN));
+    c_chk = __popcll(__ballot(checked));
+    c_uns = __popcll(__ballot(checked && compute));
+    if (lane == 0) A.tile_on[(size_t)I.tile_off + (size_t)d.grp * I.njb + d.jb] = on ? 1 : 0;
+  }
+  if (lane == 0) {
+    s_cnt[wv][0] = c_valid;
+    s_cnt[wv][1] = c_in;
+    s_cnt[wv][2] = c_chk;
+    s_cnt[wv][3] = c_uns;
+    s_cnt[wv][4] = (on && d.aux >= 0) ? 1 : 0;
+    s_cnt[wv][5] = (on && d.aux < 0) ? 1 : 0;
+    s_cnt[wv][6] = (on && d.aux < 0) ? -d.aux : 0;
+    s_cnt[wv][7] = (tile_ok && A.inst_mode[d.inst] != EM_SKIP) ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot[4] = {0, 0, 0, 0};
+    int nmain = 0, nsg = 0, nsc = 0, ntile = 0, non = 0;
+    for (int w = 0; w < SCREEN_TILES; ++w) {
+      for (int q = 0; q < 4; ++q) tot[q] += s_cnt[w][q];
+      nmain += s_cnt[w][4];
+      nsg += s_cnt[w][5];
+      nsc += s_cnt[w][6];
+      ntile += s_cnt[w][7];
+      non += s_cnt[w][4] + s_cnt[w][5];
+    }
+    s_base[0] = nmain ? atomicAdd(&A.counts[0], nmain) : 0;
+    s_base[1] = nsg ? atomicAdd(&A.counts[1], nsg) : 0;
+    s_base[2] = nsc ? atomicAdd(&A.counts[2], nsc) : 0;
+    unsigned long long* C = (unsigned long long*)A.counters;
+    if (tot[0]) atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)tot[0]);
+    if (tot[1]) atomicAdd(&C[CNT_PAIRS_N], (unsigned long long)tot[1]);
+    if (tot[2]) atomicAdd(&C[CNT_PAIRS_CHECKED], (unsigned long long)tot[2]);
+    if (tot[3]) atomicAdd(&C[CNT_PAIRS_UNSKIPPED], (unsigned long long)tot[3]);
+    if (ntile) atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)ntile);
+    if (non) atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)non);
+  }
+  __syncthreads();
+  // list positions in tile order within the block
+  if (lane == 0 && on) {
+    int pm = s_base[0], ps = s_base[1], pc = s_base[2];
+    for (int w = 0; w < wv; ++w) {
+      pm += s_cnt[w][4];
+      ps += s_cnt[w][5];
+      pc += s_cnt[w][6];
+    }
+    if (d.aux >= 0) {
+      A.list_main[pm] = d;
+    } else {
+      TileDesc e = d;
+      e.aux = 0;
+      A.list_sg[ps] = e;
+      for (int c = 0; c < -d.aux; ++c) {
+        e.aux = c;
+        A.list_sc[pc + c] = e;
       }
     }
   }
