@@ -53,10 +53,10 @@ def grad_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(ns, nt, L, tj=64):
+def algorithmic_bytes(ns, nt, L, tj=32):
     """Bytes one dense gradient-tile launch must move at minimum: the cost
     once (4 B per entry), alpha and beta once, the row partials (one float per
-    row and 64-column block), column sums and excess per (class, target)."""
+    row and 32-column block), column sums and excess per (class, target)."""
     njb = -(-nt // tj)
     return 4 * ns * nt + 4 * (ns + nt) + 4 * ns * njb + 8 * L * nt
 
@@ -124,7 +124,11 @@ def main():
     grad_ms, grad_n = h.kernel_time(O.KERNEL_GRAD)
     ms_step = 1e3 * el / args.steps
     value = ns * nt * args.steps / el
-    grad_avg_s = grad_ms * 1e-3 / max(grad_n, 1)
+    # per-launch duration of the gradient-tile kernel: HIP events around
+    # `steps` back-to-back launches on the stream the kernel runs on
+    h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
+    grad_us = h.profile_tiles(args.steps)
+    grad_avg_s = grad_us * 1e-6
     alg_bytes = algorithmic_bytes(ns, nt, L)
     achieved = alg_bytes / grad_avg_s / 1e9
     traffic = None
@@ -202,8 +206,9 @@ def main():
                     point="after 200 dense L-BFGS iterations from zero", parallelism="single GPU"),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel="k_grad_tiles<0>", algorithmic_bytes_per_launch=alg_bytes,
-                      avg_launch_us=grad_avg_s * 1e6, launches=grad_n),
+                      kernel="k_grad_tiles<16,0,false>", algorithmic_bytes_per_launch=alg_bytes,
+                      avg_launch_us=grad_avg_s * 1e6, launches=args.steps,
+                      event_bracketed_us_per_call=1e3 * grad_ms / max(grad_n, 1)),
         cpu_baseline=cpu,
         screened_eval=screened,
         solves=solves,

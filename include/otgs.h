@@ -91,7 +91,8 @@ typedef struct {
     float mu;              /* >= 0                                                  */
 } ot_gs_problem;
 
-/* Screening and timing counters, cumulative since create / last reset. */
+/* Screening and timing counters, cumulative since create / last reset.
+ * A tile is (group, 32 consecutive targets of the internal layout). */
 typedef struct {
     long long evals;            /* gradient evaluations                               */
     long long pairs_total;      /* (group, target) blocks covered, summed over evals  */
@@ -99,7 +100,7 @@ typedef struct {
     long long pairs_checked;    /* blocks outside N whose upper bound was tested (s_n)*/
     long long pairs_unskipped;  /* tested blocks that could not be skipped   (s_u)    */
     long long refreshes;        /* snapshot refreshes                        (s_r)    */
-    long long tiles_total;      /* (group, 64-target) tiles covered                   */
+    long long tiles_total;      /* (group, 32-target) tiles covered                   */
     long long tiles_computed;   /* tiles actually streamed through the gradient kernel*/
 } ot_gs_stats;
 
@@ -192,6 +193,13 @@ int ot_gs_get_stats(ot_gs_handle *h, ot_gs_stats *out, int reset, void *stream);
  * returns the summed milliseconds and launch count since enabling. */
 int ot_gs_kernel_timing(ot_gs_handle *h, int enable);
 int ot_gs_kernel_time(ot_gs_handle *h, int which, double *ms, long long *launches);
+
+/* Launch-by-launch cost of the dense gradient tiles (Eq. 5 per (group, 32
+ * target) tile) at the handle's current evaluation point: `repeats`
+ * back-to-back launches of the tile kernels between two HIP events on
+ * `stream`; writes the mean microseconds per launch (host out).  Leaves the
+ * row and column partials of a dense evaluation; synchronises `stream`. */
+int ot_gs_profile_tiles(ot_gs_handle *h, int repeats, double *us_per_launch, void *stream);
 
 /* Size facts of instance k (host out, any may be NULL): groups that are
  * nonempty, padded target count of the internal layout, tiles. */

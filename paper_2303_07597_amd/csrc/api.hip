@@ -73,6 +73,8 @@ struct ot_gs_handle {
   long long tot_rows = 0, tot_cols = 0, tot_cols_pad = 0, tot_groups = 0, tot_pairs = 0,
             tot_tiles = 0, tot_c = 0, tot_r = 0, tot_chunk = 0;
   int n_main = 0, n_sg = 0, n_sc = 0;
+  int n_bucket[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int main_off[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
   int dev = 0, n_cu = 256;
   // device arrays
   InstDev* d_inst = nullptr;
@@ -90,9 +92,11 @@ struct ot_gs_handle {
   uint8_t *inN = nullptr, *tile_on = nullptr;
   TileDesc *tiles_all = nullptr, *list_main = nullptr, *list_sg = nullptr, *list_sc = nullptr;
   TileDesc *dyn_main = nullptr, *dyn_sg = nullptr, *dyn_sc = nullptr;
-  int* counts_static = nullptr;  // [3]
-  int* counts_dyn = nullptr;     // [3]
+  int* counts_static = nullptr;  // [NBUCKET + 2]
+  int* counts_dyn = nullptr;     // [NBUCKET + 2]
   long long* counters = nullptr;
+  long long* block_counters = nullptr;  // [screen blocks][CNT_NUM]
+  int n_screen_blocks = 0;
   int* err = nullptr;
   long long* t_off = nullptr;    // plan offsets
   int* inst_mode = nullptr;      // EvalMode per instance (device)
@@ -473,7 +477,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     }
     dim3 grid((unsigned)std::min<long long>(ceil_div(maxntp, 256), 64), (unsigned)std::min(maxns, 65535), count);
     hipLaunchKernelGGL(k_relayout_cost, grid, dim3(256), 0, s, h->d_inst, d_costs, d_scale, h->perm_row,
-                       h->perm_col, h->C);
+                       h->perm_col, h->row_grp, h->g_start, h->g_size, h->C);
     LAUNCHCHK();
   }
 
@@ -508,7 +512,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
 
   // ---- work lists (static for dense evaluations, dynamic for screened ones)
   {
-    std::vector<TileDesc> all, mainl, sg, sc;
+    std::vector<TileDesc> all, sg, sc;
+    std::vector<TileDesc> bucket[NBUCKET];
     for (int k = 0; k < count; ++k) {
       const InstHost& ih = h->inst[k];
       for (int g = 0; g < ih.d.Le; ++g) {
@@ -516,16 +521,22 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
         const bool split = n > CHUNK;
         const int nch = (int)ceil_div(n, CHUNK);
         for (int jb = 0; jb < ih.d.njb; ++jb) {
-          TileDesc t{k, g, jb, split ? -nch : row_class(n)};
+          TileDesc t{k, g, jb, split ? -nch : row_bucket(n)};
           all.push_back(t);
           if (!split) {
-            mainl.push_back(t);
+            bucket[t.aux].push_back(t);
           } else {
             sg.push_back(TileDesc{k, g, jb, 0});
             for (int c = 0; c < nch; ++c) sc.push_back(TileDesc{k, g, jb, c});
           }
         }
       }
+    }
+    std::vector<TileDesc> mainl;
+    for (int b = 0; b < NBUCKET; ++b) {
+      h->main_off[b] = (int)mainl.size();
+      h->n_bucket[b] = (int)bucket[b].size();
+      mainl.insert(mainl.end(), bucket[b].begin(), bucket[b].end());
     }
     h->n_main = (int)mainl.size();
     h->n_sg = (int)sg.size();
@@ -546,11 +557,14 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     TRY(up(h->list_main, mainl));
     TRY(up(h->list_sg, sg));
     TRY(up(h->list_sc, sc));
-    TRY(h->alloc(&h->counts_static, 3));
-    TRY(h->alloc(&h->counts_dyn, 3));
-    int hc[3] = {h->n_main, h->n_sg, h->n_sc};
+    TRY(h->alloc(&h->counts_static, NBUCKET + 2));
+    TRY(h->alloc(&h->counts_dyn, NBUCKET + 2));
+    int hc[NBUCKET + 2];
+    for (int b = 0; b < NBUCKET; ++b) hc[b] = h->n_bucket[b];
+    hc[NBUCKET] = h->n_sg;
+    hc[NBUCKET + 1] = h->n_sc;
     HIPCHK(hipMemcpyAsync(h->counts_static, hc, sizeof hc, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(h->counts_dyn, 0, sizeof(int) * 3, s));
+    HIPCHK(hipMemsetAsync(h->counts_dyn, 0, sizeof(int) * (NBUCKET + 2), s));
   }
 
   // ---- evaluation state
@@ -581,6 +595,9 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   TRY(h->alloc(&h->gstats, std::max<long long>(h->tot_groups, 1)));
   TRY(h->alloc(&h->obj, count));
   TRY(h->alloc(&h->counters, CNT_NUM));
+  h->n_screen_blocks = (int)ceil_div(h->tot_tiles, SCREEN_TILES);
+  TRY(h->alloc(&h->block_counters, (size_t)h->n_screen_blocks * CNT_NUM));
+  HIPCHK(hipMemsetAsync(h->block_counters, 0, sizeof(long long) * h->n_screen_blocks * CNT_NUM, s));
   TRY(h->alloc(&h->t_off, count));
   HIPCHK(hipMemsetAsync(h->alpha_s, 0, sizeof(float) * h->tot_rows, s));
   HIPCHK(hipMemsetAsync(h->beta_s, 0, sizeof(float) * h->tot_cols_pad, s));
@@ -649,7 +666,9 @@ static ScreenArgs screen_args(ot_gs_handle* h, int use_lower) {
   S.list_sg = h->dyn_sg;
   S.list_sc = h->dyn_sc;
   S.counts = h->counts_dyn;
+  for (int b = 0; b < NBUCKET; ++b) S.main_off[b] = h->main_off[b];
   S.counters = h->counters;
+  S.block_counters = h->block_counters;
   S.inst_mode = h->inst_mode;
   S.use_lower = use_lower;
   return S;
@@ -689,35 +708,64 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   return R;
 }
 
+// Gradient-tile launches over the static (every tile) or dynamic (screen
+// output) work lists: one kernel per row bucket, plus the split-group passes.
+static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_possible, hipStream_t s) {
+  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
+  TileDesc* mlist = dynamic ? h->dyn_main : h->list_main;
+  for (int b = 0; b < NBUCKET; ++b) {
+    if (h->n_bucket[b] == 0) continue;
+    A.list = mlist + h->main_off[b];
+    A.count = cnt + b;
+    const dim3 grid(grid_for(h, h->n_bucket[b])), block(BLOCK);
+    for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+#define OTGS_LAUNCH_BUCKET(RR)                                                         \
+  if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true>), grid, block, 0, s, A);      \
+  else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false>), grid, block, 0, s, A);
+      switch (b) {
+        case 0: OTGS_LAUNCH_BUCKET(4) break;
+        case 1: OTGS_LAUNCH_BUCKET(8) break;
+        case 2: OTGS_LAUNCH_BUCKET(12) break;
+        case 3: OTGS_LAUNCH_BUCKET(16) break;
+        case 4: OTGS_LAUNCH_BUCKET(20) break;
+        case 5: OTGS_LAUNCH_BUCKET(24) break;
+        case 6: OTGS_LAUNCH_BUCKET(28) break;
+        default: OTGS_LAUNCH_BUCKET(32) break;
+      }
+#undef OTGS_LAUNCH_BUCKET
+      LAUNCHCHK();
+    }
+  }
+  if (h->n_sg > 0) {
+    A.list = dynamic ? h->dyn_sc : h->list_sc;
+    A.count = cnt + NBUCKET + 1;
+    for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+      if (sp) hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, true>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, false>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+      LAUNCHCHK();
+    }
+    A.list = dynamic ? h->dyn_sg : h->list_sg;
+    A.count = cnt + NBUCKET;
+    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
+    LAUNCHCHK();
+    A.list = dynamic ? h->dyn_sc : h->list_sc;
+    A.count = cnt + NBUCKET + 1;
+    hipLaunchKernelGGL((k_grad_tiles<RMAX, 2, false>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
+    LAUNCHCHK();
+  }
+  return OT_GS_OK;
+}
+
 // Gradient tiles over the static (every tile) or dynamic (screen output)
 // work lists, then the fixed-order assembly.
 static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, float* gb_out,
-                                hipStream_t s, bool write_kappa, bool finalize = true) {
+                                hipStream_t s, bool write_kappa, bool finalize = true,
+                                bool snap_possible = false) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_GRAD, s, &e0));
   GradArgs A = grad_args(h);
   A.write_kappa = write_kappa ? 1 : 0;
-  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
-  if (h->n_main > 0) {
-    A.list = dynamic ? h->dyn_main : h->list_main;
-    A.count = cnt + 0;
-    hipLaunchKernelGGL(k_grad_tiles<0>, dim3(grid_for(h, h->n_main)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-  }
-  if (h->n_sg > 0) {
-    A.list = dynamic ? h->dyn_sc : h->list_sc;
-    A.count = cnt + 2;
-    hipLaunchKernelGGL(k_grad_tiles<1>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-    A.list = dynamic ? h->dyn_sg : h->list_sg;
-    A.count = cnt + 1;
-    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
-    LAUNCHCHK();
-    A.list = dynamic ? h->dyn_sc : h->list_sc;
-    A.count = cnt + 2;
-    hipLaunchKernelGGL(k_grad_tiles<2>, dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-    LAUNCHCHK();
-  }
+  TRY(launch_tiles(h, A, dynamic, snap_possible, s));
   TRY(tend(h, KT_GRAD, s, e0));
   TRY(tbegin(h, KT_REDUCE, s, &e0));
   ReduceArgs R = reduce_args(h, dynamic, ga_out, gb_out);
@@ -735,7 +783,8 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
 // (bounds, extraction at refreshes, work lists), tiles, assembly, snapshot.
 static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float* ga_out,
                             float* gb_out, bool write_kappa = false, bool finalize = true,
-                            bool snapshot_copy = true, bool group_stats = true) {
+                            bool snapshot_copy = true, bool group_stats = true,
+                            bool snap_possible = true) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_SCREEN, s, &e0));
   ScreenArgs S = screen_args(h, use_lower);
@@ -749,7 +798,7 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
     LAUNCHCHK();
   }
   TRY(tend(h, KT_SCREEN, s, e0));
-  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa, finalize));
+  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa, finalize, snap_possible));
   if (!snapshot_copy) return OT_GS_OK;
   hipLaunchKernelGGL(k_snapshot_copy, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns + h->max_ntp, 256), 256), h->count),
                      dim3(256), 0, s, h->d_inst, h->inst_mode, h->alpha, h->alpha_s, h->beta, h->beta_s);
@@ -765,7 +814,8 @@ static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hip
                      h->tot_pairs_valid, h->tot_tiles);
   LAUNCHCHK();
   if (mode != OT_GS_DENSE) {
-    TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa));
+    TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa, true, true, true,
+                         mode == OT_GS_SNAPSHOT));
     if (mode == OT_GS_SNAPSHOT) h->has_snapshot = true;
     return OT_GS_OK;
   }
@@ -814,7 +864,7 @@ int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T,
   TRY(evaluate(h, OT_GS_DENSE, nullptr, nullptr, s, true));
   dim3 grid((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 16), (unsigned)std::min(h->max_ns, 4096), h->count);
   hipLaunchKernelGGL(k_plan_dense, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
-                     h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
+                     h->g_start, h->g_size, h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
   LAUNCHCHK();
   return OT_GS_OK;
 }
@@ -830,8 +880,13 @@ int ot_gs_get_stats(ot_gs_handle* h, ot_gs_stats* out, int reset, void* stream) 
   if (!h || !out) return fail(OT_GS_EINVAL, "get_stats: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   long long c[CNT_NUM];
+  std::vector<long long> bc((size_t)h->n_screen_blocks * CNT_NUM);
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipMemcpy(c, h->counters, sizeof c, hipMemcpyDeviceToHost));
+  if (!bc.empty())
+    HIPCHK(hipMemcpy(bc.data(), h->block_counters, sizeof(long long) * bc.size(), hipMemcpyDeviceToHost));
+  for (size_t b = 0; b < (size_t)h->n_screen_blocks; ++b)
+    for (int q = 0; q < CNT_NUM; ++q) c[q] += bc[b * CNT_NUM + q];
   out->evals = c[CNT_EVALS];
   out->pairs_total = c[CNT_PAIRS_TOTAL];
   out->pairs_in_N = c[CNT_PAIRS_N];
@@ -840,7 +895,35 @@ int ot_gs_get_stats(ot_gs_handle* h, ot_gs_stats* out, int reset, void* stream) 
   out->refreshes = c[CNT_REFRESH];
   out->tiles_total = c[CNT_TILES_TOTAL];
   out->tiles_computed = c[CNT_TILES_COMPUTED];
-  if (reset) HIPCHK(hipMemset(h->counters, 0, sizeof c));
+  if (reset) {
+    HIPCHK(hipMemset(h->counters, 0, sizeof c));
+    if (!bc.empty()) HIPCHK(hipMemset(h->block_counters, 0, sizeof(long long) * bc.size()));
+  }
+  return OT_GS_OK;
+}
+
+int ot_gs_profile_tiles(ot_gs_handle* h, int repeats, double* us_per_launch, void* stream) {
+  if (!h || repeats < 1 || !us_per_launch) return fail(OT_GS_EINVAL, "profile_tiles: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, (int)OT_GS_DENSE,
+                     h->counters, 0LL, 0LL);
+  LAUNCHCHK();
+  const bool was_on = h->timing.on;
+  h->timing.on = false;
+  GradArgs A = grad_args(h);
+  HIPCHK(hipEventRecord(e0, s));
+  for (int i = 0; i < repeats; ++i) TRY(launch_tiles(h, A, false, false, s));
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  h->timing.on = was_on;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us_per_launch = 1e3 * (double)ms / repeats;
   return OT_GS_OK;
 }
 
@@ -983,9 +1066,11 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
 }
 
 // One function evaluation of every live instance and one step of its solver.
-static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, hipStream_t s) {
+static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_screen,
+                       int init_user, hipStream_t s) {
   // the control kernel finalises D and the update kernel records snapshots
-  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false));
+  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, true,
+                       use_screen != 0));
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
@@ -1035,7 +1120,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;
   const int check_every = 16;
   for (long long step = 0; step < max_steps; ++step) {
-    TRY(solver_step(h, A, P.use_lower, s));
+    TRY(solver_step(h, A, P.use_lower, P.use_screen, o.init_user, s));
     if ((step + 1) % check_every == 0 || step + 1 == max_steps) {
       HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));

@@ -85,36 +85,41 @@ __device__ __forceinline__ void transposed_row_sums(float (&v)[RP], float (&x)[R
 }
 
 // PHASE 0: whole group; 1: split chunk, column partials; 2: split chunk, rows.
-// R rows per lane: row k of wavefront w is r0 + w + NW k (NW R >= rows).
-template <int R, int PHASE>
+// Lane layout: lane = 32 h + c, c the column of the tile (TJ = 32), h the row
+// parity.  Load k of wavefront w covers the two tile rows 2 (w + NW k) + h:
+// 64 consecutive floats of the tile-major pool.  R loads per lane cover
+// 2 NW R >= rows of the tile.  SNAP: also form o~ = ||[f]_-||.
+template <int R, int PHASE, bool SNAP>
 __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
                                           float (*red)[NW][TJ]) {
   const InstDev I = A.inst[d.inst];
   const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gs = A.g_start[I.grp_off + d.grp];
   const int gn = A.g_size[I.grp_off + d.grp];
-  int r0 = gs, r1 = gs + gn;
+  int r0 = 0, r1 = gn;   // rows of this tile, relative to the group start
   if (PHASE != 0) {
-    r0 = gs + d.aux * CHUNK;
-    r1 = min(r0 + CHUNK, r1);
+    r0 = d.aux * CHUNK;
+    r1 = min(r0 + CHUNK, gn);
   }
-  const int col = d.jb * TJ + lane;
+  const int col = d.jb * TJ + c;
   const bool colok = col < I.nt;
   const float bj = A.beta[I.col_off + col];
-  const bool snap = A.inst_mode[d.inst] == EM_SNAPSHOT && PHASE != 2;
-  const int rw = r0 + w;
-  // rows of this wavefront inside the tile (wave-uniform)
-  const int nk = rw < r1 ? min(R, (r1 - rw + NW - 1) / NW) : 0;
-  // alpha of row k sits in lane k
-  const float av = (lane < nk) ? A.alpha[I.row_off + rw + NW * lane] : 0.f;
-  // Raw buffer loads: scalar descriptor at this wavefront's first row, one
-  // per-lane byte offset (the column) and a scalar offset per row.  Rows past
-  // the tile re-read the last valid row (a cache hit) and are masked below.
-  const float* Cw = A.C + I.c_off + (size_t)rw * I.nt_pad + (size_t)d.jb * TJ;
+  constexpr bool snap = SNAP && PHASE != 2;
+  const int rw = r0 + 2 * w;           // first row of this wavefront (h = 0)
+  // loads of this wavefront that touch a row of the tile (wave-uniform)
+  const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
+  // alpha of the row of load k, parity h, sits in lane 2 k + h
+  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+  const float av = ((lane >> 1) < nk && arow < r1) ? A.alpha[I.row_off + gs + arow] : 0.f;
+  // Raw buffer loads: scalar descriptor at this wavefront's first row pair,
+  // one per-lane byte offset and a scalar offset per load.  Loads past the
+  // tile re-read the last valid pair (a cache hit) and are masked below.
+  const float* Cw = A.C + c_index(I, gs, gn, gs + rw, d.jb * TJ);
   const __amdgpu_buffer_rsrc_t rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
-  const int stride_b = __builtin_amdgcn_readfirstlane(NW * I.nt_pad * 4);
+  const int stride_b = 2 * NW * TJ * 4;
   const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
 
   float p[R];
@@ -122,12 +127,16 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
   for (int k = 0; k < R; ++k)
     p[k] = __uint_as_float(
         __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+  // keep every load of the wavefront in flight before any is consumed
+  __builtin_amdgcn_sched_barrier(0);
   float z2 = 0.f, s1 = 0.f, o2 = 0.f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const float ak = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), k));
+    const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k));
+    const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k + 1));
+    const float ak = h ? a1 : a0;
     const float f = (ak + bj) - p[k];
-    const bool ok = (k < nk) && colok;
+    const bool ok = (k < nk) && (rw + 2 * NW * k + h < r1) && colok;
     const float pk = ok ? fmaxf(f, 0.f) : 0.f;
     if (PHASE != 2) {
       z2 = fmaf(pk, pk, z2);
@@ -142,23 +151,29 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
 
   float kap = 0.f;
   if (PHASE != 2) {
-    red[0][w][lane] = z2;
-    red[1][w][lane] = s1;
-    if (snap) red[2][w][lane] = o2;
+    // the two row parities of a column, then the wavefronts in order
+    z2 += __shfl_xor(z2, 32);
+    s1 += __shfl_xor(s1, 32);
+    if (snap) o2 += __shfl_xor(o2, 32);
+    if (h == 0) {
+      red[0][w][c] = z2;
+      red[1][w][c] = s1;
+      if (snap) red[2][w][c] = o2;
+    }
     __syncthreads();
     float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
 #pragma unroll 4
     for (int v = 0; v < NW; ++v) {
-      Z2 += red[0][v][lane];
-      S1 += red[1][v][lane];
+      Z2 += red[0][v][c];
+      S1 += red[1][v][c];
     }
     if (snap) {
 #pragma unroll 4
-      for (int v = 0; v < NW; ++v) O2 += red[2][v][lane];
+      for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
     }
     if (PHASE == 1) {
       // column partial sums of chunk `aux` of a split group
-      if (w == 0) {
+      if (w == 0 && h == 0) {
         const long long q = I.chunk_off +
                             (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
         A.part[q] = Z2;
@@ -173,7 +188,7 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
       num = z - I.thr;
       kap = num / (I.gamma * z);
     }
-    if (w == 0) {
+    if (w == 0 && h == 0) {
       const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
       A.colsum[pr] = kap * S1;
       A.excess[pr] = num;
@@ -187,57 +202,46 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
     kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
   }
 
-  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + rw;
+  // row partials of this column block, rows relative to the instance
+  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
   if (__ballot(kap > 0.f) == 0ull) {
     // every block of the tile is zero: its row sums are exact zeros
-    if (lane < nk) rp[NW * lane] = 0.f;
+    if ((lane >> 1) < nk && arow < r1) rp[arow] = 0.f;
     return;
   }
-  constexpr int RP = R < 4 ? 4 : (R + 3) / 4 * 4;
-  constexpr int Q = RP / 4;
-  float v[RP];
+  // Row sums, two loads (four rows) at a time: a permlane16 swap pairs the
+  // lane rows of loads k0 = 2m and k1 = 2m + 1, DPP shifts finish inside 16
+  // lanes; lane 16 q + 15 then holds the row of load k0 + (q & 1), parity
+  // q >> 1.
+  const int q = lane >> 4;
 #pragma unroll
-  for (int k = 0; k < RP; ++k) v[k] = (k < R) ? kap * p[(k < R) ? k : 0] : 0.f;
-  float x[Q];
-  transposed_row_sums<RP>(v, x);
-  if ((lane & 15) == 15) {
-    const int q = lane >> 4;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int k = i + q * Q;
-      if (k < nk) rp[NW * k] = x[i];
-    }
+  for (int m = 0; m < (R + 1) / 2; ++m) {
+    const float va = kap * p[2 * m];
+    const float vb = (2 * m + 1 < R) ? kap * p[(2 * m + 1 < R) ? 2 * m + 1 : 0] : 0.f;
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(va), __float_as_uint(vb), false, false);
+    const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+    const int k = 2 * m + (q & 1);
+    const int row = rw + 2 * NW * k + (q >> 1);
+    if ((lane & 15) == 15 && k < nk && row < r1) rp[row] = x;
   }
 }
 
-template <int PHASE>
+// One instantiation per row bucket R (a multiple of 4) for whole-group tiles
+// (PHASE 0), R = RMAX for the two passes over split-group chunks.  SNAP
+// kernels take only the tiles of instances evaluated at a snapshot, the
+// others the rest (separate kernels keep the common path's register count
+// low enough for two workgroups per compute unit).
+template <int R, int PHASE, bool SNAP>
 __global__ void __launch_bounds__(BLOCK) k_grad_tiles(GradArgs A) {
   __shared__ float red[3][NW][TJ];
   const int n = *A.count;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
-    if (PHASE == 0) {
-      switch (d.aux) {
-#define OTGS_CASE(r) \
-  case r:            \
-    grad_tile<r, 0>(A, d, red); \
-    break;
-        OTGS_CASE(1) OTGS_CASE(2) OTGS_CASE(3) OTGS_CASE(4) OTGS_CASE(5) OTGS_CASE(6)
-        OTGS_CASE(7) OTGS_CASE(8) OTGS_CASE(9) OTGS_CASE(10) OTGS_CASE(11) OTGS_CASE(12)
-        OTGS_CASE(13) OTGS_CASE(14) OTGS_CASE(15) OTGS_CASE(16) OTGS_CASE(17) OTGS_CASE(18)
-        OTGS_CASE(19) OTGS_CASE(20) OTGS_CASE(21) OTGS_CASE(22) OTGS_CASE(23) OTGS_CASE(24)
-        OTGS_CASE(25) OTGS_CASE(26) OTGS_CASE(27) OTGS_CASE(28) OTGS_CASE(29) OTGS_CASE(30)
-        OTGS_CASE(31)
-#undef OTGS_CASE
-        default: grad_tile<32, 0>(A, d, red); break;
-      }
-    } else {
-      grad_tile<RMAX, PHASE>(A, d, red);
-    }
+    if ((A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
+    grad_tile<R, PHASE, SNAP>(A, d, red);
     __syncthreads();
   }
 }
-
 
 // Split groups: combine the chunk partials of every listed (group, column
 // block) in chunk order and finalise kappa, the column sums, the objective
@@ -246,6 +250,7 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles(GradArgs A) {
 __global__ void __launch_bounds__(WAVE) k_split_combine(GradArgs A) {
   const int n = *A.count;
   const int lane = threadIdx.x;
+  if (lane >= TJ) return;   // one lane per column of the tile
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
     const InstDev I = A.inst[d.inst];
@@ -342,6 +347,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       const int g = A.row_grp[I.row_off + r];
       const float* rp = A.rowpart + I.r_off + r;
       const uint8_t* on = A.tile_on ? A.tile_on + I.tile_off + (size_t)g * I.njb : nullptr;
+#pragma unroll 8
       for (int jb = q; jb < I.njb; jb += ASM_LPR) {
         const float v = rp[(size_t)jb * I.ns];
         s += (!on || on[jb]) ? v : 0.f;   // skipped tiles: exact zeros (stale data ignored)
@@ -364,12 +370,14 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       const int jb = c / TJ;
       float s = 0.f;
       double e2 = 0.0;
+#pragma unroll 4
       for (int g = 0; g < I.Le; ++g) {
-        if (A.tile_on && !A.tile_on[I.tile_off + (size_t)g * I.njb + jb]) continue;
+        const bool on = !A.tile_on || A.tile_on[I.tile_off + (size_t)g * I.njb + jb];
         const size_t pr = (size_t)I.pair_off + (size_t)g * I.nt_pad + c;
-        s += A.colsum[pr];
+        const float cv = A.colsum[pr];
         const double e = A.excess[pr];
-        e2 += e * e;
+        s += on ? cv : 0.f;
+        e2 += on ? e * e : 0.0;
       }
       const float gval = (c < I.nt) ? A.b_int[I.col_off + c] - s : 0.f;
       if (A.gb_int) A.gb_int[I.col_off + c] = gval;
@@ -477,6 +485,8 @@ __global__ void __launch_bounds__(256) k_plan_dense(const InstDev* __restrict__ 
                                                     const int* __restrict__ perm_row,
                                                     const int* __restrict__ perm_col,
                                                     const int* __restrict__ row_grp,
+                                                    const int* __restrict__ g_start,
+                                                    const int* __restrict__ g_size,
                                                     const float* __restrict__ C,
                                                     const float* __restrict__ alpha,
                                                     const float* __restrict__ beta,
@@ -486,12 +496,12 @@ __global__ void __launch_bounds__(256) k_plan_dense(const InstDev* __restrict__ 
   const InstDev I = inst[blockIdx.z];
   for (int r = blockIdx.y; r < I.ns; r += gridDim.y) {
     const int g = row_grp[I.row_off + r];
+    const int gs = g_start[I.grp_off + g], gn = g_size[I.grp_off + g];
     const float a = alpha[I.row_off + r];
     float* trow = T + t_off[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
-    const float* crow = C + I.c_off + (size_t)r * I.nt_pad;
     const float* krow = kappa + I.pair_off + (size_t)g * I.nt_pad;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt; c += gridDim.x * blockDim.x) {
-      const float f = (a + beta[I.col_off + c]) - crow[c];
+      const float f = (a + beta[I.col_off + c]) - C[c_index(I, gs, gn, r, c)];
       trow[perm_col[I.col_off + c]] = krow[c] * fmaxf(f, 0.f);
     }
   }

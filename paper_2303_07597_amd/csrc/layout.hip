@@ -156,21 +156,25 @@ __global__ void k_col_assign(const InstDev* __restrict__ inst, const float* cons
   colkey[I.scol_off + j] = bg;
 }
 
-// Internal cost: C_int[r][c] = fl32(C[perm_row[r]][perm_col[c]] * scale), 0 on
-// padding columns.  grid.x: columns / 256, grid.y: rows, grid.z: instance.
+// Internal cost: C_int(r, c) = fl32(C[perm_row[r]][perm_col[c]] * scale) in the
+// tile-major layout, 0 on padding columns.  grid.x: columns / 256, grid.y:
+// rows (strided), grid.z: instance.
 __global__ void k_relayout_cost(const InstDev* __restrict__ inst, const float* const* __restrict__ costs,
                                 const float* __restrict__ scales, const int* __restrict__ perm_row,
-                                const int* __restrict__ perm_col, float* __restrict__ Cint) {
+                                const int* __restrict__ perm_col, const int* __restrict__ row_grp,
+                                const int* __restrict__ g_start, const int* __restrict__ g_size,
+                                float* __restrict__ Cint) {
   const InstDev I = inst[blockIdx.z];
-  const int r = blockIdx.y;
-  if (r >= I.ns) return;
   const float s = scales[blockIdx.z];
-  const float* src = costs[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
-  float* dst = Cint + I.c_off + (size_t)r * I.nt_pad;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
-    float v = 0.f;
-    if (c < I.nt) v = src[perm_col[I.col_off + c]] * s;
-    dst[c] = v;
+  for (int r = blockIdx.y; r < I.ns; r += gridDim.y) {
+    const int g = row_grp[I.row_off + r];
+    const int gs = g_start[I.grp_off + g], gn = g_size[I.grp_off + g];
+    const float* src = costs[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
+      float v = 0.f;
+      if (c < I.nt) v = src[perm_col[I.col_off + c]] * s;
+      Cint[c_index(I, gs, gn, r, c)] = v;
+    }
   }
 }
 

@@ -9,7 +9,9 @@
 //             row and size.
 //   pairs   - (group, padded column) arrays, [Le x nt_pad] at pair_off.
 //   tiles   - (group, block of TJ columns), [Le x njb] at tile_off.
-//   cost    - C in the internal layout, [ns x nt_pad] at c_off.
+//   cost    - C in the internal layout at c_off, tile-major: the rows of a
+//             group form njb consecutive tiles of [g x TJ] floats, so a tile
+//             (group, column block) is one contiguous stream; see c_index.
 //   rowpart - row partial sums of T per column block, [njb x ns] at r_off.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -18,12 +20,13 @@
 namespace otgs {
 
 constexpr int WAVE = 64;
-constexpr int TJ = 64;                 // target columns per tile (one per lane)
+constexpr int TJ = 32;                 // target columns per tile (lane = 32 h + column)
 constexpr int NW = 16;                 // waves per gradient workgroup
 constexpr int BLOCK = NW * WAVE;       // 1024 threads
 constexpr int RMAX = 32;               // rows per thread in the largest class
-constexpr int CHUNK = NW * RMAX;       // 512: largest group handled in one pass
-constexpr int NCLASS = 32;             // row classes R = 1..32 rows per lane
+constexpr int CHUNK = 2 * NW * RMAX;   // 1024: largest group handled in one pass
+constexpr int RSTEP = 4;               // row buckets: R = 4, 8, ..., 32 rows per lane
+constexpr int NBUCKET = RMAX / RSTEP;  // 8
 constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
 
 struct InstDev {
@@ -79,7 +82,18 @@ enum EvalMode { EM_DENSE = 0, EM_SCREEN = 1, EM_SNAPSHOT = 2, EM_SKIP = 3 };
 // pair state written by the screen / extraction kernels
 enum PairFlag : uint8_t { PAIR_SKIP = 0, PAIR_CHECK = 1, PAIR_IN_N = 2 };
 
-// rows per lane of a whole-group tile: smallest R with NW R >= rows
-__host__ __device__ inline int row_class(int rows) { return rows <= NW ? 1 : (rows + NW - 1) / NW; }
+// position of internal cost entry (row r of the group starting at gs with gn
+// rows, padded column c) in the tile-major pool
+__host__ __device__ inline size_t c_index(const InstDev& I, int gs, int gn, int r, int c) {
+  return (size_t)I.c_off + (size_t)gs * I.nt_pad + (size_t)(c / TJ) * gn * TJ +
+         (size_t)(r - gs) * TJ + (size_t)(c % TJ);
+}
+
+// row bucket of a whole-group tile: b such that R = RSTEP (b + 1) is the
+// smallest multiple of RSTEP with 2 NW R >= rows (two rows per load)
+__host__ __device__ inline int row_bucket(int rows) {
+  const int r = (rows + 2 * NW - 1) / (2 * NW);
+  return r <= RSTEP ? 0 : (r + RSTEP - 1) / RSTEP - 1;
+}
 
 }  // namespace otgs

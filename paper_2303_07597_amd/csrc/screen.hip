@@ -43,11 +43,13 @@ struct ScreenArgs {
   GroupStats* gstats;
   uint8_t* inN;              // per pair
   uint8_t* tile_on;          // per group tile
-  TileDesc* list_main;
+  TileDesc* list_main;       // whole-group tiles, bucket b at main_off[b]
   TileDesc* list_sg;         // split group tiles (combine)
   TileDesc* list_sc;         // split chunk tiles
-  int* counts;               // [3]: main, split groups, split chunks
+  int* counts;               // [NBUCKET + 2]: per bucket, split groups, split chunks
+  int main_off[NBUCKET];
   long long* counters;
+  long long* block_counters; // [screen blocks][CNT_NUM]
   const int* inst_mode;      // EvalMode per instance
   int use_lower;             // build N at snapshot refreshes
 };
@@ -104,11 +106,8 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
       if (m != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
       if (m == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
     }
-    if (gidx == 0) {
-      A.counts[0] = 0;
-      A.counts[1] = 0;
-      A.counts[2] = 0;
-    }
+    if (gidx == 0)
+      for (int q = 0; q < NBUCKET + 2; ++q) A.counts[q] = 0;
   }
 }
 
@@ -123,7 +122,8 @@ constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
 __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A) {
   __shared__ int s_cnt[SCREEN_TILES][8];   // valid, inN, checked, unskipped, main, split,
                                            // chunks of an active split tile, tile counted
-  __shared__ int s_base[3];
+  __shared__ int s_bkt[SCREEN_TILES];
+  __shared__ int s_base[NBUCKET + 2];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
   const int t = blockIdx.x * SCREEN_TILES + wv;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     const int mode = A.inst_mode[d.inst];
     const int gidx = I.grp_off + d.grp;
     const int col = d.jb * TJ + lane;
-    const bool valid = col < I.nt && mode != EM_SKIP;
+    const bool valid = lane < TJ && col < I.nt && mode != EM_SKIP;
     const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
     bool inN = false, checked = false, compute = false;
     if (valid) {
@@ -188,42 +188,47 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     s_cnt[wv][5] = (on && d.aux < 0) ? 1 : 0;
     s_cnt[wv][6] = (on && d.aux < 0) ? -d.aux : 0;
     s_cnt[wv][7] = (tile_ok && A.inst_mode[d.inst] != EM_SKIP) ? 1 : 0;
+    s_bkt[wv] = d.aux >= 0 ? d.aux : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot[4] = {0, 0, 0, 0};
-    int nmain = 0, nsg = 0, nsc = 0, ntile = 0, non = 0;
+    int nb[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int nsg = 0, nsc = 0, ntile = 0, non = 0;
     for (int w = 0; w < SCREEN_TILES; ++w) {
       for (int q = 0; q < 4; ++q) tot[q] += s_cnt[w][q];
-      nmain += s_cnt[w][4];
+      if (s_cnt[w][4]) nb[s_bkt[w]]++;
       nsg += s_cnt[w][5];
       nsc += s_cnt[w][6];
       ntile += s_cnt[w][7];
       non += s_cnt[w][4] + s_cnt[w][5];
     }
-    s_base[0] = nmain ? atomicAdd(&A.counts[0], nmain) : 0;
-    s_base[1] = nsg ? atomicAdd(&A.counts[1], nsg) : 0;
-    s_base[2] = nsc ? atomicAdd(&A.counts[2], nsc) : 0;
-    unsigned long long* C = (unsigned long long*)A.counters;
-    if (tot[0]) atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)tot[0]);
-    if (tot[1]) atomicAdd(&C[CNT_PAIRS_N], (unsigned long long)tot[1]);
-    if (tot[2]) atomicAdd(&C[CNT_PAIRS_CHECKED], (unsigned long long)tot[2]);
-    if (tot[3]) atomicAdd(&C[CNT_PAIRS_UNSKIPPED], (unsigned long long)tot[3]);
-    if (ntile) atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)ntile);
-    if (non) atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)non);
+    for (int q = 0; q < NBUCKET; ++q) s_base[q] = nb[q] ? atomicAdd(&A.counts[q], nb[q]) : 0;
+    s_base[NBUCKET] = nsg ? atomicAdd(&A.counts[NBUCKET], nsg) : 0;
+    s_base[NBUCKET + 1] = nsc ? atomicAdd(&A.counts[NBUCKET + 1], nsc) : 0;
+    // counters: every block owns a slot (evaluations are ordered on the
+    // stream, so a plain update suffices); slots are summed on request
+    long long* C = A.block_counters + (size_t)blockIdx.x * CNT_NUM;
+    C[CNT_PAIRS_TOTAL] += tot[0];
+    C[CNT_PAIRS_N] += tot[1];
+    C[CNT_PAIRS_CHECKED] += tot[2];
+    C[CNT_PAIRS_UNSKIPPED] += tot[3];
+    C[CNT_TILES_TOTAL] += ntile;
+    C[CNT_TILES_COMPUTED] += non;
   }
   __syncthreads();
   // list positions in tile order within the block
   if (lane == 0 && on) {
-    int pm = s_base[0], ps = s_base[1], pc = s_base[2];
-    for (int w = 0; w < wv; ++w) {
-      pm += s_cnt[w][4];
-      ps += s_cnt[w][5];
-      pc += s_cnt[w][6];
-    }
     if (d.aux >= 0) {
-      A.list_main[pm] = d;
+      int pm = s_base[d.aux];
+      for (int w = 0; w < wv; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
+      A.list_main[A.main_off[d.aux] + pm] = d;
     } else {
+      int ps = s_base[NBUCKET], pc = s_base[NBUCKET + 1];
+      for (int w = 0; w < wv; ++w) {
+        ps += s_cnt[w][5];
+        pc += s_cnt[w][6];
+      }
       TileDesc e = d;
       e.aux = 0;
       A.list_sg[ps] = e;

@@ -85,6 +85,7 @@ def _load():
     lib.ot_gs_get_stats.argtypes = [vp, ct.POINTER(ot_gs_stats), i, vp]
     lib.ot_gs_kernel_timing.argtypes = [vp, i]
     lib.ot_gs_kernel_time.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(ct.c_longlong)]
+    lib.ot_gs_profile_tiles.argtypes = [vp, i, ct.POINTER(d), vp]
     lib.ot_gs_layout_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
@@ -222,6 +223,11 @@ class Handle:
         _check(lib().ot_gs_kernel_time(self.h, int(which), ct.byref(ms), ct.byref(n)))
         return ms.value, n.value
 
+    def profile_tiles(self, repeats=100, stream=None):
+        us = ct.c_double()
+        _check(lib().ot_gs_profile_tiles(self.h, int(repeats), ct.byref(us), _stream(stream)))
+        return us.value
+
     def layout_info(self, k=0):
         g, tp, nt = ct.c_int(), ct.c_int(), ct.c_int()
         _check(lib().ot_gs_layout_info(self.h, k, ct.byref(g), ct.byref(tp), ct.byref(nt)))
@@ -231,5 +237,5 @@ class Handle:
 EXPORTED = [
     "ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_default_options",
     "ot_gs_plan", "ot_gs_rho_to_mu", "ot_gs_get_stats", "ot_gs_kernel_timing", "ot_gs_kernel_time",
-    "ot_gs_layout_info", "ot_gs_last_error", "ot_gs_version",
+    "ot_gs_layout_info", "ot_gs_last_error", "ot_gs_version", "ot_gs_profile_tiles",
 ]
