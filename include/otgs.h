@@ -68,7 +68,11 @@ extern "C" {
 #define OT_GS_COST_GIVEN       0  /* caller passes C [n_src x n_tgt] row-major        */
 #define OT_GS_COST_MATERIALIZE 1  /* C = ||x_i - x_j||^2 built once from features    */
 #define OT_GS_COST_ONTHEFLY    2  /* C tiles recomputed from features in every
-                                     evaluation on FP32 matrix cores; never stored   */
+                                     evaluation on FP32 matrix cores; never stored.
+                                     c_ij = s max(|x_i|^2 + |x_j|^2 - 2 x_i.x_j, 0)
+                                     with float32 norms and an FP32 dot product;
+                                     1 <= dim <= 256; every instance of a handle
+                                     must then use this mode                        */
 
 typedef struct ot_gs_handle ot_gs_handle;
 
@@ -84,7 +88,8 @@ typedef struct {
     const float *cost;     /* [n_src * n_tgt] row-major, C >= 0 (COST_GIVEN)       */
     const float *x_src;    /* [n_src * dim] row-major (COST_MATERIALIZE/ONTHEFLY)  */
     const float *x_tgt;    /* [n_tgt * dim] row-major                              */
-    float cost_scale;      /* C is multiplied by this; 0 = 1 / max_ij C_ij         */
+    float cost_scale;      /* C is multiplied by this; 0 = 1 / max_ij C_ij (for
+                              ONTHEFLY: of the unscaled float32 cost above)        */
     const float *a;        /* [n_src] source marginal, NULL = 1/n_src              */
     const float *b;        /* [n_tgt] target marginal, NULL = 1/n_tgt              */
     float gamma;           /* > 0                                                   */
@@ -174,6 +179,14 @@ int ot_gs_solve(ot_gs_handle *h, const ot_gs_options *opts, float *alpha_io,
  * order.  Errors as ot_gs_dual_grad. */
 int ot_gs_plan(ot_gs_handle *h, const float *alpha, const float *beta, float *T,
                void *stream);
+
+/* The scaled cost the evaluations use (Sec. 2.1; for COST_ONTHEFLY the
+ * values its matrix-core tiles produce, bit for bit), written to C_out in
+ * the layout of ot_gs_plan: instance k at offset sum_{k'<k} n_src n_tgt,
+ * row-major, caller order.  C_out: device, caller-owned.  For tests and
+ * inspection; the hot path never writes the cost.  Errors: OT_GS_EINVAL
+ * (NULL), OT_GS_EDEVICE. */
+int ot_gs_cost(ot_gs_handle *h, float *C_out, void *stream);
 
 /* ------------------------------------------------------------ utilities */
 

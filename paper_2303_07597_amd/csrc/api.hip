@@ -47,7 +47,7 @@ static inline long long ceil_div(long long a, long long b) { return (a + b - 1) 
 struct InstHost {
   InstDev d;
   int cost_mode;
-  std::vector<int> g_size, g_start, g_chunk0;
+  std::vector<int> g_size, g_start, g_chunk0, g_xblk;
   int n_chunk_rows;
 };
 
@@ -71,7 +71,7 @@ struct ot_gs_handle {
   std::vector<void*> allocs;
   // totals
   long long tot_rows = 0, tot_cols = 0, tot_cols_pad = 0, tot_groups = 0, tot_pairs = 0,
-            tot_tiles = 0, tot_c = 0, tot_r = 0, tot_chunk = 0;
+            tot_tiles = 0, tot_c = 0, tot_r = 0, tot_chunk = 0, tot_x = 0, tot_y = 0;
   int n_main = 0, n_sg = 0, n_sc = 0;
   int n_bucket[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
   int main_off[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -81,6 +81,10 @@ struct ot_gs_handle {
   int *perm_row = nullptr, *row_grp = nullptr, *perm_col = nullptr;
   int *g_start = nullptr, *g_size = nullptr, *g_chunk0 = nullptr, *grp_inst = nullptr;
   float* C = nullptr;
+  // on-the-fly cost: packed features and squared norms, per-group block offsets
+  bool onthefly = false;
+  float *Xp = nullptr, *Yp = nullptr, *xn = nullptr, *yn = nullptr;
+  int* g_xblk = nullptr;
   float *a_int = nullptr, *b_int = nullptr;
   int *a_uniform = nullptr, *b_uniform = nullptr;
   float *alpha = nullptr, *beta = nullptr, *ga = nullptr, *gb = nullptr;
@@ -178,6 +182,163 @@ static int sync_err(ot_gs_handle* h, hipStream_t s, int* out) {
   return OT_GS_OK;
 }
 
+// Work lists over the (group, 32-target block) tiles: static lists for dense
+// evaluations (whole groups by row bucket; split groups by chunk), and the
+// dynamic lists the screen fills.  On-the-fly handles use a single bucket.
+static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
+  const int count = h->count;
+  {
+    std::vector<TileDesc> all, sg, sc;
+    std::vector<TileDesc> bucket[NBUCKET];
+    for (int k = 0; k < count; ++k) {
+      const InstHost& ih = h->inst[k];
+      for (int g = 0; g < ih.d.Le; ++g) {
+        const int n = ih.g_size[g];
+        const bool split = n > CHUNK;
+        const int nch = (int)ceil_div(n, CHUNK);
+        for (int jb = 0; jb < ih.d.njb; ++jb) {
+          TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? 0 : row_bucket(n))};
+          all.push_back(t);
+          if (!split) {
+            bucket[t.aux].push_back(t);
+          } else {
+            sg.push_back(TileDesc{k, g, jb, 0});
+            for (int c = 0; c < nch; ++c) sc.push_back(TileDesc{k, g, jb, c});
+          }
+        }
+      }
+    }
+    std::vector<TileDesc> mainl;
+    for (int b = 0; b < NBUCKET; ++b) {
+      h->main_off[b] = (int)mainl.size();
+      h->n_bucket[b] = (int)bucket[b].size();
+      mainl.insert(mainl.end(), bucket[b].begin(), bucket[b].end());
+    }
+    h->n_main = (int)mainl.size();
+    h->n_sg = (int)sg.size();
+    h->n_sc = (int)sc.size();
+    TRY(h->alloc(&h->tiles_all, all.size()));
+    TRY(h->alloc(&h->list_main, mainl.size()));
+    TRY(h->alloc(&h->list_sg, sg.size()));
+    TRY(h->alloc(&h->list_sc, sc.size()));
+    TRY(h->alloc(&h->dyn_main, mainl.size()));
+    TRY(h->alloc(&h->dyn_sg, sg.size()));
+    TRY(h->alloc(&h->dyn_sc, sc.size()));
+    auto up = [&](TileDesc* dst, const std::vector<TileDesc>& v) -> int {
+      if (!v.empty())
+        HIPCHK(hipMemcpyAsync(dst, v.data(), sizeof(TileDesc) * v.size(), hipMemcpyHostToDevice, s));
+      return OT_GS_OK;
+    };
+    TRY(up(h->tiles_all, all));
+    TRY(up(h->list_main, mainl));
+    TRY(up(h->list_sg, sg));
+    TRY(up(h->list_sc, sc));
+    TRY(h->alloc(&h->counts_static, NBUCKET + 2));
+    TRY(h->alloc(&h->counts_dyn, NBUCKET + 2));
+    int hc[NBUCKET + 2];
+    for (int b = 0; b < NBUCKET; ++b) hc[b] = h->n_bucket[b];
+    hc[NBUCKET] = h->n_sg;
+    hc[NBUCKET + 1] = h->n_sc;
+    HIPCHK(hipMemcpyAsync(h->counts_static, hc, sizeof hc, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(h->counts_dyn, 0, sizeof(int) * (NBUCKET + 2), s));
+  }
+  return OT_GS_OK;
+}
+
+// On-the-fly cost setup: pack the source features per group and the target
+// features in natural order, one pass over every (group, 32-target) tile for
+// the largest unscaled cost (normalisation) and each column's least cost per
+// group (nearest-class key), then the scale and max C of every instance.
+static int setup_onthefly(ot_gs_handle* h, const ot_gs_problem* probs, int* colkey,
+                          std::vector<float*>& temps, hipStream_t s) {
+  const int count = h->count;
+  TRY(h->alloc(&h->Xp, h->tot_x));
+  TRY(h->alloc(&h->xn, h->tot_rows));
+  TRY(h->alloc(&h->Yp, h->tot_y));
+  TRY(h->alloc(&h->yn, h->tot_cols_pad));
+  HIPCHK(hipMemsetAsync(h->Xp, 0, sizeof(float) * std::max<long long>(h->tot_x, 1), s));
+  float *ynat = nullptr, *ynnat = nullptr, *colmin = nullptr;
+  HIPCHK(hipMalloc(&ynat, sizeof(float) * std::max<long long>(h->tot_y, 1)));
+  temps.push_back(ynat);
+  HIPCHK(hipMalloc(&ynnat, sizeof(float) * h->tot_cols_pad));
+  temps.push_back(ynnat);
+  HIPCHK(hipMalloc(&colmin, sizeof(float) * std::max<long long>(h->tot_pairs, 1)));
+  temps.push_back(colmin);
+  TRY(h->alloc(&h->d_inst, count));
+  std::vector<InstDev> hd(count);
+  for (int k = 0; k < count; ++k) hd[k] = h->inst[k].d;
+  HIPCHK(hipMemcpyAsync(h->d_inst, hd.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
+  const float** dxs = nullptr;
+  const float** dxt = nullptr;
+  unsigned int* maxbits = nullptr;
+  TRY(h->alloc(&dxs, count));
+  TRY(h->alloc(&dxt, count));
+  TRY(h->alloc(&maxbits, count));
+  std::vector<const float*> hxs(count), hxt(count);
+  int maxns = 1, maxntp = 64, maxnt = 1;
+  for (int k = 0; k < count; ++k) {
+    hxs[k] = probs[k].x_src;
+    hxt[k] = probs[k].x_tgt;
+    maxns = std::max(maxns, h->inst[k].d.ns);
+    maxntp = std::max(maxntp, h->inst[k].d.nt_pad);
+    maxnt = std::max(maxnt, h->inst[k].d.nt);
+  }
+  HIPCHK(hipMemcpyAsync(dxs, hxs.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dxt, hxt.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(maxbits, 0, sizeof(unsigned int) * count, s));
+  hipLaunchKernelGGL(k_otf_pack_x, dim3((unsigned)std::min<long long>(ceil_div(maxns, 256), 1024), count),
+                     dim3(256), 0, s, h->d_inst, dxs, (const int*)h->perm_row, (const int*)h->row_grp,
+                     (const int*)h->g_start, (const int*)h->g_xblk, h->Xp, h->xn, h->err);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_otf_pack_y, dim3((unsigned)ceil_div(maxntp, 256), count), dim3(256), 0, s,
+                     h->d_inst, dxt, (const int*)nullptr, ynat, ynnat, h->err);
+  LAUNCHCHK();
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
+  if (herr & 2) return fail(OT_GS_ENUMERIC, "a feature (or its squared norm) is NaN or Inf");
+  if (h->tot_tiles > 0) {
+    GradArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.inst = h->d_inst;
+    A.g_start = h->g_start;
+    A.g_size = h->g_size;
+    A.g_xblk = h->g_xblk;
+    A.Xp = h->Xp;
+    A.xn = h->xn;
+    A.list = h->tiles_all;
+    const int n = (int)h->tot_tiles;
+    hipLaunchKernelGGL(k_otf_setup, dim3(std::max(1, std::min(n, 2 * h->n_cu))), dim3(BLOCK), 0, s, A, n,
+                       (const float*)ynat, (const float*)ynnat, colmin, maxbits);
+    LAUNCHCHK();
+  }
+  std::vector<unsigned int> hmax(count);
+  HIPCHK(hipMemcpyAsync(hmax.data(), maxbits, sizeof(unsigned int) * count, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < count; ++k) {
+    InstDev& d = h->inst[k].d;
+    float umax;
+    std::memcpy(&umax, &hmax[k], sizeof umax);
+    float sc = probs[k].cost_scale;
+    if (sc == 0.f) {
+      if (!(umax > 0.f)) return fail(OT_GS_ENUMERIC, "instance %d: max C is 0, cannot normalise", k);
+      sc = (float)(1.0 / (double)umax);
+    }
+    // C = max(sc u, 0) is monotone in u; the slack covers any difference in
+    // the last bit between this pass and the gradient tiles
+    const float cm = umax * sc * (1.f + 1.0f / 65536.f);
+    if (!std::isfinite(cm)) return fail(OT_GS_ENUMERIC, "instance %d: scaled cost overflows", k);
+    d.cscale = sc;
+    d.cmax = cm;
+    hd[k] = d;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_inst, hd.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_otf_assign, dim3((unsigned)ceil_div(maxnt, 256), count), dim3(256), 0, s,
+                     (const InstDev*)h->d_inst, (const float*)colmin, colkey);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return OT_GS_OK;
+}
+
 static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out, hipStream_t s) {
   if (!probs || !out || count < 1) return fail(OT_GS_EINVAL, "create: bad arguments");
   for (int k = 0; k < count; ++k) {
@@ -196,13 +357,20 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       if (!p.x_src || !p.x_tgt || p.dim < 1)
         return fail(OT_GS_EINVAL, "instance %d: COST_MATERIALIZE needs x_src, x_tgt and dim >= 1", k);
     } else if (p.cost_mode == OT_GS_COST_ONTHEFLY) {
-      return fail(OT_GS_EINVAL, "instance %d: COST_ONTHEFLY is not available in this build", k);
+      if (!p.x_src || !p.x_tgt || p.dim < 1 || p.dim > DP_MAX)
+        return fail(OT_GS_EINVAL, "instance %d: COST_ONTHEFLY needs x_src, x_tgt and 1 <= dim <= %d", k,
+                    DP_MAX);
     } else {
       return fail(OT_GS_EINVAL, "instance %d: unknown cost_mode %d", k, p.cost_mode);
     }
   }
+  const bool otf = probs[0].cost_mode == OT_GS_COST_ONTHEFLY;
+  for (int k = 1; k < count; ++k)
+    if ((probs[k].cost_mode == OT_GS_COST_ONTHEFLY) != otf)
+      return fail(OT_GS_EINVAL, "instance %d: COST_ONTHEFLY cannot be mixed with materialized costs in one handle", k);
   auto* h = new ot_gs_handle();
   std::unique_ptr<ot_gs_handle> guard(h);
+  h->onthefly = otf;
   h->count = count;
   h->inst.resize(count);
   HIPCHK(hipGetDevice(&h->dev));
@@ -231,6 +399,11 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     d.gamma = p.gamma;
     d.mu = p.mu;
     d.thr = (float)((double)p.mu * (double)p.gamma);
+    if (otf) {
+      d.onthefly = 1;
+      d.dim = p.dim;
+      d.dp = (int)ceil_div(p.dim, 16) * 16;
+    }
     h->inst[k].cost_mode = p.cost_mode;
     lab_off[k] = lab_tot;
     lab_tot += p.n_groups;
@@ -310,6 +483,17 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
         ih.g_chunk0.push_back(-1);
       }
     }
+    if (otf) {
+      d.x_off = h->tot_x;
+      d.y_off = h->tot_y;
+      int xb = 0;
+      for (int g = 0; g < d.Le; ++g) {
+        ih.g_xblk.push_back(xb);
+        xb += (int)ceil_div(ih.g_size[g], 32);
+      }
+      h->tot_x += (long long)xb * 32 * d.dp;
+      h->tot_y += (long long)d.njb * 32 * d.dp;
+    }
     h->tot_groups += d.Le;
     h->tot_pairs += (long long)d.Le * d.nt_pad;
     h->tot_tiles += (long long)d.Le * d.njb;
@@ -320,9 +504,10 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       return fail(OT_GS_EINVAL, "total pair count exceeds the 32-bit index range");
   }
   {
-    std::vector<int> gs, gn, gc, gi;
+    std::vector<int> gs, gn, gc, gi, gx;
     for (int k = 0; k < count; ++k) {
       const InstHost& ih = h->inst[k];
+      gx.insert(gx.end(), ih.g_xblk.begin(), ih.g_xblk.end());
       gs.insert(gs.end(), ih.g_start.begin(), ih.g_start.end());
       gn.insert(gn.end(), ih.g_size.begin(), ih.g_size.end());
       gc.insert(gc.end(), ih.g_chunk0.begin(), ih.g_chunk0.end());
@@ -336,27 +521,19 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     HIPCHK(hipMemcpyAsync(h->g_size, gn.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->g_chunk0, gc.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->grp_inst, gi.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    if (otf) {
+      TRY(h->alloc(&h->g_xblk, gs.size()));
+      HIPCHK(hipMemcpyAsync(h->g_xblk, gx.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
+    }
     HIPCHK(hipStreamSynchronize(s));
   }
+  TRY(build_work_lists(h, s));
 
-  // ---- cost in the caller's order (given or built from features)
-  std::vector<const float*> hcost(count);
+  // ---- cost provider: a materialized pool, or packed features for the
+  // on-the-fly cost; both give the scale, max C and the column clustering key
+  int* colkey = nullptr;
+  TRY(h->alloc(&colkey, h->tot_cols));
   std::vector<float*> temps;
-  for (int k = 0; k < count; ++k) {
-    const ot_gs_problem& p = probs[k];
-    if (p.cost_mode == OT_GS_COST_GIVEN) {
-      hcost[k] = p.cost;
-    } else {
-      float* tmp = nullptr;
-      HIPCHK(hipMalloc(&tmp, sizeof(float) * (size_t)p.n_src * p.n_tgt));
-      temps.push_back(tmp);
-      dim3 grid((unsigned)ceil_div(p.n_tgt, 64), (unsigned)ceil_div(p.n_src, 64));
-      hipLaunchKernelGGL(k_cost_features, grid, dim3(256), 0, s, p.x_src, p.x_tgt, p.n_src, p.n_tgt,
-                         p.dim, tmp);
-      LAUNCHCHK();
-      hcost[k] = tmp;
-    }
-  }
   struct TempFree {
     std::vector<float*>& v;
     ~TempFree() {
@@ -364,72 +541,91 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     }
   } tfree{temps};
   const float** d_costs = nullptr;
-  long long* d_sizes = nullptr;
-  unsigned int* d_max = nullptr;
   float* d_scale = nullptr;
-  TRY(h->alloc(&d_costs, count));
-  TRY(h->alloc(&d_sizes, count));
-  TRY(h->alloc(&d_max, count));
-  TRY(h->alloc(&d_scale, count));
-  std::vector<long long> hsizes(count);
-  long long maxsize = 1;
-  for (int k = 0; k < count; ++k) {
-    hsizes[k] = (long long)probs[k].n_src * probs[k].n_tgt;
-    maxsize = std::max(maxsize, hsizes[k]);
-  }
-  HIPCHK(hipMemcpyAsync(d_costs, hcost.data(), sizeof(float*) * count, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(d_sizes, hsizes.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(d_max, 0, sizeof(unsigned int) * count, s));
-  {
-    dim3 grid((unsigned)std::min<long long>(ceil_div(maxsize, 256 * 8), 2048), count);
-    hipLaunchKernelGGL(k_cost_max, grid, dim3(256), 0, s, d_costs, d_sizes, d_max, h->err);
-    LAUNCHCHK();
-  }
-  TRY(sync_err(h, s, &herr));
-  if (herr & 2) return fail(OT_GS_ENUMERIC, "the cost has a negative, NaN or Inf entry");
-  std::vector<unsigned int> hmax(count);
-  std::vector<float> hscale(count);
-  HIPCHK(hipMemcpy(hmax.data(), d_max, sizeof(unsigned int) * count, hipMemcpyDeviceToHost));
-  for (int k = 0; k < count; ++k) {
-    float cmax;
-    std::memcpy(&cmax, &hmax[k], sizeof cmax);
-    float sc = probs[k].cost_scale;
-    if (sc == 0.f) {
-      if (!(cmax > 0.f)) return fail(OT_GS_ENUMERIC, "instance %d: max C is 0, cannot normalise", k);
-      sc = (float)(1.0 / (double)cmax);
+  if (!otf) {
+    // ---- cost in the caller's order (given or built from features)
+    std::vector<const float*> hcost(count);
+    for (int k = 0; k < count; ++k) {
+      const ot_gs_problem& p = probs[k];
+      if (p.cost_mode == OT_GS_COST_GIVEN) {
+        hcost[k] = p.cost;
+      } else {
+        float* tmp = nullptr;
+        HIPCHK(hipMalloc(&tmp, sizeof(float) * (size_t)p.n_src * p.n_tgt));
+        temps.push_back(tmp);
+        dim3 grid((unsigned)ceil_div(p.n_tgt, 64), (unsigned)ceil_div(p.n_src, 64));
+        hipLaunchKernelGGL(k_cost_features, grid, dim3(256), 0, s, p.x_src, p.x_tgt, p.n_src, p.n_tgt,
+                           p.dim, tmp);
+        LAUNCHCHK();
+        hcost[k] = tmp;
+      }
     }
-    hscale[k] = sc;
-    const float cm = cmax * sc;   // rounding is monotone: max of the scaled cost
-    if (!std::isfinite(cm)) return fail(OT_GS_ENUMERIC, "instance %d: scaled cost overflows", k);
-    h->inst[k].d.cmax = cm;
-  }
-  HIPCHK(hipMemcpyAsync(d_scale, hscale.data(), sizeof(float) * count, hipMemcpyHostToDevice, s));
+    long long* d_sizes = nullptr;
+    unsigned int* d_max = nullptr;
+    TRY(h->alloc(&d_costs, count));
+    TRY(h->alloc(&d_sizes, count));
+    TRY(h->alloc(&d_max, count));
+    TRY(h->alloc(&d_scale, count));
+    std::vector<long long> hsizes(count);
+    long long maxsize = 1;
+    for (int k = 0; k < count; ++k) {
+      hsizes[k] = (long long)probs[k].n_src * probs[k].n_tgt;
+      maxsize = std::max(maxsize, hsizes[k]);
+    }
+    HIPCHK(hipMemcpyAsync(d_costs, hcost.data(), sizeof(float*) * count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_sizes, hsizes.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(d_max, 0, sizeof(unsigned int) * count, s));
+    {
+      dim3 grid((unsigned)std::min<long long>(ceil_div(maxsize, 256 * 8), 2048), count);
+      hipLaunchKernelGGL(k_cost_max, grid, dim3(256), 0, s, d_costs, d_sizes, d_max, h->err);
+      LAUNCHCHK();
+    }
+    TRY(sync_err(h, s, &herr));
+    if (herr & 2) return fail(OT_GS_ENUMERIC, "the cost has a negative, NaN or Inf entry");
+    std::vector<unsigned int> hmax(count);
+    std::vector<float> hscale(count);
+    HIPCHK(hipMemcpy(hmax.data(), d_max, sizeof(unsigned int) * count, hipMemcpyDeviceToHost));
+    for (int k = 0; k < count; ++k) {
+      float cmax;
+      std::memcpy(&cmax, &hmax[k], sizeof cmax);
+      float sc = probs[k].cost_scale;
+      if (sc == 0.f) {
+        if (!(cmax > 0.f)) return fail(OT_GS_ENUMERIC, "instance %d: max C is 0, cannot normalise", k);
+        sc = (float)(1.0 / (double)cmax);
+      }
+      hscale[k] = sc;
+      const float cm = cmax * sc;   // rounding is monotone: max of the scaled cost
+      if (!std::isfinite(cm)) return fail(OT_GS_ENUMERIC, "instance %d: scaled cost overflows", k);
+      h->inst[k].d.cmax = cm;
+    }
+    HIPCHK(hipMemcpyAsync(d_scale, hscale.data(), sizeof(float) * count, hipMemcpyHostToDevice, s));
 
-  // ---- instance descriptors
-  TRY(h->alloc(&h->d_inst, count));
-  {
-    std::vector<InstDev> hd(count);
-    for (int k = 0; k < count; ++k) hd[k] = h->inst[k].d;
-    HIPCHK(hipMemcpyAsync(h->d_inst, hd.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
-  }
+    // ---- instance descriptors
+    TRY(h->alloc(&h->d_inst, count));
+    {
+      std::vector<InstDev> hd(count);
+      for (int k = 0; k < count; ++k) hd[k] = h->inst[k].d;
+      HIPCHK(hipMemcpyAsync(h->d_inst, hd.data(), sizeof(InstDev) * count, hipMemcpyHostToDevice, s));
+    }
 
+    {
+      int maxnt = 1;
+      for (int k = 0; k < count; ++k) maxnt = std::max(maxnt, probs[k].n_tgt);
+      hipLaunchKernelGGL(k_col_assign, dim3((unsigned)ceil_div(maxnt, 256), count), dim3(256), 0, s,
+                         h->d_inst, d_costs, h->perm_row, h->row_grp, colkey);
+      LAUNCHCHK();
+    }
+  } else {
+    TRY(setup_onthefly(h, probs, colkey, temps, s));
+  }
   // ---- column clustering: nearest source class, then a stable sort by it
-  int* colkey = nullptr;
   int *ccnt = nullptr, *cstart = nullptr;
   SegDesc* csegs = nullptr;
-  TRY(h->alloc(&colkey, h->tot_cols));
   TRY(h->alloc(&ccnt, std::max<long long>(h->tot_groups, 1)));
   TRY(h->alloc(&cstart, std::max<long long>(h->tot_groups, 1)));
   TRY(h->alloc(&csegs, count));
   TRY(h->alloc(&h->perm_col, h->tot_cols_pad));
   HIPCHK(hipMemsetAsync(h->perm_col, 0xff, sizeof(int) * h->tot_cols_pad, s));
-  {
-    int maxnt = 1;
-    for (int k = 0; k < count; ++k) maxnt = std::max(maxnt, probs[k].n_tgt);
-    hipLaunchKernelGGL(k_col_assign, dim3((unsigned)ceil_div(maxnt, 256), count), dim3(256), 0, s,
-                       h->d_inst, d_costs, h->perm_row, h->row_grp, colkey);
-    LAUNCHCHK();
-  }
   std::vector<SegDesc> cseg(count);
   int maxLe = 1;
   for (int k = 0; k < count; ++k) {
@@ -459,26 +655,43 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
                      cstart, (const int*)nullptr, h->perm_col, (int*)nullptr);
   LAUNCHCHK();
 
-  // ---- internal cost
-  // the gradient kernel may read up to CHUNK rows past a group (masked), so
-  // the pool carries CHUNK zero rows of the widest instance at its end
-  {
-    long long maxntp = 64;
-    for (int k = 0; k < count; ++k) maxntp = std::max<long long>(maxntp, h->inst[k].d.nt_pad);
-    const long long pad = (long long)CHUNK * maxntp;
-    TRY(h->alloc(&h->C, h->tot_c + pad));
-    HIPCHK(hipMemsetAsync(h->C + h->tot_c, 0, sizeof(float) * pad, s));
-  }
-  {
-    int maxns = 1, maxntp = 64;
+  if (otf) {
+    // target features in the internal column order
+    const float** dxt = nullptr;
+    TRY(h->alloc(&dxt, count));
+    std::vector<const float*> hx(count);
+    int maxntp = 64;
     for (int k = 0; k < count; ++k) {
-      maxns = std::max(maxns, h->inst[k].d.ns);
+      hx[k] = probs[k].x_tgt;
       maxntp = std::max(maxntp, h->inst[k].d.nt_pad);
     }
-    dim3 grid((unsigned)std::min<long long>(ceil_div(maxntp, 256), 64), (unsigned)std::min(maxns, 65535), count);
-    hipLaunchKernelGGL(k_relayout_cost, grid, dim3(256), 0, s, h->d_inst, d_costs, d_scale, h->perm_row,
-                       h->perm_col, h->row_grp, h->g_start, h->g_size, h->C);
+    HIPCHK(hipMemcpyAsync(dxt, hx.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_otf_pack_y, dim3((unsigned)ceil_div(maxntp, 256), count), dim3(256), 0, s,
+                       h->d_inst, dxt, (const int*)h->perm_col, h->Yp, h->yn, h->err);
     LAUNCHCHK();
+  } else {
+    // ---- internal cost
+    // the gradient kernel may read up to CHUNK rows past a group (masked), so
+    // the pool carries CHUNK zero rows of the widest instance at its end
+    {
+      long long maxntp = 64;
+      for (int k = 0; k < count; ++k) maxntp = std::max<long long>(maxntp, h->inst[k].d.nt_pad);
+      const long long pad = (long long)CHUNK * maxntp;
+      TRY(h->alloc(&h->C, h->tot_c + pad));
+      HIPCHK(hipMemsetAsync(h->C + h->tot_c, 0, sizeof(float) * pad, s));
+    }
+    {
+      int maxns = 1, maxntp = 64;
+      for (int k = 0; k < count; ++k) {
+        maxns = std::max(maxns, h->inst[k].d.ns);
+        maxntp = std::max(maxntp, h->inst[k].d.nt_pad);
+      }
+      dim3 grid((unsigned)std::min<long long>(ceil_div(maxntp, 256), 64), (unsigned)std::min(maxns, 65535), count);
+      hipLaunchKernelGGL(k_relayout_cost, grid, dim3(256), 0, s, h->d_inst, d_costs, d_scale, h->perm_row,
+                         h->perm_col, h->row_grp, h->g_start, h->g_size, h->C);
+      LAUNCHCHK();
+    }
+
   }
 
   // ---- marginals
@@ -508,63 +721,6 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     hipLaunchKernelGGL(k_marginals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), count),
                        dim3(256), 0, s, h->d_inst, da, db, h->perm_row, h->perm_col, h->a_int, h->b_int);
     LAUNCHCHK();
-  }
-
-  // ---- work lists (static for dense evaluations, dynamic for screened ones)
-  {
-    std::vector<TileDesc> all, sg, sc;
-    std::vector<TileDesc> bucket[NBUCKET];
-    for (int k = 0; k < count; ++k) {
-      const InstHost& ih = h->inst[k];
-      for (int g = 0; g < ih.d.Le; ++g) {
-        const int n = ih.g_size[g];
-        const bool split = n > CHUNK;
-        const int nch = (int)ceil_div(n, CHUNK);
-        for (int jb = 0; jb < ih.d.njb; ++jb) {
-          TileDesc t{k, g, jb, split ? -nch : row_bucket(n)};
-          all.push_back(t);
-          if (!split) {
-            bucket[t.aux].push_back(t);
-          } else {
-            sg.push_back(TileDesc{k, g, jb, 0});
-            for (int c = 0; c < nch; ++c) sc.push_back(TileDesc{k, g, jb, c});
-          }
-        }
-      }
-    }
-    std::vector<TileDesc> mainl;
-    for (int b = 0; b < NBUCKET; ++b) {
-      h->main_off[b] = (int)mainl.size();
-      h->n_bucket[b] = (int)bucket[b].size();
-      mainl.insert(mainl.end(), bucket[b].begin(), bucket[b].end());
-    }
-    h->n_main = (int)mainl.size();
-    h->n_sg = (int)sg.size();
-    h->n_sc = (int)sc.size();
-    TRY(h->alloc(&h->tiles_all, all.size()));
-    TRY(h->alloc(&h->list_main, mainl.size()));
-    TRY(h->alloc(&h->list_sg, sg.size()));
-    TRY(h->alloc(&h->list_sc, sc.size()));
-    TRY(h->alloc(&h->dyn_main, mainl.size()));
-    TRY(h->alloc(&h->dyn_sg, sg.size()));
-    TRY(h->alloc(&h->dyn_sc, sc.size()));
-    auto up = [&](TileDesc* dst, const std::vector<TileDesc>& v) -> int {
-      if (!v.empty())
-        HIPCHK(hipMemcpyAsync(dst, v.data(), sizeof(TileDesc) * v.size(), hipMemcpyHostToDevice, s));
-      return OT_GS_OK;
-    };
-    TRY(up(h->tiles_all, all));
-    TRY(up(h->list_main, mainl));
-    TRY(up(h->list_sg, sg));
-    TRY(up(h->list_sc, sc));
-    TRY(h->alloc(&h->counts_static, NBUCKET + 2));
-    TRY(h->alloc(&h->counts_dyn, NBUCKET + 2));
-    int hc[NBUCKET + 2];
-    for (int b = 0; b < NBUCKET; ++b) hc[b] = h->n_bucket[b];
-    hc[NBUCKET] = h->n_sg;
-    hc[NBUCKET + 1] = h->n_sc;
-    HIPCHK(hipMemcpyAsync(h->counts_static, hc, sizeof hc, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(h->counts_dyn, 0, sizeof(int) * (NBUCKET + 2), s));
   }
 
   // ---- evaluation state
@@ -630,6 +786,11 @@ static GradArgs grad_args(ot_gs_handle* h) {
   A.g_size = h->g_size;
   A.g_chunk0 = h->g_chunk0;
   A.C = h->C;
+  A.g_xblk = h->g_xblk;
+  A.Xp = h->Xp;
+  A.Yp = h->Yp;
+  A.xn = h->xn;
+  A.yn = h->yn;
   A.alpha = h->alpha;
   A.beta = h->beta;
   A.rowpart = h->rowpart;
@@ -713,6 +874,40 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
 static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_possible, hipStream_t s) {
   const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
   TileDesc* mlist = dynamic ? h->dyn_main : h->list_main;
+  if (h->onthefly) {
+    // one bucket: whole groups of up to CHUNK rows, then the split passes
+    if (h->n_bucket[0] > 0) {
+      A.list = mlist;
+      A.count = cnt;
+      const dim3 grid(grid_for(h, h->n_bucket[0])), block(BLOCK);
+      hipLaunchKernelGGL((k_grad_tiles_otf<0, false>), grid, block, 0, s, A);
+      LAUNCHCHK();
+      if (snap_possible) {
+        hipLaunchKernelGGL((k_grad_tiles_otf<0, true>), grid, block, 0, s, A);
+        LAUNCHCHK();
+      }
+    }
+    if (h->n_sg > 0) {
+      A.list = dynamic ? h->dyn_sc : h->list_sc;
+      A.count = cnt + NBUCKET + 1;
+      const dim3 grid(grid_for(h, h->n_sc)), block(BLOCK);
+      hipLaunchKernelGGL((k_grad_tiles_otf<1, false>), grid, block, 0, s, A);
+      LAUNCHCHK();
+      if (snap_possible) {
+        hipLaunchKernelGGL((k_grad_tiles_otf<1, true>), grid, block, 0, s, A);
+        LAUNCHCHK();
+      }
+      A.list = dynamic ? h->dyn_sg : h->list_sg;
+      A.count = cnt + NBUCKET;
+      hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
+      LAUNCHCHK();
+      A.list = dynamic ? h->dyn_sc : h->list_sc;
+      A.count = cnt + NBUCKET + 1;
+      hipLaunchKernelGGL((k_grad_tiles_otf<2, false>), grid, block, 0, s, A);
+      LAUNCHCHK();
+    }
+    return OT_GS_OK;
+  }
   for (int b = 0; b < NBUCKET; ++b) {
     if (h->n_bucket[b] == 0) continue;
     A.list = mlist + h->main_off[b];
@@ -862,9 +1057,41 @@ int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T,
   hipStream_t s = (hipStream_t)stream;
   TRY(gather(h, alpha, beta, s));
   TRY(evaluate(h, OT_GS_DENSE, nullptr, nullptr, s, true));
+  if (h->onthefly) {
+    GradArgs A = grad_args(h);
+    A.list = h->tiles_all;
+    const int n = (int)h->tot_tiles;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_otf_emit<1>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n,
+                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, T);
+      LAUNCHCHK();
+    }
+    return OT_GS_OK;
+  }
   dim3 grid((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 16), (unsigned)std::min(h->max_ns, 4096), h->count);
   hipLaunchKernelGGL(k_plan_dense, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
                      h->g_start, h->g_size, h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+int ot_gs_cost(ot_gs_handle* h, float* C_out, void* stream) {
+  if (!h || !C_out) return fail(OT_GS_EINVAL, "cost: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if (h->onthefly) {
+    GradArgs A = grad_args(h);
+    A.list = h->tiles_all;
+    const int n = (int)h->tot_tiles;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_otf_emit<0>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n,
+                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, C_out);
+      LAUNCHCHK();
+    }
+    return OT_GS_OK;
+  }
+  dim3 grid((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 16), (unsigned)std::min(h->max_ns, 4096), h->count);
+  hipLaunchKernelGGL(k_cost_dump, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
+                     h->g_start, h->g_size, h->C, h->t_off, C_out);
   LAUNCHCHK();
   return OT_GS_OK;
 }

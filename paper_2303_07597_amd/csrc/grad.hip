@@ -27,6 +27,11 @@ struct GradArgs {
   const int* g_start;
   const int* g_size;
   const int* g_chunk0;    // first chunk row of a split group (-1: not split)
+  const int* g_xblk;      // on-the-fly: first packed 32-row feature block of a group
+  const float* Xp;        // on-the-fly: packed source / target features, norms
+  const float* Yp;
+  const float* xn;
+  const float* yn;
   const TileDesc* list;   // work list
   const int* count;       // number of entries (device)
   const float* C;
@@ -505,6 +510,347 @@ __global__ void __launch_bounds__(256) k_plan_dense(const InstDev* __restrict__ 
       trow[perm_col[I.col_off + c]] = krow[c] * fmaxf(f, 0.f);
     }
   }
+}
+
+
+// The scaled internal cost in the caller's order (materialized pool).
+__global__ void __launch_bounds__(256) k_cost_dump(const InstDev* __restrict__ inst,
+                                                   const int* __restrict__ perm_row,
+                                                   const int* __restrict__ perm_col,
+                                                   const int* __restrict__ row_grp,
+                                                   const int* __restrict__ g_start,
+                                                   const int* __restrict__ g_size,
+                                                   const float* __restrict__ C,
+                                                   const long long* __restrict__ t_off,
+                                                   float* __restrict__ out) {
+  const InstDev I = inst[blockIdx.z];
+  for (int r = blockIdx.y; r < I.ns; r += gridDim.y) {
+    const int g = row_grp[I.row_off + r];
+    const int gs = g_start[I.grp_off + g], gn = g_size[I.grp_off + g];
+    float* orow = out + t_off[blockIdx.z] + (size_t)perm_row[I.row_off + r] * I.nt;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt; c += gridDim.x * blockDim.x)
+      orow[perm_col[I.col_off + c]] = C[c_index(I, gs, gn, r, c)];
+  }
+}
+
+// ---------------------------------------------------------------- on-the-fly cost
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// x_i . y_j for the 32 rows of a packed source block and the 32 columns of the
+// packed target block in LDS, on v_mfma_f32_32x32x2f32 (two dims per
+// instruction, dims in increasing order).  Result layout: lane l, element q
+// holds row 8 (q / 4) + 4 (l / 32) + (q % 4), column l % 32.
+__device__ __forceinline__ floatx16 otf_dot_block(const float* __restrict__ xblk, const float* ylds,
+                                                  int DP, int lane) {
+  floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int c = lane & 31, h = lane >> 5;
+  const float4* xa = (const float4*)(xblk + ((size_t)h * 32 + c) * 8);
+  const float4* ya = (const float4*)(ylds + (h * 32 + c) * 8);
+  const int nm = DP / 16;
+  for (int m8 = 0; m8 < nm; ++m8) {
+    const float4 x0 = xa[m8 * 128], x1 = xa[m8 * 128 + 1];   // 2 * 32 * 8 floats per chunk
+    const float4 y0 = ya[m8 * 128], y1 = ya[m8 * 128 + 1];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, y0.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, y0.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, y0.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.w, y0.w, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.x, y1.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, y1.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, y1.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, y1.w, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// stage the packed target block of column block jb into LDS (whole block)
+__device__ __forceinline__ void otf_stage_y(const GradArgs& A, const InstDev& I, int jb, float* ylds) {
+  const float4* src = (const float4*)(A.Yp + I.y_off + (size_t)jb * 32 * I.dp);
+  float4* dst = (float4*)ylds;
+  for (int i = threadIdx.x; i < 8 * I.dp; i += blockDim.x) dst[i] = src[i];
+}
+
+// Cost of element q of the block (rows i, column j) in the MFMA layout:
+// C = max(s ((|x_i|^2 + |y_j|^2) - 2 x_i.y_j), 0).
+__device__ __forceinline__ float otf_cost(float xn_i, float yn_j, float dot, float s) {
+  return fmaxf(s * ((xn_i + yn_j) - 2.f * dot), 0.f);
+}
+
+// Gradient tile with the cost computed on matrix cores.  Up to two 32-row
+// blocks per wavefront (1024 rows per workgroup); PHASE as in grad_tile.
+template <int PHASE, bool SNAP>
+__device__ __forceinline__ void grad_tile_otf(const GradArgs& A, const TileDesc& d,
+                                              float (*red)[NW][TJ], float* ylds) {
+  const InstDev I = A.inst[d.inst];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gs = A.g_start[I.grp_off + d.grp];
+  const int gn = A.g_size[I.grp_off + d.grp];
+  int r0 = 0, r1 = gn;
+  if (PHASE != 0) {
+    r0 = d.aux * CHUNK;
+    r1 = min(r0 + CHUNK, gn);
+  }
+  const int col = d.jb * TJ + c;
+  const bool colok = col < I.nt;
+  const float bj = A.beta[I.col_off + col];
+  const float ynj = A.yn[I.col_off + col];
+  constexpr bool snap = SNAP && PHASE != 2;
+  otf_stage_y(A, I, d.jb, ylds);
+  __syncthreads();
+
+  float p[2][16];
+  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int rb = w + NW * b;          // 32-row block of this chunk
+    const int i0 = r0 + 32 * rb;        // first row, relative to the group
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p[b][q] = 0.f;
+    if (i0 >= r1) continue;             // wave-uniform
+    const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
+    const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
+    const bool rowin = i0 + c < r1;
+    const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;   // lane c: row i0 + c
+    const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int rr0 = 8 * (q / 4) + (q % 4);   // row within the block for h = 0; +4 for h = 1
+      const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0));
+      const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0 + 4));
+      const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
+      const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
+      const float ai = h ? a1 : a0, xi = h ? x1 : x0;
+      const float C = otf_cost(xi, ynj, acc[q], I.cscale);
+      const float f = (ai + bj) - C;
+      const bool ok = (i0 + rr0 + 4 * h < r1) && colok;
+      const float pk = ok ? fmaxf(f, 0.f) : 0.f;
+      if (PHASE != 2) {
+        z2 = fmaf(pk, pk, z2);
+        s1 += pk;
+        if (snap) {
+          const float nkv = ok ? fminf(f, 0.f) : 0.f;
+          o2 = fmaf(nkv, nkv, o2);
+        }
+      }
+      p[b][q] = pk;
+    }
+  }
+
+  float kap = 0.f;
+  if (PHASE != 2) {
+    z2 += __shfl_xor(z2, 32);
+    s1 += __shfl_xor(s1, 32);
+    if (snap) o2 += __shfl_xor(o2, 32);
+    if (h == 0) {
+      red[0][w][c] = z2;
+      red[1][w][c] = s1;
+      if (snap) red[2][w][c] = o2;
+    }
+    __syncthreads();
+    float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+#pragma unroll 4
+    for (int v = 0; v < NW; ++v) {
+      Z2 += red[0][v][c];
+      S1 += red[1][v][c];
+    }
+    if (snap) {
+#pragma unroll 4
+      for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
+    }
+    if (PHASE == 1) {
+      if (w == 0 && h == 0) {
+        const long long qq = I.chunk_off +
+                             (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
+        A.part[qq] = Z2;
+        A.part[qq + A.part_stride] = S1;
+        A.part[qq + 2 * A.part_stride] = O2;
+      }
+      return;
+    }
+    const float z = sqrtf(Z2);
+    float num = 0.f;
+    if (z > I.thr) {
+      num = z - I.thr;
+      kap = num / (I.gamma * z);
+    }
+    if (w == 0 && h == 0) {
+      const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+      A.colsum[pr] = kap * S1;
+      A.excess[pr] = num;
+      if (A.write_kappa) A.kappa[pr] = kap;
+      if (snap) {
+        A.zsnap[pr] = z;
+        A.osnap[pr] = sqrtf(O2);
+      }
+    }
+  } else {
+    kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
+  }
+
+  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
+  const bool anyk = __ballot(kap > 0.f) != 0ull;
+  const int Q = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int i0 = r0 + 32 * (w + NW * b);
+    if (i0 >= r1) continue;
+    if (!anyk) {
+      if (lane < 32 && i0 + lane < r1) rp[i0 + lane] = 0.f;
+      continue;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      // rows of elements qa = 2m and qb = 2m + 1 (both parities)
+      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(kap * p[b][2 * m]),
+                                                       __float_as_uint(kap * p[b][2 * m + 1]), false, false);
+      const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+      const int qsel = 2 * m + (Q & 1);
+      const int row = i0 + 8 * (qsel / 4) + (qsel % 4) + 4 * (Q >> 1);
+      if ((lane & 15) == 15 && row < r1) rp[row] = x;
+    }
+  }
+}
+
+template <int PHASE, bool SNAP>
+__global__ void __launch_bounds__(BLOCK) k_grad_tiles_otf(GradArgs A) {
+  __shared__ float red[3][NW][TJ];
+  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
+  const int n = *A.count;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TileDesc d = A.list[t];
+    if ((A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
+    grad_tile_otf<PHASE, SNAP>(A, d, red, ylds);
+    __syncthreads();
+  }
+}
+
+// Setup pass over natural-order target blocks: per (group, target) the least
+// unscaled cost u = |x|^2 + |y|^2 - 2 x.y over the group's rows (nearest-class
+// clustering) and the largest u of the instance (normalisation).  grid: one
+// workgroup per (group, natural 32-column block) in `list` (aux unused).
+__global__ void __launch_bounds__(BLOCK) k_otf_setup(GradArgs A, int n, const float* __restrict__ Ynat,
+                                                     const float* __restrict__ ynnat,
+                                                     float* __restrict__ colmin,
+                                                     unsigned int* __restrict__ maxbits) {
+  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
+  __shared__ float red[NW][TJ];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TileDesc d = A.list[t];
+    const InstDev I = A.inst[d.inst];
+    const int gs = A.g_start[I.grp_off + d.grp];
+    const int gn = A.g_size[I.grp_off + d.grp];
+    {
+      const float4* src = (const float4*)(Ynat + I.y_off + (size_t)d.jb * 32 * I.dp);
+      float4* dst = (float4*)ylds;
+      for (int i = threadIdx.x; i < 8 * I.dp; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
+    const int col = d.jb * TJ + c;
+    const float ynj = ynnat[I.col_off + col];
+    float mn = INFINITY, mx = 0.f;
+    for (int i0 = 32 * w; i0 < gn; i0 += 32 * NW) {
+      const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
+      const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
+      const float xv = (i0 + c < gn) ? A.xn[I.row_off + gs + i0 + c] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int rr0 = 8 * (q / 4) + (q % 4);
+        const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
+        const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
+        const float u = (( h ? x1 : x0) + ynj) - 2.f * acc[q];
+        if (i0 + rr0 + 4 * h < gn && col < I.nt) {
+          mn = fminf(mn, u);
+          mx = fmaxf(mx, u);
+        }
+      }
+    }
+    mn = fminf(mn, __shfl_xor(mn, 32));
+    if (h == 0) red[w][c] = mn;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) atomicMax(&maxbits[d.inst], __float_as_uint(mx));
+    __syncthreads();
+    if (w == 0 && h == 0 && col < I.nt) {
+      float m = INFINITY;
+      for (int v = 0; v < NW; ++v) m = fminf(m, red[v][c]);
+      colmin[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col] = m;
+    }
+    __syncthreads();
+  }
+}
+
+// The cost (MODE 0) or the plan T_ij = kappa_lj [f_ij]_+ (MODE 1) of the
+// tiles of `list` (all rows of each group), written in the caller's order at
+// out[t_off + perm_row(i) n_tgt + perm_col(j)].  Same arithmetic as the
+// gradient tiles, so the values are the ones the gradient used.
+template <int MODE>
+__global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int* __restrict__ perm_row,
+                                                    const int* __restrict__ perm_col,
+                                                    const long long* __restrict__ t_off,
+                                                    float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = threadIdx.x >> 6;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TileDesc d = A.list[t];
+    const InstDev I = A.inst[d.inst];
+    const int gs = A.g_start[I.grp_off + d.grp];
+    const int gn = A.g_size[I.grp_off + d.grp];
+    otf_stage_y(A, I, d.jb, ylds);
+    __syncthreads();
+    const int col = d.jb * TJ + c;
+    const bool colok = col < I.nt;
+    const float ynj = A.yn[I.col_off + col];
+    const float bj = A.beta[I.col_off + col];
+    const float kap = MODE ? A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col] : 0.f;
+    const int dcol = colok ? perm_col[I.col_off + col] : 0;
+    float* o = out + t_off[d.inst];
+    for (int i0 = 32 * w; i0 < gn; i0 += 32 * NW) {
+      const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
+      const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
+      const bool rowin = i0 + c < gn;
+      const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
+      const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;
+      const int pv = rowin ? perm_row[I.row_off + gs + i0 + c] : 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int rr0 = 8 * (q / 4) + (q % 4);
+        const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
+        const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
+        const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0));
+        const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0 + 4));
+        const int p0 = __builtin_amdgcn_readlane(pv, rr0), p1 = __builtin_amdgcn_readlane(pv, rr0 + 4);
+        const float C = otf_cost(h ? x1 : x0, ynj, acc[q], I.cscale);
+        const float v = MODE ? kap * fmaxf(((h ? a1 : a0) + bj) - C, 0.f) : C;
+        if (i0 + rr0 + 4 * h < gn && colok) o[(size_t)(h ? p1 : p0) * I.nt + dcol] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// nearest source class of every target column from the per-group minima
+__global__ void k_otf_assign(const InstDev* __restrict__ inst, const float* __restrict__ colmin,
+                             int* __restrict__ colkey) {
+  const InstDev I = inst[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= I.nt) return;
+  float best = INFINITY;
+  int bg = 0;
+  for (int g = 0; g < I.Le; ++g) {
+    const float v = colmin[(size_t)I.pair_off + (size_t)g * I.nt_pad + j];
+    if (v < best) {
+      best = v;
+      bg = g;
+    }
+  }
+  colkey[I.scol_off + j] = bg;
 }
 
 }  // namespace otgs

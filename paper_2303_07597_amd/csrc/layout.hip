@@ -193,3 +193,69 @@ __global__ void k_marginals(const InstDev* __restrict__ inst, const float* const
 }
 
 }  // namespace otgs
+
+namespace otgs {
+
+// ---------------------------------------------------------------- on-the-fly cost
+//
+// Features are packed for the FP32 matrix-core instruction v_mfma_f32_32x32x2f32
+// (A operand: lane l gives row l%32, dim 2m + l/32; B operand: column l%32,
+// dim 2m + l/32).  Dimensions are padded with zeros to DP (a multiple of 16)
+// and stored per block of 32 rows (or columns) as [DP/16][2][32][8]: for
+// chunk m8 (dims 16 m8 .. 16 m8 + 15), lane (c, h) finds its 8 values
+// (dims 2 (8 m8 + u) + h, u < 8) contiguously at ((2 m8 + h) 32 + c) 8, so a
+// wavefront's operand load is 1 KB of consecutive memory.
+__host__ __device__ inline size_t otf_block_index(int DP, int c, int dim) {
+  const int m = dim >> 1, h = dim & 1;
+  return ((size_t)((m >> 3) * 2 + h) * 32 + c) * 8 + (m & 7);
+}
+
+// Source features: internal row r (group ge, local row q) goes to the block
+// of rows of its group; groups are padded to whole 32-row blocks.  Also the
+// squared norms in float32 (fixed order over dims).  grid (row blocks, count)
+__global__ void k_otf_pack_x(const InstDev* __restrict__ inst, const float* const* __restrict__ xs,
+                             const int* __restrict__ perm_row, const int* __restrict__ row_grp,
+                             const int* __restrict__ g_start, const int* __restrict__ g_xblk,
+                             float* __restrict__ Xp, float* __restrict__ xn, int* __restrict__ err) {
+  const InstDev I = inst[blockIdx.y];
+  const float* x = xs[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
+    const int g = row_grp[I.row_off + r];
+    const int q = r - g_start[I.grp_off + g];
+    float* blk = Xp + I.x_off + ((size_t)g_xblk[I.grp_off + g] + q / 32) * 32 * I.dp;
+    const float* src = x + (size_t)perm_row[I.row_off + r] * I.dim;
+    float s = 0.f;
+    for (int k = 0; k < I.dp; ++k) {
+      const float v = k < I.dim ? src[k] : 0.f;
+      if (!isfinite(v)) atomicOr(err, 2);
+      s = fmaf(v, v, s);
+      blk[otf_block_index(I.dp, q % 32, k)] = v;
+    }
+    if (!isfinite(s)) atomicOr(err, 2);
+    xn[I.row_off + r] = s;
+  }
+}
+
+// Target features, column c of the internal order (perm_col maps to the
+// caller's column; NULL: natural order), block c / 32; padding columns 0.
+__global__ void k_otf_pack_y(const InstDev* __restrict__ inst, const float* const* __restrict__ xt,
+                             const int* __restrict__ perm_col, float* __restrict__ Yp,
+                             float* __restrict__ yn, int* __restrict__ err) {
+  const InstDev I = inst[blockIdx.y];
+  const float* y = xt[blockIdx.y];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
+    float* blk = Yp + I.y_off + (size_t)(c / 32) * 32 * I.dp;
+    const int src_c = c < I.nt ? (perm_col ? perm_col[I.col_off + c] : c) : -1;
+    float s = 0.f;
+    for (int k = 0; k < I.dp; ++k) {
+      const float v = (src_c >= 0 && k < I.dim) ? y[(size_t)src_c * I.dim + k] : 0.f;
+      if (!isfinite(v)) atomicOr(err, 2);
+      s = fmaf(v, v, s);
+      blk[otf_block_index(I.dp, c % 32, k)] = v;
+    }
+    if (!isfinite(s)) atomicOr(err, 2);
+    yn[I.col_off + c] = s;
+  }
+}
+
+}  // namespace otgs

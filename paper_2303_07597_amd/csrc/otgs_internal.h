@@ -28,6 +28,7 @@ constexpr int CHUNK = 2 * NW * RMAX;   // 1024: largest group handled in one pas
 constexpr int RSTEP = 4;               // row buckets: R = 4, 8, ..., 32 rows per lane
 constexpr int NBUCKET = RMAX / RSTEP;  // 8
 constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
+constexpr int DP_MAX = 256;            // on-the-fly cost: padded feature dims
 
 struct InstDev {
   int ns, nt, nt_pad, njb;
@@ -45,6 +46,10 @@ struct InstDev {
   long long r_off;  // row-partial pool offset (floats)
   float gamma, mu, thr;  // thr = fl32(mu * gamma)
   float cmax;            // max of the internal (scaled) cost
+  // on-the-fly cost (features on matrix cores); unused otherwise
+  int onthefly, dim, dp, pad1;   // dp: dims padded to a multiple of 16
+  long long x_off, y_off;        // packed feature pools (floats)
+  float cscale, pad2;            // C = max(cscale (|x|^2 + |y|^2 - 2 x.y), 0)
 };
 
 // A segment of keys for the stable counting sort: n keys in [0, K) at

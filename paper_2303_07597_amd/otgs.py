@@ -81,6 +81,7 @@ def _load():
     lib.ot_gs_default_options.argtypes = [ct.POINTER(ot_gs_options)]
     lib.ot_gs_default_options.restype = None
     lib.ot_gs_plan.argtypes = [vp, vp, vp, vp, vp]
+    lib.ot_gs_cost.argtypes = [vp, vp, vp]
     lib.ot_gs_rho_to_mu.argtypes = [d, d, ct.POINTER(d), ct.POINTER(d)]
     lib.ot_gs_get_stats.argtypes = [vp, ct.POINTER(ot_gs_stats), i, vp]
     lib.ot_gs_kernel_timing.argtypes = [vp, i]
@@ -210,6 +211,9 @@ class Handle:
     def plan(self, alpha, beta, T, stream=None):
         _check(lib().ot_gs_plan(self.h, _ptr(alpha), _ptr(beta), _ptr(T), _stream(stream)))
 
+    def cost(self, C_out, stream=None):
+        _check(lib().ot_gs_cost(self.h, _ptr(C_out), _stream(stream)))
+
     def stats(self, reset=False, stream=None):
         st = ot_gs_stats()
         _check(lib().ot_gs_get_stats(self.h, ct.byref(st), int(reset), _stream(stream)))
@@ -236,6 +240,6 @@ class Handle:
 
 EXPORTED = [
     "ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_default_options",
-    "ot_gs_plan", "ot_gs_rho_to_mu", "ot_gs_get_stats", "ot_gs_kernel_timing", "ot_gs_kernel_time",
+    "ot_gs_plan", "ot_gs_cost", "ot_gs_rho_to_mu", "ot_gs_get_stats", "ot_gs_kernel_timing", "ot_gs_kernel_time",
     "ot_gs_layout_info", "ot_gs_last_error", "ot_gs_version", "ot_gs_profile_tiles",
 ]
