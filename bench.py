@@ -36,10 +36,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mu", type=float, default=0.1)
-    ap.add_argument("--solve-iters", type=int, default=400)
-    ap.add_argument("--ref-iters", type=int, default=3000)
+    ap.add_argument("--solve-iters", type=int, default=1500)
+    ap.add_argument("--ref-iters", type=int, default=6000)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-solve", action="store_true", help="omit the time-to-tolerance solves")
+    ap.add_argument("--skip-onthefly", action="store_true",
+                    help="omit the on-the-fly (matrix-core cost) workload")
+    ap.add_argument("--otf-n", type=int, default=32768, help="on-the-fly workload: n_src = n_tgt")
+    ap.add_argument("--otf-iters", type=int, default=500, help="on-the-fly workload: L-BFGS iterations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (traffic counter calibration)")
     return ap.parse_args()
@@ -81,6 +85,70 @@ def cpu_baseline(inst, alpha, beta, budget_s=12.0):
                        f"{el:.1f} s")
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def bench_onthefly(args, torch, synth, O):
+    """Many-class workload with the cost recomputed from features on FP32
+    matrix cores in every evaluation: n_src = n_tgt = 32768, d = 256, 100
+    classes with Zipf(1.1) sizes, gamma = 0.05, mu = 0.5.  Reports the dense
+    evaluation rate, the matrix-core utilisation of the tile kernels
+    (2 d flop per entry over their summed launch time), and `otf_iters`
+    L-BFGS iterations dense and screened (same trajectory)."""
+    dev = torch.device("cuda")
+    n, d = args.otf_n, 256
+    inst = synth.zipf_blobs(seed=3, n_src=n, n_tgt=n, d=d, n_groups=100, gamma=0.05, mu=0.5)
+    h = O.Handle([dict(labels=torch.from_numpy(inst["labels"]).to(dev), n_groups=100,
+                       gamma=inst["gamma"], mu=inst["mu"],
+                       x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
+                       cost_mode=O.OT_GS_COST_ONTHEFLY, cost_scale=0.0)])
+    a_pt, b_pt, _, _ = h.solve(max_iter=20, use_screen=0)
+    ga, gb = torch.empty_like(a_pt), torch.empty_like(b_pt)
+    obj = torch.empty(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    tiles_us = h.profile_tiles(reps)
+    flops = 2.0 * d * n * n
+    achieved = flops / (tiles_us * 1e-6) / 1e12
+    out = dict(workload=f"zipf n_src=n_tgt={n} d={d} classes=100 gamma=0.05 mu=0.5, cost on the fly",
+               point="after 20 dense L-BFGS iterations from zero",
+               entries_per_s=n * n / el, ms_per_eval=1e3 * el,
+               mfma=dict(bound="mfma", achieved=achieved, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=achieved / FP32_MFMA_PEAK_TFLOPS, flop_per_launch=flops,
+                         avg_launch_us=tiles_us, kernel="k_grad_tiles_otf (all buckets and passes)"))
+    if args.otf_iters > 0:
+        K = args.otf_iters
+        runs = {}
+        for name, scr in (("dense", 0), ("screened", 1)):
+            otr = torch.full((K + 1,), float("nan"), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            h.stats(reset=True)
+            t0 = time.perf_counter()
+            _, _, inf, _ = h.solve(max_iter=K, use_screen=scr, obj_trace=otr)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = h.stats(reset=True)
+            runs[name] = dict(wall_s=wall, iters=inf[0]["iters"], evals=inf[0]["evals"], obj=inf[0]["obj"],
+                              tiles_computed_frac=st["tiles_computed"] / max(st["tiles_total"], 1),
+                              pairs_skipped_frac=(1 - (st["pairs_unskipped"] + st["pairs_in_N"]) /
+                                                  max(st["pairs_total"], 1)) if scr else 0.0)
+        runs["speedup_screened"] = runs["dense"]["wall_s"] / runs["screened"]["wall_s"]
+        out["solve"] = runs
+    h.close()
+    return out
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -99,6 +167,7 @@ def main():
                        x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
                        cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0)])
 
+    log("dense workload created")
     # point of measurement: 200 L-BFGS iterations from zero (dense solve)
     a_pt, b_pt, info, _ = h.solve(max_iter=200, use_screen=0)
     torch.cuda.synchronize()
@@ -138,6 +207,7 @@ def main():
         if tr.get("source_hash") == grad_source_hash():
             traffic = tr.get("bytes_per_launch")
 
+    log(f"dense evaluations: {ms_step:.4f} ms each, tiles {grad_us:.2f} us per launch")
     # screened evaluation at the same point after a snapshot there
     h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_SNAPSHOT)
     h.stats(reset=True)
@@ -154,6 +224,7 @@ def main():
                     tiles_computed_frac=st["tiles_computed"] / max(st["tiles_total"], 1),
                     pairs_skipped_frac=1 - (st["pairs_unskipped"] + st["pairs_in_N"]) / max(st["pairs_total"], 1))
 
+    log(f"screened evaluations: {screened['ms_per_eval']:.4f} ms each")
     solves = None
     if not args.skip_solve:
         M = args.ref_iters
@@ -193,6 +264,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
 
+    log("solves done")
+    otf = None
+    if not args.skip_onthefly:
+        otf = bench_onthefly(args, torch, synth, O)
+        log(f"on-the-fly workload: {otf['ms_per_eval']:.3f} ms per dense evaluation")
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(inst, a_pt.cpu().numpy(), b_pt.cpu().numpy())
@@ -212,6 +289,7 @@ def main():
         cpu_baseline=cpu,
         screened_eval=screened,
         solves=solves,
+        onthefly=otf,
     )
     print(json.dumps(line), flush=True)
 

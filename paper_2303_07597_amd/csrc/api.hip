@@ -197,7 +197,7 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
         const bool split = n > CHUNK;
         const int nch = (int)ceil_div(n, CHUNK);
         for (int jb = 0; jb < ih.d.njb; ++jb) {
-          TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? 0 : row_bucket(n))};
+          TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? otf_bucket(n) : row_bucket(n))};
           all.push_back(t);
           if (!split) {
             bucket[t.aux].push_back(t);
@@ -875,15 +875,30 @@ static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
   const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
   TileDesc* mlist = dynamic ? h->dyn_main : h->list_main;
   if (h->onthefly) {
-    // one bucket: whole groups of up to CHUNK rows, then the split passes
-    if (h->n_bucket[0] > 0) {
-      A.list = mlist;
-      A.count = cnt;
-      const dim3 grid(grid_for(h, h->n_bucket[0])), block(BLOCK);
-      hipLaunchKernelGGL((k_grad_tiles_otf<0, false>), grid, block, 0, s, A);
-      LAUNCHCHK();
-      if (snap_possible) {
-        hipLaunchKernelGGL((k_grad_tiles_otf<0, true>), grid, block, 0, s, A);
+    // whole groups: bucket b < 5 has teams of 1 << b wavefronts with one
+    // row block each, bucket 5 teams of 16 with two; workgroups of
+    // max(team, 4) wavefronts
+    for (int b = 0; b < OTF_NBUCKET; ++b) {
+      if (h->n_bucket[b] == 0) continue;
+      A.list = mlist + h->main_off[b];
+      A.count = cnt + b;
+      const int WT = 1 << std::min(b, 4), NWV = std::max(WT, 4), K = NWV / WT;
+      const int per_cu = (b < 5 ? 32 : 16) / NWV;    // resident workgroups per CU
+      const dim3 grid(std::max(1, std::min((h->n_bucket[b] + K - 1) / K, 2 * per_cu * h->n_cu))),
+          block(64 * NWV);
+      for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+#define OTGS_LAUNCH_OTF(WW, BB)                                                              \
+  if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, true>), grid, block, 0, s, A);    \
+  else hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, false>), grid, block, 0, s, A);
+        switch (b) {
+          case 0: OTGS_LAUNCH_OTF(1, 1) break;
+          case 1: OTGS_LAUNCH_OTF(2, 1) break;
+          case 2: OTGS_LAUNCH_OTF(4, 1) break;
+          case 3: OTGS_LAUNCH_OTF(8, 1) break;
+          case 4: OTGS_LAUNCH_OTF(16, 1) break;
+          default: OTGS_LAUNCH_OTF(16, 2) break;
+        }
+#undef OTGS_LAUNCH_OTF
         LAUNCHCHK();
       }
     }
@@ -891,10 +906,10 @@ static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
       A.list = dynamic ? h->dyn_sc : h->list_sc;
       A.count = cnt + NBUCKET + 1;
       const dim3 grid(grid_for(h, h->n_sc)), block(BLOCK);
-      hipLaunchKernelGGL((k_grad_tiles_otf<1, false>), grid, block, 0, s, A);
+      hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, false>), grid, block, 0, s, A);
       LAUNCHCHK();
       if (snap_possible) {
-        hipLaunchKernelGGL((k_grad_tiles_otf<1, true>), grid, block, 0, s, A);
+        hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, true>), grid, block, 0, s, A);
         LAUNCHCHK();
       }
       A.list = dynamic ? h->dyn_sg : h->list_sg;
@@ -903,7 +918,7 @@ static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
       LAUNCHCHK();
       A.list = dynamic ? h->dyn_sc : h->list_sc;
       A.count = cnt + NBUCKET + 1;
-      hipLaunchKernelGGL((k_grad_tiles_otf<2, false>), grid, block, 0, s, A);
+      hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 2, false>), grid, block, 0, s, A);
       LAUNCHCHK();
     }
     return OT_GS_OK;

@@ -242,7 +242,8 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles(GradArgs A) {
   const int n = *A.count;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
-    if ((A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
+    // the row-sum pass of split groups has one variant for every mode
+    if (PHASE != 2 && (A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
     grad_tile<R, PHASE, SNAP>(A, d, red);
     __syncthreads();
   }
@@ -537,20 +538,29 @@ __global__ void __launch_bounds__(256) k_cost_dump(const InstDev* __restrict__ i
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// x_i . y_j for the 32 rows of a packed source block and the 32 columns of the
-// packed target block in LDS, on v_mfma_f32_32x32x2f32 (two dims per
-// instruction, dims in increasing order).  Result layout: lane l, element q
-// holds row 8 (q / 4) + 4 (l / 32) + (q % 4), column l % 32.
-__device__ __forceinline__ floatx16 otf_dot_block(const float* __restrict__ xblk, const float* ylds,
-                                                  int DP, int lane) {
+// x_i . y_j for the 32 rows of a packed source block and the 32 columns of a
+// packed target block, on v_mfma_f32_32x32x2f32 (two dims per instruction,
+// dims in increasing order).  Both operands come from global memory, 1 KB
+// contiguous per wavefront load, the next 16 dims in flight while the
+// current ones are multiplied.  Result: lane l, element q holds row
+// 8 (q / 4) + 4 (l / 32) + (q % 4) of the block, column l % 32.
+template <bool PREFETCH = true>
+__device__ __forceinline__ floatx16 otf_dot_block(const float* __restrict__ xblk,
+                                                  const float* __restrict__ yblk, int DP, int lane) {
   floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const int c = lane & 31, h = lane >> 5;
-  const float4* xa = (const float4*)(xblk + ((size_t)h * 32 + c) * 8);
-  const float4* ya = (const float4*)(ylds + (h * 32 + c) * 8);
-  const int nm = DP / 16;
+  const float4* xa = (const float4*)(xblk + lane * 8);   // lane = 32 h + c
+  const float4* ya = (const float4*)(yblk + lane * 8);
+  const int nm = DP >> 4;                                // chunks of 16 dims: 128 float4
+  float4 x0 = xa[0], x1 = xa[1], y0 = ya[0], y1 = ya[1];
   for (int m8 = 0; m8 < nm; ++m8) {
-    const float4 x0 = xa[m8 * 128], x1 = xa[m8 * 128 + 1];   // 2 * 32 * 8 floats per chunk
-    const float4 y0 = ya[m8 * 128], y1 = ya[m8 * 128 + 1];
+    float4 nx0, nx1, ny0, ny1;
+    if (PREFETCH) {
+      const int nx = min(m8 + 1, nm - 1) * 128;
+      nx0 = xa[nx];
+      nx1 = xa[nx + 1];
+      ny0 = ya[nx];
+      ny1 = ya[nx + 1];
+    }
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.x, y0.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.y, y0.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x0.z, y0.z, acc, 0, 0, 0);
@@ -559,169 +569,193 @@ __device__ __forceinline__ floatx16 otf_dot_block(const float* __restrict__ xblk
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.y, y1.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.z, y1.z, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(x1.w, y1.w, acc, 0, 0, 0);
+    if (PREFETCH) {
+      x0 = nx0;
+      x1 = nx1;
+      y0 = ny0;
+      y1 = ny1;
+    } else if (m8 + 1 < nm) {
+      const int nx = (m8 + 1) * 128;
+      x0 = xa[nx];
+      x1 = xa[nx + 1];
+      y0 = ya[nx];
+      y1 = ya[nx + 1];
+    }
   }
   return acc;
 }
 
-// stage the packed target block of column block jb into LDS (whole block)
-__device__ __forceinline__ void otf_stage_y(const GradArgs& A, const InstDev& I, int jb, float* ylds) {
-  const float4* src = (const float4*)(A.Yp + I.y_off + (size_t)jb * 32 * I.dp);
-  float4* dst = (float4*)ylds;
-  for (int i = threadIdx.x; i < 8 * I.dp; i += blockDim.x) dst[i] = src[i];
-}
-
-// Cost of element q of the block (rows i, column j) in the MFMA layout:
-// C = max(s ((|x_i|^2 + |y_j|^2) - 2 x_i.y_j), 0).
+// Cost of one element: C = max(s ((|x_i|^2 + |y_j|^2) - 2 x_i.y_j), 0).
 __device__ __forceinline__ float otf_cost(float xn_i, float yn_j, float dot, float s) {
   return fmaxf(s * ((xn_i + yn_j) - 2.f * dot), 0.f);
 }
 
-// Gradient tile with the cost computed on matrix cores.  Up to two 32-row
-// blocks per wavefront (1024 rows per workgroup); PHASE as in grad_tile.
-template <int PHASE, bool SNAP>
-__device__ __forceinline__ void grad_tile_otf(const GradArgs& A, const TileDesc& d,
-                                              float (*red)[NW][TJ], float* ylds) {
-  const InstDev I = A.inst[d.inst];
+// lane value of row r (0..31) of a 32-row block whose values sit one per lane
+// in lanes 0..31 (and again in 32..63): element q of the MFMA layout needs row
+// 8 (q / 4) + (q % 4) in lanes 0..31 and that row + 4 in lanes 32..63.
+__device__ __forceinline__ float otf_row_value(float v, int q, int h) {
+  const int r = 8 * (q / 4) + (q % 4);
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), r));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), r + 4));
+  return h ? b : a;
+}
+
+// Gradient tiles with the cost computed on matrix cores.  A team of WT
+// wavefronts takes one entry of the work list; each wavefront covers up to
+// BPW 32-row blocks of its tile (its p values stay in registers), so a team
+// holds 32 BPW WT rows (tiles are bucketed by group size to fit; larger
+// groups are cut in chunks of CHUNK = 64 NW rows, WT = NW, BPW = 2).  A
+// workgroup holds K = NWV / WT teams, NWV = max(WT, 4) wavefronts.  PHASE as
+// in grad_tile: 0 whole group, 1 chunk column partials, 2 chunk row sums (only
+// tiles with a nonzero kappa recompute their cost).
+template <int WT>
+constexpr int otf_waves() { return WT < 4 ? 4 : WT; }
+
+template <int WT, int BPW, int PHASE, bool SNAP>
+__global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1) ? 8 : 1)
+    k_grad_tiles_otf(GradArgs A) {
+  constexpr int NWV = otf_waves<WT>();
+  constexpr int K = NWV / WT;
+  constexpr bool snap = SNAP && PHASE != 2;
+  __shared__ float red[3][NWV][TJ];
+  const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gs = A.g_start[I.grp_off + d.grp];
-  const int gn = A.g_size[I.grp_off + d.grp];
-  int r0 = 0, r1 = gn;
-  if (PHASE != 0) {
-    r0 = d.aux * CHUNK;
-    r1 = min(r0 + CHUNK, gn);
-  }
-  const int col = d.jb * TJ + c;
-  const bool colok = col < I.nt;
-  const float bj = A.beta[I.col_off + col];
-  const float ynj = A.yn[I.col_off + col];
-  constexpr bool snap = SNAP && PHASE != 2;
-  otf_stage_y(A, I, d.jb, ylds);
-  __syncthreads();
+  const int team = w / WT, v = w % WT;
+  for (int t0 = blockIdx.x * K; t0 < n; t0 += gridDim.x * K) {
+    const int t = t0 + team;
+    TileDesc d{0, 0, 0, 0};
+    bool act = t < n;
+    if (act) {
+      d = A.list[t];
+      act = PHASE == 2 || (A.inst_mode[d.inst] == EM_SNAPSHOT) == SNAP;
+    }
+    const InstDev I = A.inst[d.inst];
+    const int gs = A.g_start[I.grp_off + d.grp];
+    const int gn = A.g_size[I.grp_off + d.grp];
+    int r0 = 0, r1 = gn;
+    if (PHASE != 0) {
+      r0 = d.aux * CHUNK;
+      r1 = min(r0 + CHUNK, gn);
+    }
+    const int col = d.jb * TJ + c;
+    const bool colok = col < I.nt;
+    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+    const float* xg = A.Xp + I.x_off + (size_t)A.g_xblk[I.grp_off + d.grp] * 32 * I.dp;
+    const float* yb = A.Yp + I.y_off + (size_t)d.jb * 32 * I.dp;
 
-  float p[2][16];
-  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
+    float kap = 0.f;
+    bool anyk = true;
+    if (PHASE == 2 && act) {
+      kap = A.kappa[pr];
+      anyk = __ballot(kap > 0.f) != 0ull;
+    }
+    float p[BPW][16];
+    float z2 = 0.f, s1 = 0.f, o2 = 0.f;
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int rb = w + NW * b;          // 32-row block of this chunk
-    const int i0 = r0 + 32 * rb;        // first row, relative to the group
+    for (int b = 0; b < BPW; ++b) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) p[b][q] = 0.f;
-    if (i0 >= r1) continue;             // wave-uniform
-    const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
-    const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
-    const bool rowin = i0 + c < r1;
-    const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;   // lane c: row i0 + c
-    const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
+      for (int q = 0; q < 16; ++q) p[b][q] = 0.f;
+      const int i0 = r0 + 32 * (v + WT * b);   // first row of the block, in the group
+      if (!act || i0 >= r1 || !anyk) continue;  // wave-uniform
+      const floatx16 acc = otf_dot_block<PHASE != 1>(xg + (size_t)(i0 / 32) * 32 * I.dp, yb, I.dp, lane);
+      const bool rowin = i0 + c < r1;
+      const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;
+      const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
+      const float bj = A.beta[I.col_off + col];
+      const float ynj = A.yn[I.col_off + col];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int rr0 = 8 * (q / 4) + (q % 4);   // row within the block for h = 0; +4 for h = 1
-      const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0));
-      const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0 + 4));
-      const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
-      const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
-      const float ai = h ? a1 : a0, xi = h ? x1 : x0;
-      const float C = otf_cost(xi, ynj, acc[q], I.cscale);
-      const float f = (ai + bj) - C;
-      const bool ok = (i0 + rr0 + 4 * h < r1) && colok;
-      const float pk = ok ? fmaxf(f, 0.f) : 0.f;
-      if (PHASE != 2) {
-        z2 = fmaf(pk, pk, z2);
-        s1 += pk;
-        if (snap) {
-          const float nkv = ok ? fminf(f, 0.f) : 0.f;
-          o2 = fmaf(nkv, nkv, o2);
+      for (int q = 0; q < 16; ++q) {
+        const int rr = 8 * (q / 4) + (q % 4) + 4 * h;
+        const float C = otf_cost(otf_row_value(xv, q, h), ynj, acc[q], I.cscale);
+        const float f = (otf_row_value(av, q, h) + bj) - C;
+        const bool ok = (i0 + rr < r1) && colok;
+        const float pk = ok ? fmaxf(f, 0.f) : 0.f;
+        if (PHASE != 2) {
+          z2 = fmaf(pk, pk, z2);
+          s1 += pk;
+          if (snap) {
+            const float nkv = ok ? fminf(f, 0.f) : 0.f;
+            o2 = fmaf(nkv, nkv, o2);
+          }
+        }
+        p[b][q] = pk;
+      }
+    }
+
+    if (PHASE != 2) {
+      z2 += __shfl_xor(z2, 32);
+      s1 += __shfl_xor(s1, 32);
+      if (snap) o2 += __shfl_xor(o2, 32);
+      if (act && h == 0) {
+        red[0][w][c] = z2;
+        red[1][w][c] = s1;
+        if (snap) red[2][w][c] = o2;
+      }
+      __syncthreads();
+      if (act) {
+        float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+#pragma unroll
+        for (int u = 0; u < WT; ++u) {
+          Z2 += red[0][team * WT + u][c];
+          S1 += red[1][team * WT + u][c];
+          if (snap) O2 += red[2][team * WT + u][c];
+        }
+        if (PHASE == 1) {
+          if (v == 0 && h == 0) {
+            const long long qq = I.chunk_off +
+                                 (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
+            A.part[qq] = Z2;
+            A.part[qq + A.part_stride] = S1;
+            A.part[qq + 2 * A.part_stride] = O2;
+          }
+        } else {
+          const float z = sqrtf(Z2);
+          float num = 0.f;
+          if (z > I.thr) {
+            num = z - I.thr;
+            kap = num / (I.gamma * z);
+          }
+          if (v == 0 && h == 0) {
+            A.colsum[pr] = kap * S1;
+            A.excess[pr] = num;
+            if (A.write_kappa) A.kappa[pr] = kap;
+            if (snap) {
+              A.zsnap[pr] = z;
+              A.osnap[pr] = sqrtf(O2);
+            }
+          }
+          anyk = __ballot(kap > 0.f) != 0ull;
         }
       }
-      p[b][q] = pk;
     }
-  }
 
-  float kap = 0.f;
-  if (PHASE != 2) {
-    z2 += __shfl_xor(z2, 32);
-    s1 += __shfl_xor(s1, 32);
-    if (snap) o2 += __shfl_xor(o2, 32);
-    if (h == 0) {
-      red[0][w][c] = z2;
-      red[1][w][c] = s1;
-      if (snap) red[2][w][c] = o2;
-    }
-    __syncthreads();
-    float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
-#pragma unroll 4
-    for (int v = 0; v < NW; ++v) {
-      Z2 += red[0][v][c];
-      S1 += red[1][v][c];
-    }
-    if (snap) {
-#pragma unroll 4
-      for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
-    }
-    if (PHASE == 1) {
-      if (w == 0 && h == 0) {
-        const long long qq = I.chunk_off +
-                             (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
-        A.part[qq] = Z2;
-        A.part[qq + A.part_stride] = S1;
-        A.part[qq + 2 * A.part_stride] = O2;
-      }
-      return;
-    }
-    const float z = sqrtf(Z2);
-    float num = 0.f;
-    if (z > I.thr) {
-      num = z - I.thr;
-      kap = num / (I.gamma * z);
-    }
-    if (w == 0 && h == 0) {
-      const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
-      A.colsum[pr] = kap * S1;
-      A.excess[pr] = num;
-      if (A.write_kappa) A.kappa[pr] = kap;
-      if (snap) {
-        A.zsnap[pr] = z;
-        A.osnap[pr] = sqrtf(O2);
+    if (PHASE != 1 && act) {
+      float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
+      const int Q = lane >> 4;
+#pragma unroll
+      for (int b = 0; b < BPW; ++b) {
+        const int i0 = r0 + 32 * (v + WT * b);
+        if (i0 >= r1) continue;
+        if (!anyk) {
+          if (lane < 32 && i0 + lane < r1) rp[i0 + lane] = 0.f;
+          continue;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          // rows of elements 2m and 2m + 1, both halves: after the swap and
+          // the row-16 sums, lane 16 Q + 15 holds row 8 (qs / 4) + qs % 4 + 4 (Q / 2)
+          // with qs = 2m + Q % 2
+          const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(kap * p[b][2 * m]),
+                                                           __float_as_uint(kap * p[b][2 * m + 1]), false, false);
+          const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+          const int qs = 2 * m + (Q & 1);
+          const int row = i0 + 8 * (qs / 4) + (qs % 4) + 4 * (Q >> 1);
+          if ((lane & 15) == 15 && row < r1) rp[row] = x;
+        }
       }
     }
-  } else {
-    kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
-  }
-
-  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
-  const bool anyk = __ballot(kap > 0.f) != 0ull;
-  const int Q = lane >> 4;
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const int i0 = r0 + 32 * (w + NW * b);
-    if (i0 >= r1) continue;
-    if (!anyk) {
-      if (lane < 32 && i0 + lane < r1) rp[i0 + lane] = 0.f;
-      continue;
-    }
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      // rows of elements qa = 2m and qb = 2m + 1 (both parities)
-      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(kap * p[b][2 * m]),
-                                                       __float_as_uint(kap * p[b][2 * m + 1]), false, false);
-      const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
-      const int qsel = 2 * m + (Q & 1);
-      const int row = i0 + 8 * (qsel / 4) + (qsel % 4) + 4 * (Q >> 1);
-      if ((lane & 15) == 15 && row < r1) rp[row] = x;
-    }
-  }
-}
-
-template <int PHASE, bool SNAP>
-__global__ void __launch_bounds__(BLOCK) k_grad_tiles_otf(GradArgs A) {
-  __shared__ float red[3][NW][TJ];
-  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
-  const int n = *A.count;
-  for (int t = blockIdx.x; t < n; t += gridDim.x) {
-    const TileDesc d = A.list[t];
-    if ((A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
-    grad_tile_otf<PHASE, SNAP>(A, d, red, ylds);
     __syncthreads();
   }
 }
@@ -734,7 +768,6 @@ __global__ void __launch_bounds__(BLOCK) k_otf_setup(GradArgs A, int n, const fl
                                                      const float* __restrict__ ynnat,
                                                      float* __restrict__ colmin,
                                                      unsigned int* __restrict__ maxbits) {
-  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
   __shared__ float red[NW][TJ];
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
@@ -744,25 +777,18 @@ __global__ void __launch_bounds__(BLOCK) k_otf_setup(GradArgs A, int n, const fl
     const InstDev I = A.inst[d.inst];
     const int gs = A.g_start[I.grp_off + d.grp];
     const int gn = A.g_size[I.grp_off + d.grp];
-    {
-      const float4* src = (const float4*)(Ynat + I.y_off + (size_t)d.jb * 32 * I.dp);
-      float4* dst = (float4*)ylds;
-      for (int i = threadIdx.x; i < 8 * I.dp; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
+    const float* yb = Ynat + I.y_off + (size_t)d.jb * 32 * I.dp;
     const int col = d.jb * TJ + c;
     const float ynj = ynnat[I.col_off + col];
     float mn = INFINITY, mx = 0.f;
     for (int i0 = 32 * w; i0 < gn; i0 += 32 * NW) {
       const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
-      const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
+      const floatx16 acc = otf_dot_block(xblk, yb, I.dp, lane);
       const float xv = (i0 + c < gn) ? A.xn[I.row_off + gs + i0 + c] : 0.f;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int rr0 = 8 * (q / 4) + (q % 4);
-        const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
-        const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
-        const float u = (( h ? x1 : x0) + ynj) - 2.f * acc[q];
+        const float u = (otf_row_value(xv, q, h) + ynj) - 2.f * acc[q];
         if (i0 + rr0 + 4 * h < gn && col < I.nt) {
           mn = fminf(mn, u);
           mx = fmaxf(mx, u);
@@ -793,7 +819,6 @@ __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int
                                                     const int* __restrict__ perm_col,
                                                     const long long* __restrict__ t_off,
                                                     float* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) float ylds[32 * DP_MAX];
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = threadIdx.x >> 6;
@@ -802,8 +827,7 @@ __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int
     const InstDev I = A.inst[d.inst];
     const int gs = A.g_start[I.grp_off + d.grp];
     const int gn = A.g_size[I.grp_off + d.grp];
-    otf_stage_y(A, I, d.jb, ylds);
-    __syncthreads();
+    const float* yb = A.Yp + I.y_off + (size_t)d.jb * 32 * I.dp;
     const int col = d.jb * TJ + c;
     const bool colok = col < I.nt;
     const float ynj = A.yn[I.col_off + col];
@@ -813,7 +837,7 @@ __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int
     float* o = out + t_off[d.inst];
     for (int i0 = 32 * w; i0 < gn; i0 += 32 * NW) {
       const float* xblk = A.Xp + I.x_off + ((size_t)A.g_xblk[I.grp_off + d.grp] + i0 / 32) * 32 * I.dp;
-      const floatx16 acc = otf_dot_block(xblk, ylds, I.dp, lane);
+      const floatx16 acc = otf_dot_block(xblk, yb, I.dp, lane);
       const bool rowin = i0 + c < gn;
       const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
       const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;
@@ -821,17 +845,12 @@ __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int rr0 = 8 * (q / 4) + (q % 4);
-        const float x0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0));
-        const float x1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xv), rr0 + 4));
-        const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0));
-        const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), rr0 + 4));
-        const int p0 = __builtin_amdgcn_readlane(pv, rr0), p1 = __builtin_amdgcn_readlane(pv, rr0 + 4);
-        const float C = otf_cost(h ? x1 : x0, ynj, acc[q], I.cscale);
-        const float v = MODE ? kap * fmaxf(((h ? a1 : a0) + bj) - C, 0.f) : C;
-        if (i0 + rr0 + 4 * h < gn && colok) o[(size_t)(h ? p1 : p0) * I.nt + dcol] = v;
+        const int prow = __float_as_int(otf_row_value(__int_as_float(pv), q, h));
+        const float C = otf_cost(otf_row_value(xv, q, h), ynj, acc[q], I.cscale);
+        const float v = MODE ? kap * fmaxf((otf_row_value(av, q, h) + bj) - C, 0.f) : C;
+        if (i0 + rr0 + 4 * h < gn && colok) o[(size_t)prow * I.nt + dcol] = v;
       }
     }
-    __syncthreads();
   }
 }
 

@@ -101,4 +101,14 @@ __host__ __device__ inline int row_bucket(int rows) {
   return r <= RSTEP ? 0 : (r + RSTEP - 1) / RSTEP - 1;
 }
 
+// on-the-fly tiles: bucket b < 5 holds whole groups of up to 32 << b rows,
+// one per team of 1 << b wavefronts with one 32-row block each; bucket 5
+// groups of up to 1024 rows, teams of 16 wavefronts with two blocks each
+constexpr int OTF_NBUCKET = 6;
+__host__ __device__ inline int otf_bucket(int rows) {
+  int b = 0;
+  while (b < 5 && rows > (32 << b)) ++b;
+  return b;
+}
+
 }  // namespace otgs

@@ -131,16 +131,20 @@ def test_batch_is_bitwise_equal_to_single_instances():
         ob += P.nt
 
 
-def test_screened_is_bitwise_equal_to_dense():
+@pytest.mark.parametrize("n_src,n_groups", [(1200, 6), (2600, 2)])   # (2600, 2): split groups
+def test_screened_is_bitwise_equal_to_dense(n_src, n_groups):
     """Theorem 2 on the device: after a snapshot, screened evaluations at
-    nearby points reproduce the dense ones exactly, and skip tiles."""
+    nearby points reproduce the dense ones exactly, and skip tiles.  The
+    snapshot evaluation itself (first call on a fresh handle) matches the
+    oracle."""
     O = _otgs()
-    inst = synth.blobs(seed=11, n_src=1200, n_tgt=900, d=8, n_groups=6, gamma=0.1, mu=0.5)
+    inst = synth.blobs(seed=11, n_src=n_src, n_tgt=900, d=8, n_groups=n_groups, gamma=0.1, mu=0.5)
     C32, P = cases.with_cost(inst)
     h = make_handle(C32, P)
     r = oracle.solve(P, max_iter=60)
     base_a, base_b = r["alpha"].astype(np.float32), r["beta"].astype(np.float32)
-    gpu_grad(h, base_a, base_b, mode=O.OT_GS_SNAPSHOT)
+    snap = gpu_grad(h, base_a, base_b, mode=O.OT_GS_SNAPSHOT)
+    check_parity(P, base_a, base_b, *snap[:2], snap[2][0])
     h.stats(reset=True)
     rng = np.random.default_rng(0)
     for k in range(6):
@@ -155,6 +159,21 @@ def test_screened_is_bitwise_equal_to_dense():
     st = h.stats()
     assert st["tiles_computed"] < st["tiles_total"]
     assert st["pairs_checked"] > 0
+
+
+def test_modes_after_an_evaluation_elsewhere():
+    """Each mode recomputes every partial it uses: after an evaluation at
+    another point, SNAPSHOT, SCREENED and DENSE at a new point agree with the
+    oracle there (split groups included)."""
+    O = _otgs()
+    inst = cases.ragged(41, 2900, 150, [1500, 1100, 300])
+    C32, P = cases.with_cost(inst)
+    h = make_handle(C32, P)
+    pts = trajectory_points(P, [5, 15, 16])
+    gpu_grad(h, *pts[0], mode=O.OT_GS_DENSE)
+    for mode, (a32, b32) in ((O.OT_GS_SNAPSHOT, pts[1]), (O.OT_GS_SCREENED, pts[2]), (O.OT_GS_DENSE, pts[1])):
+        ga, gb, D = gpu_grad(h, a32, b32, mode=mode)
+        check_parity(P, a32, b32, ga, gb, D[0])
 
 
 def test_plan_matches_oracle():

@@ -219,3 +219,20 @@ def test_onthefly_argument_errors():
     nan = dict(good, x_src=_dev(np.full((20, 8), np.nan, np.float32)))
     with pytest.raises(O.OTGSError):
         O.Handle([nan])
+
+
+def test_onthefly_screened_trajectory_is_dense_trajectory():
+    """Every bucket (groups of 32 to over 1024 rows): the screened solve
+    takes bit for bit the dense solve's steps."""
+    inst = synth.zipf_blobs(seed=33, n_src=6000, n_tgt=1500, d=64, n_groups=30, gamma=0.05, mu=0.5)
+    h = otf_handle(inst, 0.0)
+    K = 150
+    traces = []
+    for scr in (0, 1):
+        tr = torch.full((K + 1,), float("nan"), dtype=torch.float64, device="cuda")
+        a, b, info, _ = h.solve(max_iter=K, use_screen=scr, obj_trace=tr)
+        torch.cuda.synchronize()
+        traces.append((tr.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy(), info[0]))
+    np.testing.assert_array_equal(traces[0][0], traces[1][0])
+    np.testing.assert_array_equal(traces[0][1], traces[1][1])
+    np.testing.assert_array_equal(traces[0][2], traces[1][2])

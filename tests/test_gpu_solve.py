@@ -61,8 +61,9 @@ def test_solve_small_matches_oracle_optimum():
     assert np.all(np.diff(t) >= -1e-12 * abs(t[-1]))
 
 
-def test_screened_trajectory_is_bitwise_dense():
-    inst = synth.blobs(seed=12, n_src=800, n_tgt=700, d=8, n_groups=5, gamma=0.1, mu=0.3)
+@pytest.mark.parametrize("n_src,n_groups", [(800, 5), (2600, 2)])   # (2600, 2): split groups
+def test_screened_trajectory_is_bitwise_dense(n_src, n_groups):
+    inst = synth.blobs(seed=12, n_src=n_src, n_tgt=700, d=8, n_groups=n_groups, gamma=0.1, mu=0.3)
     C32, P = cases.with_cost(inst)
     h = handle_for(C32, P)
     ad, bd, infod, trd, _ = run(h, 120, use_screen=0)
