@@ -219,6 +219,81 @@ int ot_gs_profile_tiles(ot_gs_handle *h, int repeats, double *us_per_launch, voi
 int ot_gs_layout_info(ot_gs_handle *h, int k, int *n_groups_nonempty,
                       int *n_tgt_padded, int *n_tiles);
 
+/* ------------------------------------------------------------ warm start
+ *
+ * Not part of the paper's method (Algorithm 1 starts from zero duals): a
+ * network that predicts a starting point (alpha, beta) from per-sample
+ * features, trained on converged duals of the plain solver.  Any starting
+ * point leads the solver to the same optimum (Eq. 4 is concave); a good one
+ * saves iterations.  ot_gs_solve with init_user = 1 takes the prediction and
+ * makes its first evaluation a snapshot (Algorithm 1's snapshot must be
+ * exact at the start).
+ *
+ * Features (dim + 8 per sample, float32): the feature vector times
+ * sqrt(cost_scale); the squared distance (times cost_scale) to the sample's
+ * own centroid (a source's class centroid; a target's pseudo-class centroid,
+ * the pseudo-class being the class of its nearest source centroid); the
+ * least squared distance (times cost_scale) to the other side's centroids;
+ * the fraction of its side in its (pseudo-)class; side (0 source, 1
+ * target); log gamma; log max(mu, 1e-8); log n_src; log n_tgt.
+ *
+ * Network: Linear(d_in, w) - GELU - Linear(w, w) - GELU - Linear(w, 1),
+ * GELU(z) = z Phi(z) (exact normal CDF).  The three products run on bf16
+ * matrix cores: their operands are rounded to bfloat16 (nearest even),
+ * accumulation and all other arithmetic is float32.  Parameters form one
+ * float32 vector: W1 [d_in x w] row-major (row = input), b1 [w],
+ * W2 [w x w], b2 [w], w3 [w], b3 [1].  Training minimises the mean squared
+ * error with Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+typedef struct ot_gs_mlp ot_gs_mlp;
+
+/* Network for d_in inputs and width w; buffers for up to max_rows rows per
+ * product (inference and training batches).  Parameters start at zero; set
+ * them with ot_gs_mlp_set_params.  Errors: OT_GS_EINVAL, OT_GS_ENOMEM. */
+int ot_gs_mlp_create(int d_in, int width, int max_rows, ot_gs_mlp **out /* host */);
+void ot_gs_mlp_destroy(ot_gs_mlp *m);
+int ot_gs_mlp_n_params(const ot_gs_mlp *m);
+
+/* Copies the parameter vector in (and resets the Adam moments) or out;
+ * params: device [n_params]. */
+int ot_gs_mlp_set_params(ot_gs_mlp *m, const float *params, void *stream);
+int ot_gs_mlp_get_params(ot_gs_mlp *m, float *params, void *stream);
+
+/* out[i] = network(F[i, :]) for n_rows rows of F (device, row-major
+ * [n_rows x d_in]); out: device [n_rows]. */
+int ot_gs_mlp_forward(ot_gs_mlp *m, const float *F, long long n_rows, float *out, void *stream);
+
+/* Mean squared error of the network on rows F, targets y (device
+ * [n_rows], 1 <= n_rows <= max_rows): loss (device float64, may be NULL)
+ * and its gradient (device [n_params], same layout as the parameters, may
+ * be NULL). */
+int ot_gs_mlp_loss_grad(ot_gs_mlp *m, const float *F, const float *y, int n_rows, double *loss,
+                        float *grad, void *stream);
+
+/* `epochs` passes over consecutive batches of `batch` rows of (F, y), one
+ * Adam step (learning rate lr) per batch; the caller shuffles the rows.
+ * loss_trace: optional device float64 [epochs * ceil(n_rows / batch)], the
+ * loss of every batch before its step. */
+int ot_gs_mlp_train(ot_gs_mlp *m, const float *F, const float *y, long long n_rows, int batch,
+                    int epochs, float lr, double *loss_trace, void *stream);
+
+/* Features of `count` instances (probs as for ot_gs_create, with x_src,
+ * x_tgt and one common dim) into F (device, [sum n_src + sum n_tgt] x
+ * (dim + 8)): the sources of every instance in order, then the targets.
+ * scales: host [count], the cost scale of each instance (see
+ * ot_gs_cost_scale).  Synchronises `stream`. */
+int ot_gs_features(const ot_gs_problem *probs, int count, const float *scales, float *F, void *stream);
+
+/* The cost scale each instance of a handle uses (host out [count]). */
+int ot_gs_cost_scale(ot_gs_handle *h, float *scales);
+
+/* Predicted starting point of every instance of h: features of probs (the
+ * problems h was created from; they need x_src and x_tgt) through the
+ * network; alpha_out [sum n_src], beta_out [sum n_tgt] (device).  Errors:
+ * OT_GS_EINVAL (NULL, network input size), OT_GS_ESHAPE (probs do not match
+ * h), OT_GS_ENOMEM, OT_GS_EDEVICE.  Synchronises `stream`. */
+int ot_gs_warm_start(ot_gs_handle *h, ot_gs_mlp *m, const ot_gs_problem *probs, float *alpha_out,
+                     float *beta_out, void *stream);
+
 const char *ot_gs_last_error(void);
 const char *ot_gs_version(void);
 

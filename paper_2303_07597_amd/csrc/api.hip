@@ -594,6 +594,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
         sc = (float)(1.0 / (double)cmax);
       }
       hscale[k] = sc;
+      h->inst[k].d.cscale = sc;
       const float cm = cmax * sc;   // rounding is monotone: max of the scaled cost
       if (!std::isfinite(cm)) return fail(OT_GS_ENUMERIC, "instance %d: scaled cost overflows", k);
       h->inst[k].d.cmax = cm;

@@ -536,8 +536,6 @@ __global__ void __launch_bounds__(256) k_cost_dump(const InstDev* __restrict__ i
 
 // ---------------------------------------------------------------- on-the-fly cost
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
 // x_i . y_j for the 32 rows of a packed source block and the 32 columns of a
 // packed target block, on v_mfma_f32_32x32x2f32 (two dims per instruction,
 // dims in increasing order).  Both operands come from global memory, 1 KB

@@ -5,3 +5,5 @@
 #include "screen.hip"
 #include "lbfgs.hip"
 #include "api.hip"
+#include "mlp.hip"
+#include "api_ws.hip"

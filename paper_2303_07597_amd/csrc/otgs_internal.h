@@ -30,6 +30,8 @@ constexpr int NBUCKET = RMAX / RSTEP;  // 8
 constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
 constexpr int DP_MAX = 256;            // on-the-fly cost: padded feature dims
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));   // 32 x 32 matrix-core accumulator
+
 struct InstDev {
   int ns, nt, nt_pad, njb;
   int L;          // label range

@@ -88,6 +88,18 @@ def _load():
     lib.ot_gs_kernel_time.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(ct.c_longlong)]
     lib.ot_gs_profile_tiles.argtypes = [vp, i, ct.POINTER(d), vp]
     lib.ot_gs_layout_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
+    lib.ot_gs_mlp_create.argtypes = [i, i, i, ct.POINTER(vp)]
+    lib.ot_gs_mlp_destroy.argtypes = [vp]
+    lib.ot_gs_mlp_destroy.restype = None
+    lib.ot_gs_mlp_n_params.argtypes = [vp]
+    lib.ot_gs_mlp_set_params.argtypes = [vp, vp, vp]
+    lib.ot_gs_mlp_get_params.argtypes = [vp, vp, vp]
+    lib.ot_gs_mlp_forward.argtypes = [vp, vp, ct.c_longlong, vp, vp]
+    lib.ot_gs_mlp_loss_grad.argtypes = [vp, vp, vp, i, vp, vp, vp]
+    lib.ot_gs_mlp_train.argtypes = [vp, vp, vp, ct.c_longlong, i, i, ct.c_float, vp, vp]
+    lib.ot_gs_features.argtypes = [ct.POINTER(ot_gs_problem), i, ct.POINTER(ct.c_float), vp, vp]
+    lib.ot_gs_cost_scale.argtypes = [vp, ct.POINTER(ct.c_float)]
+    lib.ot_gs_warm_start.argtypes = [vp, vp, ct.POINTER(ot_gs_problem), vp, vp, vp]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
     return lib
@@ -141,6 +153,81 @@ def ot_gs_rho_to_mu(gamma, rho):
     return g.value, m.value
 
 
+def problem_array(problems):
+    """ctypes array of ot_gs_problem for a list of problem dicts (see Handle)."""
+    n = len(problems)
+    arr = (ot_gs_problem * n)()
+    n_src, n_tgt = [], []
+    for k, p in enumerate(problems):
+        labels = p["labels"]
+        mode = p.get("cost_mode", OT_GS_COST_GIVEN if p.get("cost") is not None else OT_GS_COST_MATERIALIZE)
+        ns = int(labels.numel())
+        nt = int(p["cost"].shape[1]) if p.get("cost") is not None else int(p["x_tgt"].shape[0])
+        dim = int(p["x_src"].shape[1]) if p.get("x_src") is not None else 0
+        arr[k] = ot_gs_problem(ns, nt, dim, int(p["n_groups"]), _ptr(labels), mode,
+                               _ptr(p.get("cost")), _ptr(p.get("x_src")), _ptr(p.get("x_tgt")),
+                               float(p.get("cost_scale", 0.0)), _ptr(p.get("a")), _ptr(p.get("b")),
+                               float(p["gamma"]), float(p["mu"]))
+        n_src.append(ns)
+        n_tgt.append(nt)
+    return arr, n_src, n_tgt
+
+
+def features(problems, scales, F, stream=None):
+    """Warm-start features of the problems into F (float32 cuda
+    [sum n_src + sum n_tgt, dim + 8]); scales: per-instance cost scales."""
+    arr, _, _ = problem_array(problems)
+    sc = (ct.c_float * len(problems))(*[float(x) for x in scales])
+    _check(lib().ot_gs_features(arr, len(problems), sc, _ptr(F), _stream(stream)))
+
+
+class Mlp:
+    """Owner of an ``ot_gs_mlp`` (warm-start network)."""
+
+    def __init__(self, d_in, width=256, max_rows=65536):
+        m = ct.c_void_p()
+        _check(lib().ot_gs_mlp_create(int(d_in), int(width), int(max_rows), ct.byref(m)))
+        self.m = m
+        self.d_in, self.width, self.max_rows = d_in, width, max_rows
+        self.n_params = lib().ot_gs_mlp_n_params(m)
+
+    def close(self):
+        if getattr(self, "m", None):
+            lib().ot_gs_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p, stream=None):
+        _check(lib().ot_gs_mlp_set_params(self.m, _ptr(p), _stream(stream)))
+
+    def get_params(self, stream=None):
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().ot_gs_mlp_get_params(self.m, _ptr(p), _stream(stream)))
+        return p
+
+    def forward(self, F, out=None, stream=None):
+        if out is None:
+            out = torch.empty(F.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().ot_gs_mlp_forward(self.m, _ptr(F), int(F.shape[0]), _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, F, y, stream=None):
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().ot_gs_mlp_loss_grad(self.m, _ptr(F), _ptr(y), int(F.shape[0]), _ptr(loss), _ptr(g),
+                                         _stream(stream)))
+        return loss, g
+
+    def train(self, F, y, batch, epochs, lr, loss_trace=None, stream=None):
+        _check(lib().ot_gs_mlp_train(self.m, _ptr(F), _ptr(y), int(F.shape[0]), int(batch), int(epochs),
+                                     float(lr), _ptr(loss_trace), _stream(stream)))
+
+
 class Handle:
     """Owner of an ``ot_gs_handle``.  ``problems`` is a list of dicts with keys
     labels (int32 cuda), n_groups, gamma, mu and either cost (float32 cuda
@@ -150,24 +237,8 @@ class Handle:
     def __init__(self, problems, stream=None):
         if isinstance(problems, dict):
             problems = [problems]
+        arr, self.n_src, self.n_tgt = problem_array(problems)
         n = len(problems)
-        arr = (ot_gs_problem * n)()
-        self.n_src, self.n_tgt = [], []
-        for k, p in enumerate(problems):
-            labels = p["labels"]
-            mode = p.get("cost_mode", OT_GS_COST_GIVEN if p.get("cost") is not None else OT_GS_COST_MATERIALIZE)
-            ns = int(labels.numel())
-            if p.get("cost") is not None:
-                nt = int(p["cost"].shape[1])
-            else:
-                nt = int(p["x_tgt"].shape[0])
-            dim = int(p["x_src"].shape[1]) if p.get("x_src") is not None else 0
-            arr[k] = ot_gs_problem(ns, nt, dim, int(p["n_groups"]), _ptr(labels), mode,
-                                   _ptr(p.get("cost")), _ptr(p.get("x_src")), _ptr(p.get("x_tgt")),
-                                   float(p.get("cost_scale", 0.0)), _ptr(p.get("a")), _ptr(p.get("b")),
-                                   float(p["gamma"]), float(p["mu"]))
-            self.n_src.append(ns)
-            self.n_tgt.append(nt)
         h = ct.c_void_p()
         _check(lib().ot_gs_create(arr, n, ct.byref(h), _stream(stream)))
         self.h = h
@@ -232,6 +303,19 @@ class Handle:
         _check(lib().ot_gs_profile_tiles(self.h, int(repeats), ct.byref(us), _stream(stream)))
         return us.value
 
+    def cost_scale(self):
+        sc = (ct.c_float * self.count)()
+        _check(lib().ot_gs_cost_scale(self.h, sc))
+        return [float(x) for x in sc]
+
+    def warm_start(self, mlp, problems, stream=None):
+        """Predicted starting point (alpha, beta) of every instance."""
+        arr, _, _ = problem_array(problems)
+        alpha = torch.empty(sum(self.n_src), dtype=torch.float32, device="cuda")
+        beta = torch.empty(sum(self.n_tgt), dtype=torch.float32, device="cuda")
+        _check(lib().ot_gs_warm_start(self.h, mlp.m, arr, _ptr(alpha), _ptr(beta), _stream(stream)))
+        return alpha, beta
+
     def layout_info(self, k=0):
         g, tp, nt = ct.c_int(), ct.c_int(), ct.c_int()
         _check(lib().ot_gs_layout_info(self.h, k, ct.byref(g), ct.byref(tp), ct.byref(nt)))
@@ -242,4 +326,7 @@ EXPORTED = [
     "ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_default_options",
     "ot_gs_plan", "ot_gs_cost", "ot_gs_rho_to_mu", "ot_gs_get_stats", "ot_gs_kernel_timing", "ot_gs_kernel_time",
     "ot_gs_layout_info", "ot_gs_last_error", "ot_gs_version", "ot_gs_profile_tiles",
+    "ot_gs_mlp_create", "ot_gs_mlp_destroy", "ot_gs_mlp_n_params", "ot_gs_mlp_set_params",
+    "ot_gs_mlp_get_params", "ot_gs_mlp_forward", "ot_gs_mlp_loss_grad", "ot_gs_mlp_train",
+    "ot_gs_features", "ot_gs_cost_scale", "ot_gs_warm_start",
 ]
