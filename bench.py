@@ -44,6 +44,13 @@ def parse():
                     help="omit the on-the-fly (matrix-core cost) workload")
     ap.add_argument("--otf-n", type=int, default=32768, help="on-the-fly workload: n_src = n_tgt")
     ap.add_argument("--otf-iters", type=int, default=500, help="on-the-fly workload: L-BFGS iterations")
+    ap.add_argument("--skip-batched", action="store_true", help="omit the 256-instance batched workload")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--skip-warmstart", action="store_true", help="omit the learned warm-start workload")
+    ap.add_argument("--ws-train", type=int, default=2048, help="training instances (cold solves)")
+    ap.add_argument("--ws-held", type=int, default=256, help="held-out instances")
+    ap.add_argument("--ws-epochs", type=int, default=30)
+    ap.add_argument("--ws-save", default=None, help="write the trained network parameters (.npy) here")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (traffic counter calibration)")
     return ap.parse_args()
@@ -143,6 +150,181 @@ def bench_onthefly(args, torch, synth, O):
         out["solve"] = runs
     h.close()
     return out
+
+
+def _trace_hits(tr, tt, dstar, tol=1e-6):
+    """Per instance: first iteration within tol of D* and its device time (s)."""
+    its, ts = [], []
+    for k in range(tr.shape[0]):
+        rel = (dstar[k] - tr[k]) / abs(dstar[k])
+        hit = np.nonzero(rel <= tol)[0]
+        if hit.size:
+            its.append(int(hit[0]))
+            ts.append((tt[k, hit[0]] - tt[k, 0]) / 100e6)
+        else:
+            its.append(None)
+            ts.append(None)
+    return its, ts
+
+
+def _solve_traced(h, count, K, torch, **kw):
+    dev = torch.device("cuda")
+    tr = torch.full((count * (K + 1),), float("nan"), dtype=torch.float64, device=dev)
+    tt = torch.zeros(count * (K + 1), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, info, _ = h.solve(max_iter=K, obj_trace=tr, time_trace=tt, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return (a, b, info, tr.cpu().numpy().reshape(count, K + 1), tt.cpu().numpy().reshape(count, K + 1), wall)
+
+
+def _problems(insts, torch, O):
+    dev = torch.device("cuda")
+    return [dict(labels=torch.from_numpy(i["labels"]).to(dev), n_groups=i["n_groups"], gamma=i["gamma"],
+                 mu=i["mu"], x_src=torch.from_numpy(i["xs"]).to(dev), x_tgt=torch.from_numpy(i["xt"]).to(dev),
+                 cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0) for i in insts]
+
+
+def bench_batched(args, torch, synth, O):
+    """256 uneven instances (n, m ~ U[64, 2048], 2-31 classes with Dirichlet
+    shares, d = 64, gamma, mu log-uniform) solved in one batched handle with
+    screening, against the same instances solved one after another, cold,
+    each in its own handle.  Time to 1e-6 relative objective for all."""
+    K = 4000
+    insts = synth.batch_instances(seed=4, count=args.batch_count)
+    probs = _problems(insts, torch, O)
+    hb = O.Handle(probs)
+    n = len(insts)
+    _, _, info, tr, tt, wall = _solve_traced(hb, n, K, torch, use_screen=1)
+    dstar = np.nanmax(tr, axis=1)
+    singles = []
+    seq_total = 0.0
+    for k in range(n):
+        h = O.Handle([probs[k]])
+        _, _, inf1, tr1, tt1, w1 = _solve_traced(h, 1, K, torch, use_screen=1)
+        h.close()
+        dstar[k] = max(dstar[k], np.nanmax(tr1[0]))
+        singles.append((tr1[0], tt1[0], w1))
+    its_b, ts_b = _trace_hits(tr, tt, dstar)
+    its_s, ts_s = [], []
+    for k, (t1, tt1, w1) in enumerate(singles):
+        i1, s1 = _trace_hits(t1[None], tt1[None], dstar[k:k + 1])
+        its_s.append(i1[0])
+        ts_s.append(s1[0])
+    ok_b = all(t is not None for t in ts_b)
+    ok_s = all(t is not None for t in ts_s)
+    t_b = max(t for t in ts_b if t is not None)
+    t_s = float(sum(t for t in ts_s if t is not None))
+    hb.close()
+    return dict(workload=f"{n} instances, n and m uniform in [64, 2048], d=64, 2-31 classes (Dirichlet shares), "
+                         "gamma in [0.05, 1], mu in [0.01, 1] log-uniform, screened",
+                all_reached_1e6=ok_b and ok_s, batched_time_to_all_1e6_s=t_b, batched_wall_s=wall,
+                sequential_time_to_1e6_sum_s=t_s, speedup=t_s / t_b,
+                batched_iters_to_1e6_median=float(np.median([i for i in its_b if i is not None])),
+                entries_per_instance_mean=float(np.mean([i["xs"].shape[0] * i["xt"].shape[0] for i in insts])))
+
+
+def bench_warmstart(args, torch, synth, O):
+    """Learned warm start: the network trained (on this GPU, by the library's
+    kernels) on gauge-fixed converged duals of `ws_train` instances of the
+    batched generator, evaluated on `ws_held` held-out instances with n, m up
+    to 4096.  Iterations and time to 1e-6 relative objective from zero and
+    from the prediction (inference included), and the final objectives."""
+    import math
+    dev = torch.device("cuda")
+    d, w = 64, 256
+    K = 4000
+    # training data: batched cold solves
+    feats, targets = [], []
+    t_data = time.perf_counter()
+    for c0 in range(0, args.ws_train, 256):
+        insts = [synth.instance_from_generator((5, i)) for i in range(c0, min(args.ws_train, c0 + 256))]
+        probs = _problems(insts, torch, O)
+        h = O.Handle(probs)
+        a, b, info, _ = h.solve(max_iter=K, use_screen=1)
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        tn = sum(i["xs"].shape[0] for i in insts)
+        tm = sum(i["xt"].shape[0] for i in insts)
+        F = torch.empty((tn + tm, d + 8), dtype=torch.float32, device=dev)
+        O.features(probs, h.cost_scale(), F)
+        ys, yt, os_, ot_ = [], [], 0, 0
+        for i in insts:
+            n, m = i["xs"].shape[0], i["xt"].shape[0]
+            al, be = a[os_:os_ + n].astype(np.float64), b[ot_:ot_ + m].astype(np.float64)
+            t = (al.mean() - be.mean()) / 2.0          # gauge: a.alpha = b.beta (uniform marginals)
+            ys.append(al - t)
+            yt.append(be + t)
+            os_ += n
+            ot_ += m
+        feats.append(F)
+        targets.append(torch.from_numpy(np.concatenate(ys + yt).astype(np.float32)).to(dev))
+        h.close()
+    F = torch.cat(feats)
+    y = torch.cat(targets)
+    t_data = time.perf_counter() - t_data
+    perm = torch.from_numpy(np.random.default_rng(5).permutation(y.numel())).to(dev)
+    F, y = F[perm].contiguous(), y[perm].contiguous()
+    batch = 4096
+    M = O.Mlp(d + 8, w, max_rows=batch)
+    r = np.random.default_rng(5)
+    p0 = np.concatenate([r.standard_normal((d + 8) * w) * math.sqrt(2.0 / (d + 8)), np.zeros(w),
+                         r.standard_normal(w * w) * math.sqrt(2.0 / w), np.zeros(w),
+                         r.standard_normal(w) * math.sqrt(1.0 / w), [0.0]]).astype(np.float32)
+    M.set_params(torch.from_numpy(p0).to(dev))
+    steps = args.ws_epochs * ((y.numel() + batch - 1) // batch)
+    ltr = torch.zeros(steps, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter()
+    M.train(F, y, batch=batch, epochs=args.ws_epochs, lr=1e-3, loss_trace=ltr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    lt = ltr.cpu().numpy()
+    if args.ws_save:
+        np.save(args.ws_save, M.get_params().cpu().numpy())
+    del F, y
+    # held-out instances
+    held = [synth.instance_from_generator((6, i), n_hi=4096) for i in range(args.ws_held)]
+    probs = _problems(held, torch, O)
+    h = O.Handle(probs)
+    n = len(held)
+    _, _, inf_c, tr_c, tt_c, wall_c = _solve_traced(h, n, K, torch, use_screen=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a0, b0 = h.warm_start(M, probs)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    tr_w = torch.full((n * (K + 1),), float("nan"), dtype=torch.float64, device=dev)
+    tt_w = torch.zeros(n * (K + 1), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, inf_w, _ = h.solve(a0, b0, max_iter=K, use_screen=1, init_user=1, obj_trace=tr_w, time_trace=tt_w)
+    torch.cuda.synchronize()
+    wall_w = time.perf_counter() - t0
+    tr_w = tr_w.cpu().numpy().reshape(n, K + 1)
+    tt_w = tt_w.cpu().numpy().reshape(n, K + 1)
+    dstar = np.maximum(np.nanmax(tr_c, axis=1), np.nanmax(tr_w, axis=1))
+    its_c, ts_c = _trace_hits(tr_c, tt_c, dstar)
+    its_w, ts_w = _trace_hits(tr_w, tt_w, dstar)
+    fin_c = np.array([x["obj"] for x in inf_c])
+    fin_w = np.array([x["obj"] for x in inf_w])
+    ok = all(x is not None for x in its_c + its_w)
+    ic = np.array([x if x is not None else K for x in its_c], dtype=float)
+    iw = np.array([x if x is not None else K for x in its_w], dtype=float)
+    tc = max(x for x in ts_c if x is not None)
+    tw = max(x for x in ts_w if x is not None) + t_inf
+    h.close()
+    return dict(workload=f"train {args.ws_train} / held-out {n} instances of the batched generator "
+                         f"(held-out n, m up to 4096), network {d + 8}-{w}-{w}-1",
+                train_rows=int(perm.numel()), train_data_s=t_data, train_s=t_train,
+                train_steps=int(steps), loss_first=float(lt[:10].mean()), loss_last=float(lt[-10:].mean()),
+                all_reached_1e6=ok,
+                iters_to_1e6_cold_median=float(np.median(ic)), iters_to_1e6_warm_median=float(np.median(iw)),
+                iters_to_1e6_cold_mean=float(ic.mean()), iters_to_1e6_warm_mean=float(iw.mean()),
+                frac_instances_fewer_iters=float(np.mean(iw < ic)),
+                time_to_all_1e6_cold_s=tc, time_to_all_1e6_warm_s=tw, inference_s=t_inf,
+                speedup_time=tc / tw,
+                final_obj_max_rel_diff=float(np.max(np.abs(fin_w - fin_c) / np.abs(fin_c))))
 
 
 def log(msg):
@@ -270,6 +452,16 @@ def main():
         otf = bench_onthefly(args, torch, synth, O)
         log(f"on-the-fly workload: {otf['ms_per_eval']:.3f} ms per dense evaluation")
 
+    batched = None
+    if not args.skip_batched:
+        batched = bench_batched(args, torch, synth, O)
+        log(f"batched workload: speedup {batched['speedup']:.2f} over sequential solves")
+    warm = None
+    if not args.skip_warmstart:
+        warm = bench_warmstart(args, torch, synth, O)
+        log(f"warm start: median iterations {warm['iters_to_1e6_cold_median']} -> "
+            f"{warm['iters_to_1e6_warm_median']}")
+
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline(inst, a_pt.cpu().numpy(), b_pt.cpu().numpy())
@@ -290,6 +482,8 @@ def main():
         screened_eval=screened,
         solves=solves,
         onthefly=otf,
+        batched=batched,
+        warm_start=warm,
     )
     print(json.dumps(line), flush=True)
 

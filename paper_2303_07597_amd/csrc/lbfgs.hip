@@ -41,7 +41,7 @@ struct LbState {
   int count, head;            // history ring
   int accept, push, slot, newdir;
   int since_refresh, mode_eval;   // mode_eval: mode of the evaluation just done
-  int pad1, pad2;
+  int force, pad2;                // force: accept the next evaluation (best step of a failed search)
   double f, gtd0, gmax;
   double t, t_prev, f_prev, dp_prev;
   double t_lo, f_lo, dp_lo, t_hi, f_hi, dp_hi;
@@ -255,16 +255,18 @@ __device__ double lb_direction(LbState& S, LbGram& G, int hist) {
   return dG;
 }
 
-__device__ void lb_new_direction(LbState& S, LbGram& G, const LbParams& P) {
+// steepest ascent from the accepted point, the L-BFGS memory cleared
+__device__ double lb_steepest(LbState& S, const LbParams& P) {
   const int lane = threadIdx.x & 63;
-  double gtd = lb_direction(S, G, P.hist);
-  if (!(gtd < 0.0)) {  // not a descent direction: restart from steepest descent
-    S.count = 0;
-    S.head = 0;
-    if (lane < P.hist) S.cs[lane] = S.cy[lane] = 0.0;
-    S.cg = -1.0;
-    gtd = -S.GG;
-  }
+  S.count = 0;
+  S.head = 0;
+  if (lane < P.hist) S.cs[lane] = S.cy[lane] = 0.0;
+  S.cg = -1.0;
+  return -S.GG;
+}
+
+// start a line search along the direction whose slope is gtd
+__device__ void lb_start_search(LbState& S, double gtd) {
   S.gtd0 = gtd;
   S.t = (S.count == 0) ? 1.0 / sqrt(S.GG) : 1.0;
   S.t_prev = 0.0;
@@ -274,6 +276,12 @@ __device__ void lb_new_direction(LbState& S, LbGram& G, const LbParams& P) {
   S.nls = 0;
   S.t_next = S.t;
   S.newdir = 1;
+}
+
+__device__ void lb_new_direction(LbState& S, LbGram& G, const LbParams& P) {
+  double gtd = lb_direction(S, G, P.hist);
+  if (!(gtd < 0.0)) gtd = lb_steepest(S, P);   // not a descent direction
+  lb_start_search(S, gtd);
 }
 
 __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, const double* dots,
@@ -332,7 +340,12 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   const double t = S.t, dp = Gtd;
   bool ok = false;
   S.nls++;
-  if (!S.zoom) {
+  if (S.force) {
+    // the best step of a search that ran out of trials, evaluated again
+    // (sufficient increase holds there): accept it
+    S.force = 0;
+    ok = true;
+  } else if (!S.zoom) {
     if (ft > S.f + P.c1 * t * S.gtd0 || (S.nls > 1 && ft >= S.f_prev)) {
       S.zoom = 1;
       S.t_lo = S.t_prev; S.f_lo = S.f_prev; S.dp_lo = S.dp_prev;
@@ -363,6 +376,21 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   }
   if (!ok) {
     if (S.nls >= P.max_ls) {
+      if (S.zoom && S.t_lo > 0.0 && S.f_lo < S.f) {
+        // out of trials inside a bracket: take its best step
+        S.force = 1;
+        S.t = S.t_lo;
+        S.t_next = S.t;
+        if (l0) atomicAdd(A.n_active, 1);
+        return;
+      }
+      if (S.count > 0) {
+        // no step along the quasi-Newton direction: drop the memory and
+        // search along the gradient before giving up
+        lb_start_search(S, lb_steepest(S, P));
+        if (l0) atomicAdd(A.n_active, 1);
+        return;
+      }
       S.status = LB_LSFAIL;
       if (l0) A.inst_mode[k] = EM_SKIP;
       S.t_next = 0.0;
@@ -594,6 +622,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     S.iter = S.evals = S.nls = S.zoom = 0;
     S.count = S.head = 0;
     S.accept = S.push = S.newdir = 0;
+    S.force = 0;
     S.since_refresh = 0;
     S.t_next = 0.0;
     S.GG = 0.0;
