@@ -154,6 +154,9 @@ typedef struct {
                              each accepted iteration (k = 0 is the starting point)    */
     long long *time_trace;/* optional DEVICE [count * (max_iter + 1)]: device clock
                              (wall_clock64, 100 MHz) at each accepted iteration        */
+    int use_graph;        /* 1 (default): record the launches of 16 solver steps
+                             into a HIP graph once per call and replay it; same
+                             results as 0 (direct launches)                          */
 } ot_gs_options;
 
 /* Fills `o` with the defaults listed above. */

@@ -123,6 +123,7 @@ struct ot_gs_handle {
   } sol;
   Timing timing;
   bool has_snapshot = false;
+  hipStream_t cap_stream = nullptr;   // stream that records solver steps into a graph
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -140,6 +141,7 @@ struct ot_gs_handle {
     sol = Solver();
   }
   ~ot_gs_handle() {
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     free_solver();
     for (void* p : allocs) (void)hipFree(p);
     for (auto& v : timing.ev)
@@ -1227,6 +1229,8 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->c2 = 0.9;
   o->gtol = 0.0;
   o->obj_trace = nullptr;
+  o->time_trace = nullptr;
+  o->use_graph = 1;
 }
 
 }  // extern "C"
@@ -1328,6 +1332,31 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   return OT_GS_OK;
 }
 
+// Records `n` solver steps on the handle's capture stream into an
+// executable graph.
+static int capture_steps(ot_gs_handle* h, const LbArgs& A, const LbParams& P, int init_user, int n,
+                         hipGraphExec_t* exec) {
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = OT_GS_OK;
+  for (int i = 0; i < n && rc == OT_GS_OK; ++i)
+    rc = solver_step(h, A, P.use_lower, P.use_screen, init_user, h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc != OT_GS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(OT_GS_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    *exec = nullptr;
+    return fail(OT_GS_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
+  }
+  return OT_GS_OK;
+}
+
 extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* alpha_io,
                            float* beta_io, ot_gs_info* info, void* stream) {
   if (!h || !opts || !alpha_io || !beta_io) return fail(OT_GS_EINVAL, "solve: NULL argument");
@@ -1362,13 +1391,29 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   // upper bound on evaluations: the first one plus max_ls per iteration
   const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;
   const int check_every = 16;
-  for (long long step = 0; step < max_steps; ++step) {
-    TRY(solver_step(h, A, P.use_lower, P.use_screen, o.init_user, s));
-    if ((step + 1) % check_every == 0 || step + 1 == max_steps) {
-      HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (*h->sol.h_active == 0) break;
+  // the steps between two checks, recorded once into a graph and replayed
+  // (every argument is a device pointer or a constant of this solve); not
+  // while kernel timing records events
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph && !h->timing.on) TRY(capture_steps(h, A, P, o.init_user, check_every, &exec));
+  struct ExecFree {
+    hipGraphExec_t& e;
+    ~ExecFree() {
+      if (e) (void)hipGraphExecDestroy(e);
     }
+  } exec_free{exec};
+  for (long long step = 0; step < max_steps;) {
+    if (exec && step + check_every <= max_steps) {
+      HIPCHK(hipGraphLaunch(exec, s));
+      step += check_every;
+    } else {
+      TRY(solver_step(h, A, P.use_lower, P.use_screen, o.init_user, s));
+      ++step;
+      if (step % check_every != 0 && step != max_steps) continue;
+    }
+    HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (*h->sol.h_active == 0) break;
   }
   // final points: X of every instance, back in the caller's order
   hipLaunchKernelGGL(k_lbfgs_export, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),

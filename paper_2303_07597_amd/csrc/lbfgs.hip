@@ -49,7 +49,7 @@ struct LbState {
   double GG, cg;
   double SG[HMAX], YG[HMAX], rho[HMAX];
   double cs[HMAX], cy[HMAX];
-  double pad3;
+  double f_restart;   // objective when the memory was last dropped after a failed search
 };
 // The Gram matrices s_i.y_j and y_i.y_j of an instance live next to the state
 // as [2][hist][hist] float64 (row-major, stride hist); the control kernel
@@ -376,17 +376,20 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   }
   if (!ok) {
     if (S.nls >= P.max_ls) {
-      if (S.zoom && S.t_lo > 0.0 && S.f_lo < S.f) {
-        // out of trials inside a bracket: take its best step
+      if (S.zoom && S.t_lo > 0.0 && S.f - S.f_lo > 1e-9 * fabs(S.f)) {
+        // out of trials inside a bracket: take its best step if it gains
+        // more than the rounding noise of the objective
         S.force = 1;
         S.t = S.t_lo;
         S.t_next = S.t;
         if (l0) atomicAdd(A.n_active, 1);
         return;
       }
-      if (S.count > 0) {
+      if (S.count > 0 && !(S.f_restart - S.f <= 1e-9 * fabs(S.f))) {
         // no step along the quasi-Newton direction: drop the memory and
-        // search along the gradient before giving up
+        // search along the gradient before giving up (once per real gain:
+        // at the rounding floor of the objective the search stops)
+        S.f_restart = S.f;
         lb_start_search(S, lb_steepest(S, P));
         if (l0) atomicAdd(A.n_active, 1);
         return;
@@ -623,6 +626,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     S.count = S.head = 0;
     S.accept = S.push = S.newdir = 0;
     S.force = 0;
+    S.f_restart = INFINITY;
     S.since_refresh = 0;
     S.t_next = 0.0;
     S.GG = 0.0;

@@ -114,3 +114,23 @@ def test_user_start_at_the_optimum_stays_there():
     a, b, info, rc = h.solve(a0, b0, max_iter=50, init_user=1, use_screen=1, gtol=1e-5)
     assert info[0]["iters"] <= 5
     assert abs(info[0]["obj"] - ref["obj"]) <= 1e-5 * abs(ref["obj"])
+
+
+def test_graph_replay_equals_direct_launches():
+    """The solver's recorded steps, replayed many times, give bit for bit the
+    trajectory of direct launches (batched, screened, with refreshes)."""
+    O = _O()
+    insts = [synth.instance_from_generator((77, i), n_lo=40, n_hi=400, d=8) for i in range(6)]
+    probs = [dict(labels=_dev(i["labels"]), n_groups=i["n_groups"], gamma=i["gamma"], mu=i["mu"],
+                  x_src=_dev(i["xs"]), x_tgt=_dev(i["xt"]), cost_mode=O.OT_GS_COST_MATERIALIZE,
+                  cost_scale=0.0) for i in insts]
+    h = O.Handle(probs)
+    res = []
+    for g in (0, 1, 1):
+        a, b, info, tr, rc = run(h, 300, use_screen=1, use_graph=g)
+        res.append((a, b, tr, [x["evals"] for x in info]))
+    for r in res[1:]:
+        np.testing.assert_array_equal(res[0][0], r[0])
+        np.testing.assert_array_equal(res[0][1], r[1])
+        np.testing.assert_array_equal(res[0][2], r[2])
+        assert res[0][3] == r[3]
