@@ -217,6 +217,25 @@ int ot_gs_kernel_time(ot_gs_handle *h, int which, double *ms, long long *launche
  * row and column partials of a dense evaluation; synchronises `stream`. */
 int ot_gs_profile_tiles(ot_gs_handle *h, int repeats, double *us_per_launch, void *stream);
 
+/* Tile configuration.  The gradient tiles are launched per bucket of the
+ * work lists (groups of similar size; bucket NBUCKET = 8 holds the chunks
+ * of groups over 1024 rows).  A bucket has a team-shape variant (on-the-fly
+ * cost, buckets 1-4: 0 = one 32-row block per wavefront, 1 = two blocks per
+ * wavefront and half the wavefronts; other buckets have variant 0 only) and
+ * a grid multiplier (workgroups launched per resident workgroup slot, 1-16,
+ * default 2).  Every configuration gives bit-identical results.
+ *
+ * ot_gs_autotune times every variant with multipliers 1, 2 and 4 on the
+ * handle's buckets (`repeats` dense launches each, at the handle's current
+ * point), keeps the fastest, and, when the environment variable
+ * OTGS_AUTOTUNE_CACHE names a file, records them there ("key variant
+ * multiplier" lines; the key names the device, the cost path, the bucket,
+ * the feature padding and the tile count's power of two).  ot_gs_create
+ * applies matching entries of that file.  Synchronises `stream`. */
+int ot_gs_autotune(ot_gs_handle *h, int repeats, void *stream);
+int ot_gs_tile_config(ot_gs_handle *h, int bucket, int variant, int grid_mult);
+int ot_gs_get_tile_config(ot_gs_handle *h, int bucket, int *variant, int *grid_mult, int *n_tiles);
+
 /* Size facts of instance k (host out, any may be NULL): groups that are
  * nonempty, padded target count of the internal layout, tiles. */
 int ot_gs_layout_info(ot_gs_handle *h, int k, int *n_groups_nonempty,

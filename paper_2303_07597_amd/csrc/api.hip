@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -124,6 +125,11 @@ struct ot_gs_handle {
   Timing timing;
   bool has_snapshot = false;
   hipStream_t cap_stream = nullptr;   // stream that records solver steps into a graph
+  // tile configuration (autotuned or set): per bucket of the tile lists the
+  // team-shape variant (on-the-fly) and the grid multiplier (workgroups per
+  // resident slot); index NBUCKET: the split-group passes
+  int tile_var[NBUCKET + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int tile_gm[NBUCKET + 1] = {2, 2, 2, 2, 2, 2, 2, 2, 2};
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -246,6 +252,8 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
   }
   return OT_GS_OK;
 }
+
+static void cache_apply(ot_gs_handle* h);
 
 // On-the-fly cost setup: pack the source features per group and the target
 // features in natural order, one pass over every (group, 32-target) tile for
@@ -775,6 +783,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   }
   TRY(sync_err(h, s, &herr));
   if (herr) return fail(OT_GS_EDEVICE, "setup kernels reported error flags %d", herr);
+  cache_apply(h);
   *out = guard.release();
   return OT_GS_OK;
 }
@@ -872,100 +881,118 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   return R;
 }
 
-// Gradient-tile launches over the static (every tile) or dynamic (screen
-// output) work lists: one kernel per row bucket, plus the split-group passes.
-static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_possible, hipStream_t s) {
-  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
-  TileDesc* mlist = dynamic ? h->dyn_main : h->list_main;
-  if (h->onthefly) {
-    // whole groups: bucket b < 5 has teams of 1 << b wavefronts with one
-    // row block each, bucket 5 teams of 16 with two; workgroups of
-    // max(team, 4) wavefronts
-    for (int b = 0; b < OTF_NBUCKET; ++b) {
-      if (h->n_bucket[b] == 0) continue;
-      A.list = mlist + h->main_off[b];
-      A.count = cnt + b;
-      const int WT = 1 << std::min(b, 4), NWV = std::max(WT, 4), K = NWV / WT;
-      const int per_cu = (b < 5 ? 32 : 16) / NWV;    // resident workgroups per CU
-      const dim3 grid(std::max(1, std::min((h->n_bucket[b] + K - 1) / K, 2 * per_cu * h->n_cu))),
-          block(64 * NWV);
-      for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
-#define OTGS_LAUNCH_OTF(WW, BB)                                                              \
-  if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, true>), grid, block, 0, s, A);    \
-  else hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, false>), grid, block, 0, s, A);
-        switch (b) {
-          case 0: OTGS_LAUNCH_OTF(1, 1) break;
-          case 1: OTGS_LAUNCH_OTF(2, 1) break;
-          case 2: OTGS_LAUNCH_OTF(4, 1) break;
-          case 3: OTGS_LAUNCH_OTF(8, 1) break;
-          case 4: OTGS_LAUNCH_OTF(16, 1) break;
-          default: OTGS_LAUNCH_OTF(16, 2) break;
-        }
-#undef OTGS_LAUNCH_OTF
-        LAUNCHCHK();
-      }
-    }
-    if (h->n_sg > 0) {
-      A.list = dynamic ? h->dyn_sc : h->list_sc;
-      A.count = cnt + NBUCKET + 1;
-      const dim3 grid(grid_for(h, h->n_sc)), block(BLOCK);
-      hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, false>), grid, block, 0, s, A);
-      LAUNCHCHK();
-      if (snap_possible) {
-        hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, true>), grid, block, 0, s, A);
-        LAUNCHCHK();
-      }
-      A.list = dynamic ? h->dyn_sg : h->list_sg;
-      A.count = cnt + NBUCKET;
-      hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
-      LAUNCHCHK();
-      A.list = dynamic ? h->dyn_sc : h->list_sc;
-      A.count = cnt + NBUCKET + 1;
-      hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 2, false>), grid, block, 0, s, A);
-      LAUNCHCHK();
-    }
-    return OT_GS_OK;
+// On-the-fly team shapes: bucket b has variant 0 = (1 << b wavefronts, one
+// row block each) for b < 5 and (16, 2) for b = 5; variant 1 halves the
+// team and gives every wavefront two blocks (b = 1..4).  Same results for
+// every variant (per-block partial sums in block order).
+static int otf_variants(int b) { return (b >= 1 && b <= 4) ? 2 : 1; }
+
+static void otf_shape(int b, int var, int* WT, int* BPW) {
+  if (b >= 5) {
+    *WT = NW;
+    *BPW = 2;
+  } else if (var == 0) {
+    *WT = 1 << b;
+    *BPW = 1;
+  } else {
+    *WT = 1 << (b - 1);
+    *BPW = 2;
   }
-  for (int b = 0; b < NBUCKET; ++b) {
-    if (h->n_bucket[b] == 0) continue;
-    A.list = mlist + h->main_off[b];
-    A.count = cnt + b;
-    const dim3 grid(grid_for(h, h->n_bucket[b])), block(BLOCK);
-    for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+}
+
+// resident workgroups per CU of a tile kernel shape (VGPR-bound occupancy)
+static int otf_resident(int WT, int BPW) {
+  const int nwv = std::max(WT, 4);
+  return (BPW == 1 ? 32 : 16) / nwv;
+}
+
+static int launch_otf_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
+  int WT, BPW;
+  otf_shape(b, h->tile_var[b], &WT, &BPW);
+  const int NWV = std::max(WT, 4), K = NWV / WT;
+  const dim3 grid(std::max(1, std::min((n + K - 1) / K, h->tile_gm[b] * otf_resident(WT, BPW) * h->n_cu))),
+      block(64 * NWV);
+  for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+#define OTGS_OTF(WW, BB)                                                                   \
+  if (WT == WW && BPW == BB) {                                                            \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, true>), grid, block, 0, s, A); \
+    else hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, false>), grid, block, 0, s, A);   \
+  }
+    OTGS_OTF(1, 1) OTGS_OTF(2, 1) OTGS_OTF(4, 1) OTGS_OTF(8, 1) OTGS_OTF(16, 1)
+    OTGS_OTF(1, 2) OTGS_OTF(2, 2) OTGS_OTF(4, 2) OTGS_OTF(8, 2) OTGS_OTF(16, 2)
+#undef OTGS_OTF
+    LAUNCHCHK();
+  }
+  return OT_GS_OK;
+}
+
+static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
+  const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
+  for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
 #define OTGS_LAUNCH_BUCKET(RR)                                                         \
   if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true>), grid, block, 0, s, A);      \
   else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false>), grid, block, 0, s, A);
-      switch (b) {
-        case 0: OTGS_LAUNCH_BUCKET(4) break;
-        case 1: OTGS_LAUNCH_BUCKET(8) break;
-        case 2: OTGS_LAUNCH_BUCKET(12) break;
-        case 3: OTGS_LAUNCH_BUCKET(16) break;
-        case 4: OTGS_LAUNCH_BUCKET(20) break;
-        case 5: OTGS_LAUNCH_BUCKET(24) break;
-        case 6: OTGS_LAUNCH_BUCKET(28) break;
-        default: OTGS_LAUNCH_BUCKET(32) break;
-      }
+    switch (b) {
+      case 0: OTGS_LAUNCH_BUCKET(4) break;
+      case 1: OTGS_LAUNCH_BUCKET(8) break;
+      case 2: OTGS_LAUNCH_BUCKET(12) break;
+      case 3: OTGS_LAUNCH_BUCKET(16) break;
+      case 4: OTGS_LAUNCH_BUCKET(20) break;
+      case 5: OTGS_LAUNCH_BUCKET(24) break;
+      case 6: OTGS_LAUNCH_BUCKET(28) break;
+      default: OTGS_LAUNCH_BUCKET(32) break;
+    }
 #undef OTGS_LAUNCH_BUCKET
-      LAUNCHCHK();
-    }
-  }
-  if (h->n_sg > 0) {
-    A.list = dynamic ? h->dyn_sc : h->list_sc;
-    A.count = cnt + NBUCKET + 1;
-    for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
-      if (sp) hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, true>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-      else hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, false>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
-      LAUNCHCHK();
-    }
-    A.list = dynamic ? h->dyn_sg : h->list_sg;
-    A.count = cnt + NBUCKET;
-    hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
-    LAUNCHCHK();
-    A.list = dynamic ? h->dyn_sc : h->list_sc;
-    A.count = cnt + NBUCKET + 1;
-    hipLaunchKernelGGL((k_grad_tiles<RMAX, 2, false>), dim3(grid_for(h, h->n_sc)), dim3(BLOCK), 0, s, A);
     LAUNCHCHK();
   }
+  return OT_GS_OK;
+}
+
+// split groups: chunk column partials, combine, chunk row sums
+static int launch_split(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_possible, hipStream_t s) {
+  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
+  const int gm = h->tile_gm[NBUCKET];
+  A.list = dynamic ? h->dyn_sc : h->list_sc;
+  A.count = cnt + NBUCKET + 1;
+  const dim3 block(BLOCK);
+  const dim3 g1(std::max(1, std::min(h->n_sc, gm * (h->onthefly ? 2 : 1) * h->n_cu)));
+  const dim3 g2(std::max(1, std::min(h->n_sc, gm * h->n_cu)));
+  for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
+    if (h->onthefly) {
+      if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, true>), g1, block, 0, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, false>), g1, block, 0, s, A);
+    } else {
+      if (sp) hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, true>), g1, block, 0, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, false>), g1, block, 0, s, A);
+    }
+    LAUNCHCHK();
+  }
+  A.list = dynamic ? h->dyn_sg : h->list_sg;
+  A.count = cnt + NBUCKET;
+  hipLaunchKernelGGL(k_split_combine, dim3(grid_for(h, h->n_sg) * 4), dim3(WAVE), 0, s, A);
+  LAUNCHCHK();
+  A.list = dynamic ? h->dyn_sc : h->list_sc;
+  A.count = cnt + NBUCKET + 1;
+  if (h->onthefly) hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 2, false>), g2, block, 0, s, A);
+  else hipLaunchKernelGGL((k_grad_tiles<RMAX, 2, false>), g2, block, 0, s, A);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+// Gradient-tile launches over the static (every tile) or dynamic (screen
+// output) work lists: one kernel per bucket, plus the split-group passes.
+static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_possible, hipStream_t s) {
+  const int* cnt = dynamic ? h->counts_dyn : h->counts_static;
+  TileDesc* mlist = dynamic ? h->dyn_main : h->list_main;
+  const int nb = h->onthefly ? OTF_NBUCKET : NBUCKET;
+  for (int b = 0; b < nb; ++b) {
+    if (h->n_bucket[b] == 0) continue;
+    A.list = mlist + h->main_off[b];
+    A.count = cnt + b;
+    if (h->onthefly) TRY(launch_otf_bucket(h, A, b, h->n_bucket[b], snap_possible, s));
+    else TRY(launch_mat_bucket(h, A, b, h->n_bucket[b], snap_possible, s));
+  }
+  if (h->n_sg > 0) TRY(launch_split(h, A, dynamic, snap_possible, s));
   return OT_GS_OK;
 }
 
@@ -1041,6 +1068,145 @@ static int gather(ot_gs_handle* h, const float* alpha, const float* beta, hipStr
                      dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, alpha, beta, h->alpha, h->beta,
                      h->err);
   LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+
+// Cache of tuned tile configurations: a text file named by the environment
+// variable OTGS_AUTOTUNE_CACHE, one "key variant grid_mult" line per entry.
+// The key names the kernel family, the bucket, the feature padding and the
+// size class (power of two of the tile count) and the device.
+static std::string tune_key(ot_gs_handle* h, int b, int n) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, h->dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ') c = '_';
+  int lg = 0;
+  while ((1 << (lg + 1)) <= std::max(n, 1)) ++lg;
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s|%s|b%d|dp%d|n%d|cu%d", arch.c_str(), h->onthefly ? "otf" : "mat", b,
+           h->onthefly ? h->inst[0].d.dp : 0, lg, h->n_cu);
+  return buf;
+}
+
+static std::vector<std::pair<std::string, std::pair<int, int>>> cache_read() {
+  std::vector<std::pair<std::string, std::pair<int, int>>> v;
+  const char* path = std::getenv("OTGS_AUTOTUNE_CACHE");
+  if (!path || !*path) return v;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return v;
+  char key[256];
+  int a, b;
+  while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3) v.push_back({key, {a, b}});
+  std::fclose(f);
+  return v;
+}
+
+static void cache_write(const std::vector<std::pair<std::string, std::pair<int, int>>>& v) {
+  const char* path = std::getenv("OTGS_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (auto& e : v) std::fprintf(f, "%s %d %d\n", e.first.c_str(), e.second.first, e.second.second);
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+static int bucket_tiles(ot_gs_handle* h, int b) { return b < NBUCKET ? h->n_bucket[b] : h->n_sc; }
+
+// apply cached configurations that match this handle
+static void cache_apply(ot_gs_handle* h) {
+  const auto v = cache_read();
+  if (v.empty()) return;
+  for (int b = 0; b <= NBUCKET; ++b) {
+    const int n = bucket_tiles(h, b);
+    if (n == 0) continue;
+    const std::string k = tune_key(h, b, n);
+    for (auto& e : v)
+      if (e.first == k) {
+        const int nvar = (h->onthefly && b < OTF_NBUCKET) ? otf_variants(b) : 1;
+        if (e.second.first >= 0 && e.second.first < nvar && e.second.second >= 1 && e.second.second <= 16) {
+          h->tile_var[b] = e.second.first;
+          h->tile_gm[b] = e.second.second;
+        }
+      }
+  }
+}
+
+// time `repeats` dense launches of one bucket's tile kernel (or the split
+// passes, b = NBUCKET) under the handle's current configuration
+static int time_bucket(ot_gs_handle* h, int b, int repeats, hipStream_t s, float* ms) {
+  GradArgs A = grad_args(h);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto run = [&]() -> int {
+    if (b == NBUCKET) return launch_split(h, A, false, false, s);
+    A.list = h->list_main + h->main_off[b];
+    A.count = h->counts_static + b;
+    return h->onthefly ? launch_otf_bucket(h, A, b, h->n_bucket[b], false, s)
+                       : launch_mat_bucket(h, A, b, h->n_bucket[b], false, s);
+  };
+  int rc = run();   // warm-up
+  if (rc == OT_GS_OK) {
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < repeats && rc == OT_GS_OK; ++i) rc = run();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
+  const bool was_on = h->timing.on;
+  h->timing.on = false;
+  // dense mode for every instance: every listed tile is computed
+  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, (int)OT_GS_DENSE,
+                     h->counters, 0LL, 0LL);
+  LAUNCHCHK();
+  auto cache = cache_read();
+  static const int gms[] = {1, 2, 4};
+  for (int b = 0; b <= NBUCKET; ++b) {
+    const int n = bucket_tiles(h, b);
+    if (n == 0 || (h->onthefly && b >= OTF_NBUCKET && b < NBUCKET)) continue;
+    const int nvar = (h->onthefly && b < OTF_NBUCKET) ? otf_variants(b) : 1;
+    float best = INFINITY;
+    int bv = h->tile_var[b], bg = h->tile_gm[b];
+    for (int var = 0; var < nvar; ++var)
+      for (int gm : gms) {
+        h->tile_var[b] = var;
+        h->tile_gm[b] = gm;
+        float ms = 0.f;
+        const int rc = time_bucket(h, b, repeats, s, &ms);
+        if (rc != OT_GS_OK) {
+          h->timing.on = was_on;
+          return rc;
+        }
+        if (ms < best) {
+          best = ms;
+          bv = var;
+          bg = gm;
+        }
+      }
+    h->tile_var[b] = bv;
+    h->tile_gm[b] = bg;
+    const std::string k = tune_key(h, b, n);
+    bool found = false;
+    for (auto& e : cache)
+      if (e.first == k) {
+        e.second = {bv, bg};
+        found = true;
+      }
+    if (!found) cache.push_back({k, {bv, bg}});
+  }
+  cache_write(cache);
+  h->timing.on = was_on;
   return OT_GS_OK;
 }
 
@@ -1170,6 +1336,30 @@ int ot_gs_profile_tiles(ot_gs_handle* h, int repeats, double* us_per_launch, voi
   (void)hipEventDestroy(e1);
   *us_per_launch = 1e3 * (double)ms / repeats;
   return OT_GS_OK;
+}
+
+int ot_gs_tile_config(ot_gs_handle* h, int bucket, int variant, int grid_mult) {
+  if (!h || bucket < 0 || bucket > NBUCKET) return fail(OT_GS_EINVAL, "tile_config: bad bucket");
+  const int nvar = (h->onthefly && bucket < OTF_NBUCKET) ? otf_variants(bucket) : 1;
+  if (variant < 0 || variant >= nvar) return fail(OT_GS_EINVAL, "tile_config: bucket %d has %d variants", bucket, nvar);
+  if (grid_mult < 1 || grid_mult > 16) return fail(OT_GS_EINVAL, "tile_config: grid_mult must lie in [1, 16]");
+  h->tile_var[bucket] = variant;
+  h->tile_gm[bucket] = grid_mult;
+  return OT_GS_OK;
+}
+
+int ot_gs_get_tile_config(ot_gs_handle* h, int bucket, int* variant, int* grid_mult, int* n_tiles) {
+  if (!h || bucket < 0 || bucket > NBUCKET) return fail(OT_GS_EINVAL, "get_tile_config: bad bucket");
+  if (variant) *variant = h->tile_var[bucket];
+  if (grid_mult) *grid_mult = h->tile_gm[bucket];
+  if (n_tiles) *n_tiles = bucket < NBUCKET ? h->n_bucket[bucket] : h->n_sc;
+  return OT_GS_OK;
+}
+
+int ot_gs_autotune(ot_gs_handle* h, int repeats, void* stream) {
+  if (!h || repeats < 1) return fail(OT_GS_EINVAL, "autotune: bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  return autotune_impl(h, repeats, s);
 }
 
 int ot_gs_kernel_timing(ot_gs_handle* h, int enable) {

@@ -615,7 +615,10 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
   constexpr int NWV = otf_waves<WT>();
   constexpr int K = NWV / WT;
   constexpr bool snap = SNAP && PHASE != 2;
-  __shared__ float red[3][NWV][TJ];
+  constexpr int TB = WT * BPW;   // row blocks of a team
+  // per-block partial sums; a tile's sums run over its blocks in order, so
+  // the result does not depend on the team shape (WT, BPW)
+  __shared__ float red[3][K * TB][TJ];
   const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
@@ -650,13 +653,13 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
       anyk = __ballot(kap > 0.f) != 0ull;
     }
     float p[BPW][16];
-    float z2 = 0.f, s1 = 0.f, o2 = 0.f;
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) p[b][q] = 0.f;
       const int i0 = r0 + 32 * (v + WT * b);   // first row of the block, in the group
       if (!act || i0 >= r1 || !anyk) continue;  // wave-uniform
+      float z2 = 0.f, s1 = 0.f, o2 = 0.f;
       const floatx16 acc = otf_dot_block<PHASE != 1>(xg + (size_t)(i0 / 32) * 32 * I.dp, yb, I.dp, lane);
       const bool rowin = i0 + c < r1;
       const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;
@@ -680,25 +683,28 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
         }
         p[b][q] = pk;
       }
+      if (PHASE != 2) {
+        z2 += __shfl_xor(z2, 32);
+        s1 += __shfl_xor(s1, 32);
+        if (snap) o2 += __shfl_xor(o2, 32);
+        const int slot = team * TB + v + WT * b;
+        if (h == 0) {
+          red[0][slot][c] = z2;
+          red[1][slot][c] = s1;
+          if (snap) red[2][slot][c] = o2;
+        }
+      }
     }
 
     if (PHASE != 2) {
-      z2 += __shfl_xor(z2, 32);
-      s1 += __shfl_xor(s1, 32);
-      if (snap) o2 += __shfl_xor(o2, 32);
-      if (act && h == 0) {
-        red[0][w][c] = z2;
-        red[1][w][c] = s1;
-        if (snap) red[2][w][c] = o2;
-      }
       __syncthreads();
       if (act) {
         float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
-#pragma unroll
-        for (int u = 0; u < WT; ++u) {
-          Z2 += red[0][team * WT + u][c];
-          S1 += red[1][team * WT + u][c];
-          if (snap) O2 += red[2][team * WT + u][c];
+        const int nblk = (r1 - r0 + 31) / 32;
+        for (int u = 0; u < nblk; ++u) {
+          Z2 += red[0][team * TB + u][c];
+          S1 += red[1][team * TB + u][c];
+          if (snap) O2 += red[2][team * TB + u][c];
         }
         if (PHASE == 1) {
           if (v == 0 && h == 0) {

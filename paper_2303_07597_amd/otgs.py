@@ -101,6 +101,9 @@ def _load():
     lib.ot_gs_features.argtypes = [ct.POINTER(ot_gs_problem), i, ct.POINTER(ct.c_float), vp, vp]
     lib.ot_gs_cost_scale.argtypes = [vp, ct.POINTER(ct.c_float)]
     lib.ot_gs_warm_start.argtypes = [vp, vp, ct.POINTER(ot_gs_problem), vp, vp, vp]
+    lib.ot_gs_autotune.argtypes = [vp, i, vp]
+    lib.ot_gs_tile_config.argtypes = [vp, i, i, i]
+    lib.ot_gs_get_tile_config.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
     return lib
@@ -317,6 +320,17 @@ class Handle:
         _check(lib().ot_gs_warm_start(self.h, mlp.m, arr, _ptr(alpha), _ptr(beta), _stream(stream)))
         return alpha, beta
 
+    def autotune(self, repeats=10, stream=None):
+        _check(lib().ot_gs_autotune(self.h, int(repeats), _stream(stream)))
+
+    def tile_config(self, bucket, variant, grid_mult):
+        _check(lib().ot_gs_tile_config(self.h, int(bucket), int(variant), int(grid_mult)))
+
+    def get_tile_config(self, bucket):
+        v, g, n = ct.c_int(), ct.c_int(), ct.c_int()
+        _check(lib().ot_gs_get_tile_config(self.h, int(bucket), ct.byref(v), ct.byref(g), ct.byref(n)))
+        return dict(variant=v.value, grid_mult=g.value, n_tiles=n.value)
+
     def layout_info(self, k=0):
         g, tp, nt = ct.c_int(), ct.c_int(), ct.c_int()
         _check(lib().ot_gs_layout_info(self.h, k, ct.byref(g), ct.byref(tp), ct.byref(nt)))
@@ -330,4 +344,5 @@ EXPORTED = [
     "ot_gs_mlp_create", "ot_gs_mlp_destroy", "ot_gs_mlp_n_params", "ot_gs_mlp_set_params",
     "ot_gs_mlp_get_params", "ot_gs_mlp_forward", "ot_gs_mlp_loss_grad", "ot_gs_mlp_train",
     "ot_gs_features", "ot_gs_cost_scale", "ot_gs_warm_start",
+    "ot_gs_autotune", "ot_gs_tile_config", "ot_gs_get_tile_config",
 ]
