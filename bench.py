@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--ws-held", type=int, default=256, help="held-out instances")
     ap.add_argument("--ws-epochs", type=int, default=30)
     ap.add_argument("--ws-save", default=None, help="write the trained network parameters (.npy) here")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (traffic counter calibration)")
     return ap.parse_args()
@@ -110,6 +111,9 @@ def bench_onthefly(args, torch, synth, O):
                        x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
                        cost_mode=O.OT_GS_COST_ONTHEFLY, cost_scale=0.0)])
     a_pt, b_pt, _, _ = h.solve(max_iter=20, use_screen=0)
+    if not args.no_autotune:
+        h.autotune(repeats=3)
+    tiles_cfg = {b: h.get_tile_config(b) for b in range(9) if h.get_tile_config(b)["n_tiles"] > 0}
     ga, gb = torch.empty_like(a_pt), torch.empty_like(b_pt)
     obj = torch.empty(1, dtype=torch.float64, device=dev)
     for _ in range(3):
@@ -129,7 +133,8 @@ def bench_onthefly(args, torch, synth, O):
                entries_per_s=n * n / el, ms_per_eval=1e3 * el,
                mfma=dict(bound="mfma", achieved=achieved, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                          frac=achieved / FP32_MFMA_PEAK_TFLOPS, flop_per_launch=flops,
-                         avg_launch_us=tiles_us, kernel="k_grad_tiles_otf (all buckets and passes)"))
+                         avg_launch_us=tiles_us, kernel="k_grad_tiles_otf (all buckets and passes)"),
+               tile_config=tiles_cfg)
     if args.otf_iters > 0:
         K = args.otf_iters
         runs = {}
@@ -353,6 +358,9 @@ def main():
     # point of measurement: 200 L-BFGS iterations from zero (dense solve)
     a_pt, b_pt, info, _ = h.solve(max_iter=200, use_screen=0)
     torch.cuda.synchronize()
+    if not args.no_autotune:
+        h.autotune(repeats=20)
+    tiles_cfg = {b: h.get_tile_config(b) for b in range(9) if h.get_tile_config(b)["n_tiles"] > 0}
 
     ga = torch.empty_like(a_pt)
     gb = torch.empty_like(b_pt)
@@ -477,7 +485,7 @@ def main():
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                       kernel="k_grad_tiles<16,0,false>", algorithmic_bytes_per_launch=alg_bytes,
                       avg_launch_us=grad_avg_s * 1e6, launches=args.steps,
-                      event_bracketed_us_per_call=1e3 * grad_ms / max(grad_n, 1)),
+                      event_bracketed_us_per_call=1e3 * grad_ms / max(grad_n, 1), tile_config=tiles_cfg),
         cpu_baseline=cpu,
         screened_eval=screened,
         solves=solves,
