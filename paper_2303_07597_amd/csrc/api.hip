@@ -887,6 +887,12 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
 // every variant (per-block partial sums in block order).
 static int otf_variants(int b) { return (b >= 1 && b <= 4) ? 2 : 1; }
 
+// variants of a bucket of this handle's tile lists
+static int tile_variants(const ot_gs_handle* h, int b) {
+  if (b >= NBUCKET) return 1;
+  return h->onthefly ? (b < OTF_NBUCKET ? otf_variants(b) : 1) : (b <= 3 ? 3 : 2);
+}
+
 static void otf_shape(int b, int var, int* WT, int* BPW) {
   if (b >= 5) {
     *WT = NW;
@@ -926,12 +932,25 @@ static int launch_otf_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
   return OT_GS_OK;
 }
 
+// materialised buckets: variant 0 loads a tile when it starts, variant 1
+// keeps the next tile's loads in flight in registers during the current
+// tile, variant 2 (R <= 16) copies the next tile into LDS meanwhile (same bits)
 static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
   const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
+  const bool pf = h->tile_var[b] == 1;
+  const bool dma = h->tile_var[b] == 2 && b <= 3;
   for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
-#define OTGS_LAUNCH_BUCKET(RR)                                                         \
-  if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true>), grid, block, 0, s, A);      \
-  else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false>), grid, block, 0, s, A);
+#define OTGS_LAUNCH_BUCKET(RR)                                                                 \
+  if (dma) {                                                                                  \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), true>), grid, block, 0, s, A);  \
+    else hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), false>), grid, block, 0, s, A);    \
+  } else if (pf) {                                                                            \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles_pf<RR, true>), grid, block, 0, s, A);            \
+    else hipLaunchKernelGGL((k_grad_tiles_pf<RR, false>), grid, block, 0, s, A);              \
+  } else {                                                                                    \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true>), grid, block, 0, s, A);            \
+    else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false>), grid, block, 0, s, A);              \
+  }
     switch (b) {
       case 0: OTGS_LAUNCH_BUCKET(4) break;
       case 1: OTGS_LAUNCH_BUCKET(8) break;
@@ -1127,7 +1146,7 @@ static void cache_apply(ot_gs_handle* h) {
     const std::string k = tune_key(h, b, n);
     for (auto& e : v)
       if (e.first == k) {
-        const int nvar = (h->onthefly && b < OTF_NBUCKET) ? otf_variants(b) : 1;
+        const int nvar = tile_variants(h, b);
         if (e.second.first >= 0 && e.second.first < nvar && e.second.second >= 1 && e.second.second <= 16) {
           h->tile_var[b] = e.second.first;
           h->tile_gm[b] = e.second.second;
@@ -1175,7 +1194,7 @@ static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
   for (int b = 0; b <= NBUCKET; ++b) {
     const int n = bucket_tiles(h, b);
     if (n == 0 || (h->onthefly && b >= OTF_NBUCKET && b < NBUCKET)) continue;
-    const int nvar = (h->onthefly && b < OTF_NBUCKET) ? otf_variants(b) : 1;
+    const int nvar = tile_variants(h, b);
     float best = INFINITY;
     int bv = h->tile_var[b], bg = h->tile_gm[b];
     for (int var = 0; var < nvar; ++var)
@@ -1340,7 +1359,7 @@ int ot_gs_profile_tiles(ot_gs_handle* h, int repeats, double* us_per_launch, voi
 
 int ot_gs_tile_config(ot_gs_handle* h, int bucket, int variant, int grid_mult) {
   if (!h || bucket < 0 || bucket > NBUCKET) return fail(OT_GS_EINVAL, "tile_config: bad bucket");
-  const int nvar = (h->onthefly && bucket < OTF_NBUCKET) ? otf_variants(bucket) : 1;
+  const int nvar = tile_variants(h, bucket);
   if (variant < 0 || variant >= nvar) return fail(OT_GS_EINVAL, "tile_config: bucket %d has %d variants", bucket, nvar);
   if (grid_mult < 1 || grid_mult > 16) return fail(OT_GS_EINVAL, "tile_config: grid_mult must lie in [1, 16]");
   h->tile_var[bucket] = variant;

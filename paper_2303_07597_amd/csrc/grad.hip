@@ -96,7 +96,7 @@ __device__ __forceinline__ void transposed_row_sums(float (&v)[RP], float (&x)[R
 // 2 NW R >= rows of the tile.  SNAP: also form o~ = ||[f]_-||.
 template <int R, int PHASE, bool SNAP>
 __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
-                                          float (*red)[NW][TJ]) {
+                                          float (*red)[NW][TJ], float (*aw)[WAVE], float* kap_s) {
   const InstDev I = A.inst[d.inst];
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
@@ -117,7 +117,8 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
   const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
   // alpha of the row of load k, parity h, sits in lane 2 k + h
   const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-  const float av = ((lane >> 1) < nk && arow < r1) ? A.alpha[I.row_off + gs + arow] : 0.f;
+  // rows past the tile get alpha = -inf (f = -inf, p = 0 without a mask)
+  const float av = ((lane >> 1) < nk && arow < r1) ? A.alpha[I.row_off + gs + arow] : -INFINITY;
   // Raw buffer loads: scalar descriptor at this wavefront's first row pair,
   // one per-lane byte offset and a scalar offset per load.  Loads past the
   // tile re-read the last valid pair (a cache hit) and are masked below.
@@ -134,21 +135,34 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
         __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
   // keep every load of the wavefront in flight before any is consumed
   __builtin_amdgcn_sched_barrier(0);
+  // this wavefront's alpha values through its own LDS slot: lane 2 k + h
+  // holds the row of load k, parity h (no barrier: written and read by the
+  // same wavefront)
+  aw[w][lane] = av;
+  // a padding column gets beta = -inf: with alpha = -inf past the tile,
+  // every entry outside the tile has f = -inf and p exactly 0 (the entries
+  // inside are computed exactly as written); snapshots mask explicitly
+  // because they also sum [f]_-
+  const float bjm = colok ? bj : -INFINITY;
   float z2 = 0.f, s1 = 0.f, o2 = 0.f;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k));
-    const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k + 1));
-    const float ak = h ? a1 : a0;
-    const float f = (ak + bj) - p[k];
-    const bool ok = (k < nk) && (rw + 2 * NW * k + h < r1) && colok;
-    const float pk = ok ? fmaxf(f, 0.f) : 0.f;
-    if (PHASE != 2) {
-      z2 = fmaf(pk, pk, z2);
-      s1 += pk;
+    // loads past the last row (k >= nk) re-read valid memory and meet
+    // alpha = -inf, so they need no branch either (snapshots skip them)
+    float pk = 0.f;
+    if (!snap || k < nk) {
+      const float ak = aw[w][2 * k + h];
+      const float f = (ak + bjm) - p[k];
+      pk = fmaxf(f, 0.f);
       if (snap) {
+        const bool ok = (rw + 2 * NW * k + h < r1) && colok;
+        pk = ok ? pk : 0.f;
         const float nkv = ok ? fminf(f, 0.f) : 0.f;
         o2 = fmaf(nkv, nkv, o2);
+      }
+      if (PHASE != 2) {
+        z2 = fmaf(pk, pk, z2);
+        s1 += pk;
       }
     }
     p[k] = pk;
@@ -166,43 +180,51 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
       if (snap) red[2][w][c] = o2;
     }
     __syncthreads();
-    float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+    // wavefront 0 sums the wavefronts' partials in order and forms kappa;
+    // the others take kappa from LDS
+    if (w == 0) {
+      float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
 #pragma unroll 4
-    for (int v = 0; v < NW; ++v) {
-      Z2 += red[0][v][c];
-      S1 += red[1][v][c];
-    }
-    if (snap) {
-#pragma unroll 4
-      for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
-    }
-    if (PHASE == 1) {
-      // column partial sums of chunk `aux` of a split group
-      if (w == 0 && h == 0) {
-        const long long q = I.chunk_off +
-                            (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
-        A.part[q] = Z2;
-        A.part[q + A.part_stride] = S1;
-        A.part[q + 2 * A.part_stride] = O2;
+      for (int v = 0; v < NW; ++v) {
+        Z2 += red[0][v][c];
+        S1 += red[1][v][c];
       }
-      return;
-    }
-    const float z = sqrtf(Z2);
-    float num = 0.f;
-    if (z > I.thr) {
-      num = z - I.thr;
-      kap = num / (I.gamma * z);
-    }
-    if (w == 0 && h == 0) {
-      const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
-      A.colsum[pr] = kap * S1;
-      A.excess[pr] = num;
-      if (A.write_kappa) A.kappa[pr] = kap;
       if (snap) {
-        A.zsnap[pr] = z;
-        A.osnap[pr] = sqrtf(O2);
+#pragma unroll 4
+        for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
+      }
+      if (PHASE == 1) {
+        // column partial sums of chunk `aux` of a split group
+        if (h == 0) {
+          const long long q = I.chunk_off +
+                              (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
+          A.part[q] = Z2;
+          A.part[q + A.part_stride] = S1;
+          A.part[q + 2 * A.part_stride] = O2;
+        }
+      } else {
+        const float z = sqrtf(Z2);
+        float num = 0.f;
+        if (z > I.thr) {
+          num = z - I.thr;
+          kap = num / (I.gamma * z);
+        }
+        if (h == 0) {
+          const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+          A.colsum[pr] = kap * S1;
+          A.excess[pr] = num;
+          if (A.write_kappa) A.kappa[pr] = kap;
+          if (snap) {
+            A.zsnap[pr] = z;
+            A.osnap[pr] = sqrtf(O2);
+          }
+          kap_s[c] = kap;
+        }
       }
     }
+    if (PHASE == 1) return;
+    __syncthreads();
+    kap = kap_s[c];
   } else {
     kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
   }
@@ -231,20 +253,217 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
   }
 }
 
+// Whole-group tiles (PHASE 0) with the next tile's cost values in flight
+// while the current tile is reduced: the loads of grad_tile, issued one tile
+// ahead into a second register set.  Same arithmetic as grad_tile.
+template <int R>
+struct TileLoad {
+  TileDesc d;
+  float v[R];
+};
+
+template <int R>
+__device__ __forceinline__ void tile_issue(const GradArgs& A, const TileDesc& d, TileLoad<R>& L) {
+  const InstDev I = A.inst[d.inst];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gs = A.g_start[I.grp_off + d.grp];
+  const int gn = A.g_size[I.grp_off + d.grp];
+  const int rw = 2 * w;
+  const int nk = rw < gn ? min(R, (gn - rw + 2 * NW - 1) / (2 * NW)) : 0;
+  const float* Cw = A.C + c_index(I, gs, gn, gs + rw, d.jb * TJ);
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
+  const int stride_b = 2 * NW * TJ * 4;
+  const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
+  L.d = d;
+#pragma unroll
+  for (int k = 0; k < R; ++k)
+    L.v[k] = __uint_as_float(
+        __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+}
+
+template <int R, bool SNAP>
+__device__ __forceinline__ void tile_finish(const GradArgs& A, TileLoad<R>& L, float (*red)[NW][TJ]) {
+  const TileDesc d = L.d;
+  const InstDev I = A.inst[d.inst];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gs = A.g_start[I.grp_off + d.grp];
+  const int gn = A.g_size[I.grp_off + d.grp];
+  const int col = d.jb * TJ + c;
+  const bool colok = col < I.nt;
+  const float bj = A.beta[I.col_off + col];
+  const int rw = 2 * w;
+  const int nk = rw < gn ? min(R, (gn - rw + 2 * NW - 1) / (2 * NW)) : 0;
+  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+  const float av = ((lane >> 1) < nk && arow < gn) ? A.alpha[I.row_off + gs + arow] : 0.f;
+  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k));
+    const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k + 1));
+    const float ak = h ? a1 : a0;
+    const float f = (ak + bj) - L.v[k];
+    const bool ok = (k < nk) && (rw + 2 * NW * k + h < gn) && colok;
+    const float pk = ok ? fmaxf(f, 0.f) : 0.f;
+    z2 = fmaf(pk, pk, z2);
+    s1 += pk;
+    if (SNAP) {
+      const float nkv = ok ? fminf(f, 0.f) : 0.f;
+      o2 = fmaf(nkv, nkv, o2);
+    }
+    L.v[k] = pk;
+  }
+  z2 += __shfl_xor(z2, 32);
+  s1 += __shfl_xor(s1, 32);
+  if (SNAP) o2 += __shfl_xor(o2, 32);
+  if (h == 0) {
+    red[0][w][c] = z2;
+    red[1][w][c] = s1;
+    if (SNAP) red[2][w][c] = o2;
+  }
+  __syncthreads();
+  float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
+#pragma unroll 4
+  for (int v = 0; v < NW; ++v) {
+    Z2 += red[0][v][c];
+    S1 += red[1][v][c];
+  }
+  if (SNAP) {
+#pragma unroll 4
+    for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
+  }
+  const float z = sqrtf(Z2);
+  float num = 0.f, kap = 0.f;
+  if (z > I.thr) {
+    num = z - I.thr;
+    kap = num / (I.gamma * z);
+  }
+  if (w == 0 && h == 0) {
+    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+    A.colsum[pr] = kap * S1;
+    A.excess[pr] = num;
+    if (A.write_kappa) A.kappa[pr] = kap;
+    if (SNAP) {
+      A.zsnap[pr] = z;
+      A.osnap[pr] = sqrtf(O2);
+    }
+  }
+  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
+  if (__ballot(kap > 0.f) == 0ull) {
+    if ((lane >> 1) < nk && arow < gn) rp[arow] = 0.f;
+    return;
+  }
+  const int q = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < (R + 1) / 2; ++m) {
+    const float va = kap * L.v[2 * m];
+    const float vb = (2 * m + 1 < R) ? kap * L.v[(2 * m + 1 < R) ? 2 * m + 1 : 0] : 0.f;
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(va), __float_as_uint(vb), false, false);
+    const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+    const int k = 2 * m + (q & 1);
+    const int row = rw + 2 * NW * k + (q >> 1);
+    if ((lane & 15) == 15 && k < nk && row < gn) rp[row] = x;
+  }
+}
+
+template <int R, bool SNAP>
+__global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
+  __shared__ float red[3][NW][TJ];
+  const int n = *A.count;
+  int t = blockIdx.x;
+  // skip tiles of the other mode (their loads would be wasted)
+  auto next_match = [&](int from) {
+    int u = from;
+    while (u < n && (A.inst_mode[A.list[u].inst] == EM_SNAPSHOT) != SNAP) u += gridDim.x;
+    return u;
+  };
+  t = next_match(t);
+  if (t >= n) return;
+  TileLoad<R> cur, nxt;
+  tile_issue<R>(A, A.list[t], cur);
+  for (;;) {
+    const int tn = next_match(t + gridDim.x);
+    if (tn < n) tile_issue<R>(A, A.list[tn], nxt);
+    tile_finish<R, SNAP>(A, cur, red);
+    __syncthreads();
+    if (tn >= n) break;
+    t = tn;
+    cur = nxt;
+  }
+}
+
+// Whole-group tiles (PHASE 0, R <= 16) whose cost tile is copied into LDS
+// by direct buffer-to-LDS loads: the copy of the next tile runs while the
+// current one is reduced from registers.  Same arithmetic as grad_tile.
+constexpr int DMA_RMAX = 16;
+
+template <int R, bool SNAP>
+__global__ void __launch_bounds__(BLOCK) k_grad_tiles_dma(GradArgs A) {
+  static_assert(R <= DMA_RMAX, "LDS tile buffer sized for R <= 16");
+  __shared__ float red[3][NW][TJ];
+  __shared__ __attribute__((aligned(16))) float buf[2 * NW * R * TJ];   // 32 R rows of 32 floats
+  const int n = *A.count;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  auto match = [&](int u) {
+    while (u < n && (A.inst_mode[A.list[u].inst] == EM_SNAPSHOT) != SNAP) u += gridDim.x;
+    return u;
+  };
+  // the tile's rows are one contiguous [gn x 32] stream: 1 KB pieces (8
+  // rows), piece q to LDS bytes [1024 q, 1024 q + 1024); pieces past the
+  // tile read the pool's following rows (in bounds) and land inside buf
+  auto issue = [&](int u) {
+    const TileDesc d = A.list[u];
+    const InstDev I = A.inst[d.inst];
+    const int gs = A.g_start[I.grp_off + d.grp];
+    const int gn = A.g_size[I.grp_off + d.grp];
+    const float* Ct = A.C + c_index(I, gs, gn, gs, d.jb * TJ);
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)Ct, (short)0, 0x7fffffff, 0x00020000);
+    const int npc = __builtin_amdgcn_readfirstlane((gn + 7) / 8);
+    for (int q = w; q < npc; q += NW)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(buf + q * 256), 16,
+                                               lane * 16, q * 1024, 0, 0);
+  };
+  int t = match(blockIdx.x);
+  if (t >= n) return;
+  issue(t);
+  for (;;) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wavefront's copies have landed
+    __syncthreads();                 // and everybody else's
+    TileLoad<R> L;
+    L.d = A.list[t];
+#pragma unroll
+    for (int k = 0; k < R; ++k) L.v[k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
+    __syncthreads();                 // buffer free for the next tile
+    const int tn = match(t + gridDim.x);
+    if (tn < n) issue(tn);
+    tile_finish<R, SNAP>(A, L, red);
+    __syncthreads();
+    if (tn >= n) break;
+    t = tn;
+  }
+}
+
 // One instantiation per row bucket R (a multiple of 4) for whole-group tiles
 // (PHASE 0), R = RMAX for the two passes over split-group chunks.  SNAP
 // kernels take only the tiles of instances evaluated at a snapshot, the
 // others the rest (separate kernels keep the common path's register count
 // low enough for two workgroups per compute unit).
 template <int R, int PHASE, bool SNAP>
-__global__ void __launch_bounds__(BLOCK) k_grad_tiles(GradArgs A) {
+__global__ void __launch_bounds__(BLOCK, R <= 16 ? 8 : 1) k_grad_tiles(GradArgs A) {
   __shared__ float red[3][NW][TJ];
+  __shared__ float aw[NW][WAVE];
+  __shared__ float kap_s[TJ];
   const int n = *A.count;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
     // the row-sum pass of split groups has one variant for every mode
     if (PHASE != 2 && (A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
-    grad_tile<R, PHASE, SNAP>(A, d, red);
+    grad_tile<R, PHASE, SNAP>(A, d, red, aw, kap_s);
     __syncthreads();
   }
 }

@@ -61,7 +61,10 @@ def test_every_tile_configuration_gives_the_same_result(mode_name):
         cfg = h.get_tile_config(bucket)
         if cfg["n_tiles"] == 0:
             continue
-        nvar = 2 if (mode_name == "OT_GS_COST_ONTHEFLY" and 1 <= bucket <= 4) else 1
+        if mode_name == "OT_GS_COST_ONTHEFLY":
+            nvar = 2 if 1 <= bucket <= 4 else 1
+        else:
+            nvar = 2 if bucket < NBUCKET else 1       # plain / next tile in flight
         for var in range(nvar):
             for gm in (1, 3):
                 h.tile_config(bucket, var, gm)
