@@ -94,50 +94,79 @@ __device__ __forceinline__ void transposed_row_sums(float (&v)[RP], float (&x)[R
 // parity.  Load k of wavefront w covers the two tile rows 2 (w + NW k) + h:
 // 64 consecutive floats of the tile-major pool.  R loads per lane cover
 // 2 NW R >= rows of the tile.  SNAP: also form o~ = ||[f]_-||.
-template <int R, int PHASE, bool SNAP>
-__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
-                                          float (*red)[NW][TJ], float (*aw)[WAVE], float* kap_s) {
+//
+// A tile is processed in two steps: tile_loads issues the loads of alpha,
+// beta and the R cost values of every lane, tile_body forms p, the sums,
+// kappa and the row sums once they have arrived.  Kernels either run the two
+// back to back or issue the next tile's loads before the current body.
+
+// scalar context of a tile (wavefront-uniform except the per-lane fields)
+struct TileCtx {
+  int gs, gn, r0, r1, rw, col;
+  bool colok;
+};
+
+template <int PHASE>
+__device__ __forceinline__ TileCtx tile_ctx(const GradArgs& A, const InstDev& I, const TileDesc& d) {
+  TileCtx t;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  t.gs = A.g_start[I.grp_off + d.grp];
+  t.gn = A.g_size[I.grp_off + d.grp];
+  t.r0 = 0;
+  t.r1 = t.gn;   // rows of this tile, relative to the group start
+  if (PHASE != 0) {
+    t.r0 = d.aux * CHUNK;
+    t.r1 = min(t.r0 + CHUNK, t.gn);
+  }
+  t.col = d.jb * TJ + (lane & (TJ - 1));
+  t.colok = t.col < I.nt;
+  t.rw = t.r0 + 2 * w;   // first row of this wavefront (h = 0)
+  return t;
+}
+
+// Issue the loads of a tile: alpha of the row of load k, parity h, in lane
+// 2 k + h (-inf past the tile: f = -inf, p = 0 without a mask), beta of the
+// lane's column, and the R cost values (raw buffer loads: scalar descriptor
+// at the wavefront's first row pair, a scalar offset per load; loads past
+// the tile re-read the last valid pair, a cache hit).
+template <int R, int PHASE>
+__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileDesc& d, float& av, float& bj,
+                                           float (&p)[R]) {
   const InstDev I = A.inst[d.inst];
   const int lane = threadIdx.x & (WAVE - 1);
-  const int h = lane >> 5, c = lane & (TJ - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gs = A.g_start[I.grp_off + d.grp];
-  const int gn = A.g_size[I.grp_off + d.grp];
-  int r0 = 0, r1 = gn;   // rows of this tile, relative to the group start
-  if (PHASE != 0) {
-    r0 = d.aux * CHUNK;
-    r1 = min(r0 + CHUNK, gn);
-  }
-  const int col = d.jb * TJ + c;
-  const bool colok = col < I.nt;
-  const float bj = A.beta[I.col_off + col];
-  constexpr bool snap = SNAP && PHASE != 2;
-  const int rw = r0 + 2 * w;           // first row of this wavefront (h = 0)
-  // loads of this wavefront that touch a row of the tile (wave-uniform)
-  const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
-  // alpha of the row of load k, parity h, sits in lane 2 k + h
-  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-  // rows past the tile get alpha = -inf (f = -inf, p = 0 without a mask)
-  const float av = ((lane >> 1) < nk && arow < r1) ? A.alpha[I.row_off + gs + arow] : -INFINITY;
-  // Raw buffer loads: scalar descriptor at this wavefront's first row pair,
-  // one per-lane byte offset and a scalar offset per load.  Loads past the
-  // tile re-read the last valid pair (a cache hit) and are masked below.
-  const float* Cw = A.C + c_index(I, gs, gn, gs + rw, d.jb * TJ);
+  TileCtx t = tile_ctx<PHASE>(A, I, d);
+  const int nk = t.rw < t.r1 ? min(R, (t.r1 - t.rw + 2 * NW - 1) / (2 * NW)) : 0;
+  const int arow = t.rw + 2 * NW * (lane >> 1) + (lane & 1);
+  av = ((lane >> 1) < nk && arow < t.r1) ? A.alpha[I.row_off + t.gs + arow] : -INFINITY;
+  bj = A.beta[I.col_off + t.col];
+  const float* Cw = A.C + c_index(I, t.gs, t.gn, t.gs + t.rw, d.jb * TJ);
   const __amdgpu_buffer_rsrc_t rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
   const int stride_b = 2 * NW * TJ * 4;
   const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
-
-  float p[R];
 #pragma unroll
   for (int k = 0; k < R; ++k)
     p[k] = __uint_as_float(
         __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
-  // keep every load of the wavefront in flight before any is consumed
-  __builtin_amdgcn_sched_barrier(0);
-  // this wavefront's alpha values through its own LDS slot: lane 2 k + h
-  // holds the row of load k, parity h (no barrier: written and read by the
-  // same wavefront)
+}
+
+template <int R, int PHASE, bool SNAP>
+__device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, float av, float bj,
+                                          float (&p)[R], float (*red)[NW][TJ], float (*aw)[WAVE],
+                                          float* kap_s) {
+  const InstDev I = A.inst[d.inst];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const TileCtx t = tile_ctx<PHASE>(A, I, d);
+  const int gs = t.gs, r1 = t.r1, rw = t.rw, col = t.col;
+  const bool colok = t.colok;
+  const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
+  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+  constexpr bool snap = SNAP && PHASE != 2;
+  // this wavefront's alpha values through its own LDS slot (written and read
+  // by the same wavefront: no barrier)
   aw[w][lane] = av;
   // a padding column gets beta = -inf: with alpha = -inf past the tile,
   // every entry outside the tile has f = -inf and p exactly 0 (the entries
@@ -253,141 +282,49 @@ __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d,
   }
 }
 
-// Whole-group tiles (PHASE 0) with the next tile's cost values in flight
-// while the current tile is reduced: the loads of grad_tile, issued one tile
-// ahead into a second register set.  Same arithmetic as grad_tile.
+template <int R, int PHASE, bool SNAP>
+__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d, float (*red)[NW][TJ],
+                                          float (*aw)[WAVE], float* kap_s) {
+  float av, bj, p[R];
+  tile_loads<R, PHASE>(A, d, av, bj, p);
+  // keep every load of the wavefront in flight before any is consumed
+  __builtin_amdgcn_sched_barrier(0);
+  tile_body<R, PHASE, SNAP>(A, d, av, bj, p, red, aw, kap_s);
+}
+
+// Whole-group tiles (PHASE 0) with the next tile's loads in flight while the
+// current tile's body runs (same arithmetic as grad_tile).
 template <int R>
 struct TileLoad {
   TileDesc d;
+  float av, bj;
   float v[R];
 };
-
-template <int R>
-__device__ __forceinline__ void tile_issue(const GradArgs& A, const TileDesc& d, TileLoad<R>& L) {
-  const InstDev I = A.inst[d.inst];
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gs = A.g_start[I.grp_off + d.grp];
-  const int gn = A.g_size[I.grp_off + d.grp];
-  const int rw = 2 * w;
-  const int nk = rw < gn ? min(R, (gn - rw + 2 * NW - 1) / (2 * NW)) : 0;
-  const float* Cw = A.C + c_index(I, gs, gn, gs + rw, d.jb * TJ);
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
-  const int stride_b = 2 * NW * TJ * 4;
-  const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
-  L.d = d;
-#pragma unroll
-  for (int k = 0; k < R; ++k)
-    L.v[k] = __uint_as_float(
-        __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
-}
-
-template <int R, bool SNAP>
-__device__ __forceinline__ void tile_finish(const GradArgs& A, TileLoad<R>& L, float (*red)[NW][TJ]) {
-  const TileDesc d = L.d;
-  const InstDev I = A.inst[d.inst];
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int h = lane >> 5, c = lane & (TJ - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gs = A.g_start[I.grp_off + d.grp];
-  const int gn = A.g_size[I.grp_off + d.grp];
-  const int col = d.jb * TJ + c;
-  const bool colok = col < I.nt;
-  const float bj = A.beta[I.col_off + col];
-  const int rw = 2 * w;
-  const int nk = rw < gn ? min(R, (gn - rw + 2 * NW - 1) / (2 * NW)) : 0;
-  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-  const float av = ((lane >> 1) < nk && arow < gn) ? A.alpha[I.row_off + gs + arow] : 0.f;
-  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const float a0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k));
-    const float a1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(av), 2 * k + 1));
-    const float ak = h ? a1 : a0;
-    const float f = (ak + bj) - L.v[k];
-    const bool ok = (k < nk) && (rw + 2 * NW * k + h < gn) && colok;
-    const float pk = ok ? fmaxf(f, 0.f) : 0.f;
-    z2 = fmaf(pk, pk, z2);
-    s1 += pk;
-    if (SNAP) {
-      const float nkv = ok ? fminf(f, 0.f) : 0.f;
-      o2 = fmaf(nkv, nkv, o2);
-    }
-    L.v[k] = pk;
-  }
-  z2 += __shfl_xor(z2, 32);
-  s1 += __shfl_xor(s1, 32);
-  if (SNAP) o2 += __shfl_xor(o2, 32);
-  if (h == 0) {
-    red[0][w][c] = z2;
-    red[1][w][c] = s1;
-    if (SNAP) red[2][w][c] = o2;
-  }
-  __syncthreads();
-  float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
-#pragma unroll 4
-  for (int v = 0; v < NW; ++v) {
-    Z2 += red[0][v][c];
-    S1 += red[1][v][c];
-  }
-  if (SNAP) {
-#pragma unroll 4
-    for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
-  }
-  const float z = sqrtf(Z2);
-  float num = 0.f, kap = 0.f;
-  if (z > I.thr) {
-    num = z - I.thr;
-    kap = num / (I.gamma * z);
-  }
-  if (w == 0 && h == 0) {
-    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
-    A.colsum[pr] = kap * S1;
-    A.excess[pr] = num;
-    if (A.write_kappa) A.kappa[pr] = kap;
-    if (SNAP) {
-      A.zsnap[pr] = z;
-      A.osnap[pr] = sqrtf(O2);
-    }
-  }
-  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
-  if (__ballot(kap > 0.f) == 0ull) {
-    if ((lane >> 1) < nk && arow < gn) rp[arow] = 0.f;
-    return;
-  }
-  const int q = lane >> 4;
-#pragma unroll
-  for (int m = 0; m < (R + 1) / 2; ++m) {
-    const float va = kap * L.v[2 * m];
-    const float vb = (2 * m + 1 < R) ? kap * L.v[(2 * m + 1 < R) ? 2 * m + 1 : 0] : 0.f;
-    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(va), __float_as_uint(vb), false, false);
-    const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
-    const int k = 2 * m + (q & 1);
-    const int row = rw + 2 * NW * k + (q >> 1);
-    if ((lane & 15) == 15 && k < nk && row < gn) rp[row] = x;
-  }
-}
 
 template <int R, bool SNAP>
 __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
   __shared__ float red[3][NW][TJ];
+  __shared__ float aw[NW][WAVE];
+  __shared__ float kap_s[TJ];
   const int n = *A.count;
-  int t = blockIdx.x;
   // skip tiles of the other mode (their loads would be wasted)
   auto next_match = [&](int from) {
     int u = from;
     while (u < n && (A.inst_mode[A.list[u].inst] == EM_SNAPSHOT) != SNAP) u += gridDim.x;
     return u;
   };
-  t = next_match(t);
+  int t = next_match(blockIdx.x);
   if (t >= n) return;
   TileLoad<R> cur, nxt;
-  tile_issue<R>(A, A.list[t], cur);
+  cur.d = A.list[t];
+  tile_loads<R, 0>(A, cur.d, cur.av, cur.bj, cur.v);
   for (;;) {
     const int tn = next_match(t + gridDim.x);
-    if (tn < n) tile_issue<R>(A, A.list[tn], nxt);
-    tile_finish<R, SNAP>(A, cur, red);
+    if (tn < n) {
+      nxt.d = A.list[tn];
+      tile_loads<R, 0>(A, nxt.d, nxt.av, nxt.bj, nxt.v);
+    }
+    tile_body<R, 0, SNAP>(A, cur.d, cur.av, cur.bj, cur.v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
@@ -397,13 +334,15 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
 
 // Whole-group tiles (PHASE 0, R <= 16) whose cost tile is copied into LDS
 // by direct buffer-to-LDS loads: the copy of the next tile runs while the
-// current one is reduced from registers.  Same arithmetic as grad_tile.
+// current one's body runs from registers.  Same arithmetic as grad_tile.
 constexpr int DMA_RMAX = 16;
 
 template <int R, bool SNAP>
-__global__ void __launch_bounds__(BLOCK) k_grad_tiles_dma(GradArgs A) {
+__global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   static_assert(R <= DMA_RMAX, "LDS tile buffer sized for R <= 16");
   __shared__ float red[3][NW][TJ];
+  __shared__ float aw[NW][WAVE];
+  __shared__ float kap_s[TJ];
   __shared__ __attribute__((aligned(16))) float buf[2 * NW * R * TJ];   // 32 R rows of 32 floats
   const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -414,37 +353,45 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles_dma(GradArgs A) {
   };
   // the tile's rows are one contiguous [gn x 32] stream: 1 KB pieces (8
   // rows), piece q to LDS bytes [1024 q, 1024 q + 1024); pieces past the
-  // tile read the pool's following rows (in bounds) and land inside buf
-  auto issue = [&](int u) {
+  // tile read the pool's following rows (in bounds) and land inside buf.
+  // alpha and beta of the tile are loaded into registers alongside.
+  auto issue = [&](int u, float& av, float& bj) {
     const TileDesc d = A.list[u];
     const InstDev I = A.inst[d.inst];
-    const int gs = A.g_start[I.grp_off + d.grp];
-    const int gn = A.g_size[I.grp_off + d.grp];
-    const float* Ct = A.C + c_index(I, gs, gn, gs, d.jb * TJ);
+    const TileCtx c = tile_ctx<0>(A, I, d);
+    const int nk = c.rw < c.r1 ? min(R, (c.r1 - c.rw + 2 * NW - 1) / (2 * NW)) : 0;
+    const int arow = c.rw + 2 * NW * (lane >> 1) + (lane & 1);
+    av = ((lane >> 1) < nk && arow < c.r1) ? A.alpha[I.row_off + c.gs + arow] : -INFINITY;
+    bj = A.beta[I.col_off + c.col];
+    const float* Ct = A.C + c_index(I, c.gs, c.gn, c.gs, d.jb * TJ);
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)Ct, (short)0, 0x7fffffff, 0x00020000);
-    const int npc = __builtin_amdgcn_readfirstlane((gn + 7) / 8);
+    const int npc = __builtin_amdgcn_readfirstlane((c.gn + 7) / 8);
     for (int q = w; q < npc; q += NW)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(buf + q * 256), 16,
                                                lane * 16, q * 1024, 0, 0);
   };
   int t = match(blockIdx.x);
   if (t >= n) return;
-  issue(t);
+  float av, bj;
+  issue(t, av, bj);
   for (;;) {
     __builtin_amdgcn_s_waitcnt(0);   // this wavefront's copies have landed
     __syncthreads();                 // and everybody else's
-    TileLoad<R> L;
-    L.d = A.list[t];
+    const TileDesc d = A.list[t];
+    float v[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) L.v[k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
+    for (int k = 0; k < R; ++k) v[k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
     __syncthreads();                 // buffer free for the next tile
     const int tn = match(t + gridDim.x);
-    if (tn < n) issue(tn);
-    tile_finish<R, SNAP>(A, L, red);
+    float avn = 0.f, bjn = 0.f;
+    if (tn < n) issue(tn, avn, bjn);
+    tile_body<R, 0, SNAP>(A, d, av, bj, v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
+    av = avn;
+    bj = bjn;
   }
 }
 
