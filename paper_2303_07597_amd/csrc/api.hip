@@ -84,6 +84,7 @@ struct ot_gs_handle {
   float* C = nullptr;
   // on-the-fly cost: packed features and squared norms, per-group block offsets
   bool onthefly = false;
+  int otf_dpmax = 16;   // largest padded feature count of the instances
   float *Xp = nullptr, *Yp = nullptr, *xn = nullptr, *yn = nullptr;
   int* g_xblk = nullptr;
   float *a_int = nullptr, *b_int = nullptr;
@@ -413,6 +414,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       d.onthefly = 1;
       d.dim = p.dim;
       d.dp = (int)ceil_div(p.dim, 16) * 16;
+      h->otf_dpmax = std::max(h->otf_dpmax, d.dp);
     }
     h->inst[k].cost_mode = p.cost_mode;
     lab_off[k] = lab_tot;
@@ -918,11 +920,13 @@ static int launch_otf_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
   const int NWV = std::max(WT, 4), K = NWV / WT;
   const dim3 grid(std::max(1, std::min((n + K - 1) / K, h->tile_gm[b] * otf_resident(WT, BPW) * h->n_cu))),
       block(64 * NWV);
+  // teams of 8 or more wavefronts stage the target block in LDS
+  const size_t shm = WT >= 8 ? sizeof(float) * 32 * h->otf_dpmax : 0;
   for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
-#define OTGS_OTF(WW, BB)                                                                   \
-  if (WT == WW && BPW == BB) {                                                            \
-    if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, true>), grid, block, 0, s, A); \
-    else hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, false>), grid, block, 0, s, A);   \
+#define OTGS_OTF(WW, BB)                                                                     \
+  if (WT == WW && BPW == BB) {                                                              \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, true>), grid, block, shm, s, A); \
+    else hipLaunchKernelGGL((k_grad_tiles_otf<WW, BB, 0, false>), grid, block, shm, s, A);   \
   }
     OTGS_OTF(1, 1) OTGS_OTF(2, 1) OTGS_OTF(4, 1) OTGS_OTF(8, 1) OTGS_OTF(16, 1)
     OTGS_OTF(1, 2) OTGS_OTF(2, 2) OTGS_OTF(4, 2) OTGS_OTF(8, 2) OTGS_OTF(16, 2)
@@ -978,8 +982,9 @@ static int launch_split(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
   const dim3 g2(std::max(1, std::min(h->n_sc, gm * h->n_cu)));
   for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
     if (h->onthefly) {
-      if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, true>), g1, block, 0, s, A);
-      else hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, false>), g1, block, 0, s, A);
+      const size_t shm = sizeof(float) * 32 * h->otf_dpmax;
+      if (sp) hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, true>), g1, block, shm, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles_otf<NW, 2, 1, false>), g1, block, shm, s, A);
     } else {
       if (sp) hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, true>), g1, block, 0, s, A);
       else hipLaunchKernelGGL((k_grad_tiles<RMAX, 1, false>), g1, block, 0, s, A);

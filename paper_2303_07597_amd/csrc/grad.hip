@@ -782,6 +782,12 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
   constexpr int K = NWV / WT;
   constexpr bool snap = SNAP && PHASE != 2;
   constexpr int TB = WT * BPW;   // row blocks of a team
+  // one team of 8 or more wavefronts per workgroup: every wavefront
+  // multiplies by the same target block, staged once in LDS (dynamic
+  // shared memory of 32 dp floats); the row-sum pass of split groups, which
+  // mostly skips, reads it from global memory
+  constexpr bool YL = K == 1 && WT >= 8 && PHASE != 2;
+  extern __shared__ __attribute__((aligned(16))) float ylds[];
   // per-block partial sums; a tile's sums run over its blocks in order, so
   // the result does not depend on the team shape (WT, BPW)
   __shared__ float red[3][K * TB][TJ];
@@ -812,6 +818,14 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
     const float* xg = A.Xp + I.x_off + (size_t)A.g_xblk[I.grp_off + d.grp] * 32 * I.dp;
     const float* yb = A.Yp + I.y_off + (size_t)d.jb * 32 * I.dp;
 
+    if (YL) {
+      if (act) {
+        const float4* src = (const float4*)yb;
+        float4* dst = (float4*)ylds;
+        for (int i = threadIdx.x; i < 8 * I.dp; i += blockDim.x) dst[i] = src[i];
+      }
+      __syncthreads();
+    }
     float kap = 0.f;
     bool anyk = true;
     if (PHASE == 2 && act) {
@@ -826,7 +840,11 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
       const int i0 = r0 + 32 * (v + WT * b);   // first row of the block, in the group
       if (!act || i0 >= r1 || !anyk) continue;  // wave-uniform
       float z2 = 0.f, s1 = 0.f, o2 = 0.f;
-      const floatx16 acc = otf_dot_block<PHASE != 1>(xg + (size_t)(i0 / 32) * 32 * I.dp, yb, I.dp, lane);
+      floatx16 acc;
+      if constexpr (YL)
+        acc = otf_dot_block<PHASE != 1>(xg + (size_t)(i0 / 32) * 32 * I.dp, ylds, I.dp, lane);
+      else
+        acc = otf_dot_block<PHASE != 1>(xg + (size_t)(i0 / 32) * 32 * I.dp, yb, I.dp, lane);
       const bool rowin = i0 + c < r1;
       const float av = rowin ? A.alpha[I.row_off + gs + i0 + c] : 0.f;
       const float xv = rowin ? A.xn[I.row_off + gs + i0 + c] : 0.f;
