@@ -110,6 +110,7 @@ struct ot_gs_handle {
   int max_ns = 1, max_ntp = 64;
   int n_asm = 1;                 // assembly blocks per instance
   double* obj_part = nullptr;    // [count][n_asm]
+  unsigned int* asm_done = nullptr;   // [count] assembly blocks finished (finalising evaluations)
   // solver buffers (allocated by the first solve)
   struct Solver {
     int hist = 0, maxb = 0, ndot = 0;
@@ -744,6 +745,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   }
   h->n_asm = asm_row_blocks(h->max_ns) + asm_col_blocks(h->max_ntp);
   TRY(h->alloc(&h->obj_part, (size_t)count * h->n_asm));
+  TRY(h->alloc(&h->asm_done, count));
+  HIPCHK(hipMemsetAsync(h->asm_done, 0, sizeof(unsigned int) * count, s));
   TRY(h->alloc(&h->inst_mode, count));
   HIPCHK(hipMemsetAsync(h->inst_mode, 0, sizeof(int) * count, s));
   TRY(h->alloc(&h->alpha, h->tot_rows));
@@ -880,6 +883,7 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   R.a_uniform = h->a_uniform;
   R.b_uniform = h->b_uniform;
   R.err = h->err;
+  R.done = h->asm_done;
   return R;
 }
 
@@ -1024,7 +1028,7 @@ static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
 // work lists, then the fixed-order assembly.
 static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, float* gb_out,
                                 hipStream_t s, bool write_kappa, bool finalize = true,
-                                bool snap_possible = false) {
+                                bool snap_possible = false, double* obj_out = nullptr) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_GRAD, s, &e0));
   GradArgs A = grad_args(h);
@@ -1033,12 +1037,11 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
   TRY(tend(h, KT_GRAD, s, e0));
   TRY(tbegin(h, KT_REDUCE, s, &e0));
   ReduceArgs R = reduce_args(h, dynamic, ga_out, gb_out);
+  // finalising: the last assembly block of each instance forms D
+  R.finalize = finalize ? 1 : 0;
+  R.obj_out = obj_out;
   hipLaunchKernelGGL(k_assemble, dim3(h->n_asm, h->count), dim3(ASM_BLOCK), 0, s, R);
   LAUNCHCHK();
-  if (finalize) {
-    hipLaunchKernelGGL(k_obj_finalize, dim3(h->count), dim3(64), 0, s, R);
-    LAUNCHCHK();
-  }
   TRY(tend(h, KT_REDUCE, s, e0));
   return OT_GS_OK;
 }
@@ -1048,7 +1051,7 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
 static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float* ga_out,
                             float* gb_out, bool write_kappa = false, bool finalize = true,
                             bool snapshot_copy = true, bool group_stats = true,
-                            bool snap_possible = true) {
+                            bool snap_possible = true, double* obj_out = nullptr) {
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_SCREEN, s, &e0));
   ScreenArgs S = screen_args(h, use_lower);
@@ -1062,7 +1065,7 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
     LAUNCHCHK();
   }
   TRY(tend(h, KT_SCREEN, s, e0));
-  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa, finalize, snap_possible));
+  TRY(run_tiles_and_reduce(h, true, ga_out, gb_out, s, write_kappa, finalize, snap_possible, obj_out));
   if (!snapshot_copy) return OT_GS_OK;
   hipLaunchKernelGGL(k_snapshot_copy, dim3((unsigned)std::min<long long>(ceil_div(h->max_ns + h->max_ntp, 256), 256), h->count),
                      dim3(256), 0, s, h->d_inst, h->inst_mode, h->alpha, h->alpha_s, h->beta, h->beta_s);
@@ -1072,25 +1075,34 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
 
 // Host-directed evaluation of every instance in one mode (OT_GS_DENSE uses the
 // static work lists and needs no screen pass).
+static Prologue prologue_args(ot_gs_handle* h, int mode) {
+  return Prologue{h->inst_mode, h->count, mode, h->counters, h->tot_pairs_valid, h->tot_tiles};
+}
+
+// (prologue_done: the gather kernel already ran the prologue)
 static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hipStream_t s,
-                    bool write_kappa = false) {
-  hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, mode, h->counters,
-                     h->tot_pairs_valid, h->tot_tiles);
-  LAUNCHCHK();
+                    bool write_kappa = false, bool prologue_done = false, double* obj_out = nullptr) {
+  if (!prologue_done) {
+    hipLaunchKernelGGL(k_prologue, dim3(1), dim3(256), 0, s, h->inst_mode, h->count, mode, h->counters,
+                       h->tot_pairs_valid, h->tot_tiles);
+    LAUNCHCHK();
+  }
   if (mode != OT_GS_DENSE) {
     TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa, true, true, true,
-                         mode == OT_GS_SNAPSHOT));
+                         mode == OT_GS_SNAPSHOT, obj_out));
     if (mode == OT_GS_SNAPSHOT) h->has_snapshot = true;
     return OT_GS_OK;
   }
-  return run_tiles_and_reduce(h, false, ga_out, gb_out, s, write_kappa);
+  return run_tiles_and_reduce(h, false, ga_out, gb_out, s, write_kappa, true, false, obj_out);
 }
 
-static int gather(ot_gs_handle* h, const float* alpha, const float* beta, hipStream_t s) {
+// caller-order duals into the internal order; with mode >= 0 the same launch
+// runs the evaluation prologue for that mode
+static int gather(ot_gs_handle* h, const float* alpha, const float* beta, hipStream_t s, int mode = -1) {
   const long long maxn = std::max<long long>(h->max_ns, h->max_ntp);
   hipLaunchKernelGGL(k_gather_duals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), h->count),
                      dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, alpha, beta, h->alpha, h->beta,
-                     h->err);
+                     h->err, prologue_args(h, mode < 0 ? 0 : mode), mode >= 0 ? 1 : 0);
   LAUNCHCHK();
   return OT_GS_OK;
 }
@@ -1254,9 +1266,8 @@ int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, floa
   if (mode != OT_GS_DENSE && mode != OT_GS_SCREENED && mode != OT_GS_SNAPSHOT)
     return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", mode);
   hipStream_t s = (hipStream_t)stream;
-  TRY(gather(h, alpha, beta, s));
-  TRY(evaluate(h, mode, grad_alpha, grad_beta, s));
-  if (obj) HIPCHK(hipMemcpyAsync(obj, h->obj, sizeof(double) * h->count, hipMemcpyDeviceToDevice, s));
+  TRY(gather(h, alpha, beta, s, mode));
+  TRY(evaluate(h, mode, grad_alpha, grad_beta, s, false, true, obj));
   return OT_GS_OK;
 }
 

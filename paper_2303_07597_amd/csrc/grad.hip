@@ -481,6 +481,9 @@ struct ReduceArgs {
   const int* a_uniform;     // per instance flags
   const int* b_uniform;
   int* err;
+  unsigned int* done;       // finalize: assembly blocks finished, per instance (reset by the last)
+  double* obj_out;          // finalize: caller's copy of D (may be NULL)
+  int finalize;             // 1: the last assembly block of an instance forms D
 };
 
 constexpr int ASM_BLOCK = 256;
@@ -498,8 +501,9 @@ __host__ __device__ inline int asm_col_blocks(int ntp) { return (ntp + ASM_BLOCK
 //  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order and
 //                  the block's share of b.beta - sum_l excess_lc^2 / (2 gamma).
 // Only evaluated tiles are summed (skipped ones are exact zeros).  Each
-// block writes one float64 partial of D; k_obj_finalize (or the solver's
-// control kernel) adds them in block order.
+// block writes one float64 partial of D; when finalising, the last block of
+// an instance to finish (or else the solver's control kernel) adds them in
+// block order.
 __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   __shared__ double red[ASM_BLOCK / 64];
   const int k = blockIdx.y;
@@ -565,10 +569,33 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
+  __shared__ int last;
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < ASM_BLOCK / 64; ++w) t += red[w];
     A.obj_part[(size_t)k * A.obj_stride + b] = t;
+    last = 0;
+    if (A.finalize) {
+      // the last block of the instance to finish forms D from the partials
+      __threadfence();
+      last = atomicAdd(&A.done[k], 1u) == (unsigned)(nbr + nbc - 1);
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 64) {
+    const volatile double* parts = A.obj_part + (size_t)k * A.obj_stride;
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nbr + nbc; i += 64) t += parts[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (threadIdx.x == 0) {
+      if (!isfinite(t)) atomicOr(A.err, 4);
+      A.obj[k] = t;
+      if (A.obj_out) A.obj_out[k] = t;
+      A.done[k] = 0;
+    }
   }
 }
 
@@ -583,19 +610,31 @@ __device__ __forceinline__ double obj_from_parts(const double* parts, int n) {
   return s;
 }
 
-__global__ void __launch_bounds__(64) k_obj_finalize(ReduceArgs A) {
-  const int k = blockIdx.x;
-  const InstDev I = A.inst[k];
-  const int nparts = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
-  const double D = obj_from_parts(A.obj_part + (size_t)k * A.obj_stride, nparts);
-  if (threadIdx.x == 0) {
-    if (!isfinite(D)) atomicOr(A.err, 4);
-    A.obj[k] = D;
+
+// Host-directed evaluation prologue: every instance gets `mode`; for dense
+// evaluations the counters are advanced here (screened ones count in the
+// screen pass).
+struct Prologue {
+  int* inst_mode;
+  int count, mode;
+  long long* counters;
+  long long pairs_valid, tiles;
+};
+
+__device__ __forceinline__ void prologue_body(const Prologue& P) {
+  for (int k = threadIdx.x; k < P.count; k += blockDim.x) P.inst_mode[k] = P.mode;
+  if (threadIdx.x == 0 && P.mode == EM_DENSE) {
+    unsigned long long* C = (unsigned long long*)P.counters;
+    atomicAdd(&C[CNT_EVALS], (unsigned long long)P.count);
+    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)P.pairs_valid);
+    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)P.tiles);
+    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)P.tiles);
   }
 }
 
 // caller-order (alpha, beta) -> internal order; padding columns get 0.
-// Flags non-finite inputs.  grid.y instance.
+// Flags non-finite inputs.  grid.y instance.  With do_prologue, workgroup
+// (0, 0) also runs the evaluation prologue.
 __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict__ inst,
                                                       const int* __restrict__ perm_row,
                                                       const int* __restrict__ perm_col,
@@ -603,7 +642,8 @@ __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict_
                                                       const float* __restrict__ beta,
                                                       float* __restrict__ al_int,
                                                       float* __restrict__ be_int,
-                                                      int* __restrict__ err) {
+                                                      int* __restrict__ err, Prologue P, int do_prologue) {
+  if (do_prologue && blockIdx.x == 0 && blockIdx.y == 0) prologue_body(P);
   const InstDev I = inst[blockIdx.y];
   bool bad = false;
   for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
@@ -620,19 +660,9 @@ __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict_
   if (bad) atomicOr(err, 8);
 }
 
-// Host-directed evaluation prologue: every instance gets `mode`; for dense
-// evaluations the counters are advanced here (screened ones count in the
-// screen pass).
 __global__ void k_prologue(int* inst_mode, int count, int mode, long long* counters,
                            long long pairs_valid, long long tiles) {
-  for (int k = threadIdx.x; k < count; k += blockDim.x) inst_mode[k] = mode;
-  if (threadIdx.x == 0 && mode == EM_DENSE) {
-    unsigned long long* C = (unsigned long long*)counters;
-    atomicAdd(&C[CNT_EVALS], (unsigned long long)count);
-    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)pairs_valid);
-    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)tiles);
-    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)tiles);
-  }
+  prologue_body(Prologue{inst_mode, count, mode, counters, pairs_valid, tiles});
 }
 
 // internal order -> caller order

@@ -283,6 +283,23 @@ class Handle:
         rc = _check(lib().ot_gs_solve(self.h, ct.byref(o), _ptr(alpha), _ptr(beta), info, _stream(stream)))
         return alpha, beta, [x.as_dict() for x in info], rc
 
+    def prepare_dual_grad(self, alpha, beta, grad_alpha=None, grad_beta=None, obj=None,
+                          mode=OT_GS_DENSE, stream=None):
+        """The same call as dual_grad with its arguments marshalled once:
+        returns a function of no arguments that enqueues one evaluation
+        (for loops that evaluate at buffers whose contents change in place)."""
+        f = lib().ot_gs_dual_grad
+        args = (self.h, _ptr(alpha), _ptr(beta), _ptr(grad_alpha), _ptr(grad_beta), _ptr(obj),
+                int(mode), _stream(stream))
+        keep = (alpha, beta, grad_alpha, grad_beta, obj)
+
+        def call():
+            rc = f(*args)
+            if rc < 0:
+                _check(rc)
+            return keep
+        return call
+
     def plan(self, alpha, beta, T, stream=None):
         _check(lib().ot_gs_plan(self.h, _ptr(alpha), _ptr(beta), _ptr(T), _stream(stream)))
 

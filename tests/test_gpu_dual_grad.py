@@ -209,3 +209,22 @@ def test_argument_errors():
     with pytest.raises(O.OTGSError) as e:
         O.Handle([dict(labels=_dev(P.labels), n_groups=2, gamma=0.0, mu=0.1, cost=_dev(C32), cost_scale=1.0)])
     assert e.value.code == O.OT_GS_EINVAL
+
+
+def test_prepared_call_equals_dual_grad():
+    O = _otgs()
+    inst = synth.gaussian4_2d()
+    C32, P = cases.with_cost(inst)
+    h = make_handle(C32, P)
+    a32, b32 = cases.dual_point(P, 3)
+    ga, gb, D = gpu_grad(h, a32, b32)
+    al, be = _dev(a32), _dev(b32)
+    ga2, gb2 = torch.empty_like(al), torch.empty_like(be)
+    obj = torch.empty(1, dtype=torch.float64, device="cuda")
+    call = h.prepare_dual_grad(al, be, ga2, gb2, obj, mode=O.OT_GS_DENSE)
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ga, ga2.cpu().numpy())
+    np.testing.assert_array_equal(gb, gb2.cpu().numpy())
+    assert D[0] == obj.item()
