@@ -819,6 +819,7 @@ static GradArgs grad_args(ot_gs_handle* h) {
   A.part_stride = std::max<long long>(h->tot_chunk, 1);
   A.kappa = h->kappa;
   A.inst_mode = h->inst_mode;
+  A.single_inst = h->count == 1 ? 1 : 0;
   return A;
 }
 

@@ -47,6 +47,7 @@ struct GradArgs {
   float* kappa;           // split groups: kappa per pair
   const int* inst_mode;   // EM_SNAPSHOT: also record z~ and o~
   int write_kappa;        // also store kappa per pair (plan recovery)
+  int single_inst;        // one instance: a kernel of the other snapshot mode has no work
 };
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -306,6 +307,7 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
   __shared__ float red[3][NW][TJ];
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
+  if (A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
   const int n = *A.count;
   // skip tiles of the other mode (their loads would be wasted)
   auto next_match = [&](int from) {
@@ -344,6 +346,7 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
   __shared__ __attribute__((aligned(16))) float buf[2 * NW * R * TJ];   // 32 R rows of 32 floats
+  if (A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
   const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -405,6 +408,7 @@ __global__ void __launch_bounds__(BLOCK, R <= 16 ? 8 : 1) k_grad_tiles(GradArgs 
   __shared__ float red[3][NW][TJ];
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
+  if (PHASE != 2 && A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
   const int n = *A.count;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
@@ -821,6 +825,7 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
   // per-block partial sums; a tile's sums run over its blocks in order, so
   // the result does not depend on the team shape (WT, BPW)
   __shared__ float red[3][K * TB][TJ];
+  if (PHASE != 2 && A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
   const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
