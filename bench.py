@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--ref-iters", type=int, default=6000)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-solve", action="store_true", help="omit the time-to-tolerance solves")
+    ap.add_argument("--skip-mu-sweep", action="store_true", help="omit the mu in {0.01, 0.1, 1} sweep")
     ap.add_argument("--skip-onthefly", action="store_true",
                     help="omit the on-the-fly (matrix-core cost) workload")
     ap.add_argument("--otf-n", type=int, default=32768, help="on-the-fly workload: n_src = n_tgt")
@@ -189,6 +190,41 @@ def _problems(insts, torch, O):
     return [dict(labels=torch.from_numpy(i["labels"]).to(dev), n_groups=i["n_groups"], gamma=i["gamma"],
                  mu=i["mu"], x_src=torch.from_numpy(i["xs"]).to(dev), x_tgt=torch.from_numpy(i["xt"]).to(dev),
                  cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0) for i in insts]
+
+
+def bench_mu_sweep(args, torch, synth, O):
+    """The blobs 4096 workload at mu in {0.01, 0.1, 1}: time to 1e-6 relative
+    objective of the dense and the screened solve (same trajectory), and the
+    share of tiles and (group, target) pairs the screened solve skipped."""
+    dev = torch.device("cuda")
+    out = {}
+    for mu in (0.01, 0.1, 1.0):
+        inst = synth.blobs(seed=2, n_src=4096, n_tgt=4096, d=64, n_groups=10, gamma=0.1, mu=mu)
+        h = O.Handle([dict(labels=torch.from_numpy(inst["labels"]).to(dev), n_groups=10, gamma=0.1, mu=mu,
+                           x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
+                           cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0)])
+        K = 4000
+        res = {}
+        for name, scr in (("dense", 0), ("screened", 1)):
+            h.stats(reset=True)
+            _, _, inf, tr, tt, wall = _solve_traced(h, 1, K, torch, use_screen=scr)
+            st = h.stats(reset=True)
+            res[name] = (inf[0], tr, tt, wall, st)
+        dstar = np.array([max(np.nanmax(res["dense"][1][0]), np.nanmax(res["screened"][1][0]))])
+        row = {}
+        for name in ("dense", "screened"):
+            inf, tr, tt, wall, st = res[name]
+            its, ts = _trace_hits(tr, tt, dstar)
+            row[name] = dict(iters_to_1e6=its[0], time_to_1e6_s=ts[0], iters=inf["iters"], wall_s=wall,
+                             tiles_computed_frac=st["tiles_computed"] / max(st["tiles_total"], 1))
+            if name == "screened":
+                row[name]["pairs_skipped_frac"] = 1 - (st["pairs_unskipped"] + st["pairs_in_N"]) / max(
+                    st["pairs_total"], 1)
+        td, ts_ = row["dense"]["time_to_1e6_s"], row["screened"]["time_to_1e6_s"]
+        row["speedup_time_to_1e6"] = (td / ts_) if (td and ts_) else None
+        out[f"mu={mu:g}"] = row
+        h.close()
+    return out
 
 
 def bench_batched(args, torch, synth, O):
@@ -456,6 +492,10 @@ def main():
         torch.cuda.synchronize()
 
     log("solves done")
+    sweep = None
+    if not args.skip_solve and not args.skip_mu_sweep:
+        sweep = bench_mu_sweep(args, torch, synth, O)
+        log("mu sweep done")
     otf = None
     if not args.skip_onthefly:
         otf = bench_onthefly(args, torch, synth, O)
@@ -490,6 +530,7 @@ def main():
         cpu_baseline=cpu,
         screened_eval=screened,
         solves=solves,
+        mu_sweep=sweep,
         onthefly=otf,
         batched=batched,
         warm_start=warm,

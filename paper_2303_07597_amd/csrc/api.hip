@@ -98,6 +98,9 @@ struct ot_gs_handle {
   uint8_t *inN = nullptr, *tile_on = nullptr;
   TileDesc *tiles_all = nullptr, *list_main = nullptr, *list_sg = nullptr, *list_sc = nullptr;
   TileDesc *dyn_main = nullptr, *dyn_sg = nullptr, *dyn_sc = nullptr;
+  // records of the whole-group materialized tiles: every tile (tiles_all
+  // order), the static main list and the dynamic main list (screen output)
+  TileRec *rec_all = nullptr, *rec_main = nullptr, *rec_dyn = nullptr;
   int* counts_static = nullptr;  // [NBUCKET + 2]
   int* counts_dyn = nullptr;     // [NBUCKET + 2]
   long long* counters = nullptr;
@@ -243,6 +246,42 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
     TRY(up(h->list_main, mainl));
     TRY(up(h->list_sg, sg));
     TRY(up(h->list_sc, sc));
+    if (!h->onthefly) {
+      // tile records (split tiles keep a zero record: never read)
+      auto rec = [&](const TileDesc& t) {
+        TileRec r;
+        std::memset(&r, 0, sizeof r);
+        if (t.aux < 0) return r;
+        const InstHost& ih = h->inst[t.inst];
+        const InstDev& I = ih.d;
+        const int gs = ih.g_start[t.grp], gn = ih.g_size[t.grp];
+        r.c0 = (long long)c_index(I, gs, gn, gs, t.jb * TJ);
+        r.rp0 = I.r_off + (long long)t.jb * I.ns + gs;
+        r.pr0 = (long long)I.pair_off + (long long)t.grp * I.nt_pad + (long long)t.jb * TJ;
+        r.a0 = I.row_off + gs;
+        r.b0 = I.col_off + t.jb * TJ;
+        r.gn = gn;
+        r.ncol = std::min(TJ, I.nt - t.jb * TJ);
+        r.inst = t.inst;
+        r.thr = I.thr;
+        r.gamma = I.gamma;
+        return r;
+      };
+      std::vector<TileRec> ra, rm;
+      ra.reserve(all.size());
+      rm.reserve(mainl.size());
+      for (const TileDesc& t : all) ra.push_back(rec(t));
+      for (const TileDesc& t : mainl) rm.push_back(rec(t));
+      TRY(h->alloc(&h->rec_all, ra.size()));
+      TRY(h->alloc(&h->rec_main, rm.size()));
+      TRY(h->alloc(&h->rec_dyn, rm.size()));
+      if (!ra.empty())
+        HIPCHK(hipMemcpyAsync(h->rec_all, ra.data(), sizeof(TileRec) * ra.size(), hipMemcpyHostToDevice, s));
+      if (!rm.empty())
+        HIPCHK(hipMemcpyAsync(h->rec_main, rm.data(), sizeof(TileRec) * rm.size(), hipMemcpyHostToDevice, s));
+      // the host vectors are released when this scope ends: wait for the copies
+      HIPCHK(hipStreamSynchronize(s));
+    }
     TRY(h->alloc(&h->counts_static, NBUCKET + 2));
     TRY(h->alloc(&h->counts_dyn, NBUCKET + 2));
     int hc[NBUCKET + 2];
@@ -842,6 +881,8 @@ static ScreenArgs screen_args(ot_gs_handle* h, int use_lower) {
   S.inN = h->inN;
   S.tile_on = h->tile_on;
   S.list_main = h->dyn_main;
+  S.rec_all = h->rec_all;
+  S.rec_dyn = h->rec_dyn;
   S.list_sg = h->dyn_sg;
   S.list_sc = h->dyn_sc;
   S.counts = h->counts_dyn;
@@ -948,6 +989,18 @@ static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
   const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
   const bool pf = h->tile_var[b] == 1;
   const bool dma = h->tile_var[b] == 2 && b <= 3;
+  if (!pf && !dma && snap_possible && b <= 3) {
+    // one launch takes the tiles of both modes (R <= 16: the two bodies fit
+    // the register budget of two workgroups per compute unit)
+    switch (b) {
+      case 0: hipLaunchKernelGGL((k_grad_tiles_mixed<4>), grid, block, 0, s, A); break;
+      case 1: hipLaunchKernelGGL((k_grad_tiles_mixed<8>), grid, block, 0, s, A); break;
+      case 2: hipLaunchKernelGGL((k_grad_tiles_mixed<12>), grid, block, 0, s, A); break;
+      default: hipLaunchKernelGGL((k_grad_tiles_mixed<16>), grid, block, 0, s, A); break;
+    }
+    LAUNCHCHK();
+    return OT_GS_OK;
+  }
   for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
 #define OTGS_LAUNCH_BUCKET(RR)                                                                 \
   if (dma) {                                                                                  \
@@ -1018,6 +1071,8 @@ static int launch_tiles(ot_gs_handle* h, GradArgs A, bool dynamic, bool snap_pos
     if (h->n_bucket[b] == 0) continue;
     A.list = mlist + h->main_off[b];
     A.count = cnt + b;
+    A.rec = (dynamic ? h->rec_dyn : h->rec_main) + h->main_off[b];
+    A.n_static = dynamic ? -1 : h->n_bucket[b];
     if (h->onthefly) TRY(launch_otf_bucket(h, A, b, h->n_bucket[b], snap_possible, s));
     else TRY(launch_mat_bucket(h, A, b, h->n_bucket[b], snap_possible, s));
   }
@@ -1184,6 +1239,8 @@ static int time_bucket(ot_gs_handle* h, int b, int repeats, hipStream_t s, float
     if (b == NBUCKET) return launch_split(h, A, false, false, s);
     A.list = h->list_main + h->main_off[b];
     A.count = h->counts_static + b;
+    A.rec = h->rec_main ? h->rec_main + h->main_off[b] : nullptr;
+    A.n_static = h->n_bucket[b];
     return h->onthefly ? launch_otf_bucket(h, A, b, h->n_bucket[b], false, s)
                        : launch_mat_bucket(h, A, b, h->n_bucket[b], false, s);
   };
@@ -1535,15 +1592,20 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.gram = V.gram;
   A.alpha_s = h->alpha_s;
   A.beta_s = h->beta_s;
+  A.counters = h->counters;
   return A;
 }
 
 // One function evaluation of every live instance and one step of its solver.
 static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_screen,
                        int init_user, hipStream_t s) {
-  // the control kernel finalises D and the update kernel records snapshots
-  TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, true,
-                       use_screen != 0));
+  // the control kernel finalises D and the update kernel records snapshots;
+  // unscreened solves run every tile of the live instances from the static
+  // lists, with no screen pass
+  if (use_screen)
+    TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, true, true));
+  else
+    TRY(run_tiles_and_reduce(h, false, nullptr, nullptr, s, false, false, false, nullptr));
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;

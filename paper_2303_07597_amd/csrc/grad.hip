@@ -48,13 +48,16 @@ struct GradArgs {
   const int* inst_mode;   // EM_SNAPSHOT: also record z~ and o~
   int write_kappa;        // also store kappa per pair (plan recovery)
   int single_inst;        // one instance: a kernel of the other snapshot mode has no work
+  const TileRec* rec;     // whole-group materialized tiles: records of the list's entries
+  int n_static;           // entries of a static list (-1: read the device count)
 };
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+// Does a tile kernel of snapshot kind `snap` take a tile of an instance in
+// mode m?  Instances whose solve has ended (EM_SKIP) are never evaluated.
+__device__ __forceinline__ bool mode_takes(int m, bool snap) {
+  return m != EM_SKIP && (m == EM_SNAPSHOT) == snap;
 }
+
 
 // Sum over the 16 lanes of each lane row (DPP row shifts); lane 15 of every
 // row ends with the row's total.  Fixed order: deterministic.
@@ -101,29 +104,55 @@ __device__ __forceinline__ void transposed_row_sums(float (&v)[RP], float (&x)[R
 // kappa and the row sums once they have arrived.  Kernels either run the two
 // back to back or issue the next tile's loads before the current body.
 
-// scalar context of a tile (wavefront-uniform except the per-lane fields)
-struct TileCtx {
-  int gs, gn, r0, r1, rw, col;
-  bool colok;
+// Geometry of a tile: every index its loads and its body need (wavefront
+// uniform).  Whole-group tiles take it from their precomputed record,
+// split-group chunks from the descriptor, the instance and the group tables.
+struct TileGeo {
+  long long c0;     // cost pool index of the tile stream's first entry
+  long long rp0;    // row-partial index of the group's first row, this column block
+  long long pr0;    // pair index of the block's first column
+  long long part0;  // split chunk (PHASE 1): partial index of the block's first column
+  int a0;           // alpha index of the group's first row
+  int b0;           // beta index of the block's first column
+  int r0, r1;       // rows of the tile, relative to the group start
+  int ncol;         // valid columns of the block
+  float thr, gamma;
 };
 
+__device__ __forceinline__ TileGeo geo_rec(const TileRec& r) {
+  TileGeo g;
+  g.c0 = r.c0;
+  g.rp0 = r.rp0;
+  g.pr0 = r.pr0;
+  g.part0 = 0;
+  g.a0 = r.a0;
+  g.b0 = r.b0;
+  g.r0 = 0;
+  g.r1 = r.gn;
+  g.ncol = r.ncol;
+  g.thr = r.thr;
+  g.gamma = r.gamma;
+  return g;
+}
+
 template <int PHASE>
-__device__ __forceinline__ TileCtx tile_ctx(const GradArgs& A, const InstDev& I, const TileDesc& d) {
-  TileCtx t;
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  t.gs = A.g_start[I.grp_off + d.grp];
-  t.gn = A.g_size[I.grp_off + d.grp];
-  t.r0 = 0;
-  t.r1 = t.gn;   // rows of this tile, relative to the group start
-  if (PHASE != 0) {
-    t.r0 = d.aux * CHUNK;
-    t.r1 = min(t.r0 + CHUNK, t.gn);
-  }
-  t.col = d.jb * TJ + (lane & (TJ - 1));
-  t.colok = t.col < I.nt;
-  t.rw = t.r0 + 2 * w;   // first row of this wavefront (h = 0)
-  return t;
+__device__ __forceinline__ TileGeo geo_desc(const GradArgs& A, const TileDesc& d) {
+  const InstDev I = A.inst[d.inst];
+  const int gi = I.grp_off + d.grp;
+  const int gs = A.g_start[gi], gn = A.g_size[gi];
+  TileGeo g;
+  g.c0 = (long long)c_index(I, gs, gn, gs, d.jb * TJ);
+  g.rp0 = I.r_off + (long long)d.jb * I.ns + gs;
+  g.pr0 = (long long)I.pair_off + (long long)d.grp * I.nt_pad + d.jb * TJ;
+  g.part0 = PHASE == 1 ? I.chunk_off + (long long)(A.g_chunk0[gi] + d.aux) * I.nt_pad + d.jb * TJ : 0;
+  g.a0 = I.row_off + gs;
+  g.b0 = I.col_off + d.jb * TJ;
+  g.r0 = PHASE != 0 ? d.aux * CHUNK : 0;
+  g.r1 = PHASE != 0 ? min(g.r0 + CHUNK, gn) : gn;
+  g.ncol = min(TJ, I.nt - d.jb * TJ);
+  g.thr = I.thr;
+  g.gamma = I.gamma;
+  return g;
 }
 
 // Issue the loads of a tile: alpha of the row of load k, parity h, in lane
@@ -131,17 +160,17 @@ __device__ __forceinline__ TileCtx tile_ctx(const GradArgs& A, const InstDev& I,
 // lane's column, and the R cost values (raw buffer loads: scalar descriptor
 // at the wavefront's first row pair, a scalar offset per load; loads past
 // the tile re-read the last valid pair, a cache hit).
-template <int R, int PHASE>
-__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileDesc& d, float& av, float& bj,
+template <int R>
+__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, float& av, float& bj,
                                            float (&p)[R]) {
-  const InstDev I = A.inst[d.inst];
   const int lane = threadIdx.x & (WAVE - 1);
-  TileCtx t = tile_ctx<PHASE>(A, I, d);
-  const int nk = t.rw < t.r1 ? min(R, (t.r1 - t.rw + 2 * NW - 1) / (2 * NW)) : 0;
-  const int arow = t.rw + 2 * NW * (lane >> 1) + (lane & 1);
-  av = ((lane >> 1) < nk && arow < t.r1) ? A.alpha[I.row_off + t.gs + arow] : -INFINITY;
-  bj = A.beta[I.col_off + t.col];
-  const float* Cw = A.C + c_index(I, t.gs, t.gn, t.gs + t.rw, d.jb * TJ);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rw = g.r0 + 2 * w;   // first row of this wavefront (h = 0)
+  const int nk = rw < g.r1 ? min(R, (g.r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
+  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+  av = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+  bj = A.beta[g.b0 + (lane & (TJ - 1))];
+  const float* Cw = A.C + g.c0 + (long long)rw * TJ;
   const __amdgpu_buffer_rsrc_t rsrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
   const int stride_b = 2 * NW * TJ * 4;
@@ -153,16 +182,14 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileDesc& d,
 }
 
 template <int R, int PHASE, bool SNAP>
-__device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, float av, float bj,
+__device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, float av, float bj,
                                           float (&p)[R], float (*red)[NW][TJ], float (*aw)[WAVE],
                                           float* kap_s) {
-  const InstDev I = A.inst[d.inst];
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const TileCtx t = tile_ctx<PHASE>(A, I, d);
-  const int gs = t.gs, r1 = t.r1, rw = t.rw, col = t.col;
-  const bool colok = t.colok;
+  const int r1 = g.r1, rw = g.r0 + 2 * w;
+  const bool colok = c < g.ncol;
   const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
   const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
   constexpr bool snap = SNAP && PHASE != 2;
@@ -226,8 +253,7 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, 
       if (PHASE == 1) {
         // column partial sums of chunk `aux` of a split group
         if (h == 0) {
-          const long long q = I.chunk_off +
-                              (long long)(A.g_chunk0[I.grp_off + d.grp] + d.aux) * I.nt_pad + col;
+          const long long q = g.part0 + c;
           A.part[q] = Z2;
           A.part[q + A.part_stride] = S1;
           A.part[q + 2 * A.part_stride] = O2;
@@ -235,12 +261,12 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, 
       } else {
         const float z = sqrtf(Z2);
         float num = 0.f;
-        if (z > I.thr) {
-          num = z - I.thr;
-          kap = num / (I.gamma * z);
+        if (z > g.thr) {
+          num = z - g.thr;
+          kap = num / (g.gamma * z);
         }
         if (h == 0) {
-          const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+          const size_t pr = (size_t)(g.pr0 + c);
           A.colsum[pr] = kap * S1;
           A.excess[pr] = num;
           if (A.write_kappa) A.kappa[pr] = kap;
@@ -256,11 +282,11 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, 
     __syncthreads();
     kap = kap_s[c];
   } else {
-    kap = A.kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col];
+    kap = A.kappa[(size_t)(g.pr0 + c)];
   }
 
-  // row partials of this column block, rows relative to the instance
-  float* __restrict__ rp = A.rowpart + I.r_off + (size_t)d.jb * I.ns + gs;
+  // row partials of this column block, rows relative to the group start
+  float* __restrict__ rp = A.rowpart + g.rp0;
   if (__ballot(kap > 0.f) == 0ull) {
     // every block of the tile is zero: its row sums are exact zeros
     if ((lane >> 1) < nk && arow < r1) rp[arow] = 0.f;
@@ -284,20 +310,37 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileDesc& d, 
 }
 
 template <int R, int PHASE, bool SNAP>
-__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileDesc& d, float (*red)[NW][TJ],
+__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileGeo& g, float (*red)[NW][TJ],
                                           float (*aw)[WAVE], float* kap_s) {
   float av, bj, p[R];
-  tile_loads<R, PHASE>(A, d, av, bj, p);
+  tile_loads<R>(A, g, av, bj, p);
   // keep every load of the wavefront in flight before any is consumed
   __builtin_amdgcn_sched_barrier(0);
-  tile_body<R, PHASE, SNAP>(A, d, av, bj, p, red, aw, kap_s);
+  tile_body<R, PHASE, SNAP>(A, g, av, bj, p, red, aw, kap_s);
+}
+
+// Whole-group tiles read the list's records.  A workgroup issues the loads
+// of its first record, the tile count (dynamic lists) and the mode of a
+// single instance together; the grid never exceeds the list's capacity, so
+// the first record is in bounds even past the current count.
+struct RecStart {
+  int n, mode0;
+  TileRec r;
+};
+
+__device__ __forceinline__ RecStart rec_start(const GradArgs& A) {
+  RecStart q;
+  q.r = A.rec[blockIdx.x];
+  q.mode0 = A.inst_mode[0];
+  q.n = A.n_static >= 0 ? A.n_static : *A.count;
+  return q;
 }
 
 // Whole-group tiles (PHASE 0) with the next tile's loads in flight while the
 // current tile's body runs (same arithmetic as grad_tile).
 template <int R>
 struct TileLoad {
-  TileDesc d;
+  TileGeo g;
   float av, bj;
   float v[R];
 };
@@ -307,26 +350,28 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
   __shared__ float red[3][NW][TJ];
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
-  if (A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
-  const int n = *A.count;
+  const RecStart q = rec_start(A);
+  if (A.single_inst && !mode_takes(q.mode0, SNAP)) return;
+  const int n = q.n;
   // skip tiles of the other mode (their loads would be wasted)
   auto next_match = [&](int from) {
     int u = from;
-    while (u < n && (A.inst_mode[A.list[u].inst] == EM_SNAPSHOT) != SNAP) u += gridDim.x;
+    if (!A.single_inst)
+      while (u < n && !mode_takes(A.inst_mode[A.rec[u].inst], SNAP)) u += gridDim.x;
     return u;
   };
   int t = next_match(blockIdx.x);
   if (t >= n) return;
   TileLoad<R> cur, nxt;
-  cur.d = A.list[t];
-  tile_loads<R, 0>(A, cur.d, cur.av, cur.bj, cur.v);
+  cur.g = geo_rec(t == (int)blockIdx.x ? q.r : A.rec[t]);
+  tile_loads<R>(A, cur.g, cur.av, cur.bj, cur.v);
   for (;;) {
     const int tn = next_match(t + gridDim.x);
     if (tn < n) {
-      nxt.d = A.list[tn];
-      tile_loads<R, 0>(A, nxt.d, nxt.av, nxt.bj, nxt.v);
+      nxt.g = geo_rec(A.rec[tn]);
+      tile_loads<R>(A, nxt.g, nxt.av, nxt.bj, nxt.v);
     }
-    tile_body<R, 0, SNAP>(A, cur.d, cur.av, cur.bj, cur.v, red, aw, kap_s);
+    tile_body<R, 0, SNAP>(A, cur.g, cur.av, cur.bj, cur.v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
@@ -346,75 +391,116 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
   __shared__ __attribute__((aligned(16))) float buf[2 * NW * R * TJ];   // 32 R rows of 32 floats
-  if (A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
-  const int n = *A.count;
+  const RecStart q0 = rec_start(A);
+  if (A.single_inst && !mode_takes(q0.mode0, SNAP)) return;
+  const int n = q0.n;
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   auto match = [&](int u) {
-    while (u < n && (A.inst_mode[A.list[u].inst] == EM_SNAPSHOT) != SNAP) u += gridDim.x;
+    if (!A.single_inst)
+      while (u < n && !mode_takes(A.inst_mode[A.rec[u].inst], SNAP)) u += gridDim.x;
     return u;
   };
   // the tile's rows are one contiguous [gn x 32] stream: 1 KB pieces (8
   // rows), piece q to LDS bytes [1024 q, 1024 q + 1024); pieces past the
   // tile read the pool's following rows (in bounds) and land inside buf.
   // alpha and beta of the tile are loaded into registers alongside.
-  auto issue = [&](int u, float& av, float& bj) {
-    const TileDesc d = A.list[u];
-    const InstDev I = A.inst[d.inst];
-    const TileCtx c = tile_ctx<0>(A, I, d);
-    const int nk = c.rw < c.r1 ? min(R, (c.r1 - c.rw + 2 * NW - 1) / (2 * NW)) : 0;
-    const int arow = c.rw + 2 * NW * (lane >> 1) + (lane & 1);
-    av = ((lane >> 1) < nk && arow < c.r1) ? A.alpha[I.row_off + c.gs + arow] : -INFINITY;
-    bj = A.beta[I.col_off + c.col];
-    const float* Ct = A.C + c_index(I, c.gs, c.gn, c.gs, d.jb * TJ);
+  auto issue = [&](const TileGeo& g, float& av, float& bj) {
+    const int rw = 2 * w;
+    const int nk = rw < g.r1 ? min(R, (g.r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
+    const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+    av = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+    bj = A.beta[g.b0 + (lane & (TJ - 1))];
+    const float* Ct = A.C + g.c0;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)Ct, (short)0, 0x7fffffff, 0x00020000);
-    const int npc = __builtin_amdgcn_readfirstlane((c.gn + 7) / 8);
+    const int npc = __builtin_amdgcn_readfirstlane((g.r1 + 7) / 8);
     for (int q = w; q < npc; q += NW)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(buf + q * 256), 16,
                                                lane * 16, q * 1024, 0, 0);
   };
   int t = match(blockIdx.x);
   if (t >= n) return;
+  TileGeo g = geo_rec(t == (int)blockIdx.x ? q0.r : A.rec[t]);
   float av, bj;
-  issue(t, av, bj);
+  issue(g, av, bj);
   for (;;) {
     __builtin_amdgcn_s_waitcnt(0);   // this wavefront's copies have landed
     __syncthreads();                 // and everybody else's
-    const TileDesc d = A.list[t];
     float v[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) v[k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
     __syncthreads();                 // buffer free for the next tile
     const int tn = match(t + gridDim.x);
     float avn = 0.f, bjn = 0.f;
-    if (tn < n) issue(tn, avn, bjn);
-    tile_body<R, 0, SNAP>(A, d, av, bj, v, red, aw, kap_s);
+    TileGeo gn_ = g;
+    if (tn < n) {
+      gn_ = geo_rec(A.rec[tn]);
+      issue(gn_, avn, bjn);
+    }
+    tile_body<R, 0, SNAP>(A, g, av, bj, v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
+    g = gn_;
     av = avn;
     bj = bjn;
   }
 }
 
 // One instantiation per row bucket R (a multiple of 4) for whole-group tiles
-// (PHASE 0), R = RMAX for the two passes over split-group chunks.  SNAP
-// kernels take only the tiles of instances evaluated at a snapshot, the
-// others the rest (separate kernels keep the common path's register count
-// low enough for two workgroups per compute unit).
+// (PHASE 0, over records), R = RMAX for the two passes over split-group
+// chunks (descriptors).  SNAP kernels take only the tiles of instances
+// evaluated at a snapshot, the others the rest (separate kernels keep the
+// common path's register count low enough for two workgroups per compute
+// unit).
 template <int R, int PHASE, bool SNAP>
 __global__ void __launch_bounds__(BLOCK, R <= 16 ? 8 : 1) k_grad_tiles(GradArgs A) {
   __shared__ float red[3][NW][TJ];
   __shared__ float aw[NW][WAVE];
   __shared__ float kap_s[TJ];
-  if (PHASE != 2 && A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
+  if (PHASE == 0) {
+    const RecStart q = rec_start(A);
+    if (A.single_inst && !mode_takes(q.mode0, SNAP)) return;
+    for (int t = blockIdx.x; t < q.n; t += gridDim.x) {
+      const TileRec r = t == (int)blockIdx.x ? q.r : A.rec[t];
+      if (!A.single_inst && !mode_takes(A.inst_mode[r.inst], SNAP)) continue;
+      grad_tile<R, 0, SNAP>(A, geo_rec(r), red, aw, kap_s);
+      __syncthreads();
+    }
+    return;
+  }
+  // the row-sum pass of split groups has one variant for every mode
+  if (A.single_inst && (PHASE == 2 ? A.inst_mode[0] == EM_SKIP : !mode_takes(A.inst_mode[0], SNAP))) return;
   const int n = *A.count;
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
-    // the row-sum pass of split groups has one variant for every mode
-    if (PHASE != 2 && (A.inst_mode[d.inst] == EM_SNAPSHOT) != SNAP) continue;
-    grad_tile<R, PHASE, SNAP>(A, d, red, aw, kap_s);
+    const int m = A.inst_mode[d.inst];
+    if (PHASE == 2 ? m == EM_SKIP : !mode_takes(m, SNAP)) continue;
+    grad_tile<R, PHASE, SNAP>(A, geo_desc<PHASE>(A, d), red, aw, kap_s);
+    __syncthreads();
+  }
+}
+
+// Whole-group tiles of both kinds in one launch (evaluations where some
+// instance may be at a snapshot): the mode of a tile's instance picks the
+// body, so no launch is spent on a kind that has no tile.
+template <int R>
+__global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
+  static_assert(R <= 16, "both bodies in one kernel only for R <= 16");
+  __shared__ float red[3][NW][TJ];
+  __shared__ float aw[NW][WAVE];
+  __shared__ float kap_s[TJ];
+  const RecStart q = rec_start(A);
+  for (int t = blockIdx.x; t < q.n; t += gridDim.x) {
+    const TileRec r = t == (int)blockIdx.x ? q.r : A.rec[t];
+    const int m = A.single_inst ? q.mode0 : A.inst_mode[r.inst];
+    if (m == EM_SKIP) {
+      if (A.single_inst) return;
+      continue;
+    }
+    if (m == EM_SNAPSHOT) grad_tile<R, 0, true>(A, geo_rec(r), red, aw, kap_s);
+    else grad_tile<R, 0, false>(A, geo_rec(r), red, aw, kap_s);
     __syncthreads();
   }
 }
@@ -429,6 +515,7 @@ __global__ void __launch_bounds__(WAVE) k_split_combine(GradArgs A) {
   if (lane >= TJ) return;   // one lane per column of the tile
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const TileDesc d = A.list[t];
+    if (A.inst_mode[d.inst] == EM_SKIP) continue;
     const InstDev I = A.inst[d.inst];
     const int gn = A.g_size[I.grp_off + d.grp];
     const int nch = (gn + CHUNK - 1) / CHUNK;
@@ -569,8 +656,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     }
   }
   // fixed-order block sum
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  part = wave_sum_dd(part);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
   __syncthreads();
   __shared__ int last;
@@ -592,8 +678,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     const volatile double* parts = A.obj_part + (size_t)k * A.obj_stride;
     double t = 0.0;
     for (int i = threadIdx.x; i < nbr + nbc; i += 64) t += parts[i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    t = wave_sum_dd(t);
     if (threadIdx.x == 0) {
       if (!isfinite(t)) atomicOr(A.err, 4);
       A.obj[k] = t;
@@ -603,16 +688,9 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   }
 }
 
-// D of every instance: sum of the assembly partials in block order (one
-// wavefront per instance: strided partial sums, then a fixed xor tree).
-__device__ __forceinline__ double obj_from_parts(const double* parts, int n) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int i = lane; i < n; i += 64) s += parts[i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  return s;
-}
+// D of an instance from its assembly partials: every lane sums the
+// partials i = lane (mod 64) in order, then the fixed-order wavefront sum
+// (the same association wherever D is formed).
 
 
 // Host-directed evaluation prologue: every instance gets `mode`; for dense
@@ -825,7 +903,7 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
   // per-block partial sums; a tile's sums run over its blocks in order, so
   // the result does not depend on the team shape (WT, BPW)
   __shared__ float red[3][K * TB][TJ];
-  if (PHASE != 2 && A.single_inst && (A.inst_mode[0] == EM_SNAPSHOT) != SNAP) return;
+  if (A.single_inst && (PHASE == 2 ? A.inst_mode[0] == EM_SKIP : !mode_takes(A.inst_mode[0], SNAP))) return;
   const int n = *A.count;
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
@@ -837,7 +915,8 @@ __global__ void __launch_bounds__(64 * otf_waves<WT>(), (PHASE == 1 || BPW == 1)
     bool act = t < n;
     if (act) {
       d = A.list[t];
-      act = PHASE == 2 || (A.inst_mode[d.inst] == EM_SNAPSHOT) == SNAP;
+      const int m = A.inst_mode[d.inst];
+      act = PHASE == 2 ? m != EM_SKIP : mode_takes(m, SNAP);
     }
     const InstDev I = A.inst[d.inst];
     const int gs = A.g_start[I.grp_off + d.grp];

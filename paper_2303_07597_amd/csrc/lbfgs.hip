@@ -25,7 +25,6 @@ constexpr int HMAX = 32;
 constexpr int LB_BLOCK = 64;
 constexpr int LB_PER_THREAD = 8;
 constexpr int LB_VB = LB_BLOCK * LB_PER_THREAD;   // vector elements per dots block
-constexpr int LB_STAGE = 2048;                     // doubles of LDS staging in ctrl
 
 enum LbStatus { LB_RUNNING = 0, LB_CONVERGED = 1, LB_LSFAIL = 2, LB_MAXITER = 3 };
 
@@ -82,7 +81,7 @@ struct LbArgs {
   const float* ga;  // gradient of D at the trial point
   const float* gb;
   const double* obj;
-  double* part;  // [count][maxb][ndot]
+  double* part;  // [count][ndot][maxb] dot partials per vector block
   int maxb;
   int ndot;
   const double* obj_part;   // assembly partials of D, [count][obj_stride]
@@ -91,18 +90,13 @@ struct LbArgs {
   double* gram;             // [count][2][hist][hist]
   float* alpha_s;           // snapshot point, written at snapshot evaluations
   float* beta_s;
+  long long* counters;      // unscreened solves: evaluation counters, advanced here
 };
 
 __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }
 
 // dot slots: 0 Gt.d, 1 Gt.Gt, 2 Gt.G, 3 d.d, 4 max|Gt| (as a double),
 // 5 + 3i: Gt.s_i, 6 + 3i: Gt.y_i, 7 + 3i: d.y_i
-
-__device__ __forceinline__ double wave_sum_dd(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // element e of instance k: trial gradient of F (= -grad D)
 __device__ __forceinline__ float lb_gt(const LbArgs& A, const InstDev& I, int e) {
@@ -119,32 +113,42 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
   const int lane = threadIdx.x;
   const InstDev I = A.inst[k];
-  const LbState& S = A.st[k];
-  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
+  const long long v0 = A.voff[k];
   const int n = I.ns + I.nt_pad;
   if (b * LB_VB >= n) return;           // beyond this instance: ctrl reads no such partial
-  const long long v0 = A.voff[k];
-  const bool run = S.status == LB_RUNNING;
-  const int cnt = (run && S.phase != 0) ? S.count : 0;
   const int slot = z - 1;
-  double* out = A.part + ((size_t)k * A.maxb + b) * A.ndot;
-  if (z > 0 && slot >= cnt) {
-    if (slot < A.P.hist && lane < 3) out[5 + 3 * slot + lane] = 0.0;
-    return;
-  }
-  float gt[LB_PER_THREAD], v1[LB_PER_THREAD], v2[LB_PER_THREAD];
+  // the vectors are loaded before the state is consulted (every history slot
+  // is in bounds); the entries of an idle instance or an unused slot are
+  // dropped afterwards
+  float gt[LB_PER_THREAD], v1[LB_PER_THREAD], v2[LB_PER_THREAD], dv[LB_PER_THREAD];
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
     const int e = b * LB_VB + q * LB_BLOCK + lane;
-    const bool ok = e < n && run;
+    const bool ok = e < n;
     gt[q] = ok ? lb_gt(A, I, e) : 0.f;
     if (z == 0) {
       v1[q] = ok ? A.G[v0 + e] : 0.f;    // G
       v2[q] = ok ? A.Dv[v0 + e] : 0.f;   // d
+      dv[q] = 0.f;
     } else {
       v1[q] = ok ? A.S[(size_t)slot * A.vtot + v0 + e] : 0.f;
       v2[q] = ok ? A.Y[(size_t)slot * A.vtot + v0 + e] : 0.f;
+      dv[q] = ok ? A.Dv[v0 + e] : 0.f;   // d (for d.y_i)
     }
+  }
+  const LbState& S = A.st[k];
+  const bool run = S.status == LB_RUNNING;
+  const int cnt = (run && S.phase != 0) ? S.count : 0;
+  // partial table [count][ndot][maxb]: dot d of block b at out[d * maxb]
+  double* out = A.part + (size_t)k * A.ndot * A.maxb + b;
+  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
+  if (z > 0 && slot >= cnt) {
+    if (slot < A.P.hist && lane < 3) out[(size_t)(5 + 3 * slot + lane) * A.maxb] = 0.0;
+    return;
+  }
+  if (!run) {
+#pragma unroll
+    for (int q = 0; q < LB_PER_THREAD; ++q) gt[q] = v1[q] = v2[q] = dv[q] = 0.f;
   }
   if (z == 0) {
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
@@ -163,15 +167,12 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
     rows[lane][3] = a3;
     rows[lane][4] = (double)gm;
   } else {
-    // d is needed for d.y_i
     double s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
     for (int q = 0; q < LB_PER_THREAD; ++q) {
-      const int e = b * LB_VB + q * LB_BLOCK + lane;
-      const float dv = (e < n && run) ? A.Dv[v0 + e] : 0.f;
       s0 += (double)gt[q] * v1[q];
       s1 += (double)gt[q] * v2[q];
-      s2 += (double)dv * v2[q];
+      s2 += (double)dv[q] * v2[q];
     }
     rows[lane][0] = s0;
     rows[lane][1] = s1;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
     } else {
       for (int r = 0; r < 64; ++r) t += rows[r][lane];
     }
-    out[(z == 0 ? 0 : 5 + 3 * slot) + lane] = t;
+    out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
   }
 }
 
@@ -212,41 +213,81 @@ __device__ __forceinline__ int lb_slot(const LbState& S, int hist, int j) {
   return (S.head - S.count + j + hist) % hist;
 }
 
+// float64 value of lane l (l uniform) in every lane
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Two-loop recursion on coefficients; d = -H G.  Returns d.G.  Run by all 64
-// lanes of the control wavefront: lane i keeps the coefficients of pair slot
-// i in registers and every inner product over the slots is a fixed-order
-// wavefront reduction; the state S (LDS) is read by all lanes, written with
-// identical values.
+// lanes of the control wavefront; lane i owns pair slot i: its coefficients
+// and a running sum of the Gram terms its own inner product needs.  When a
+// step fixes the coefficient of slot p, that value is broadcast (readlane)
+// and every lane adds its term with slot p, so no step needs a reduction:
+//   first loop (newest to oldest): s_p.q = s_p.G + sum_i cy_i s_p.y_i,
+//     alpha_p = rho_p s_p.q, cy_p = -alpha_p;
+//   scaling by g0 = s.y / y.y of the newest pair;
+//   second loop (oldest to newest): y_p.r = cg y_p.G + sum_i cy_i y_p.y_i +
+//     sum_i cs_i s_i.y_p, cs_p = alpha_p - rho_p y_p.r.
+// The state S (LDS) is read by all lanes, written with identical values.
 __device__ double lb_direction(LbState& S, LbGram& G, int hist) {
   const int lane = threadIdx.x & 63;
   const int m = S.count;
   const bool mine = lane < hist;
+  const double SGl = mine ? S.SG[lane] : 0.0;
+  const double YGl = mine ? S.YG[lane] : 0.0;
+  const double rhol = mine ? S.rho[lane] : 0.0;
+  int p0 = S.head - m;   // slot of the oldest pair
+  if (p0 < 0) p0 += hist;
   double cy = 0.0, cs = 0.0, al = 0.0;
-  // q = G + sum cy_i y_i
+  double acc = 0.0;   // lane l: sum over fixed slots i of cy_i s_l.y_i
+  int p = p0 + m - 1;
+  if (p >= hist) p -= hist;
+  // each step's Gram entry is read while the previous step runs
+  double gq = (mine && m > 0) ? G.sy(lane, p) : 0.0;
   for (int j = m - 1; j >= 0; --j) {
-    const int sj = lb_slot(S, hist, j);
-    const double sq = S.SG[sj] + wave_sum_dd(mine ? cy * G.sy(sj, lane) : 0.0);
-    const double a = S.rho[sj] * sq;
-    if (lane == sj) {
+    const int pu = __builtin_amdgcn_readfirstlane(p);
+    const int pn = p == 0 ? hist - 1 : p - 1;
+    const double gn = (mine && j > 0) ? G.sy(lane, pn) : 0.0;
+    const double a = lane_d(rhol * (SGl + acc), pu);
+    if (lane == pu) {
       al = a;
-      cy -= a;
+      cy = -a;
     }
+    if (mine) acc = fma(-a, gq, acc);
+    gq = gn;
+    p = pn;
   }
   double cg = 1.0;
   if (m > 0) {
-    const int sn = lb_slot(S, hist, m - 1);
+    int sn = p0 + m - 1;
+    if (sn >= hist) sn -= hist;
     const double g0 = G.sy(sn, sn) / G.yy(sn, sn);
     cg = g0;
     cy *= g0;
   }
-  for (int j = 0; j < m; ++j) {
-    const int sj = lb_slot(S, hist, j);
-    const double yr =
-        cg * S.YG[sj] + wave_sum_dd(mine ? cy * G.yy(sj, lane) + cs * G.sy(lane, sj) : 0.0);
-    const double be = S.rho[sj] * yr;
-    if (lane == sj) cs += al - be;
+  // lane l: sum_i cy_i y_l.y_i, then the s_i.y_l terms as cs_i are fixed
+  double acc2 = 0.0;
+#pragma unroll 4
+  for (int i = 0; i < hist; ++i) {
+    const double ci = lane_d(cy, i);
+    if (mine) acc2 = fma(ci, G.yy(lane, i), acc2);
   }
-  const double dG = -cg * S.GG + wave_sum_dd(mine ? -cs * S.SG[lane] - cy * S.YG[lane] : 0.0);
+  p = p0;
+  gq = (mine && m > 0) ? G.sy(p, lane) : 0.0;
+  for (int j = 0; j < m; ++j) {
+    const int pu = __builtin_amdgcn_readfirstlane(p);
+    const int pn = p + 1 == hist ? 0 : p + 1;
+    const double gn = (mine && j + 1 < m) ? G.sy(pn, lane) : 0.0;
+    const double csp = lane_d(al - rhol * (cg * YGl + acc2), pu);
+    if (lane == pu) cs = csp;
+    if (mine) acc2 = fma(csp, gq, acc2);
+    gq = gn;
+    p = pn;
+  }
+  const double dG = -cg * S.GG + wave_sum_dd(mine ? -cs * SGl - cy * YGl : 0.0);
   S.cg = -cg;
   if (mine) {
     S.cs[lane] = -cs;
@@ -301,6 +342,16 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   const double ft = -D;
   const double Gtd = dots[0], GtGt = dots[1], GtG = dots[2], dd = dots[3];
   S.evals++;
+  if (!P.use_screen && l0) {
+    // unscreened solves evaluate every tile of the live instances without a
+    // screen pass, which would otherwise keep these counts
+    const InstDev& I = A.inst[k];
+    unsigned long long* C = (unsigned long long*)A.counters;
+    atomicAdd(&C[CNT_EVALS], 1ull);
+    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)I.Le * (unsigned long long)I.nt);
+    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)I.Le * (unsigned long long)I.njb);
+    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)I.Le * (unsigned long long)I.njb);
+  }
   const size_t tr = (size_t)k * (P.max_iter + 1);
   if (!isfinite(D) || !isfinite(GtGt)) {
     S.status = LB_LSFAIL;
@@ -475,75 +526,95 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   __shared__ double dots[5 + 3 * HMAX];
   __shared__ LbState S;
   __shared__ double gram_s[2 * HMAX * HMAX];
-  __shared__ double stage[LB_STAGE];   // chunk of the dot partials
   const int k = blockIdx.x;
-  const InstDev I = A.inst[k];
   const int h = A.P.hist;
   double* gram_g = A.gram + (size_t)k * 2 * h * h;
+  // Every load of the step is issued at once, before any is used: the
+  // state, the Gram matrices, the first PD block partials of the lane's dot
+  // (lane j: dot j, and dot j + 64) and the first PO x 64 objective
+  // partials.  Both partial tables have a fixed capacity per instance, so
+  // reads past this instance's count stay in bounds (and are ignored);
+  // larger instances take the rest in further rounds.
+  constexpr int PD = 16, PO = 4;
+  constexpr int NV = (int)(sizeof(LbState) / 16);
+  static_assert(NV <= 2 * 64, "state copy assumes at most two int4 per lane");
+  const int lane = threadIdx.x;
+  const int ng = 2 * h * h;
+  const double* pk = A.part + (size_t)k * A.ndot * A.maxb;
+  const bool has1 = lane < A.ndot, has2 = lane + 64 < A.ndot;
+  const double* p1 = pk + (size_t)lane * A.maxb;
+  const double* p2 = pk + (size_t)(lane + 64) * A.maxb;
+  const double* osrc = A.obj_part + (size_t)k * A.obj_stride;
+  int4 w0, w1;
+  double g[32], pd[PD], pd2[PD], po[PO];
   {
-    // state (int4 words) and the two Gram matrices: every load is issued
-    // before any LDS store
-    constexpr int NV = (int)(sizeof(LbState) / 16);
-    static_assert(NV <= 2 * 64, "state copy assumes at most two int4 per lane");
     const int4* src = (const int4*)&A.st[k];
-    int4* dst = (int4*)&S;
-    const int i0 = threadIdx.x, i1 = threadIdx.x + 64;
-    const int4 w0 = src[i0];
-    const int4 w1 = i1 < NV ? src[i1] : int4{0, 0, 0, 0};
-    const int ng = 2 * h * h;
-    double g[32];
+    w0 = src[lane];
+    w1 = lane + 64 < NV ? src[lane + 64] : int4{0, 0, 0, 0};
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int q = u * 64 + threadIdx.x;
+      const int q = u * 64 + lane;
       g[u] = q < ng ? gram_g[q] : 0.0;
     }
-    dst[i0] = w0;
-    if (i1 < NV) dst[i1] = w1;
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      pd[u] = (has1 && u < A.maxb) ? p1[u] : 0.0;
+      pd2[u] = (has2 && u < A.maxb) ? p2[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int i = u * 64 + lane;
+      po[u] = i < A.obj_stride ? osrc[i] : 0.0;
+    }
+  }
+  const InstDev I = A.inst[k];
+  {
+    int4* dst = (int4*)&S;
+    dst[lane] = w0;
+    if (lane + 64 < NV) dst[lane + 64] = w1;
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int q = u * 64 + threadIdx.x;
+      const int q = u * 64 + lane;
       if (q < ng) gram_s[q] = g[u];
     }
   }
   LbGram G{gram_s, gram_s + h * h, h};
-  // dot partials [nb][ndot] staged through LDS in chunks of whole blocks,
-  // then summed per dot in block order
+  // lane j: dot j summed over the vector blocks in block order (dot 4 is a
+  // maximum), and dot j + 64 likewise
   const int nb = (I.ns + I.nt_pad + LB_VB - 1) / LB_VB;
-  const int per_chunk = max(1, LB_STAGE / A.ndot);
-  double acc = 0.0;   // lane j: dot j (j < ndot <= 5 + 3 HMAX <= 101 handled below)
-  double acc2 = 0.0;  // lane j: dot j + 64
-  for (int b0 = 0; b0 < nb; b0 += per_chunk) {
-    const int nbc = min(per_chunk, nb - b0);
-    const double* src = A.part + ((size_t)k * A.maxb + b0) * A.ndot;
-    const int tot = nbc * A.ndot;
-    for (int base = 0; base < tot; base += 64 * 8) {
-      double tmp[8];
+  double acc = 0.0, acc2 = 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = base + u * 64 + threadIdx.x;
-        tmp[u] = i < tot ? src[i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = base + u * 64 + threadIdx.x;
-        if (i < tot) stage[i] = tmp[u];
-      }
+  for (int u = 0; u < PD; ++u) {
+    if (u < nb) {
+      acc = lane == 4 ? fmax(acc, pd[u]) : acc + pd[u];
+      acc2 += pd2[u];
     }
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j < A.ndot) {
-      for (int b = 0; b < nbc; ++b)
-        acc = (j == 4) ? fmax(acc, stage[b * A.ndot + j]) : acc + stage[b * A.ndot + j];
-    }
-    if (j + 64 < A.ndot) {
-      for (int b = 0; b < nbc; ++b) acc2 += stage[b * A.ndot + j + 64];
-    }
-    __syncthreads();
   }
-  if (threadIdx.x < A.ndot) dots[threadIdx.x] = acc;
-  if (threadIdx.x + 64 < A.ndot) dots[threadIdx.x + 64] = acc2;
-  const double Dobj = obj_from_parts(A.obj_part + (size_t)k * A.obj_stride,
-                                     asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad));
+  for (int b0 = PD; b0 < nb; b0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      pd[u] = (has1 && b0 + u < nb) ? p1[b0 + u] : 0.0;
+      pd2[u] = (has2 && b0 + u < nb) ? p2[b0 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      if (b0 + u < nb) {
+        acc = lane == 4 ? fmax(acc, pd[u]) : acc + pd[u];
+        acc2 += pd2[u];
+      }
+    }
+  }
+  if (has1) dots[lane] = acc;
+  if (has2) dots[lane + 64] = acc2;
+  // D: lane sums the partials i = lane (mod 64) in order, then the
+  // fixed-order wavefront sum (as wherever D is formed)
+  const int nob = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
+  double os = 0.0;
+#pragma unroll
+  for (int u = 0; u < PO; ++u)
+    if (u * 64 + lane < nob) os += po[u];
+  for (int i = PO * 64 + lane; i < nob; i += 64) os += osrc[i];
+  const double Dobj = wave_sum_dd(os);
   __syncthreads();
   if (threadIdx.x == 0) A.obj_out[k] = Dobj;
   lb_ctrl_logic(A, k, S, G, dots, Dobj);

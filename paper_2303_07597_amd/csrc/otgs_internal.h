@@ -66,6 +66,68 @@ struct TileDesc {
   int inst, grp, jb, aux;
 };
 
+// float64 lane move by a DPP pattern (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// a + b where (a, b) are the two halves of a permlane swap of x with itself:
+// every lane gets x of its row (or half) plus x of the partner row (half),
+// in the same order in both
+template <bool HALF>
+__device__ __forceinline__ double swap_sum_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  unsigned l0, l1, h0, h1;
+  if (HALF) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    l0 = rl[0]; l1 = rl[1]; h0 = rh[0]; h1 = rh[1];
+  }
+  const double a = __longlong_as_double((long long)(((unsigned long long)h0 << 32) | l0));
+  const double c = __longlong_as_double((long long)(((unsigned long long)h1 << 32) | l1));
+  return a + c;
+}
+
+// Sum over the 64 lanes, the total in every lane with identical bits: pairs
+// (xor 1), quads (xor 2), half rows and rows (mirrors), row pairs and halves
+// (permlane swaps).  Every step adds two partials that are equal across the
+// lanes of a group (addition commutes), so the order is fixed.
+__device__ __forceinline__ double wave_sum_dd(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  v = swap_sum_d<false>(v);
+  v = swap_sum_d<true>(v);
+  return v;
+}
+
+// Geometry of a whole-group tile of the materialized cost, precomputed at
+// set-up so that a workgroup reaches its cost stream after a single load
+// (instead of descriptor -> instance -> group tables -> data).
+struct alignas(16) TileRec {
+  long long c0;    // cost pool index of the tile's first entry (group row 0, block column 0)
+  long long rp0;   // row-partial index of the group's first row in this column block
+  long long pr0;   // pair index of the block's first column
+  int a0;          // alpha index (internal order) of the group's first row
+  int b0;          // beta index (internal order) of the block's first column
+  int gn;          // rows of the group
+  int ncol;        // valid columns of the block (1..TJ)
+  int inst;        // instance
+  float thr, gamma;
+  int pad[3];
+};
+static_assert(sizeof(TileRec) == 64, "TileRec is one 64-byte record");
+
 // Per-group statistics of the change since the snapshot, in float64.
 struct GroupStats {
   double up;        // || [alpha - alpha~]_+ ||  over the group

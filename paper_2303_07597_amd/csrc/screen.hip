@@ -44,6 +44,8 @@ struct ScreenArgs {
   uint8_t* inN;              // per pair
   uint8_t* tile_on;          // per group tile
   TileDesc* list_main;       // whole-group tiles, bucket b at main_off[b]
+  const TileRec* rec_all;    // records of every tile (materialized cost; else null)
+  TileRec* rec_dyn;          // records of list_main's entries
   TileDesc* list_sg;         // split group tiles (combine)
   TileDesc* list_sc;         // split chunk tiles
   int* counts;               // [NBUCKET + 2]: per bucket, split groups, split chunks
@@ -223,6 +225,7 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
       int pm = s_base[d.aux];
       for (int w = 0; w < wv; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
       A.list_main[A.main_off[d.aux] + pm] = d;
+      if (A.rec_all) A.rec_dyn[A.main_off[d.aux] + pm] = A.rec_all[t];
     } else {
       int ps = s_base[NBUCKET], pc = s_base[NBUCKET + 1];
       for (int w = 0; w < wv; ++w) {
