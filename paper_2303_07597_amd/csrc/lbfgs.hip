@@ -270,7 +270,6 @@ __device__ double lb_direction(LbState& S, LbGram& G, int hist) {
   }
   // lane l: sum_i cy_i y_l.y_i, then the s_i.y_l terms as cs_i are fixed
   double acc2 = 0.0;
-#pragma unroll 4
   for (int i = 0; i < hist; ++i) {
     const double ci = lane_d(cy, i);
     if (mine) acc2 = fma(ci, G.yy(lane, i), acc2);

@@ -111,6 +111,42 @@ __device__ __forceinline__ double wave_sum_dd(double v) {
   return v;
 }
 
+// Safe-screening bounds (Def. 1 with the rounding margins derived beside
+// the screen pass, and the lower bound of Def. 2).
+constexpr double SCR_U = 5.9604644775390625e-08;   // 2^-24
+
+// per-group constants of the rounding-safe upper bound for a group of n rows
+__device__ __forceinline__ void screen_group_consts(int n, double& sg, double& fa, double& fb) {
+  const int nch = (n + CHUNK - 1) / CHUNK;
+  const double nop = (double)n + 17.0 * nch + 16.0;
+  const double gam = nop * SCR_U / (1.0 - nop * SCR_U);
+  sg = sqrt((double)n);
+  fa = (1.0 + 2.0 * SCR_U) * sqrt(1.0 + gam) * (1.0 + 1e-9);
+  fb = 1.0 / ((1.0 - 2.0 * SCR_U) * sqrt(1.0 - gam));
+}
+
+// rounding-safe upper bound on the computed norm of block (l, j): zt the
+// snapshot norm, (b, bs) beta_j now and at the snapshot, up the group's
+// ||[alpha - alpha~]_+||, amax / amax_s the group's max |alpha|, |alpha~|
+__device__ __forceinline__ double screen_upper(double zt, double b, double bs, double up, double amax,
+                                               double amax_s, double sg, double fa, double fb,
+                                               double cmax) {
+  const double u2 = 2.01 * SCR_U;
+  const double db = b - bs;
+  return fa * (zt * fb + sg * (u2 * (amax_s + amax + 2.0 * cmax + fabs(bs) + fabs(b)) +
+                               (db > 0 ? db : 0.0)) + up);
+}
+
+// lower bound on the norm of block (l, j) (membership in N): all and dn the
+// group's ||alpha - alpha~|| and ||[alpha - alpha~]_-||, ot the snapshot
+// norm of the negative part
+__device__ __forceinline__ double screen_lower(double zt, double ot, double b, double bs, double all,
+                                               double dn, double sg) {
+  const double db = b - bs;
+  const double kt = sqrt(zt * zt + ot * ot);
+  return kt - all - sg * fabs(db) - ot - dn - sg * (db < 0 ? -db : 0.0);
+}
+
 // Geometry of a whole-group tile of the materialized cost, precomputed at
 // set-up so that a workgroup reaches its cost stream after a single load
 // (instead of descriptor -> instance -> group tables -> data).

@@ -95,13 +95,7 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
     s.amax = sm[2][0];
     s.amax_s = sm[3][0];
     // per-group constants of the rounding-safe upper bound
-    const double u = 5.9604644775390625e-08;
-    const int nch = (n + CHUNK - 1) / CHUNK;
-    const double nop = (double)n + 17.0 * nch + 16.0;
-    const double gam = nop * u / (1.0 - nop * u);
-    s.sg = sqrt((double)n);
-    s.fa = (1.0 + 2.0 * u) * sqrt(1.0 + gam) * (1.0 + 1e-9);
-    s.fb = 1.0 / ((1.0 - 2.0 * u) * sqrt(1.0 - gam));
+    screen_group_consts(n, s.sg, s.fa, s.fb);
     A.gstats[gidx] = s;
     if (ge == 0) {
       const int m = A.inst_mode[k];
@@ -144,18 +138,14 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     if (valid) {
       const GroupStats S = A.gstats[gidx];
       const double b = A.beta[I.col_off + col], bs = A.beta_s[I.col_off + col];
-      const double db = b - bs;
       const double sg = S.sg;
       const double thr = (double)I.thr;
       if (mode == EM_SNAPSHOT) {
         // Algorithm 1: rebuild N from the lower bound against the old snapshot
         uint8_t f = PAIR_SKIP;
-        if (A.use_lower) {
-          const double zt = A.zsnap[pr], ot = A.osnap[pr];
-          const double kt = sqrt(zt * zt + ot * ot);
-          const double zlow = kt - S.all - sg * fabs(db) - ot - S.dn - sg * (db < 0 ? -db : 0.0);
-          if (zlow > thr) f = PAIR_IN_N;
-        }
+        if (A.use_lower &&
+            screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, S.all, S.dn, sg) > thr)
+          f = PAIR_IN_N;
         A.inN[pr] = f;
         compute = true;
       } else if (mode == EM_DENSE) {
@@ -164,13 +154,9 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
         inN = true;
         compute = true;
       } else {
-        const double u2 = 2.01 * 5.9604644775390625e-08;
         checked = true;
-        const double zt = A.zsnap[pr];
-        const double ub = S.fa * (zt * S.fb +
-                                  S.sg * (u2 * (S.amax_s + S.amax + 2.0 * (double)I.cmax +
-                                                fabs(bs) + fabs(b)) + (db > 0 ? db : 0.0)) +
-                                  S.up);
+        const double ub = screen_upper(A.zsnap[pr], b, bs, S.up, S.amax, S.amax_s, sg, S.fa, S.fb,
+                                       (double)I.cmax);
         compute = !(ub <= thr);
       }
     }
