@@ -985,16 +985,24 @@ static int launch_otf_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
 // materialised buckets: variant 0 loads a tile when it starts, variant 1
 // keeps the next tile's loads in flight in registers during the current
 // tile, variant 2 (R <= 16) copies the next tile into LDS meanwhile (same bits)
+// materialised teams: groups of up to 128 (256) rows run as 4 (2) teams of
+// 4 (8) wavefronts per workgroup in variant 0 (same bits as one tile per
+// workgroup)
+static inline int mat_teams(int b) { return b == 0 ? 4 : b == 1 ? 2 : 1; }
+
 static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
   const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
   const bool pf = h->tile_var[b] == 1;
   const bool dma = h->tile_var[b] == 2 && b <= 3;
+  // variant 0 with teams: the grid counts workgroups of K tiles
+  const int K = (!pf && !dma) ? mat_teams(b) : 1;
+  const dim3 tgrid(std::max(1, std::min((n + K - 1) / K, h->tile_gm[b] * h->n_cu)));
   if (!pf && !dma && snap_possible && b <= 3) {
     // one launch takes the tiles of both modes (R <= 16: the two bodies fit
     // the register budget of two workgroups per compute unit)
     switch (b) {
-      case 0: hipLaunchKernelGGL((k_grad_tiles_mixed<4>), grid, block, 0, s, A); break;
-      case 1: hipLaunchKernelGGL((k_grad_tiles_mixed<8>), grid, block, 0, s, A); break;
+      case 0: hipLaunchKernelGGL((k_grad_tiles_mixed<4, 4>), tgrid, block, 0, s, A); break;
+      case 1: hipLaunchKernelGGL((k_grad_tiles_mixed<8, 2>), tgrid, block, 0, s, A); break;
       case 2: hipLaunchKernelGGL((k_grad_tiles_mixed<12>), grid, block, 0, s, A); break;
       default: hipLaunchKernelGGL((k_grad_tiles_mixed<16>), grid, block, 0, s, A); break;
     }
@@ -1010,8 +1018,9 @@ static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
     if (sp) hipLaunchKernelGGL((k_grad_tiles_pf<RR, true>), grid, block, 0, s, A);            \
     else hipLaunchKernelGGL((k_grad_tiles_pf<RR, false>), grid, block, 0, s, A);              \
   } else {                                                                                    \
-    if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true>), grid, block, 0, s, A);            \
-    else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false>), grid, block, 0, s, A);              \
+    constexpr int KK = RR == 4 ? 4 : RR == 8 ? 2 : 1;                                         \
+    if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true, KK>), tgrid, block, 0, s, A);       \
+    else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false, KK>), tgrid, block, 0, s, A);         \
   }
     switch (b) {
       case 0: OTGS_LAUNCH_BUCKET(4) break;

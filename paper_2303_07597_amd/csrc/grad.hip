@@ -155,43 +155,73 @@ __device__ __forceinline__ TileGeo geo_desc(const GradArgs& A, const TileDesc& d
   return g;
 }
 
-// Issue the loads of a tile: alpha of the row of load k, parity h, in lane
-// 2 k + h (-inf past the tile: f = -inf, p = 0 without a mask), beta of the
-// lane's column, and the R cost values (raw buffer loads: scalar descriptor
-// at the wavefront's first row pair, a scalar offset per load; loads past
-// the tile re-read the last valid pair, a cache hit).
-template <int R>
-__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, float& av, float& bj,
-                                           float (&p)[R]) {
+// Issue the loads of a tile.  A wavefront plays K of the NW "virtual"
+// wavefronts of the canonical layout (K = 1: itself): team t of NW / K real
+// wavefronts takes one tile, real wavefront v of the team plays the virtual
+// wavefronts v + (NW / K) j, j < K.  Virtual wavefront w' reads at load k the
+// two tile rows 2 (w' + NW k) + h, so every tile is summed exactly as by NW
+// wavefronts (same partials, same order, same bits) whatever K is.
+// Alpha of virtual wavefront j, load k, parity h sits in lane 2 R j + 2 k + h
+// (-inf past the tile: f = -inf, p = 0 without a mask); beta of the lane's
+// column; the R K cost values by raw buffer loads (loads past the tile
+// re-read the last valid row pair, a cache hit).  An inactive team (no tile
+// this round) loads nothing.
+template <int R, int K>
+__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, bool act, float& av,
+                                           float& bj, float (&p)[K][R]) {
+  static_assert(2 * R * K <= WAVE, "alpha of a wavefront's rows in one register");
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rw = g.r0 + 2 * w;   // first row of this wavefront (h = 0)
-  const int nk = rw < g.r1 ? min(R, (g.r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
-  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-  av = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
-  bj = A.beta[g.b0 + (lane & (TJ - 1))];
-  const float* Cw = A.C + g.c0 + (long long)rw * TJ;
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
-  const int stride_b = 2 * NW * TJ * 4;
-  const int klast = __builtin_amdgcn_readfirstlane(nk > 0 ? nk - 1 : 0);
+  constexpr int WT = NW / K;
+  const int v = w % WT;
+  if (!act) {
+    av = -INFINITY;
+    bj = -INFINITY;
 #pragma unroll
-  for (int k = 0; k < R; ++k)
-    p[k] = __uint_as_float(
-        __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int k = 0; k < R; ++k) p[j][k] = 0.f;
+    return;
+  }
+  {
+    // (K = 1: lanes past 2 R hold -inf; j stays wavefront-uniform)
+    const int j = K == 1 ? 0 : lane / (2 * R), k = K == 1 ? (lane >> 1) : (lane >> 1) % R;
+    const int rwj = g.r0 + 2 * (v + WT * j);
+    const int nkj = rwj < g.r1 ? min(R, (g.r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
+    const int arow = rwj + 2 * NW * k + (lane & 1);
+    av = (lane < 2 * R * K && k < nkj && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+  }
+  bj = A.beta[g.b0 + (lane & (TJ - 1))];
+  const int stride_b = 2 * NW * TJ * 4;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int rwj = g.r0 + 2 * (v + WT * j);
+    const int nkj = rwj < g.r1 ? min(R, (g.r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
+    const float* Cw = A.C + g.c0 + (long long)rwj * TJ;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
+    const int klast = __builtin_amdgcn_readfirstlane(nkj > 0 ? nkj - 1 : 0);
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      p[j][k] = __uint_as_float(
+          __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+  }
 }
 
-template <int R, int PHASE, bool SNAP>
-__device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, float av, float bj,
-                                          float (&p)[R], float (*red)[NW][TJ], float (*aw)[WAVE],
+// red: this team's [3][NW][TJ] partials; aw: per real wavefront alpha slot;
+// kap_s: this team's TJ kappas.  act = false: the team has no tile this
+// round and only takes part in the workgroup barriers.
+template <int R, int K, int PHASE, bool SNAP>
+__device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, bool act, float av, float bj,
+                                          float (&p)[K][R], float (*red)[NW][TJ], float (*aw)[WAVE],
                                           float* kap_s) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r1 = g.r1, rw = g.r0 + 2 * w;
-  const bool colok = c < g.ncol;
-  const int nk = rw < r1 ? min(R, (r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
-  const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
+  constexpr int WT = NW / K;
+  const int v = w % WT;
+  const int r1 = g.r1;
+  const bool colok = act && c < g.ncol;
   constexpr bool snap = SNAP && PHASE != 2;
   // this wavefront's alpha values through its own LDS slot (written and read
   // by the same wavefront: no barrier)
@@ -201,58 +231,65 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, f
   // inside are computed exactly as written); snapshots mask explicitly
   // because they also sum [f]_-
   const float bjm = colok ? bj : -INFINITY;
-  float z2 = 0.f, s1 = 0.f, o2 = 0.f;
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    // loads past the last row (k >= nk) re-read valid memory and meet
-    // alpha = -inf, so they need no branch either (snapshots skip them)
-    float pk = 0.f;
-    if (!snap || k < nk) {
-      const float ak = aw[w][2 * k + h];
-      const float f = (ak + bjm) - p[k];
-      pk = fmaxf(f, 0.f);
-      if (snap) {
-        const bool ok = (rw + 2 * NW * k + h < r1) && colok;
-        pk = ok ? pk : 0.f;
-        const float nkv = ok ? fminf(f, 0.f) : 0.f;
-        o2 = fmaf(nkv, nkv, o2);
+  for (int j = 0; j < K; ++j) {
+    const int rwj = g.r0 + 2 * (v + WT * j);
+    const int nkj = (act && rwj < r1) ? min(R, (r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
+    float z2 = 0.f, s1 = 0.f, o2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      // loads past the last row (k >= nk) re-read valid memory and meet
+      // alpha = -inf, so they need no branch either (snapshots skip them)
+      float pk = 0.f;
+      if (!snap || k < nkj) {
+        const float ak = aw[w][2 * R * j + 2 * k + h];
+        const float f = (ak + bjm) - p[j][k];
+        pk = fmaxf(f, 0.f);
+        if (snap) {
+          const bool ok = (rwj + 2 * NW * k + h < r1) && colok;
+          pk = ok ? pk : 0.f;
+          const float nkv = ok ? fminf(f, 0.f) : 0.f;
+          o2 = fmaf(nkv, nkv, o2);
+        }
+        if (PHASE != 2) {
+          z2 = fmaf(pk, pk, z2);
+          s1 += pk;
+        }
       }
-      if (PHASE != 2) {
-        z2 = fmaf(pk, pk, z2);
-        s1 += pk;
+      p[j][k] = pk;
+    }
+    if (PHASE != 2) {
+      // the two row parities of a column; virtual wavefront v + WT j's partials
+      z2 += __shfl_xor(z2, 32);
+      s1 += __shfl_xor(s1, 32);
+      if (snap) o2 += __shfl_xor(o2, 32);
+      if (h == 0) {
+        red[0][v + WT * j][c] = z2;
+        red[1][v + WT * j][c] = s1;
+        if (snap) red[2][v + WT * j][c] = o2;
       }
     }
-    p[k] = pk;
   }
 
   float kap = 0.f;
   if (PHASE != 2) {
-    // the two row parities of a column, then the wavefronts in order
-    z2 += __shfl_xor(z2, 32);
-    s1 += __shfl_xor(s1, 32);
-    if (snap) o2 += __shfl_xor(o2, 32);
-    if (h == 0) {
-      red[0][w][c] = z2;
-      red[1][w][c] = s1;
-      if (snap) red[2][w][c] = o2;
-    }
     __syncthreads();
-    // wavefront 0 sums the wavefronts' partials in order and forms kappa;
-    // the others take kappa from LDS
-    if (w == 0) {
+    // wavefront 0 of the team sums the NW virtual partials in order and
+    // forms kappa; the others take kappa from LDS
+    if (v == 0) {
       float Z2 = 0.f, S1 = 0.f, O2 = 0.f;
 #pragma unroll 4
-      for (int v = 0; v < NW; ++v) {
-        Z2 += red[0][v][c];
-        S1 += red[1][v][c];
+      for (int u = 0; u < NW; ++u) {
+        Z2 += red[0][u][c];
+        S1 += red[1][u][c];
       }
       if (snap) {
 #pragma unroll 4
-        for (int v = 0; v < NW; ++v) O2 += red[2][v][c];
+        for (int u = 0; u < NW; ++u) O2 += red[2][u][c];
       }
       if (PHASE == 1) {
         // column partial sums of chunk `aux` of a split group
-        if (h == 0) {
+        if (h == 0 && act) {
           const long long q = g.part0 + c;
           A.part[q] = Z2;
           A.part[q + A.part_stride] = S1;
@@ -266,13 +303,15 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, f
           kap = num / (g.gamma * z);
         }
         if (h == 0) {
-          const size_t pr = (size_t)(g.pr0 + c);
-          A.colsum[pr] = kap * S1;
-          A.excess[pr] = num;
-          if (A.write_kappa) A.kappa[pr] = kap;
-          if (snap) {
-            A.zsnap[pr] = z;
-            A.osnap[pr] = sqrtf(O2);
+          if (act) {
+            const size_t pr = (size_t)(g.pr0 + c);
+            A.colsum[pr] = kap * S1;
+            A.excess[pr] = num;
+            if (A.write_kappa) A.kappa[pr] = kap;
+            if (snap) {
+              A.zsnap[pr] = z;
+              A.osnap[pr] = sqrtf(O2);
+            }
           }
           kap_s[c] = kap;
         }
@@ -282,14 +321,21 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, f
     __syncthreads();
     kap = kap_s[c];
   } else {
-    kap = A.kappa[(size_t)(g.pr0 + c)];
+    kap = act ? A.kappa[(size_t)(g.pr0 + c)] : 0.f;
   }
+  if (!act) return;
 
   // row partials of this column block, rows relative to the group start
   float* __restrict__ rp = A.rowpart + g.rp0;
   if (__ballot(kap > 0.f) == 0ull) {
     // every block of the tile is zero: its row sums are exact zeros
-    if ((lane >> 1) < nk && arow < r1) rp[arow] = 0.f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int rwj = g.r0 + 2 * (v + WT * j);
+      const int nkj = rwj < r1 ? min(R, (r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
+      const int arow = rwj + 2 * NW * (lane >> 1) + (lane & 1);
+      if ((lane >> 1) < nkj && arow < r1) rp[arow] = 0.f;
+    }
     return;
   }
   // Row sums, two loads (four rows) at a time: a permlane16 swap pairs the
@@ -298,25 +344,30 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, f
   // q >> 1.
   const int q = lane >> 4;
 #pragma unroll
-  for (int m = 0; m < (R + 1) / 2; ++m) {
-    const float va = kap * p[2 * m];
-    const float vb = (2 * m + 1 < R) ? kap * p[(2 * m + 1 < R) ? 2 * m + 1 : 0] : 0.f;
-    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(va), __float_as_uint(vb), false, false);
-    const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
-    const int k = 2 * m + (q & 1);
-    const int row = rw + 2 * NW * k + (q >> 1);
-    if ((lane & 15) == 15 && k < nk && row < r1) rp[row] = x;
+  for (int j = 0; j < K; ++j) {
+    const int rwj = g.r0 + 2 * (v + WT * j);
+    const int nkj = rwj < r1 ? min(R, (r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
+#pragma unroll
+    for (int m = 0; m < (R + 1) / 2; ++m) {
+      const float va = kap * p[j][2 * m];
+      const float vb = (2 * m + 1 < R) ? kap * p[j][(2 * m + 1 < R) ? 2 * m + 1 : 0] : 0.f;
+      const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(va), __float_as_uint(vb), false, false);
+      const float x = row16_sum(__uint_as_float(sw[0]) + __uint_as_float(sw[1]));
+      const int k = 2 * m + (q & 1);
+      const int row = rwj + 2 * NW * k + (q >> 1);
+      if ((lane & 15) == 15 && k < nkj && row < r1) rp[row] = x;
+    }
   }
 }
 
-template <int R, int PHASE, bool SNAP>
-__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileGeo& g, float (*red)[NW][TJ],
-                                          float (*aw)[WAVE], float* kap_s) {
-  float av, bj, p[R];
-  tile_loads<R>(A, g, av, bj, p);
+template <int R, int K, int PHASE, bool SNAP>
+__device__ __forceinline__ void grad_tile(const GradArgs& A, const TileGeo& g, bool act,
+                                          float (*red)[NW][TJ], float (*aw)[WAVE], float* kap_s) {
+  float av, bj, p[K][R];
+  tile_loads<R, K>(A, g, act, av, bj, p);
   // keep every load of the wavefront in flight before any is consumed
   __builtin_amdgcn_sched_barrier(0);
-  tile_body<R, PHASE, SNAP>(A, g, av, bj, p, red, aw, kap_s);
+  tile_body<R, K, PHASE, SNAP>(A, g, act, av, bj, p, red, aw, kap_s);
 }
 
 // Whole-group tiles read the list's records.  A workgroup issues the loads
@@ -342,7 +393,7 @@ template <int R>
 struct TileLoad {
   TileGeo g;
   float av, bj;
-  float v[R];
+  float v[1][R];
 };
 
 template <int R, bool SNAP>
@@ -364,14 +415,14 @@ __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
   if (t >= n) return;
   TileLoad<R> cur, nxt;
   cur.g = geo_rec(t == (int)blockIdx.x ? q.r : A.rec[t]);
-  tile_loads<R>(A, cur.g, cur.av, cur.bj, cur.v);
+  tile_loads<R, 1>(A, cur.g, true, cur.av, cur.bj, cur.v);
   for (;;) {
     const int tn = next_match(t + gridDim.x);
     if (tn < n) {
       nxt.g = geo_rec(A.rec[tn]);
-      tile_loads<R>(A, nxt.g, nxt.av, nxt.bj, nxt.v);
+      tile_loads<R, 1>(A, nxt.g, true, nxt.av, nxt.bj, nxt.v);
     }
-    tile_body<R, 0, SNAP>(A, cur.g, cur.av, cur.bj, cur.v, red, aw, kap_s);
+    tile_body<R, 1, 0, SNAP>(A, cur.g, true, cur.av, cur.bj, cur.v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
@@ -427,9 +478,9 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   for (;;) {
     __builtin_amdgcn_s_waitcnt(0);   // this wavefront's copies have landed
     __syncthreads();                 // and everybody else's
-    float v[R];
+    float v[1][R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) v[k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
+    for (int k = 0; k < R; ++k) v[0][k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
     __syncthreads();                 // buffer free for the next tile
     const int tn = match(t + gridDim.x);
     float avn = 0.f, bjn = 0.f;
@@ -438,7 +489,7 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
       gn_ = geo_rec(A.rec[tn]);
       issue(gn_, avn, bjn);
     }
-    tile_body<R, 0, SNAP>(A, g, av, bj, v, red, aw, kap_s);
+    tile_body<R, 1, 0, SNAP>(A, g, true, av, bj, v, red, aw, kap_s);
     __syncthreads();
     if (tn >= n) break;
     t = tn;
@@ -453,19 +504,40 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
 // chunks (descriptors).  SNAP kernels take only the tiles of instances
 // evaluated at a snapshot, the others the rest (separate kernels keep the
 // common path's register count low enough for two workgroups per compute
-// unit).
-template <int R, int PHASE, bool SNAP>
-__global__ void __launch_bounds__(BLOCK, R <= 16 ? 8 : 1) k_grad_tiles(GradArgs A) {
-  __shared__ float red[3][NW][TJ];
+// unit).  K > 1 (small groups, PHASE 0): K teams of NW / K wavefronts, team
+// t of workgroup b taking list entries b K + t, b K + t + K gridDim.x, ...;
+// every team runs each round (an idle one only joins the barriers).
+template <int R, int PHASE, bool SNAP, int K = 1>
+__global__ void __launch_bounds__(BLOCK, R * K <= 16 ? 8 : 1) k_grad_tiles(GradArgs A) {
+  static_assert(K == 1 || PHASE == 0, "teams only for whole-group tiles");
+  __shared__ float red[K][3][NW][TJ];
   __shared__ float aw[NW][WAVE];
-  __shared__ float kap_s[TJ];
+  __shared__ float kap_s[K][TJ];
+  if (PHASE == 0 && K > 1) {
+    const int team = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) / (NW / K));
+    const int n = A.n_static >= 0 ? A.n_static : *A.count;
+    const int mode0 = A.inst_mode[0];
+    if (A.single_inst && !mode_takes(mode0, SNAP)) return;
+    for (int t0 = blockIdx.x * K; t0 < n; t0 += gridDim.x * K) {
+      const int t = t0 + team;
+      bool act = t < n;
+      TileRec r = {};
+      if (act) {
+        r = A.rec[t];
+        act = A.single_inst || mode_takes(A.inst_mode[r.inst], SNAP);
+      }
+      grad_tile<R, K, 0, SNAP>(A, geo_rec(r), act, red[team], aw, kap_s[team]);
+      __syncthreads();
+    }
+    return;
+  }
   if (PHASE == 0) {
     const RecStart q = rec_start(A);
     if (A.single_inst && !mode_takes(q.mode0, SNAP)) return;
     for (int t = blockIdx.x; t < q.n; t += gridDim.x) {
       const TileRec r = t == (int)blockIdx.x ? q.r : A.rec[t];
       if (!A.single_inst && !mode_takes(A.inst_mode[r.inst], SNAP)) continue;
-      grad_tile<R, 0, SNAP>(A, geo_rec(r), red, aw, kap_s);
+      grad_tile<R, 1, 0, SNAP>(A, geo_rec(r), true, red[0], aw, kap_s[0]);
       __syncthreads();
     }
     return;
@@ -477,20 +549,42 @@ __global__ void __launch_bounds__(BLOCK, R <= 16 ? 8 : 1) k_grad_tiles(GradArgs 
     const TileDesc d = A.list[t];
     const int m = A.inst_mode[d.inst];
     if (PHASE == 2 ? m == EM_SKIP : !mode_takes(m, SNAP)) continue;
-    grad_tile<R, PHASE, SNAP>(A, geo_desc<PHASE>(A, d), red, aw, kap_s);
+    grad_tile<R, 1, PHASE, SNAP>(A, geo_desc<PHASE>(A, d), true, red[0], aw, kap_s[0]);
     __syncthreads();
   }
 }
 
 // Whole-group tiles of both kinds in one launch (evaluations where some
 // instance may be at a snapshot): the mode of a tile's instance picks the
-// body, so no launch is spent on a kind that has no tile.
-template <int R>
+// body, so no launch is spent on a kind that has no tile.  K teams as in
+// k_grad_tiles.
+template <int R, int K = 1>
 __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
-  static_assert(R <= 16, "both bodies in one kernel only for R <= 16");
-  __shared__ float red[3][NW][TJ];
+  static_assert(R * K <= 16, "both bodies in one kernel only for R K <= 16");
+  __shared__ float red[K][3][NW][TJ];
   __shared__ float aw[NW][WAVE];
-  __shared__ float kap_s[TJ];
+  __shared__ float kap_s[K][TJ];
+  if (K > 1) {
+    const int team = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) / (NW / K));
+    const int n = A.n_static >= 0 ? A.n_static : *A.count;
+    const int mode0 = A.inst_mode[0];
+    if (A.single_inst && mode0 == EM_SKIP) return;
+    for (int t0 = blockIdx.x * K; t0 < n; t0 += gridDim.x * K) {
+      const int t = t0 + team;
+      bool act = t < n;
+      TileRec r = {};
+      int m = mode0;
+      if (act) {
+        r = A.rec[t];
+        if (!A.single_inst) m = A.inst_mode[r.inst];
+        act = m != EM_SKIP;
+      }
+      if (m == EM_SNAPSHOT) grad_tile<R, K, 0, true>(A, geo_rec(r), act, red[team], aw, kap_s[team]);
+      else grad_tile<R, K, 0, false>(A, geo_rec(r), act, red[team], aw, kap_s[team]);
+      __syncthreads();
+    }
+    return;
+  }
   const RecStart q = rec_start(A);
   for (int t = blockIdx.x; t < q.n; t += gridDim.x) {
     const TileRec r = t == (int)blockIdx.x ? q.r : A.rec[t];
@@ -499,8 +593,8 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
       if (A.single_inst) return;
       continue;
     }
-    if (m == EM_SNAPSHOT) grad_tile<R, 0, true>(A, geo_rec(r), red, aw, kap_s);
-    else grad_tile<R, 0, false>(A, geo_rec(r), red, aw, kap_s);
+    if (m == EM_SNAPSHOT) grad_tile<R, 1, 0, true>(A, geo_rec(r), true, red[0], aw, kap_s[0]);
+    else grad_tile<R, 1, 0, false>(A, geo_rec(r), true, red[0], aw, kap_s[0]);
     __syncthreads();
   }
 }

@@ -112,19 +112,29 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   __shared__ double rows[64][6];
   const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
   const int lane = threadIdx.x;
+  // the instance, its vector offset and its state are read together
   const InstDev I = A.inst[k];
   const long long v0 = A.voff[k];
+  const LbState& S = A.st[k];
+  const int st_status = S.status, st_phase = S.phase, st_count = S.count;
   const int n = I.ns + I.nt_pad;
+  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
   if (b * LB_VB >= n) return;           // beyond this instance: ctrl reads no such partial
+  const bool run = st_status == LB_RUNNING;
+  const int cnt = (run && st_phase != 0) ? st_count : 0;
   const int slot = z - 1;
-  // the vectors are loaded before the state is consulted (every history slot
-  // is in bounds); the entries of an idle instance or an unused slot are
-  // dropped afterwards
+  // partial table [count][ndot][maxb]: dot d of block b at out[d * maxb]
+  double* out = A.part + (size_t)k * A.ndot * A.maxb + b;
+  if (z > 0 && slot >= cnt) {
+    if (slot < A.P.hist && lane < 3) out[(size_t)(5 + 3 * slot + lane) * A.maxb] = 0.0;
+    return;
+  }
+  // an instance whose solve has ended loads nothing (its dots are zeros)
   float gt[LB_PER_THREAD], v1[LB_PER_THREAD], v2[LB_PER_THREAD], dv[LB_PER_THREAD];
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
     const int e = b * LB_VB + q * LB_BLOCK + lane;
-    const bool ok = e < n;
+    const bool ok = e < n && run;
     gt[q] = ok ? lb_gt(A, I, e) : 0.f;
     if (z == 0) {
       v1[q] = ok ? A.G[v0 + e] : 0.f;    // G
@@ -135,20 +145,6 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
       v2[q] = ok ? A.Y[(size_t)slot * A.vtot + v0 + e] : 0.f;
       dv[q] = ok ? A.Dv[v0 + e] : 0.f;   // d (for d.y_i)
     }
-  }
-  const LbState& S = A.st[k];
-  const bool run = S.status == LB_RUNNING;
-  const int cnt = (run && S.phase != 0) ? S.count : 0;
-  // partial table [count][ndot][maxb]: dot d of block b at out[d * maxb]
-  double* out = A.part + (size_t)k * A.ndot * A.maxb + b;
-  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
-  if (z > 0 && slot >= cnt) {
-    if (slot < A.P.hist && lane < 3) out[(size_t)(5 + 3 * slot + lane) * A.maxb] = 0.0;
-    return;
-  }
-  if (!run) {
-#pragma unroll
-    for (int q = 0; q < LB_PER_THREAD; ++q) gt[q] = v1[q] = v2[q] = dv[q] = 0.f;
   }
   if (z == 0) {
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;

@@ -109,6 +109,16 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
 
 constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
 
+// a wavefront-uniform value moved to a scalar register (every active lane
+// read the same address)
+__device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni_f(float x) { return __int_as_float(uni_i(__float_as_int(x))); }
+__device__ __forceinline__ double uni_d(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)uni_i((int)(unsigned)b), hi = (unsigned)uni_i((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // One wavefront per group tile (SCREEN_TILES per block), one lane per target
 // column.  SCREEN: classify every pair (in N / bound tested / skipped), mark
 // the tile when any pair must be evaluated.  SNAPSHOT: rebuild N from the
@@ -120,31 +130,43 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
                                            // chunks of an active split tile, tile counted
   __shared__ int s_bkt[SCREEN_TILES];
   __shared__ int s_base[NBUCKET + 2];
+  __shared__ int s_nb[NBUCKET];   // main tiles per bucket (LDS: indexed at run time)
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
   const int t = blockIdx.x * SCREEN_TILES + wv;
   const bool tile_ok = t < A.n_tiles_all;
-  TileDesc d = tile_ok ? A.tiles_all[t] : TileDesc{0, 0, 0, 0};
+  TileDesc d{0, 0, 0, 0};
+  if (tile_ok) {
+    const TileDesc dl = A.tiles_all[t];
+    d = TileDesc{uni_i(dl.inst), uni_i(dl.grp), uni_i(dl.jb), uni_i(dl.aux)};
+  }
   int c_valid = 0, c_in = 0, c_chk = 0, c_uns = 0;
   bool on = false;
+  int tile_off = 0, njb = 0;
   if (tile_ok) {
-    const InstDev I = A.inst[d.inst];
-    const int mode = A.inst_mode[d.inst];
-    const int gidx = I.grp_off + d.grp;
+    // the instance fields this pass needs, in scalar registers
+    const InstDev* Ip = A.inst + d.inst;
+    const int grp_off = uni_i(Ip->grp_off), nt = uni_i(Ip->nt), pair_off = uni_i(Ip->pair_off);
+    const int nt_pad = uni_i(Ip->nt_pad), col_off = uni_i(Ip->col_off);
+    const float ithr = uni_f(Ip->thr), cmax = uni_f(Ip->cmax);
+    tile_off = uni_i(Ip->tile_off);
+    njb = uni_i(Ip->njb);
+    const int mode = uni_i(A.inst_mode[d.inst]);
+    const int gidx = grp_off + d.grp;
     const int col = d.jb * TJ + lane;
-    const bool valid = lane < TJ && col < I.nt && mode != EM_SKIP;
-    const size_t pr = (size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col;
+    const bool valid = lane < TJ && col < nt && mode != EM_SKIP;
+    const size_t pr = (size_t)pair_off + (size_t)d.grp * nt_pad + col;
     bool inN = false, checked = false, compute = false;
     if (valid) {
-      const GroupStats S = A.gstats[gidx];
-      const double b = A.beta[I.col_off + col], bs = A.beta_s[I.col_off + col];
-      const double sg = S.sg;
-      const double thr = (double)I.thr;
+      const GroupStats* Sp = A.gstats + gidx;
+      const double b = A.beta[col_off + col], bs = A.beta_s[col_off + col];
+      const double sg = uni_d(Sp->sg);
+      const double thr = (double)ithr;
       if (mode == EM_SNAPSHOT) {
         // Algorithm 1: rebuild N from the lower bound against the old snapshot
         uint8_t f = PAIR_SKIP;
         if (A.use_lower &&
-            screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, S.all, S.dn, sg) > thr)
+            screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, uni_d(Sp->all), uni_d(Sp->dn), sg) > thr)
           f = PAIR_IN_N;
         A.inN[pr] = f;
         compute = true;
@@ -155,8 +177,8 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
         compute = true;
       } else {
         checked = true;
-        const double ub = screen_upper(A.zsnap[pr], b, bs, S.up, S.amax, S.amax_s, sg, S.fa, S.fb,
-                                       (double)I.cmax);
+        const double ub = screen_upper(A.zsnap[pr], b, bs, uni_d(Sp->up), uni_d(Sp->amax), uni_d(Sp->amax_s),
+                                       sg, uni_d(Sp->fa), uni_d(Sp->fb), (double)cmax);
         compute = !(ub <= thr);
       }
     }
@@ -165,7 +187,7 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     c_in = __popcll(__ballot(inN));
     c_chk = __popcll(__ballot(checked));
     c_uns = __popcll(__ballot(checked && compute));
-    if (lane == 0) A.tile_on[(size_t)I.tile_off + (size_t)d.grp * I.njb + d.jb] = on ? 1 : 0;
+    if (lane == 0) A.tile_on[(size_t)tile_off + (size_t)d.grp * njb + d.jb] = on ? 1 : 0;
   }
   if (lane == 0) {
     s_cnt[wv][0] = c_valid;
@@ -181,17 +203,21 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot[4] = {0, 0, 0, 0};
-    int nb[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < NBUCKET; ++q) s_nb[q] = 0;
     int nsg = 0, nsc = 0, ntile = 0, non = 0;
+    // (not unrolled: one thread, and all 128 LDS words in flight at once
+    // would take as many registers from every lane of the kernel)
+#pragma unroll 1
     for (int w = 0; w < SCREEN_TILES; ++w) {
+#pragma unroll
       for (int q = 0; q < 4; ++q) tot[q] += s_cnt[w][q];
-      if (s_cnt[w][4]) nb[s_bkt[w]]++;
+      if (s_cnt[w][4]) s_nb[s_bkt[w]]++;
       nsg += s_cnt[w][5];
       nsc += s_cnt[w][6];
       ntile += s_cnt[w][7];
       non += s_cnt[w][4] + s_cnt[w][5];
     }
-    for (int q = 0; q < NBUCKET; ++q) s_base[q] = nb[q] ? atomicAdd(&A.counts[q], nb[q]) : 0;
+    for (int q = 0; q < NBUCKET; ++q) s_base[q] = s_nb[q] ? atomicAdd(&A.counts[q], s_nb[q]) : 0;
     s_base[NBUCKET] = nsg ? atomicAdd(&A.counts[NBUCKET], nsg) : 0;
     s_base[NBUCKET + 1] = nsc ? atomicAdd(&A.counts[NBUCKET + 1], nsc) : 0;
     // counters: every block owns a slot (evaluations are ordered on the
@@ -210,8 +236,14 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     if (d.aux >= 0) {
       int pm = s_base[d.aux];
       for (int w = 0; w < wv; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
-      A.list_main[A.main_off[d.aux] + pm] = d;
-      if (A.rec_all) A.rec_dyn[A.main_off[d.aux] + pm] = A.rec_all[t];
+      // the bucket's list offset (unrolled select: a kernel-argument array
+      // indexed at run time would be copied to private memory)
+      int moff = 0;
+#pragma unroll
+      for (int q = 0; q < NBUCKET; ++q)
+        if (q == d.aux) moff = A.main_off[q];
+      A.list_main[moff + pm] = d;
+      if (A.rec_all) A.rec_dyn[moff + pm] = A.rec_all[t];
     } else {
       int ps = s_base[NBUCKET], pc = s_base[NBUCKET + 1];
       for (int w = 0; w < wv; ++w) {
