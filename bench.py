@@ -114,7 +114,7 @@ def bench_onthefly(args, torch, synth, O):
     a_pt, b_pt, _, _ = h.solve(max_iter=20, use_screen=0)
     if not args.no_autotune:
         h.autotune(repeats=3)
-    tiles_cfg = {b: h.get_tile_config(b) for b in range(9) if h.get_tile_config(b)["n_tiles"] > 0}
+    tiles_cfg = {b: h.get_tile_config(b) for b in range(O.NBUCKET + 1) if h.get_tile_config(b)["n_tiles"] > 0}
     ga, gb = torch.empty_like(a_pt), torch.empty_like(b_pt)
     obj = torch.empty(1, dtype=torch.float64, device=dev)
     for _ in range(3):
@@ -396,7 +396,7 @@ def main():
     torch.cuda.synchronize()
     if not args.no_autotune:
         h.autotune(repeats=20)
-    tiles_cfg = {b: h.get_tile_config(b) for b in range(9) if h.get_tile_config(b)["n_tiles"] > 0}
+    tiles_cfg = {b: h.get_tile_config(b) for b in range(O.NBUCKET + 1) if h.get_tile_config(b)["n_tiles"] > 0}
 
     ga = torch.empty_like(a_pt)
     gb = torch.empty_like(b_pt)

@@ -74,8 +74,8 @@ struct ot_gs_handle {
   long long tot_rows = 0, tot_cols = 0, tot_cols_pad = 0, tot_groups = 0, tot_pairs = 0,
             tot_tiles = 0, tot_c = 0, tot_r = 0, tot_chunk = 0, tot_x = 0, tot_y = 0;
   int n_main = 0, n_sg = 0, n_sc = 0;
-  int n_bucket[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int main_off[NBUCKET] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int n_bucket[NBUCKET] = {};
+  int main_off[NBUCKET] = {};
   int dev = 0, n_cu = 256;
   // device arrays
   InstDev* d_inst = nullptr;
@@ -133,8 +133,8 @@ struct ot_gs_handle {
   // tile configuration (autotuned or set): per bucket of the tile lists the
   // team-shape variant (on-the-fly) and the grid multiplier (workgroups per
   // resident slot); index NBUCKET: the split-group passes
-  int tile_var[NBUCKET + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int tile_gm[NBUCKET + 1] = {2, 2, 2, 2, 2, 2, 2, 2, 2};
+  int tile_var[NBUCKET + 1] = {};
+  int tile_gm[NBUCKET + 1] = {};   // set to 2 at create
 
   template <class T>
   int alloc(T** p, size_t n) {
@@ -420,6 +420,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     if ((probs[k].cost_mode == OT_GS_COST_ONTHEFLY) != otf)
       return fail(OT_GS_EINVAL, "instance %d: COST_ONTHEFLY cannot be mixed with materialized costs in one handle", k);
   auto* h = new ot_gs_handle();
+  for (int b = 0; b <= NBUCKET; ++b) h->tile_gm[b] = 2;   // workgroups per resident slot
   std::unique_ptr<ot_gs_handle> guard(h);
   h->onthefly = otf;
   h->count = count;
@@ -938,7 +939,9 @@ static int otf_variants(int b) { return (b >= 1 && b <= 4) ? 2 : 1; }
 // variants of a bucket of this handle's tile lists
 static int tile_variants(const ot_gs_handle* h, int b) {
   if (b >= NBUCKET) return 1;
-  return h->onthefly ? (b < OTF_NBUCKET ? otf_variants(b) : 1) : (b <= 3 ? 3 : 2);
+  if (h->onthefly) return b < OTF_NBUCKET ? otf_variants(b) : 1;
+  // R = 2: teams only; R <= 16: plain, next tile in flight, LDS copy; else two
+  return bucket_R(b) <= 2 ? 1 : bucket_R(b) <= 16 ? 3 : 2;
 }
 
 static void otf_shape(int b, int var, int* WT, int* BPW) {
@@ -985,54 +988,59 @@ static int launch_otf_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
 // materialised buckets: variant 0 loads a tile when it starts, variant 1
 // keeps the next tile's loads in flight in registers during the current
 // tile, variant 2 (R <= 16) copies the next tile into LDS meanwhile (same bits)
-// materialised teams: groups of up to 128 (256) rows run as 4 (2) teams of
-// 4 (8) wavefronts per workgroup in variant 0 (same bits as one tile per
-// workgroup)
-static inline int mat_teams(int b) { return b == 0 ? 4 : b == 1 ? 2 : 1; }
+// materialised buckets: variant 0 runs bucket_K(b) teams per workgroup
+// (groups of up to 64, 128, 256 rows: 8, 4, 2 teams; same bits as one tile
+// per workgroup), variant 1 keeps the next tile's loads in flight
+// in registers during the current tile, variant 2 (R <= 16) copies the next
+// tile into LDS meanwhile
+template <int B>
+static void launch_mat_b(GradArgs A, dim3 grid, dim3 tgrid, dim3 block, bool pf, bool dma, bool mixed, int sp,
+                         hipStream_t s) {
+  constexpr int RR = bucket_R(B), KK = bucket_K(B);
+  if constexpr (RR >= 4) {
+    if (dma) {
+      if (sp) hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), true>), grid, block, 0, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), false>), grid, block, 0, s, A);
+      return;
+    }
+    if (pf) {
+      if (sp) hipLaunchKernelGGL((k_grad_tiles_pf<RR, true>), grid, block, 0, s, A);
+      else hipLaunchKernelGGL((k_grad_tiles_pf<RR, false>), grid, block, 0, s, A);
+      return;
+    }
+  }
+  if constexpr (RR <= 16) {
+    if (mixed) {
+      hipLaunchKernelGGL((k_grad_tiles_mixed<RR, KK>), tgrid, block, 0, s, A);
+      return;
+    }
+  }
+  if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true, KK>), tgrid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false, KK>), tgrid, block, 0, s, A);
+}
 
 static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
   const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
-  const bool pf = h->tile_var[b] == 1;
-  const bool dma = h->tile_var[b] == 2 && b <= 3;
+  const bool pf = h->tile_var[b] == 1 && bucket_R(b) >= 4;
+  const bool dma = h->tile_var[b] == 2 && bucket_R(b) >= 4 && bucket_R(b) <= 16;
   // variant 0 with teams: the grid counts workgroups of K tiles
-  const int K = (!pf && !dma) ? mat_teams(b) : 1;
+  const int K = (!pf && !dma) ? bucket_K(b) : 1;
   const dim3 tgrid(std::max(1, std::min((n + K - 1) / K, h->tile_gm[b] * h->n_cu)));
-  if (!pf && !dma && snap_possible && b <= 3) {
-    // one launch takes the tiles of both modes (R <= 16: the two bodies fit
-    // the register budget of two workgroups per compute unit)
+  // one launch takes the tiles of both modes when both bodies fit the
+  // register budget of two workgroups per compute unit (R <= 16)
+  const bool mixed = !pf && !dma && snap_possible && bucket_R(b) <= 16;
+  for (int sp = 0; sp < ((snap_possible && !mixed) ? 2 : 1); ++sp) {
     switch (b) {
-      case 0: hipLaunchKernelGGL((k_grad_tiles_mixed<4, 4>), tgrid, block, 0, s, A); break;
-      case 1: hipLaunchKernelGGL((k_grad_tiles_mixed<8, 2>), tgrid, block, 0, s, A); break;
-      case 2: hipLaunchKernelGGL((k_grad_tiles_mixed<12>), grid, block, 0, s, A); break;
-      default: hipLaunchKernelGGL((k_grad_tiles_mixed<16>), grid, block, 0, s, A); break;
+      case 0: launch_mat_b<0>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 1: launch_mat_b<1>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 2: launch_mat_b<2>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 3: launch_mat_b<3>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 4: launch_mat_b<4>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 5: launch_mat_b<5>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 6: launch_mat_b<6>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 7: launch_mat_b<7>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      default: launch_mat_b<8>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
     }
-    LAUNCHCHK();
-    return OT_GS_OK;
-  }
-  for (int sp = 0; sp < (snap_possible ? 2 : 1); ++sp) {
-#define OTGS_LAUNCH_BUCKET(RR)                                                                 \
-  if (dma) {                                                                                  \
-    if (sp) hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), true>), grid, block, 0, s, A);  \
-    else hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), false>), grid, block, 0, s, A);    \
-  } else if (pf) {                                                                            \
-    if (sp) hipLaunchKernelGGL((k_grad_tiles_pf<RR, true>), grid, block, 0, s, A);            \
-    else hipLaunchKernelGGL((k_grad_tiles_pf<RR, false>), grid, block, 0, s, A);              \
-  } else {                                                                                    \
-    constexpr int KK = RR == 4 ? 4 : RR == 8 ? 2 : 1;                                         \
-    if (sp) hipLaunchKernelGGL((k_grad_tiles<RR, 0, true, KK>), tgrid, block, 0, s, A);       \
-    else hipLaunchKernelGGL((k_grad_tiles<RR, 0, false, KK>), tgrid, block, 0, s, A);         \
-  }
-    switch (b) {
-      case 0: OTGS_LAUNCH_BUCKET(4) break;
-      case 1: OTGS_LAUNCH_BUCKET(8) break;
-      case 2: OTGS_LAUNCH_BUCKET(12) break;
-      case 3: OTGS_LAUNCH_BUCKET(16) break;
-      case 4: OTGS_LAUNCH_BUCKET(20) break;
-      case 5: OTGS_LAUNCH_BUCKET(24) break;
-      case 6: OTGS_LAUNCH_BUCKET(28) break;
-      default: OTGS_LAUNCH_BUCKET(32) break;
-    }
-#undef OTGS_LAUNCH_BUCKET
     LAUNCHCHK();
   }
   return OT_GS_OK;
@@ -1125,7 +1133,7 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
       hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
       LAUNCHCHK();
     }
-    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TILES)),
+    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TPB)),
                        dim3(SCREEN_TILES * 64), 0, s, S);
     LAUNCHCHK();
   }

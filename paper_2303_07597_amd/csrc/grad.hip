@@ -192,19 +192,21 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
     av = (lane < 2 * R * K && k < nkj && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
   }
   bj = A.beta[g.b0 + (lane & (TJ - 1))];
+  // one descriptor at the tile's first row; every load a scalar byte offset
+  const float* Ct = A.C + g.c0 + (long long)g.r0 * TJ;
+  const __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Ct, (short)0, 0x7fffffff, 0x00020000);
   const int stride_b = 2 * NW * TJ * 4;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int rwj = g.r0 + 2 * (v + WT * j);
     const int nkj = rwj < g.r1 ? min(R, (g.r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
-    const float* Cw = A.C + g.c0 + (long long)rwj * TJ;
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)Cw, (short)0, 0x7fffffff, 0x00020000);
+    const int base = __builtin_amdgcn_readfirstlane((rwj - g.r0) * TJ * 4);
     const int klast = __builtin_amdgcn_readfirstlane(nkj > 0 ? nkj - 1 : 0);
 #pragma unroll
     for (int k = 0; k < R; ++k)
       p[j][k] = __uint_as_float(
-          __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, min(k, klast) * stride_b, 0));
+          __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, base + min(k, klast) * stride_b, 0));
   }
 }
 
@@ -231,6 +233,7 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, b
   // inside are computed exactly as written); snapshots mask explicitly
   // because they also sum [f]_-
   const float bjm = colok ? bj : -INFINITY;
+  static_assert(WT > 1, "teams of at least two wavefronts");
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     const int rwj = g.r0 + 2 * (v + WT * j);

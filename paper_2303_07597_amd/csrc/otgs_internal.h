@@ -25,8 +25,8 @@ constexpr int NW = 16;                 // waves per gradient workgroup
 constexpr int BLOCK = NW * WAVE;       // 1024 threads
 constexpr int RMAX = 32;               // rows per thread in the largest class
 constexpr int CHUNK = 2 * NW * RMAX;   // 1024: largest group handled in one pass
-constexpr int RSTEP = 4;               // row buckets: R = 4, 8, ..., 32 rows per lane
-constexpr int NBUCKET = RMAX / RSTEP;  // 8
+constexpr int RSTEP = 4;               // row buckets: R = 2, 4, 8, ..., 32 loads per lane
+constexpr int NBUCKET = 1 + RMAX / RSTEP;   // 9
 constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
 constexpr int DP_MAX = 256;            // on-the-fly cost: padded feature dims
 
@@ -194,12 +194,24 @@ __host__ __device__ inline size_t c_index(const InstDev& I, int gs, int gn, int 
          (size_t)(r - gs) * TJ + (size_t)(c % TJ);
 }
 
-// row bucket of a whole-group tile: b such that R = RSTEP (b + 1) is the
-// smallest multiple of RSTEP with 2 NW R >= rows (two rows per load)
+// loads per lane (per virtual wavefront) of row bucket b: 2, then the
+// multiples of RSTEP up to RMAX
+__host__ __device__ constexpr int bucket_R(int b) { return b == 0 ? 2 : RSTEP * b; }
+
+// row bucket of a whole-group tile: the smallest bucket_R(b) with
+// 2 NW R >= rows (two rows per load)
 __host__ __device__ inline int row_bucket(int rows) {
   const int r = (rows + 2 * NW - 1) / (2 * NW);
-  return r <= RSTEP ? 0 : (r + RSTEP - 1) / RSTEP - 1;
+  return r <= 2 ? 0 : (r + RSTEP - 1) / RSTEP;
 }
+
+// teams of a row bucket: K tiles per workgroup, NW / K wavefronts each
+// (R K <= 16 keeps two workgroups per compute unit; a team keeps at least
+// two wavefronts)
+__host__ __device__ constexpr int bucket_K(int b) {
+  return bucket_R(b) <= 16 && 16 % bucket_R(b) == 0 ? 16 / bucket_R(b) : 1;
+}
+static_assert(bucket_K(0) <= NW / 2, "teams of at least two wavefronts");
 
 // on-the-fly tiles: bucket b < 5 holds whole groups of up to 32 << b rows,
 // one per team of 1 << b wavefronts with one 32-row block each; bucket 5

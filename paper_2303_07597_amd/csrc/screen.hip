@@ -109,64 +109,53 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
 
 constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
 
-// a wavefront-uniform value moved to a scalar register (every active lane
-// read the same address)
-__device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float uni_f(float x) { return __int_as_float(uni_i(__float_as_int(x))); }
-__device__ __forceinline__ double uni_d(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)uni_i((int)(unsigned)b), hi = (unsigned)uni_i((int)(unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
-// One wavefront per group tile (SCREEN_TILES per block), one lane per target
-// column.  SCREEN: classify every pair (in N / bound tested / skipped), mark
-// the tile when any pair must be evaluated.  SNAPSHOT: rebuild N from the
-// lower bound, then evaluate densely.  DENSE: every tile.  SKIP: nothing.
-// Active tiles are appended to the work lists; counters and list positions
-// are aggregated per block so each block issues one atomic per quantity.
+constexpr int SCREEN_TPB = 2 * SCREEN_TILES;   // group tiles per screen block
+
+// One half wavefront per group tile (SCREEN_TPB per block: only 32 lanes of
+// a tile have a column), one lane per target column.  SCREEN: classify
+// every pair (in N / bound tested / skipped), mark the tile when any pair
+// must be evaluated.  SNAPSHOT: rebuild N from the lower bound, then
+// evaluate densely.  DENSE: every tile.  SKIP: nothing.  Active tiles are
+// appended to the work lists; counters and list positions are aggregated
+// per block so each block issues one atomic per quantity.
 __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A) {
-  __shared__ int s_cnt[SCREEN_TILES][8];   // valid, inN, checked, unskipped, main, split,
-                                           // chunks of an active split tile, tile counted
-  __shared__ int s_bkt[SCREEN_TILES];
+  __shared__ int s_cnt[SCREEN_TPB][8];   // valid, inN, checked, unskipped, main, split,
+                                         // chunks of an active split tile, tile counted
+  __shared__ int s_bkt[SCREEN_TPB];
   __shared__ int s_base[NBUCKET + 2];
   __shared__ int s_nb[NBUCKET];   // main tiles per bucket (LDS: indexed at run time)
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
-  const int t = blockIdx.x * SCREEN_TILES + wv;
+  const int half = lane >> 5, c = lane & (TJ - 1);
+  const int slot = 2 * wv + half;   // the tile's slot in the block
+  const int t = blockIdx.x * SCREEN_TPB + slot;
   const bool tile_ok = t < A.n_tiles_all;
   TileDesc d{0, 0, 0, 0};
+  if (tile_ok) d = A.tiles_all[t];
+  int mode = EM_SKIP, tile_off = 0, njb = 0;
+  bool valid = false, inN = false, checked = false, compute = false;
   if (tile_ok) {
-    const TileDesc dl = A.tiles_all[t];
-    d = TileDesc{uni_i(dl.inst), uni_i(dl.grp), uni_i(dl.jb), uni_i(dl.aux)};
-  }
-  int c_valid = 0, c_in = 0, c_chk = 0, c_uns = 0;
-  bool on = false;
-  int tile_off = 0, njb = 0;
-  if (tile_ok) {
-    // the instance fields this pass needs, in scalar registers
     const InstDev* Ip = A.inst + d.inst;
-    const int grp_off = uni_i(Ip->grp_off), nt = uni_i(Ip->nt), pair_off = uni_i(Ip->pair_off);
-    const int nt_pad = uni_i(Ip->nt_pad), col_off = uni_i(Ip->col_off);
-    const float ithr = uni_f(Ip->thr), cmax = uni_f(Ip->cmax);
-    tile_off = uni_i(Ip->tile_off);
-    njb = uni_i(Ip->njb);
-    const int mode = uni_i(A.inst_mode[d.inst]);
+    const int grp_off = Ip->grp_off, nt = Ip->nt, pair_off = Ip->pair_off;
+    const int nt_pad = Ip->nt_pad, col_off = Ip->col_off;
+    const float ithr = Ip->thr, cmax = Ip->cmax;
+    tile_off = Ip->tile_off;
+    njb = Ip->njb;
+    mode = A.inst_mode[d.inst];
     const int gidx = grp_off + d.grp;
-    const int col = d.jb * TJ + lane;
-    const bool valid = lane < TJ && col < nt && mode != EM_SKIP;
+    const int col = d.jb * TJ + c;
+    valid = col < nt && mode != EM_SKIP;
     const size_t pr = (size_t)pair_off + (size_t)d.grp * nt_pad + col;
-    bool inN = false, checked = false, compute = false;
     if (valid) {
       const GroupStats* Sp = A.gstats + gidx;
       const double b = A.beta[col_off + col], bs = A.beta_s[col_off + col];
-      const double sg = uni_d(Sp->sg);
+      const double sg = Sp->sg;
       const double thr = (double)ithr;
       if (mode == EM_SNAPSHOT) {
         // Algorithm 1: rebuild N from the lower bound against the old snapshot
         uint8_t f = PAIR_SKIP;
-        if (A.use_lower &&
-            screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, uni_d(Sp->all), uni_d(Sp->dn), sg) > thr)
+        if (A.use_lower && screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, Sp->all, Sp->dn, sg) > thr)
           f = PAIR_IN_N;
         A.inN[pr] = f;
         compute = true;
@@ -177,38 +166,39 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
         compute = true;
       } else {
         checked = true;
-        const double ub = screen_upper(A.zsnap[pr], b, bs, uni_d(Sp->up), uni_d(Sp->amax), uni_d(Sp->amax_s),
-                                       sg, uni_d(Sp->fa), uni_d(Sp->fb), (double)cmax);
+        const double ub = screen_upper(A.zsnap[pr], b, bs, Sp->up, Sp->amax, Sp->amax_s, sg, Sp->fa,
+                                       Sp->fb, (double)cmax);
         compute = !(ub <= thr);
       }
     }
-    on = __ballot(compute) != 0ull;
-    c_valid = __popcll(__ballot(valid));
-    c_in = __popcll(__ballot(inN));
-    c_chk = __popcll(__ballot(checked));
-    c_uns = __popcll(__ballot(checked && compute));
-    if (lane == 0) A.tile_on[(size_t)tile_off + (size_t)d.grp * njb + d.jb] = on ? 1 : 0;
   }
-  if (lane == 0) {
-    s_cnt[wv][0] = c_valid;
-    s_cnt[wv][1] = c_in;
-    s_cnt[wv][2] = c_chk;
-    s_cnt[wv][3] = c_uns;
-    s_cnt[wv][4] = (on && d.aux >= 0) ? 1 : 0;
-    s_cnt[wv][5] = (on && d.aux < 0) ? 1 : 0;
-    s_cnt[wv][6] = (on && d.aux < 0) ? -d.aux : 0;
-    s_cnt[wv][7] = (tile_ok && A.inst_mode[d.inst] != EM_SKIP) ? 1 : 0;
-    s_bkt[wv] = d.aux >= 0 ? d.aux : 0;
+  // per-half tallies
+  const int sh = 32 * half;
+  auto halfcount = [&](bool x) { return __popcll((__ballot(x) >> sh) & 0xffffffffull); };
+  const int c_valid = halfcount(valid), c_in = halfcount(inN), c_chk = halfcount(checked);
+  const int c_uns = halfcount(checked && compute);
+  const bool on = tile_ok && halfcount(compute) != 0;
+  if (c == 0) {
+    if (tile_ok) A.tile_on[(size_t)tile_off + (size_t)d.grp * njb + d.jb] = on ? 1 : 0;
+    s_cnt[slot][0] = c_valid;
+    s_cnt[slot][1] = c_in;
+    s_cnt[slot][2] = c_chk;
+    s_cnt[slot][3] = c_uns;
+    s_cnt[slot][4] = (on && d.aux >= 0) ? 1 : 0;
+    s_cnt[slot][5] = (on && d.aux < 0) ? 1 : 0;
+    s_cnt[slot][6] = (on && d.aux < 0) ? -d.aux : 0;
+    s_cnt[slot][7] = (tile_ok && mode != EM_SKIP) ? 1 : 0;
+    s_bkt[slot] = d.aux >= 0 ? d.aux : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot[4] = {0, 0, 0, 0};
     for (int q = 0; q < NBUCKET; ++q) s_nb[q] = 0;
     int nsg = 0, nsc = 0, ntile = 0, non = 0;
-    // (not unrolled: one thread, and all 128 LDS words in flight at once
+    // (not unrolled: one thread, and all the LDS words in flight at once
     // would take as many registers from every lane of the kernel)
 #pragma unroll 1
-    for (int w = 0; w < SCREEN_TILES; ++w) {
+    for (int w = 0; w < SCREEN_TPB; ++w) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) tot[q] += s_cnt[w][q];
       if (s_cnt[w][4]) s_nb[s_bkt[w]]++;
@@ -232,10 +222,11 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
   }
   __syncthreads();
   // list positions in tile order within the block
-  if (lane == 0 && on) {
+  if (c == 0 && on) {
     if (d.aux >= 0) {
       int pm = s_base[d.aux];
-      for (int w = 0; w < wv; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
+#pragma unroll 1
+      for (int w = 0; w < slot; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
       // the bucket's list offset (unrolled select: a kernel-argument array
       // indexed at run time would be copied to private memory)
       int moff = 0;
@@ -246,16 +237,17 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
       if (A.rec_all) A.rec_dyn[moff + pm] = A.rec_all[t];
     } else {
       int ps = s_base[NBUCKET], pc = s_base[NBUCKET + 1];
-      for (int w = 0; w < wv; ++w) {
+#pragma unroll 1
+      for (int w = 0; w < slot; ++w) {
         ps += s_cnt[w][5];
         pc += s_cnt[w][6];
       }
       TileDesc e = d;
       e.aux = 0;
       A.list_sg[ps] = e;
-      for (int c = 0; c < -d.aux; ++c) {
-        e.aux = c;
-        A.list_sc[pc + c] = e;
+      for (int q = 0; q < -d.aux; ++q) {
+        e.aux = q;
+        A.list_sc[pc + q] = e;
       }
     }
   }

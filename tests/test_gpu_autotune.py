@@ -12,9 +12,6 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-NBUCKET = 8
-
-
 def _O():
     import paper_2303_07597_amd.otgs as O
     return O
@@ -57,6 +54,7 @@ def test_every_tile_configuration_gives_the_same_result(mode_name):
     pts = [(a, b), (a2, b)]
     ref = _evals(h, pts, O)
     tried = 0
+    NBUCKET = O.NBUCKET
     for bucket in range(NBUCKET + 1):
         cfg = h.get_tile_config(bucket)
         if cfg["n_tiles"] == 0:
@@ -64,7 +62,8 @@ def test_every_tile_configuration_gives_the_same_result(mode_name):
         if mode_name == "OT_GS_COST_ONTHEFLY":
             nvar = 2 if 1 <= bucket <= 4 else 1
         else:
-            nvar = 2 if bucket < NBUCKET else 1       # plain / next tile in flight
+            # teams (or plain) / next tile in flight / LDS copy; bucket 0: teams only
+            nvar = 1 if bucket in (0, NBUCKET) else (3 if bucket <= 4 else 2)
         for var in range(nvar):
             for gm in (1, 3):
                 h.tile_config(bucket, var, gm)
@@ -86,13 +85,13 @@ def test_autotune_caches_and_applies(tmp_path):
         a, b, _, _ = h.solve(max_iter=10, use_screen=0)
         ref = _evals(h, [(a, b)], O)
         h.autotune(repeats=3)
-        tuned = [h.get_tile_config(k) for k in range(NBUCKET + 1)]
+        tuned = [h.get_tile_config(k) for k in range(O.NBUCKET + 1)]
         assert os.path.exists(path)
         lines = open(path).read().split("\n")
         assert sum(1 for x in lines if x.strip()) == sum(1 for t in tuned if t["n_tiles"] > 0)
         for x, y in zip(ref, _evals(h, [(a, b)], O)):
             np.testing.assert_array_equal(x, y)
         h2 = _handle(inst, O.OT_GS_COST_ONTHEFLY)
-        assert [h2.get_tile_config(k) for k in range(NBUCKET + 1)] == tuned
+        assert [h2.get_tile_config(k) for k in range(O.NBUCKET + 1)] == tuned
     finally:
         del os.environ["OTGS_AUTOTUNE_CACHE"]
