@@ -201,6 +201,31 @@ static int sync_err(ot_gs_handle* h, hipStream_t s, int* out) {
 static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
   const int count = h->count;
   {
+    // Materialised cost: a row bucket with few tiles joins the next larger
+    // nonempty one (one launch less per evaluation; a tile evaluated with
+    // more loads per lane than it needs gives the same bits, the extra loads
+    // adding exact zeros)
+    int remap[NBUCKET];
+    for (int b = 0; b < NBUCKET; ++b) remap[b] = b;
+    if (!h->onthefly) {
+      long long cnt[NBUCKET] = {};
+      for (int k = 0; k < count; ++k) {
+        const InstHost& ih = h->inst[k];
+        for (int g = 0; g < ih.d.Le; ++g)
+          if (ih.g_size[g] <= CHUNK) cnt[row_bucket(ih.g_size[g])] += ih.d.njb;
+      }
+      const long long few = 2LL * h->n_cu;   // fewer tiles than two workgroups per compute unit
+      for (int b = 0; b < NBUCKET; ++b) {
+        if (cnt[b] == 0 || cnt[b] >= few) continue;
+        int b2 = b + 1;
+        while (b2 < NBUCKET && cnt[b2] == 0) ++b2;
+        if (b2 == NBUCKET) break;
+        cnt[b2] += cnt[b];
+        cnt[b] = 0;
+        for (int q = 0; q < NBUCKET; ++q)
+          if (remap[q] == b) remap[q] = b2;
+      }
+    }
     std::vector<TileDesc> all, sg, sc;
     std::vector<TileDesc> bucket[NBUCKET];
     for (int k = 0; k < count; ++k) {
@@ -210,7 +235,7 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
         const bool split = n > CHUNK;
         const int nch = (int)ceil_div(n, CHUNK);
         for (int jb = 0; jb < ih.d.njb; ++jb) {
-          TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? otf_bucket(n) : row_bucket(n))};
+          TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? otf_bucket(n) : remap[row_bucket(n)])};
           all.push_back(t);
           if (!split) {
             bucket[t.aux].push_back(t);

@@ -111,6 +111,7 @@ constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
 
 
 constexpr int SCREEN_TPB = 2 * SCREEN_TILES;   // group tiles per screen block
+static_assert(SCREEN_TPB <= WAVE && NBUCKET + 2 <= WAVE, "the block tally uses one lane per slot");
 
 // One half wavefront per group tile (SCREEN_TPB per block: only 32 lanes of
 // a tile have a column), one lane per target column.  SCREEN: classify
@@ -124,7 +125,6 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
                                          // chunks of an active split tile, tile counted
   __shared__ int s_bkt[SCREEN_TPB];
   __shared__ int s_base[NBUCKET + 2];
-  __shared__ int s_nb[NBUCKET];   // main tiles per bucket (LDS: indexed at run time)
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
   const int half = lane >> 5, c = lane & (TJ - 1);
@@ -191,57 +191,87 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     s_bkt[slot] = d.aux >= 0 ? d.aux : 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    long long tot[4] = {0, 0, 0, 0};
-    for (int q = 0; q < NBUCKET; ++q) s_nb[q] = 0;
-    int nsg = 0, nsc = 0, ntile = 0, non = 0;
-    // (not unrolled: one thread, and all the LDS words in flight at once
-    // would take as many registers from every lane of the kernel)
-#pragma unroll 1
-    for (int w = 0; w < SCREEN_TPB; ++w) {
+  // Block tally by wavefront 0, lane l standing for slot l: per-bucket
+  // counts and each slot's rank by ballots, split offsets by wavefront
+  // sums, one atomic per quantity (issued by different lanes together)
+  if (wv == 0) {
+    const bool has = lane < SCREEN_TPB;
+    const int m4 = has ? s_cnt[lane][4] : 0, m5 = has ? s_cnt[lane][5] : 0;
+    const int m6 = has ? s_cnt[lane][6] : 0, bk = has ? s_bkt[lane] : 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int rank = 0, nb_mine = 0;   // lane q < NBUCKET: tiles of bucket q in the block
 #pragma unroll
-      for (int q = 0; q < 4; ++q) tot[q] += s_cnt[w][q];
-      if (s_cnt[w][4]) s_nb[s_bkt[w]]++;
-      nsg += s_cnt[w][5];
-      nsc += s_cnt[w][6];
-      ntile += s_cnt[w][7];
-      non += s_cnt[w][4] + s_cnt[w][5];
+    for (int q = 0; q < NBUCKET; ++q) {
+      const unsigned long long bq = __ballot(m4 && bk == q);
+      if (bk == q) rank = __popcll(bq & below);
+      if (lane == q) nb_mine = __popcll(bq);
     }
-    for (int q = 0; q < NBUCKET; ++q) s_base[q] = s_nb[q] ? atomicAdd(&A.counts[q], s_nb[q]) : 0;
-    s_base[NBUCKET] = nsg ? atomicAdd(&A.counts[NBUCKET], nsg) : 0;
-    s_base[NBUCKET + 1] = nsc ? atomicAdd(&A.counts[NBUCKET + 1], nsc) : 0;
+    // exclusive prefixes of split tiles and chunks over the slots
+    int ps = m5, pc = m6;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int ys = __shfl_up(ps, o), yc = __shfl_up(pc, o);
+      if (lane >= o) {
+        ps += ys;
+        pc += yc;
+      }
+    }
+    const int nsg = __shfl(ps, WAVE - 1), nsc = __shfl(pc, WAVE - 1);
+    ps -= m5;
+    pc -= m6;
+    // list bases: lane q < NBUCKET for bucket q, NBUCKET split groups,
+    // NBUCKET + 1 split chunks
+    int base = 0;
+    if (lane < NBUCKET && nb_mine) base = atomicAdd(&A.counts[lane], nb_mine);
+    if (lane == NBUCKET && nsg) base = atomicAdd(&A.counts[NBUCKET], nsg);
+    if (lane == NBUCKET + 1 && nsc) base = atomicAdd(&A.counts[NBUCKET + 1], nsc);
+    if (lane < NBUCKET + 2) s_base[lane] = base;
+    if (has) {
+      s_cnt[lane][4] = rank;   // reused: position within the block's bucket
+      s_cnt[lane][5] = ps;     // split group position within the block
+      s_cnt[lane][6] = pc;     // split chunk position within the block
+    }
     // counters: every block owns a slot (evaluations are ordered on the
     // stream, so a plain update suffices); slots are summed on request
-    long long* C = A.block_counters + (size_t)blockIdx.x * CNT_NUM;
-    C[CNT_PAIRS_TOTAL] += tot[0];
-    C[CNT_PAIRS_N] += tot[1];
-    C[CNT_PAIRS_CHECKED] += tot[2];
-    C[CNT_PAIRS_UNSKIPPED] += tot[3];
-    C[CNT_TILES_TOTAL] += ntile;
-    C[CNT_TILES_COMPUTED] += non;
+    long long tq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      long long v = has ? s_cnt[lane][q] : 0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      tq[q] = v;
+    }
+    int nt_ = has ? s_cnt[lane][7] : 0, non = m4 + m5;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      nt_ += __shfl_xor(nt_, o);
+      non += __shfl_xor(non, o);
+    }
+    if (lane == 0) {
+      long long* C = A.block_counters + (size_t)blockIdx.x * CNT_NUM;
+      C[CNT_PAIRS_TOTAL] += tq[0];
+      C[CNT_PAIRS_N] += tq[1];
+      C[CNT_PAIRS_CHECKED] += tq[2];
+      C[CNT_PAIRS_UNSKIPPED] += tq[3];
+      C[CNT_TILES_TOTAL] += nt_;
+      C[CNT_TILES_COMPUTED] += non;
+    }
   }
   __syncthreads();
-  // list positions in tile order within the block
+  // list entries in tile order within the block
   if (c == 0 && on) {
     if (d.aux >= 0) {
-      int pm = s_base[d.aux];
-#pragma unroll 1
-      for (int w = 0; w < slot; ++w) pm += (s_cnt[w][4] && s_bkt[w] == d.aux) ? 1 : 0;
       // the bucket's list offset (unrolled select: a kernel-argument array
       // indexed at run time would be copied to private memory)
       int moff = 0;
 #pragma unroll
       for (int q = 0; q < NBUCKET; ++q)
         if (q == d.aux) moff = A.main_off[q];
+      const int pm = s_base[d.aux] + s_cnt[slot][4];
       A.list_main[moff + pm] = d;
       if (A.rec_all) A.rec_dyn[moff + pm] = A.rec_all[t];
     } else {
-      int ps = s_base[NBUCKET], pc = s_base[NBUCKET + 1];
-#pragma unroll 1
-      for (int w = 0; w < slot; ++w) {
-        ps += s_cnt[w][5];
-        pc += s_cnt[w][6];
-      }
+      const int ps = s_base[NBUCKET] + s_cnt[slot][5], pc = s_base[NBUCKET + 1] + s_cnt[slot][6];
       TileDesc e = d;
       e.aux = 0;
       A.list_sg[ps] = e;
