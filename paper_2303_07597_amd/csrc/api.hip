@@ -101,6 +101,10 @@ struct ot_gs_handle {
   // records of the whole-group materialized tiles: every tile (tiles_all
   // order), the static main list and the dynamic main list (screen output)
   TileRec *rec_all = nullptr, *rec_main = nullptr, *rec_dyn = nullptr;
+  // screened solves: the update kernel forms the next evaluation's group
+  // statistics (every group at most CHUNK rows)
+  bool upd_stats = false;
+  int max_le = 1;                // most nonempty groups of an instance
   int* counts_static = nullptr;  // [NBUCKET + 2]
   int* counts_dyn = nullptr;     // [NBUCKET + 2]
   long long* counters = nullptr;
@@ -255,6 +259,9 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
     h->n_main = (int)mainl.size();
     h->n_sg = (int)sg.size();
     h->n_sc = (int)sc.size();
+    h->upd_stats = h->n_sg == 0;
+    h->max_le = 1;
+    for (int k = 0; k < count; ++k) h->max_le = std::max(h->max_le, h->inst[k].d.Le);
     TRY(h->alloc(&h->tiles_all, all.size()));
     TRY(h->alloc(&h->list_main, mainl.size()));
     TRY(h->alloc(&h->list_sg, sg.size()));
@@ -1635,6 +1642,11 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.alpha_s = h->alpha_s;
   A.beta_s = h->beta_s;
   A.counters = h->counters;
+  A.gstats = h->gstats;
+  A.g_start = h->g_start;
+  A.g_size = h->g_size;
+  A.counts = h->counts_dyn;
+  A.max_le = h->max_le;
   return A;
 }
 
@@ -1644,8 +1656,10 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   // the control kernel finalises D and the update kernel records snapshots;
   // unscreened solves run every tile of the live instances from the static
   // lists, with no screen pass
+  // (with upd_stats the previous step's update formed the group statistics)
+  const bool upd = use_screen && h->upd_stats;
   if (use_screen)
-    TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, true, true));
+    TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, !upd, true));
   else
     TRY(run_tiles_and_reduce(h, false, nullptr, nullptr, s, false, false, false, nullptr));
   hipEvent_t e0 = nullptr;
@@ -1655,8 +1669,12 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   LAUNCHCHK();
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
-                     dim3(256), 0, s, A);
+  if (upd)
+    hipLaunchKernelGGL(k_lbfgs_update_gs, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, 256)), h->count),
+                       dim3(256), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                       dim3(256), 0, s, A);
   LAUNCHCHK();
   TRY(tend(h, KT_LBFGS, s, e0));
   return OT_GS_OK;
@@ -1718,6 +1736,12 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
                      h->inN, P.use_screen);
   LAUNCHCHK();
   h->has_snapshot = P.use_screen != 0;
+  if (P.use_screen && h->upd_stats && h->tot_groups > 0) {
+    // statistics of the first evaluation (later ones come from the update)
+    ScreenArgs S = screen_args(h, P.use_lower);
+    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+    LAUNCHCHK();
+  }
   // upper bound on evaluations: the first one plus max_ls per iteration
   const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;
   const int check_every = 16;

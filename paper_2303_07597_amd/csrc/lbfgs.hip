@@ -91,6 +91,12 @@ struct LbArgs {
   float* alpha_s;           // snapshot point, written at snapshot evaluations
   float* beta_s;
   long long* counters;      // unscreened solves: evaluation counters, advanced here
+  // group statistics formed by the update (k_lbfgs_update_gs)
+  GroupStats* gstats;
+  const int* g_start;
+  const int* g_size;
+  int* counts;              // work-list counts of the next screen pass
+  int max_le;               // most groups of an instance
 };
 
 __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }
@@ -621,6 +627,45 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
     for (int i = threadIdx.x; i < (int)(sizeof(LbState) / 16); i += 64) dst[i] = src[i];
   }
 }
+// the vector work of one element e of instance k: record the snapshot,
+// accept the trial point, push (s, y), form the new direction and the next
+// trial point; returns the new trial value and, in snap_out, alpha~ after
+// this step
+__device__ __forceinline__ float lb_update_elem(const LbArgs& A, const InstDev& I, const LbState& S, int e,
+                                                long long v0, int h, bool snap, float& snap_out) {
+  float* tp = e < I.ns ? &A.alpha[I.row_off + e] : &A.beta[I.col_off + (e - I.ns)];
+  float* sp = e < I.ns ? &A.alpha_s[I.row_off + e] : &A.beta_s[I.col_off + (e - I.ns)];
+  const float told = *tp;
+  if (snap) *sp = told;   // the point just evaluated densely becomes the snapshot
+  snap_out = snap ? told : *sp;
+  float x = A.X[v0 + e];
+  if (S.accept) {
+    const float gt = lb_gt(A, I, e);
+    x = told;
+    if (S.push) {
+      A.S[(size_t)S.slot * A.vtot + v0 + e] = (float)S.t_acc * A.Dv[v0 + e];
+      A.Y[(size_t)S.slot * A.vtot + v0 + e] = gt - A.G[v0 + e];
+    }
+    A.X[v0 + e] = x;
+    A.G[v0 + e] = gt;
+  }
+  if (S.newdir) {
+    // d = cg G + sum over ring slots (in age order) of cs_i s_i + cy_i y_i
+    double d = S.cg * (double)A.G[v0 + e];
+    const int cnt = S.count;
+#pragma unroll 8
+    for (int j = 0; j < cnt; ++j) {
+      const int i = lb_slot(S, h, j);
+      d += S.cs[i] * (double)A.S[(size_t)i * A.vtot + v0 + e] +
+           S.cy[i] * (double)A.Y[(size_t)i * A.vtot + v0 + e];
+    }
+    A.Dv[v0 + e] = (float)d;
+  }
+  const float xn = x + (float)S.t_next * A.Dv[v0 + e];
+  *tp = xn;
+  return xn;
+}
+
 // grid (vector blocks, count); accept, push, new direction, next trial point
 __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const int k = blockIdx.y;
@@ -631,36 +676,76 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const int h = A.P.hist;
   const bool snap = S.mode_eval == EM_SNAPSHOT;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-    float* tp = e < I.ns ? &A.alpha[I.row_off + e] : &A.beta[I.col_off + (e - I.ns)];
-    if (snap) {
-      // the point just evaluated densely becomes the snapshot (alpha~, beta~)
-      if (e < I.ns) A.alpha_s[I.row_off + e] = *tp;
-      else A.beta_s[I.col_off + (e - I.ns)] = *tp;
+    float so;
+    lb_update_elem(A, I, S, e, v0, h, snap, so);
+  }
+}
+
+// The same update, with the group statistics of alpha - alpha~ that the
+// next screened evaluation needs formed on the way (handles whose groups
+// all have at most CHUNK rows).  grid (max groups + max column blocks,
+// count): block g < L_e takes the rows of group g (thread t the rows
+// g_start + t + 256 j, then the same fixed-order tree as k_group_stats, so
+// the statistics are bit-identical to that kernel's), the others 256
+// columns each.  Block (0, 0) also resets the work-list counts of the next
+// screen pass, and each instance's group-0 block counts its next
+// evaluation, as k_group_stats does.
+__global__ void __launch_bounds__(256) k_lbfgs_update_gs(LbArgs A) {
+  __shared__ double sm[4][256];
+  const int k = blockIdx.y;
+  const InstDev I = A.inst[k];
+  const LbState& S = A.st[k];
+  const long long v0 = A.voff[k];
+  const int h = A.P.hist;
+  const bool snap = S.mode_eval == EM_SNAPSHOT;
+  const int bx = blockIdx.x;
+  if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
+  if (bx >= A.max_le) {
+    const int c = (bx - A.max_le) * 256 + threadIdx.x;
+    if (c < I.nt_pad) {
+      float so;
+      lb_update_elem(A, I, S, I.ns + c, v0, h, snap, so);
     }
-    float x = A.X[v0 + e];
-    if (S.accept) {
-      const float gt = lb_gt(A, I, e);
-      x = *tp;
-      if (S.push) {
-        A.S[(size_t)S.slot * A.vtot + v0 + e] = (float)S.t_acc * A.Dv[v0 + e];
-        A.Y[(size_t)S.slot * A.vtot + v0 + e] = gt - A.G[v0 + e];
-      }
-      A.X[v0 + e] = x;
-      A.G[v0 + e] = gt;
+    return;
+  }
+  if (bx >= I.Le) return;
+  const int gidx = I.grp_off + bx;
+  const int r0 = A.g_start[gidx], n = A.g_size[gidx];
+  double up = 0, dn = 0, am = 0, ams = 0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    float as;
+    const double a = lb_update_elem(A, I, S, r0 + q, v0, h, snap, as);
+    const double d = a - (double)as;
+    if (d > 0) up += d * d; else dn += d * d;
+    am = fmax(am, fabs(a));
+    ams = fmax(ams, fabs((double)as));
+  }
+  sm[0][threadIdx.x] = up; sm[1][threadIdx.x] = dn;
+  sm[2][threadIdx.x] = am; sm[3][threadIdx.x] = ams;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
+      sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+      sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + o]);
+      sm[3][threadIdx.x] = fmax(sm[3][threadIdx.x], sm[3][threadIdx.x + o]);
     }
-    if (S.newdir) {
-      // d = cg G + sum over ring slots (in age order) of cs_i s_i + cy_i y_i
-      double d = S.cg * (double)A.G[v0 + e];
-      const int cnt = S.count;
-#pragma unroll 8
-      for (int j = 0; j < cnt; ++j) {
-        const int i = lb_slot(S, h, j);
-        d += S.cs[i] * (double)A.S[(size_t)i * A.vtot + v0 + e] +
-             S.cy[i] * (double)A.Y[(size_t)i * A.vtot + v0 + e];
-      }
-      A.Dv[v0 + e] = (float)d;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    GroupStats g;
+    g.up = sqrt(sm[0][0]);
+    g.dn = sqrt(sm[1][0]);
+    g.all = sqrt(sm[0][0] + sm[1][0]);
+    g.amax = sm[2][0];
+    g.amax_s = sm[3][0];
+    screen_group_consts(n, g.sg, g.fa, g.fb);
+    A.gstats[gidx] = g;
+    if (bx == 0) {
+      const int m = A.inst_mode[k];
+      if (m != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
+      if (m == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
     }
-    *tp = x + (float)S.t_next * A.Dv[v0 + e];
   }
 }
 
