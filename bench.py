@@ -45,6 +45,8 @@ def parse():
                     help="omit the on-the-fly (matrix-core cost) workload")
     ap.add_argument("--otf-n", type=int, default=32768, help="on-the-fly workload: n_src = n_tgt")
     ap.add_argument("--otf-iters", type=int, default=500, help="on-the-fly workload: L-BFGS iterations")
+    ap.add_argument("--skip-hbm", action="store_true", help="omit the 16384^2 (1 GiB cost) workload")
+    ap.add_argument("--hbm-n", type=int, default=16384, help="HBM-scale workload: n_src = n_tgt")
     ap.add_argument("--skip-batched", action="store_true", help="omit the 256-instance batched workload")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--skip-warmstart", action="store_true", help="omit the learned warm-start workload")
@@ -192,14 +194,14 @@ def _problems(insts, torch, O):
                  cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0) for i in insts]
 
 
-def bench_mu_sweep(args, torch, synth, O):
-    """The blobs 4096 workload at mu in {0.01, 0.1, 1}: time to 1e-6 relative
+def bench_mu_sweep(args, torch, synth, O, n=4096):
+    """The blobs n x n workload at mu in {0.01, 0.1, 1}: time to 1e-6 relative
     objective of the dense and the screened solve (same trajectory), and the
     share of tiles and (group, target) pairs the screened solve skipped."""
     dev = torch.device("cuda")
     out = {}
     for mu in (0.01, 0.1, 1.0):
-        inst = synth.blobs(seed=2, n_src=4096, n_tgt=4096, d=64, n_groups=10, gamma=0.1, mu=mu)
+        inst = synth.blobs(seed=2, n_src=n, n_tgt=n, d=64, n_groups=10, gamma=0.1, mu=mu)
         h = O.Handle([dict(labels=torch.from_numpy(inst["labels"]).to(dev), n_groups=10, gamma=0.1, mu=mu,
                            x_src=torch.from_numpy(inst["xs"]).to(dev), x_tgt=torch.from_numpy(inst["xt"]).to(dev),
                            cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0)])
@@ -224,6 +226,49 @@ def bench_mu_sweep(args, torch, synth, O):
         row["speedup_time_to_1e6"] = (td / ts_) if (td and ts_) else None
         out[f"mu={mu:g}"] = row
         h.close()
+    return out
+
+
+def bench_hbm(args, torch, synth, O):
+    """Blobs at n_src = n_tgt = 16384 (d = 64, 10 classes of ~1640 rows, so
+    every group runs in 1024-row chunks; gamma = 0.1, mu = 0.1): the
+    materialised cost is 1 GiB, four times the last-level cache, so each tile
+    pass streams it from HBM.  Dense evaluation rate, the tile pass (every
+    tile launch of one evaluation, HIP events) against 8 TB/s, and the mu
+    sweep at this size."""
+    dev = torch.device("cuda")
+    n = args.hbm_n
+    inst = synth.blobs(seed=2, n_src=n, n_tgt=n, d=64, n_groups=10, gamma=0.1, mu=args.mu)
+    h = O.Handle(_problems([inst], torch, O))
+    a_pt, b_pt, _, _ = h.solve(max_iter=200, use_screen=0)
+    if not args.no_autotune:
+        h.autotune(repeats=5)
+    tiles_cfg = {b: h.get_tile_config(b) for b in range(O.NBUCKET + 1) if h.get_tile_config(b)["n_tiles"] > 0}
+    ga, gb = torch.empty_like(a_pt), torch.empty_like(b_pt)
+    obj = torch.empty(1, dtype=torch.float64, device=dev)
+    dense = h.prepare_dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
+    for _ in range(5):
+        dense()
+    torch.cuda.synchronize()
+    reps = 50
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dense()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    tiles_us = h.profile_tiles(reps)
+    alg = algorithmic_bytes(n, n, 10)
+    achieved = alg / (tiles_us * 1e-6) / 1e9
+    h.close()
+    out = dict(workload=f"blobs n_src=n_tgt={n} d=64 classes=10 gamma=0.1 mu={args.mu:g}, cost 1 GiB",
+               point="after 200 dense L-BFGS iterations from zero",
+               entries_per_s=n * n / el, ms_per_eval=1e3 * el,
+               roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_pass=alg,
+                             avg_pass_us=tiles_us, kernel="k_grad_tiles (chunks) + k_split_combine"),
+               tile_config=tiles_cfg)
+    if not args.skip_solve and not args.skip_mu_sweep:
+        out["mu_sweep"] = bench_mu_sweep(args, torch, synth, O, n=n)
     return out
 
 
@@ -408,13 +453,18 @@ def main():
     for _ in range(args.warmup):
         dense()
     torch.cuda.synchronize()
-    h.kernel_timing(True)
-    h.kernel_time(O.KERNEL_GRAD)          # clear
     t0 = time.perf_counter()
     for _ in range(args.steps):
         dense()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # a separate pass with per-kernel events (they add host and launch
+    # overhead, so the timed steps above run without them)
+    h.kernel_timing(True)
+    h.kernel_time(O.KERNEL_GRAD)          # clear
+    for _ in range(args.steps):
+        dense()
+    torch.cuda.synchronize()
     h.kernel_timing(False)
     grad_ms, grad_n = h.kernel_time(O.KERNEL_GRAD)
     ms_step = 1e3 * el / args.steps
@@ -496,6 +546,10 @@ def main():
     if not args.skip_solve and not args.skip_mu_sweep:
         sweep = bench_mu_sweep(args, torch, synth, O)
         log("mu sweep done")
+    hbm = None
+    if not args.skip_hbm:
+        hbm = bench_hbm(args, torch, synth, O)
+        log(f"HBM-scale workload: {hbm['ms_per_eval']:.3f} ms per dense evaluation")
     otf = None
     if not args.skip_onthefly:
         otf = bench_onthefly(args, torch, synth, O)
@@ -531,6 +585,7 @@ def main():
         screened_eval=screened,
         solves=solves,
         mu_sweep=sweep,
+        hbm_scale=hbm,
         onthefly=otf,
         batched=batched,
         warm_start=warm,

@@ -218,14 +218,16 @@ int ot_gs_kernel_time(ot_gs_handle *h, int which, double *ms, long long *launche
 int ot_gs_profile_tiles(ot_gs_handle *h, int repeats, double *us_per_launch, void *stream);
 
 /* Tile configuration.  The gradient tiles are launched per bucket of the
- * work lists (groups of similar size; buckets 0..8, bucket 9 holds the
- * chunks of groups over 1024 rows).  A bucket has a variant and a grid
- * multiplier (workgroups launched per resident workgroup slot, 1-16,
- * default 2).  Materialized cost, bucket b of groups up to 64 (b = 0) or
- * 128 b rows: variant 0 = teams (8, 4, 2 tiles per workgroup for groups up
- * to 64, 128, 256 rows, else one), 1 = the next tile's loads in flight
- * during the current tile, 2 = the next tile copied into LDS meanwhile
- * (groups up to 512 rows); bucket 0 has variant 0 only.  On-the-fly cost,
+ * work lists (groups of similar size; buckets 0..12, bucket 13 holds the
+ * chunks of split groups: over 2048 rows with the materialized cost, over
+ * 1024 on the fly).  A bucket has a variant and a grid multiplier
+ * (workgroups launched per resident workgroup slot, 1-16, default 2).
+ * Materialized cost, bucket b of groups up to 64 (b = 0), 128 b rows
+ * (b = 1..8) or 1024 + 256 (b - 8) rows (b = 9..12): variant 0 = teams (8,
+ * 4, 2 tiles per workgroup for groups up to 64, 128, 256 rows, else one),
+ * 1 = the next tile's loads in flight during the current tile (b <= 8),
+ * 2 = the next tile copied into LDS meanwhile (groups up to 512 rows);
+ * buckets 0 and 9..12 have variant 0 only.  On-the-fly cost,
  * buckets 1-4: 0 = one 32-row block per wavefront, 1 = two blocks per
  * wavefront and half the wavefronts; other buckets variant 0 only.  Every
  * configuration gives bit-identical results.

@@ -202,6 +202,11 @@ static int sync_err(ot_gs_handle* h, hipStream_t s, int* out) {
 // Work lists over the (group, 32-target block) tiles: static lists for dense
 // evaluations (whole groups by row bucket; split groups by chunk), and the
 // dynamic lists the screen fills.  On-the-fly handles use a single bucket.
+// A group runs in CHUNK-row chunks (two passes and a combine) when it has
+// more rows than one tile holds: WHOLE_MAX for the materialised cost, CHUNK
+// for the cost computed on the fly.
+static bool group_split(bool onthefly, int rows) { return rows > (onthefly ? CHUNK : WHOLE_MAX); }
+
 static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
   const int count = h->count;
   {
@@ -216,7 +221,7 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
       for (int k = 0; k < count; ++k) {
         const InstHost& ih = h->inst[k];
         for (int g = 0; g < ih.d.Le; ++g)
-          if (ih.g_size[g] <= CHUNK) cnt[row_bucket(ih.g_size[g])] += ih.d.njb;
+          if (!group_split(false, ih.g_size[g])) cnt[row_bucket(ih.g_size[g])] += ih.d.njb;
       }
       const long long few = 2LL * h->n_cu;   // fewer tiles than two workgroups per compute unit
       for (int b = 0; b < NBUCKET; ++b) {
@@ -236,7 +241,7 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
       const InstHost& ih = h->inst[k];
       for (int g = 0; g < ih.d.Le; ++g) {
         const int n = ih.g_size[g];
-        const bool split = n > CHUNK;
+        const bool split = group_split(h->onthefly, n);
         const int nch = (int)ceil_div(n, CHUNK);
         for (int jb = 0; jb < ih.d.njb; ++jb) {
           TileDesc t{k, g, jb, split ? -nch : (h->onthefly ? otf_bucket(n) : remap[row_bucket(n)])};
@@ -561,7 +566,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     d.chunk_off = h->tot_chunk;
     ih.n_chunk_rows = 0;
     for (int g = 0; g < d.Le; ++g) {
-      if (ih.g_size[g] > CHUNK) {
+      if (group_split(otf, ih.g_size[g])) {
         ih.g_chunk0.push_back(ih.n_chunk_rows);
         ih.n_chunk_rows += (int)ceil_div(ih.g_size[g], CHUNK);
       } else {
@@ -972,8 +977,9 @@ static int otf_variants(int b) { return (b >= 1 && b <= 4) ? 2 : 1; }
 static int tile_variants(const ot_gs_handle* h, int b) {
   if (b >= NBUCKET) return 1;
   if (h->onthefly) return b < OTF_NBUCKET ? otf_variants(b) : 1;
-  // R = 2: teams only; R <= 16: plain, next tile in flight, LDS copy; else two
-  return bucket_R(b) <= 2 ? 1 : bucket_R(b) <= 16 ? 3 : 2;
+  // R = 2: teams only; R <= 16: plain, next tile in flight, LDS copy; up to
+  // RMAX: plain, next tile in flight; beyond: plain
+  return bucket_R(b) <= 2 ? 1 : bucket_R(b) <= 16 ? 3 : bucket_R(b) <= RMAX ? 2 : 1;
 }
 
 static void otf_shape(int b, int var, int* WT, int* BPW) {
@@ -1029,7 +1035,7 @@ template <int B>
 static void launch_mat_b(GradArgs A, dim3 grid, dim3 tgrid, dim3 block, bool pf, bool dma, bool mixed, int sp,
                          hipStream_t s) {
   constexpr int RR = bucket_R(B), KK = bucket_K(B);
-  if constexpr (RR >= 4) {
+  if constexpr (RR >= 4 && RR <= RMAX) {
     if (dma) {
       if (sp) hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), true>), grid, block, 0, s, A);
       else hipLaunchKernelGGL((k_grad_tiles_dma<(RR <= 16 ? RR : 16), false>), grid, block, 0, s, A);
@@ -1053,7 +1059,7 @@ static void launch_mat_b(GradArgs A, dim3 grid, dim3 tgrid, dim3 block, bool pf,
 
 static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool snap_possible, hipStream_t s) {
   const dim3 grid(std::max(1, std::min(n, h->tile_gm[b] * h->n_cu))), block(BLOCK);
-  const bool pf = h->tile_var[b] == 1 && bucket_R(b) >= 4;
+  const bool pf = h->tile_var[b] == 1 && bucket_R(b) >= 4 && bucket_R(b) <= RMAX;
   const bool dma = h->tile_var[b] == 2 && bucket_R(b) >= 4 && bucket_R(b) <= 16;
   // variant 0 with teams: the grid counts workgroups of K tiles
   const int K = (!pf && !dma) ? bucket_K(b) : 1;
@@ -1071,7 +1077,11 @@ static int launch_mat_bucket(ot_gs_handle* h, GradArgs A, int b, int n, bool sna
       case 5: launch_mat_b<5>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
       case 6: launch_mat_b<6>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
       case 7: launch_mat_b<7>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
-      default: launch_mat_b<8>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 8: launch_mat_b<8>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 9: launch_mat_b<9>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 10: launch_mat_b<10>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      case 11: launch_mat_b<11>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
+      default: launch_mat_b<12>(A, grid, tgrid, block, pf, dma, mixed, sp, s); break;
     }
     LAUNCHCHK();
   }

@@ -161,21 +161,24 @@ __device__ __forceinline__ TileGeo geo_desc(const GradArgs& A, const TileDesc& d
 // wavefronts v + (NW / K) j, j < K.  Virtual wavefront w' reads at load k the
 // two tile rows 2 (w' + NW k) + h, so every tile is summed exactly as by NW
 // wavefronts (same partials, same order, same bits) whatever K is.
-// Alpha of virtual wavefront j, load k, parity h sits in lane 2 R j + 2 k + h
-// (-inf past the tile: f = -inf, p = 0 without a mask); beta of the lane's
+// Alpha of virtual wavefront j, load k, parity h sits in slot s = 2 R j + 2 k + h,
+// lane s mod 64 of register s / 64 (-inf past the tile: f = -inf, p = 0
+// without a mask); beta of the lane's
 // column; the R K cost values by raw buffer loads (loads past the tile
 // re-read the last valid row pair, a cache hit).  An inactive team (no tile
 // this round) loads nothing.
 template <int R, int K>
-__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, bool act, float& av,
-                                           float& bj, float (&p)[K][R]) {
-  static_assert(2 * R * K <= WAVE, "alpha of a wavefront's rows in one register");
+__device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, bool act,
+                                           float (&av)[av_regs(R, K)], float& bj, float (&p)[K][R]) {
+  static_assert(K == 1 || 2 * R * K <= WAVE, "teams keep their alpha values in one register");
+  constexpr int NA = av_regs(R, K);
   const int lane = threadIdx.x & (WAVE - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr int WT = NW / K;
   const int v = w % WT;
   if (!act) {
-    av = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) av[a] = -INFINITY;
     bj = -INFINITY;
 #pragma unroll
     for (int j = 0; j < K; ++j)
@@ -183,13 +186,15 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
       for (int k = 0; k < R; ++k) p[j][k] = 0.f;
     return;
   }
-  {
-    // (K = 1: lanes past 2 R hold -inf; j stays wavefront-uniform)
-    const int j = K == 1 ? 0 : lane / (2 * R), k = K == 1 ? (lane >> 1) : (lane >> 1) % R;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    // (K = 1: slots past 2 R hold -inf; j stays wavefront-uniform)
+    const int sl = a * WAVE + lane;
+    const int j = K == 1 ? 0 : sl / (2 * R), k = K == 1 ? (sl >> 1) : (sl >> 1) % R;
     const int rwj = g.r0 + 2 * (v + WT * j);
     const int nkj = rwj < g.r1 ? min(R, (g.r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
     const int arow = rwj + 2 * NW * k + (lane & 1);
-    av = (lane < 2 * R * K && k < nkj && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+    av[a] = (sl < 2 * R * K && k < nkj && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
   }
   bj = A.beta[g.b0 + (lane & (TJ - 1))];
   // one descriptor at the tile's first row; every load a scalar byte offset
@@ -214,8 +219,9 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
 // kap_s: this team's TJ kappas.  act = false: the team has no tile this
 // round and only takes part in the workgroup barriers.
 template <int R, int K, int PHASE, bool SNAP>
-__device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, bool act, float av, float bj,
-                                          float (&p)[K][R], float (*red)[NW][TJ], float (*aw)[WAVE],
+__device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, bool act,
+                                          const float (&av)[av_regs(R, K)], float bj, float (&p)[K][R],
+                                          float (*red)[NW][TJ], float (*aw)[WAVE * av_regs(R, K)],
                                           float* kap_s) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
@@ -227,7 +233,8 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, b
   constexpr bool snap = SNAP && PHASE != 2;
   // this wavefront's alpha values through its own LDS slot (written and read
   // by the same wavefront: no barrier)
-  aw[w][lane] = av;
+#pragma unroll
+  for (int a = 0; a < av_regs(R, K); ++a) aw[w][a * WAVE + lane] = av[a];
   // a padding column gets beta = -inf: with alpha = -inf past the tile,
   // every entry outside the tile has f = -inf and p exactly 0 (the entries
   // inside are computed exactly as written); snapshots mask explicitly
@@ -331,13 +338,18 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, b
   // row partials of this column block, rows relative to the group start
   float* __restrict__ rp = A.rowpart + g.rp0;
   if (__ballot(kap > 0.f) == 0ull) {
-    // every block of the tile is zero: its row sums are exact zeros
+    // every block of the tile is zero: its row sums are exact zeros (slot
+    // s = 2 k + h of load k, parity h; 2 R slots per virtual wavefront)
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const int rwj = g.r0 + 2 * (v + WT * j);
       const int nkj = rwj < r1 ? min(R, (r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
-      const int arow = rwj + 2 * NW * (lane >> 1) + (lane & 1);
-      if ((lane >> 1) < nkj && arow < r1) rp[arow] = 0.f;
+#pragma unroll
+      for (int a = 0; a < (2 * R + WAVE - 1) / WAVE; ++a) {
+        const int kk = (a * WAVE + lane) >> 1;
+        const int arow = rwj + 2 * NW * kk + (lane & 1);
+        if (kk < nkj && arow < r1) rp[arow] = 0.f;
+      }
     }
     return;
   }
@@ -365,8 +377,9 @@ __device__ __forceinline__ void tile_body(const GradArgs& A, const TileGeo& g, b
 
 template <int R, int K, int PHASE, bool SNAP>
 __device__ __forceinline__ void grad_tile(const GradArgs& A, const TileGeo& g, bool act,
-                                          float (*red)[NW][TJ], float (*aw)[WAVE], float* kap_s) {
-  float av, bj, p[K][R];
+                                          float (*red)[NW][TJ], float (*aw)[WAVE * av_regs(R, K)],
+                                          float* kap_s) {
+  float av[av_regs(R, K)], bj, p[K][R];
   tile_loads<R, K>(A, g, act, av, bj, p);
   // keep every load of the wavefront in flight before any is consumed
   __builtin_amdgcn_sched_barrier(0);
@@ -395,14 +408,15 @@ __device__ __forceinline__ RecStart rec_start(const GradArgs& A) {
 template <int R>
 struct TileLoad {
   TileGeo g;
-  float av, bj;
+  float av[av_regs(R, 1)], bj;
   float v[1][R];
 };
 
 template <int R, bool SNAP>
 __global__ void __launch_bounds__(BLOCK) k_grad_tiles_pf(GradArgs A) {
+  static_assert(R <= RMAX, "two tiles in registers only up to RMAX loads per lane");
   __shared__ float red[3][NW][TJ];
-  __shared__ float aw[NW][WAVE];
+  __shared__ float aw[NW][WAVE * av_regs(R, 1)];
   __shared__ float kap_s[TJ];
   const RecStart q = rec_start(A);
   if (A.single_inst && !mode_takes(q.mode0, SNAP)) return;
@@ -442,7 +456,7 @@ template <int R, bool SNAP>
 __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   static_assert(R <= DMA_RMAX, "LDS tile buffer sized for R <= 16");
   __shared__ float red[3][NW][TJ];
-  __shared__ float aw[NW][WAVE];
+  __shared__ float aw[NW][WAVE * av_regs(R, 1)];
   __shared__ float kap_s[TJ];
   __shared__ __attribute__((aligned(16))) float buf[2 * NW * R * TJ];   // 32 R rows of 32 floats
   const RecStart q0 = rec_start(A);
@@ -459,11 +473,11 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   // rows), piece q to LDS bytes [1024 q, 1024 q + 1024); pieces past the
   // tile read the pool's following rows (in bounds) and land inside buf.
   // alpha and beta of the tile are loaded into registers alongside.
-  auto issue = [&](const TileGeo& g, float& av, float& bj) {
+  auto issue = [&](const TileGeo& g, float (&av)[1], float& bj) {
     const int rw = 2 * w;
     const int nk = rw < g.r1 ? min(R, (g.r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
     const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-    av = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+    av[0] = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
     bj = A.beta[g.b0 + (lane & (TJ - 1))];
     const float* Ct = A.C + g.c0;
     const __amdgpu_buffer_rsrc_t rsrc =
@@ -476,7 +490,7 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
   int t = match(blockIdx.x);
   if (t >= n) return;
   TileGeo g = geo_rec(t == (int)blockIdx.x ? q0.r : A.rec[t]);
-  float av, bj;
+  float av[1], bj;
   issue(g, av, bj);
   for (;;) {
     __builtin_amdgcn_s_waitcnt(0);   // this wavefront's copies have landed
@@ -486,7 +500,7 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
     for (int k = 0; k < R; ++k) v[0][k] = buf[(2 * w + 2 * NW * k) * TJ + lane];   // rows 2 (w + 16 k) + h
     __syncthreads();                 // buffer free for the next tile
     const int tn = match(t + gridDim.x);
-    float avn = 0.f, bjn = 0.f;
+    float avn[1] = {0.f}, bjn = 0.f;
     TileGeo gn_ = g;
     if (tn < n) {
       gn_ = geo_rec(A.rec[tn]);
@@ -497,7 +511,7 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
     if (tn >= n) break;
     t = tn;
     g = gn_;
-    av = avn;
+    av[0] = avn[0];
     bj = bjn;
   }
 }
@@ -513,8 +527,9 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
 template <int R, int PHASE, bool SNAP, int K = 1>
 __global__ void __launch_bounds__(BLOCK, R * K <= 16 ? 8 : 1) k_grad_tiles(GradArgs A) {
   static_assert(K == 1 || PHASE == 0, "teams only for whole-group tiles");
+  static_assert(PHASE == 0 || R == RMAX, "split-group chunks run with RMAX loads per lane");
   __shared__ float red[K][3][NW][TJ];
-  __shared__ float aw[NW][WAVE];
+  __shared__ float aw[NW][WAVE * av_regs(R, K)];
   __shared__ float kap_s[K][TJ];
   if (PHASE == 0 && K > 1) {
     const int team = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) / (NW / K));
@@ -565,7 +580,7 @@ template <int R, int K = 1>
 __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
   static_assert(R * K <= 16, "both bodies in one kernel only for R K <= 16");
   __shared__ float red[K][3][NW][TJ];
-  __shared__ float aw[NW][WAVE];
+  __shared__ float aw[NW][WAVE * av_regs(R, K)];
   __shared__ float kap_s[K][TJ];
   if (K > 1) {
     const int team = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6) / (NW / K));
@@ -677,10 +692,65 @@ struct ReduceArgs {
 constexpr int ASM_BLOCK = 256;
 constexpr int ASM_LPR = 8;                      // lanes per row
 constexpr int ASM_ROWS = ASM_BLOCK / ASM_LPR;   // rows per assembly block
+constexpr int ASM_U = 16;                      // loads per lane in flight
 
 // Blocks of the assembly kernel per instance: row blocks, then column blocks.
 __host__ __device__ inline int asm_row_blocks(int ns) { return (ns + ASM_ROWS - 1) / ASM_ROWS; }
 __host__ __device__ inline int asm_col_blocks(int ntp) { return (ntp + ASM_BLOCK - 1) / ASM_BLOCK; }
+
+// Row sum of lane q of a row: jb = q, q + ASM_LPR, ... added in that order.
+// Each batch issues all its ASM_U loads before the first add; indices past
+// the end are clamped to the last slot (a valid address) and not added.
+// With MASK, a tile the screen skipped adds an exact zero (its slot holds
+// stale data, discarded by the select).
+template <bool MASK>
+__device__ __forceinline__ float asm_row_sum(const float* rp, int ns, int njb, const uint8_t* on, int q) {
+  float s = 0.f;
+  for (int j0 = q; j0 < njb; j0 += ASM_U * ASM_LPR) {
+    float v[ASM_U];
+    uint8_t f[ASM_U];
+#pragma unroll
+    for (int u = 0; u < ASM_U; ++u) {
+      const int jb = min(j0 + u * ASM_LPR, njb - 1);
+      v[u] = rp[(size_t)jb * ns];
+      if (MASK) f[u] = on[jb];
+    }
+#pragma unroll
+    for (int u = 0; u < ASM_U; ++u)
+      if (j0 + u * ASM_LPR < njb) s += (!MASK || f[u]) ? v[u] : 0.f;
+  }
+  return s;
+}
+
+// Column c over the groups of its instance, in group order: sum of the
+// column partials and of excess^2 (float64); batches as in asm_row_sum.
+template <bool MASK>
+__device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, int nt_pad, int Le,
+                                            const uint8_t* on, int njb, float& s, double& e2) {
+  s = 0.f;
+  e2 = 0.0;
+  for (int g0 = 0; g0 < Le; g0 += ASM_U) {
+    float cv[ASM_U], ev[ASM_U];
+    uint8_t f[ASM_U];
+#pragma unroll
+    for (int u = 0; u < ASM_U; ++u) {
+      const int g = min(g0 + u, Le - 1);
+      cv[u] = cs[(size_t)g * nt_pad];
+      ev[u] = ex[(size_t)g * nt_pad];
+      if (MASK) f[u] = on[(size_t)g * njb];
+    }
+#pragma unroll
+    for (int u = 0; u < ASM_U; ++u) {
+      if (g0 + u < Le) {
+        const bool keep = !MASK || f[u];
+        const double e = ev[u];
+        s += keep ? cv[u] : 0.f;
+        e2 += keep ? e * e : 0.0;
+      }
+    }
+  }
+}
+
 
 // Assembly, grid (max row blocks + max column blocks, count):
 //  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 lanes per row
@@ -707,48 +777,52 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     const int r = b * ASM_ROWS + threadIdx.x / ASM_LPR;
     const int q = threadIdx.x % ASM_LPR;
     float s = 0.f;
-    if (r < I.ns) {
-      const int g = A.row_grp[I.row_off + r];
+    // the row's own operands are loaded together with its partials
+    const bool rok = r < I.ns;
+    const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
+    const float al_r = rok ? A.alpha[I.row_off + r] : 0.f;
+    const int pm_r = (rok && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
+    const bool a_uni = A.a_uniform[k];
+    if (rok) {
       const float* rp = A.rowpart + I.r_off + r;
-      const uint8_t* on = A.tile_on ? A.tile_on + I.tile_off + (size_t)g * I.njb : nullptr;
-#pragma unroll 8
-      for (int jb = q; jb < I.njb; jb += ASM_LPR) {
-        const float v = rp[(size_t)jb * I.ns];
-        s += (!on || on[jb]) ? v : 0.f;   // skipped tiles: exact zeros (stale data ignored)
-      }
+      if (A.tile_on)
+        s = asm_row_sum<true>(rp, I.ns, I.njb, A.tile_on + I.tile_off + (size_t)A.row_grp[I.row_off + r] * I.njb, q);
+      else
+        s = asm_row_sum<false>(rp, I.ns, I.njb, nullptr, q);
     }
     // fixed-order combine of the lanes of a row (xor tree over 8 lanes)
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
     s += __shfl_xor(s, 4);
-    if (q == 0 && r < I.ns) {
-      const float gval = A.a_int[I.row_off + r] - s;
+    if (q == 0 && rok) {
+      const float gval = a_r - s;
       if (A.ga_int) A.ga_int[I.row_off + r] = gval;
-      if (A.ga_out) A.ga_out[I.row_off + A.perm_row[I.row_off + r]] = gval;
-      const double av = A.a_uniform[k] ? 1.0 / (double)I.ns : (double)A.a_int[I.row_off + r];
-      part = av * (double)A.alpha[I.row_off + r];
+      if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
+      const double av = a_uni ? 1.0 / (double)I.ns : (double)a_r;
+      part = av * (double)al_r;
     }
   } else {
     const int c = (b - nbr) * ASM_BLOCK + threadIdx.x;
     if (c < I.nt_pad) {
-      const int jb = c / TJ;
-      float s = 0.f;
-      double e2 = 0.0;
-#pragma unroll 4
-      for (int g = 0; g < I.Le; ++g) {
-        const bool on = !A.tile_on || A.tile_on[I.tile_off + (size_t)g * I.njb + jb];
-        const size_t pr = (size_t)I.pair_off + (size_t)g * I.nt_pad + c;
-        const float cv = A.colsum[pr];
-        const double e = A.excess[pr];
-        s += on ? cv : 0.f;
-        e2 += on ? e * e : 0.0;
-      }
-      const float gval = (c < I.nt) ? A.b_int[I.col_off + c] - s : 0.f;
+      const bool cok = c < I.nt;
+      const float b_c = cok ? A.b_int[I.col_off + c] : 0.f;
+      const float be_c = cok ? A.beta[I.col_off + c] : 0.f;
+      const int pm_c = (cok && A.gb_out) ? A.perm_col[I.col_off + c] : 0;
+      const bool b_uni = A.b_uniform[k];
+      const float* cs = A.colsum + (size_t)I.pair_off + c;
+      const float* ex = A.excess + (size_t)I.pair_off + c;
+      float s;
+      double e2;
+      if (A.tile_on)
+        asm_col_sum<true>(cs, ex, I.nt_pad, I.Le, A.tile_on + I.tile_off + c / TJ, I.njb, s, e2);
+      else
+        asm_col_sum<false>(cs, ex, I.nt_pad, I.Le, nullptr, I.njb, s, e2);
+      const float gval = cok ? b_c - s : 0.f;
       if (A.gb_int) A.gb_int[I.col_off + c] = gval;
-      if (A.gb_out && c < I.nt) A.gb_out[I.scol_off + A.perm_col[I.col_off + c]] = gval;
-      if (c < I.nt) {
-        const double bv = A.b_uniform[k] ? 1.0 / (double)I.nt : (double)A.b_int[I.col_off + c];
-        part = bv * (double)A.beta[I.col_off + c] - e2 * (0.5 / (double)I.gamma);
+      if (A.gb_out && cok) A.gb_out[I.scol_off + pm_c] = gval;
+      if (cok) {
+        const double bv = b_uni ? 1.0 / (double)I.nt : (double)b_c;
+        part = bv * (double)be_c - e2 * (0.5 / (double)I.gamma);
       }
     }
   }

@@ -23,10 +23,13 @@ constexpr int WAVE = 64;
 constexpr int TJ = 32;                 // target columns per tile (lane = 32 h + column)
 constexpr int NW = 16;                 // waves per gradient workgroup
 constexpr int BLOCK = NW * WAVE;       // 1024 threads
-constexpr int RMAX = 32;               // rows per thread in the largest class
-constexpr int CHUNK = 2 * NW * RMAX;   // 1024: largest group handled in one pass
-constexpr int RSTEP = 4;               // row buckets: R = 2, 4, 8, ..., 32 loads per lane
-constexpr int NBUCKET = 1 + RMAX / RSTEP;   // 9
+constexpr int RMAX = 32;               // loads per lane of a split-group chunk
+constexpr int CHUNK = 2 * NW * RMAX;   // 1024: rows of a split-group chunk
+constexpr int RSTEP = 4;               // row buckets: R = 2, 4, 8, ..., 32 loads per lane,
+constexpr int RBIG = 64;               // then 40, 48, 56, 64 (one workgroup per compute unit)
+constexpr int RSTEP_BIG = 8;
+constexpr int WHOLE_MAX = 2 * NW * RBIG;   // 2048: largest whole-group tile (materialised cost)
+constexpr int NBUCKET = 1 + RMAX / RSTEP + (RBIG - RMAX) / RSTEP_BIG;   // 13
 constexpr int MAX_GROUPS = 16384;      // label range limit (LDS histogram)
 constexpr int DP_MAX = 256;            // on-the-fly cost: padded feature dims
 
@@ -195,15 +198,22 @@ __host__ __device__ inline size_t c_index(const InstDev& I, int gs, int gn, int 
 }
 
 // loads per lane (per virtual wavefront) of row bucket b: 2, then the
-// multiples of RSTEP up to RMAX
-__host__ __device__ constexpr int bucket_R(int b) { return b == 0 ? 2 : RSTEP * b; }
+// multiples of RSTEP up to RMAX, then of RSTEP_BIG up to RBIG
+__host__ __device__ constexpr int bucket_R(int b) {
+  return b == 0 ? 2 : b <= RMAX / RSTEP ? RSTEP * b : RMAX + RSTEP_BIG * (b - RMAX / RSTEP);
+}
 
 // row bucket of a whole-group tile: the smallest bucket_R(b) with
 // 2 NW R >= rows (two rows per load)
 __host__ __device__ inline int row_bucket(int rows) {
   const int r = (rows + 2 * NW - 1) / (2 * NW);
-  return r <= 2 ? 0 : (r + RSTEP - 1) / RSTEP;
+  if (r <= 2) return 0;
+  if (r <= RMAX) return (r + RSTEP - 1) / RSTEP;
+  return RMAX / RSTEP + (r - RMAX + RSTEP_BIG - 1) / RSTEP_BIG;
 }
+
+// registers per lane holding the alpha values of a wavefront's 2 R K rows
+__host__ __device__ constexpr int av_regs(int R, int K) { return (2 * R * K + WAVE - 1) / WAVE; }
 
 // teams of a row bucket: K tiles per workgroup, NW / K wavefronts each
 // (R K <= 16 keeps two workgroups per compute unit; a team keeps at least

@@ -34,7 +34,7 @@ OT_GS_COST_MATERIALIZE = 1
 OT_GS_COST_ONTHEFLY = 2
 
 KERNEL_GRAD, KERNEL_SCREEN, KERNEL_REDUCE, KERNEL_LBFGS = 0, 1, 2, 3
-NBUCKET = 9   # row buckets of the tile lists; tile-configuration bucket NBUCKET = split chunks
+NBUCKET = 13   # row buckets of the tile lists; tile-configuration bucket NBUCKET = split chunks
 
 
 class ot_gs_problem(ct.Structure):

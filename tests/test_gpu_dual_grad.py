@@ -78,9 +78,10 @@ def test_dense_matches_oracle_on_trajectory_small():
 
 
 @pytest.mark.parametrize("seed,sizes,nt", [
-    (1, [1, 17, 0, 600, 64, 3], 129),      # empty label, singleton, a split group, ragged columns
+    (1, [1, 17, 0, 600, 64, 3], 129),      # empty label, singleton, a 600-row group, ragged columns
     (2, [16, 16, 32, 31, 33], 64),         # sizes on and around the 16-row class edges
-    (3, [513, 1100, 7], 200),              # several chunks of split groups
+    (3, [513, 1100, 7], 200),              # a group in the 1024-2048 row buckets
+    (6, [2100, 4500, 30, 1800], 70),       # split groups (3 and 5 chunks), a 1800-row whole group
     (4, [5], 1),                           # one group, one column
     (5, [2, 1], 70),
 ])
@@ -131,7 +132,8 @@ def test_batch_is_bitwise_equal_to_single_instances():
         ob += P.nt
 
 
-@pytest.mark.parametrize("n_src,n_groups", [(1200, 6), (2600, 2)])   # (2600, 2): split groups
+# (2600, 2): 1300-row whole groups; (4400, 2): split groups (3 chunks)
+@pytest.mark.parametrize("n_src,n_groups", [(1200, 6), (2600, 2), (4400, 2)])
 def test_screened_is_bitwise_equal_to_dense(n_src, n_groups):
     """Theorem 2 on the device: after a snapshot, screened evaluations at
     nearby points reproduce the dense ones exactly, and skip tiles.  The
@@ -166,7 +168,7 @@ def test_modes_after_an_evaluation_elsewhere():
     another point, SNAPSHOT, SCREENED and DENSE at a new point agree with the
     oracle there (split groups included)."""
     O = _otgs()
-    inst = cases.ragged(41, 2900, 150, [1500, 1100, 300])
+    inst = cases.ragged(41, 3700, 150, [2300, 1100, 300])
     C32, P = cases.with_cost(inst)
     h = make_handle(C32, P)
     pts = trajectory_points(P, [5, 15, 16])
