@@ -28,6 +28,7 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(HERE, "profiles", "grad_tiles_blobs4096_traffic.json")
+PROFILE_TRAFFIC_HBM = os.path.join(HERE, "profiles", "grad_tiles_blobs16384_traffic.json")
 
 
 def parse():
@@ -230,8 +231,8 @@ def bench_mu_sweep(args, torch, synth, O, n=4096):
 
 
 def bench_hbm(args, torch, synth, O):
-    """Blobs at n_src = n_tgt = 16384 (d = 64, 10 classes of ~1640 rows, so
-    every group runs in 1024-row chunks; gamma = 0.1, mu = 0.1): the
+    """Blobs at n_src = n_tgt = 16384 (d = 64, 10 classes of ~1640 rows,
+    whole-group tiles of 56 loads per lane; gamma = 0.1, mu = 0.1): the
     materialised cost is 1 GiB, four times the last-level cache, so each tile
     pass streams it from HBM.  Dense evaluation rate, the tile pass (every
     tile launch of one evaluation, HIP events) against 8 TB/s, and the mu
@@ -260,12 +261,19 @@ def bench_hbm(args, torch, synth, O):
     alg = algorithmic_bytes(n, n, 10)
     achieved = alg / (tiles_us * 1e-6) / 1e9
     h.close()
+    traffic = None
+    if n == 16384 and os.path.exists(PROFILE_TRAFFIC_HBM):
+        with open(PROFILE_TRAFFIC_HBM) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == grad_source_hash():
+            traffic = tr.get("bytes_per_launch")
     out = dict(workload=f"blobs n_src=n_tgt={n} d=64 classes=10 gamma=0.1 mu={args.mu:g}, cost 1 GiB",
                point="after 200 dense L-BFGS iterations from zero",
                entries_per_s=n * n / el, ms_per_eval=1e3 * el,
                roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=achieved / HBM_PEAK_GBS, algorithmic_bytes_per_pass=alg,
-                             avg_pass_us=tiles_us, kernel="k_grad_tiles (chunks) + k_split_combine"),
+                             frac=achieved / HBM_PEAK_GBS, traffic=traffic, algorithmic_bytes_per_pass=alg,
+                             avg_pass_us=tiles_us,
+                             kernel="k_grad_tiles<56,0,false,1> (every tile launch of one evaluation)"),
                tile_config=tiles_cfg)
     if not args.skip_solve and not args.skip_mu_sweep:
         out["mu_sweep"] = bench_mu_sweep(args, torch, synth, O, n=n)
