@@ -272,9 +272,12 @@ __device__ double lb_direction(LbState& S, LbGram& G, int hist) {
   }
   // lane l: sum_i cy_i y_l.y_i, then the s_i.y_l terms as cs_i are fixed
   double acc2 = 0.0;
+  double yq = mine ? G.yy(lane, 0) : 0.0;   // each entry read while the previous step runs
   for (int i = 0; i < hist; ++i) {
+    const double yn = (mine && i + 1 < hist) ? G.yy(lane, i + 1) : 0.0;
     const double ci = lane_d(cy, i);
-    if (mine) acc2 = fma(ci, G.yy(lane, i), acc2);
+    if (mine) acc2 = fma(ci, yq, acc2);
+    yq = yn;
   }
   p = p0;
   gq = (mine && m > 0) ? G.sy(p, lane) : 0.0;
