@@ -54,9 +54,9 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true", help="omit the 256-instance batched workload")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--skip-warmstart", action="store_true", help="omit the learned warm-start workload")
-    ap.add_argument("--ws-train", type=int, default=2048, help="training instances (cold solves)")
-    ap.add_argument("--ws-held", type=int, default=256, help="held-out instances")
-    ap.add_argument("--ws-epochs", type=int, default=30)
+    ap.add_argument("--ws-train", type=int, default=20000, help="training instances (cold solves)")
+    ap.add_argument("--ws-held", type=int, default=1024, help="held-out instances")
+    ap.add_argument("--ws-epochs", type=int, default=3)
     ap.add_argument("--ws-save", default=None, help="write the trained network parameters (.npy) here")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--copy-probe", action="store_true",
@@ -359,6 +359,8 @@ def bench_warmstart(args, torch, synth, O):
         feats.append(F)
         targets.append(torch.from_numpy(np.concatenate(ys + yt).astype(np.float32)).to(dev))
         h.close()
+        if (c0 // 256) % 10 == 9:
+            log(f"warm start: {c0 + 256} training instances solved")
     F = torch.cat(feats)
     y = torch.cat(targets)
     t_data = time.perf_counter() - t_data
@@ -378,6 +380,7 @@ def bench_warmstart(args, torch, synth, O):
     M.train(F, y, batch=batch, epochs=args.ws_epochs, lr=1e-3, loss_trace=ltr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
+    log(f"warm start: network trained ({steps} steps, {t_train:.1f} s)")
     lt = ltr.cpu().numpy()
     if args.ws_save:
         np.save(args.ws_save, M.get_params().cpu().numpy())
@@ -389,6 +392,7 @@ def bench_warmstart(args, torch, synth, O):
     n = len(held)
     _, _, inf_c, tr_c, tt_c, wall_c = _solve_traced(h, n, K, torch, use_screen=1)
     torch.cuda.synchronize()
+    log("warm start: held-out cold solves done")
     t0 = time.perf_counter()
     a0, b0 = h.warm_start(M, probs)
     torch.cuda.synchronize()
@@ -418,9 +422,12 @@ def bench_warmstart(args, torch, synth, O):
                 train_rows=int(perm.numel()), train_data_s=t_data, train_s=t_train,
                 train_steps=int(steps), loss_first=float(lt[:10].mean()), loss_last=float(lt[-10:].mean()),
                 all_reached_1e6=ok,
+                frac_reached_1e6_cold=float(np.mean([x is not None for x in its_c])),
+                frac_reached_1e6_warm=float(np.mean([x is not None for x in its_w])),
                 iters_to_1e6_cold_median=float(np.median(ic)), iters_to_1e6_warm_median=float(np.median(iw)),
                 iters_to_1e6_cold_mean=float(ic.mean()), iters_to_1e6_warm_mean=float(iw.mean()),
                 frac_instances_fewer_iters=float(np.mean(iw < ic)),
+                # over the instances that reach 1e-6 in that run
                 time_to_all_1e6_cold_s=tc, time_to_all_1e6_warm_s=tw, inference_s=t_inf,
                 speedup_time=tc / tw,
                 final_obj_max_rel_diff=float(np.max(np.abs(fin_w - fin_c) / np.abs(fin_c))))
