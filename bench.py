@@ -390,6 +390,7 @@ def bench_warmstart(args, torch, synth, O):
     probs = _problems(held, torch, O)
     h = O.Handle(probs)
     n = len(held)
+    K = 10000   # the slowest cold solves need more than 4000 iterations to reach 1e-6
     _, _, inf_c, tr_c, tt_c, wall_c = _solve_traced(h, n, K, torch, use_screen=1)
     torch.cuda.synchronize()
     log("warm start: held-out cold solves done")
@@ -417,6 +418,18 @@ def bench_warmstart(args, torch, synth, O):
     tc = max(x for x in ts_c if x is not None)
     tw = max(x for x in ts_w if x is not None) + t_inf
     h.close()
+    # the instances that miss 1e-6 of the better run in either run: status
+    # (0 converged, 1 iteration limit, 2 no line-search step), iterations and
+    # relative gap of each run
+    missed = []
+    for k in range(n):
+        if its_c[k] is None or its_w[k] is None:
+            gc = float((dstar[k] - fin_c[k]) / abs(dstar[k]))
+            gw = float((dstar[k] - fin_w[k]) / abs(dstar[k]))
+            missed.append(dict(k=k, n_src=int(held[k]["xs"].shape[0]), n_tgt=int(held[k]["xt"].shape[0]),
+                               gamma=held[k]["gamma"], mu=held[k]["mu"],
+                               cold=[inf_c[k]["status"], inf_c[k]["iters"], gc],
+                               warm=[inf_w[k]["status"], inf_w[k]["iters"], gw]))
     return dict(workload=f"train {args.ws_train} / held-out {n} instances of the batched generator "
                          f"(held-out n, m up to 4096), network {d + 8}-{w}-{w}-1",
                 train_rows=int(perm.numel()), train_data_s=t_data, train_s=t_train,
@@ -430,7 +443,8 @@ def bench_warmstart(args, torch, synth, O):
                 # over the instances that reach 1e-6 in that run
                 time_to_all_1e6_cold_s=tc, time_to_all_1e6_warm_s=tw, inference_s=t_inf,
                 speedup_time=tc / tw,
-                final_obj_max_rel_diff=float(np.max(np.abs(fin_w - fin_c) / np.abs(fin_c))))
+                final_obj_max_rel_diff=float(np.max(np.abs(fin_w - fin_c) / np.abs(fin_c))),
+                missed_1e6=missed[:16])
 
 
 def log(msg):
