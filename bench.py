@@ -454,8 +454,8 @@ def log(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (every box here has "
-              "one GPU; see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs on a "
+              "single MI355X; sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth

@@ -14,8 +14,8 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run in one process on the GPU machine; nothing to reorder here,
-    # but make sure a GPU test never runs silently on a machine without one.
+    # GPU tests run in one process; nothing to reorder here, but make sure a
+    # GPU test never runs silently on a machine without a GPU.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
