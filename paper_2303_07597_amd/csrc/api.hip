@@ -1172,7 +1172,7 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
   ScreenArgs S = screen_args(h, use_lower);
   if (h->tot_groups > 0) {
     if (group_stats) {
-      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(GS_THREADS), 0, s, S);
       LAUNCHCHK();
     }
     hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TPB)),
@@ -1680,8 +1680,8 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();
   if (upd)
-    hipLaunchKernelGGL(k_lbfgs_update_gs, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, 256)), h->count),
-                       dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_lbfgs_update_gs, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_THREADS)), h->count),
+                       dim3(GS_THREADS), 0, s, A);
   else
     hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
                        dim3(256), 0, s, A);
@@ -1749,7 +1749,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   if (P.use_screen && h->upd_stats && h->tot_groups > 0) {
     // statistics of the first evaluation (later ones come from the update)
     ScreenArgs S = screen_args(h, P.use_lower);
-    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(256), 0, s, S);
+    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(GS_THREADS), 0, s, S);
     LAUNCHCHK();
   }
   // upper bound on evaluations: the first one plus max_ls per iteration

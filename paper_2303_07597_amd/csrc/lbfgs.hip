@@ -693,8 +693,8 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
 // columns each.  Block (0, 0) also resets the work-list counts of the next
 // screen pass, and each instance's group-0 block counts its next
 // evaluation, as k_group_stats does.
-__global__ void __launch_bounds__(256) k_lbfgs_update_gs(LbArgs A) {
-  __shared__ double sm[4][256];
+__global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
+  __shared__ double sm[4][GS_THREADS];
   const int k = blockIdx.y;
   const InstDev I = A.inst[k];
   const LbState& S = A.st[k];
@@ -704,7 +704,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_update_gs(LbArgs A) {
   const int bx = blockIdx.x;
   if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
   if (bx >= A.max_le) {
-    const int c = (bx - A.max_le) * 256 + threadIdx.x;
+    const int c = (bx - A.max_le) * GS_THREADS + threadIdx.x;
     if (c < I.nt_pad) {
       float so;
       lb_update_elem(A, I, S, I.ns + c, v0, h, snap, so);
@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_update_gs(LbArgs A) {
   sm[0][threadIdx.x] = up; sm[1][threadIdx.x] = dn;
   sm[2][threadIdx.x] = am; sm[3][threadIdx.x] = ams;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = GS_THREADS / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
       sm[1][threadIdx.x] += sm[1][threadIdx.x + o];

@@ -167,6 +167,11 @@ struct alignas(16) TileRec {
 };
 static_assert(sizeof(TileRec) == 64, "TileRec is one 64-byte record");
 
+// threads of a per-group statistics workgroup (k_group_stats and the L-BFGS
+// update that forms the same statistics): one row per thread for groups of
+// up to this many rows, and the same fixed-order tree in both kernels
+constexpr int GS_THREADS = 1024;
+
 // Per-group statistics of the change since the snapshot, in float64.
 struct GroupStats {
   double up;        // || [alpha - alpha~]_+ ||  over the group

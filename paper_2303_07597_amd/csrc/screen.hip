@@ -59,8 +59,8 @@ struct ScreenArgs {
 // Per-group float64 statistics of alpha - alpha~ (and max |alpha|, |alpha~|);
 // one block per nonempty group of every instance.  Block 0 also resets the
 // work-list counts of the screen that follows.
-__global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
-  __shared__ double sm[5][256];
+__global__ void __launch_bounds__(GS_THREADS) k_group_stats(ScreenArgs A) {
+  __shared__ double sm[4][GS_THREADS];
   const int gidx = blockIdx.x;
   const int k = A.grp_inst[gidx];
   const InstDev I = A.inst[k];
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) k_group_stats(ScreenArgs A) {
   sm[0][threadIdx.x] = up; sm[1][threadIdx.x] = dn;
   sm[2][threadIdx.x] = am; sm[3][threadIdx.x] = ams;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = GS_THREADS / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
       sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
