@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
 // screen pass, and each instance's group-0 block counts its next
 // evaluation, as k_group_stats does.
 __global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
-  __shared__ double sm[4][GS_THREADS];
+  __shared__ double sm[4][GS_THREADS / 64];
   const int k = blockIdx.y;
   const InstDev I = A.inst[k];
   const LbState& S = A.st[k];
@@ -723,25 +723,14 @@ __global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
     am = fmax(am, fabs(a));
     ams = fmax(ams, fabs((double)as));
   }
-  sm[0][threadIdx.x] = up; sm[1][threadIdx.x] = dn;
-  sm[2][threadIdx.x] = am; sm[3][threadIdx.x] = ams;
-  __syncthreads();
-  for (int o = GS_THREADS / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
-      sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
-      sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + o]);
-      sm[3][threadIdx.x] = fmax(sm[3][threadIdx.x], sm[3][threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
+  gs_reduce(up, dn, am, ams, sm);
   if (threadIdx.x == 0) {
     GroupStats g;
-    g.up = sqrt(sm[0][0]);
-    g.dn = sqrt(sm[1][0]);
-    g.all = sqrt(sm[0][0] + sm[1][0]);
-    g.amax = sm[2][0];
-    g.amax_s = sm[3][0];
+    g.up = sqrt(up);
+    g.dn = sqrt(dn);
+    g.all = sqrt(up + dn);
+    g.amax = am;
+    g.amax_s = ams;
     screen_group_consts(n, g.sg, g.fa, g.fb);
     A.gstats[gidx] = g;
     if (bx == 0) {

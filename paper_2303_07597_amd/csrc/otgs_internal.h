@@ -169,8 +169,42 @@ static_assert(sizeof(TileRec) == 64, "TileRec is one 64-byte record");
 
 // threads of a per-group statistics workgroup (k_group_stats and the L-BFGS
 // update that forms the same statistics): one row per thread for groups of
-// up to this many rows, and the same fixed-order tree in both kernels
+// up to this many rows, and the same fixed-order reduction in both kernels
 constexpr int GS_THREADS = 1024;
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// The four statistics of a group over a GS_THREADS workgroup in a fixed
+// order (wavefront trees, then the wavefronts in order); the totals are
+// valid in thread 0.  sm: [4][GS_THREADS / 64] of LDS.
+__device__ __forceinline__ void gs_reduce(double& up, double& dn, double& am, double& ams,
+                                          double (*sm)[GS_THREADS / 64]) {
+  up = wave_sum_dd(up);
+  dn = wave_sum_dd(dn);
+  am = wave_max_d(am);
+  ams = wave_max_d(ams);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[0][w] = up;
+    sm[1][w] = dn;
+    sm[2][w] = am;
+    sm[3][w] = ams;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    up = dn = am = ams = 0.0;
+    for (int i = 0; i < GS_THREADS / 64; ++i) {
+      up += sm[0][i];
+      dn += sm[1][i];
+      am = fmax(am, sm[2][i]);
+      ams = fmax(ams, sm[3][i]);
+    }
+  }
+}
 
 // Per-group statistics of the change since the snapshot, in float64.
 struct GroupStats {

@@ -60,7 +60,7 @@ struct ScreenArgs {
 // one block per nonempty group of every instance.  Block 0 also resets the
 // work-list counts of the screen that follows.
 __global__ void __launch_bounds__(GS_THREADS) k_group_stats(ScreenArgs A) {
-  __shared__ double sm[4][GS_THREADS];
+  __shared__ double sm[4][GS_THREADS / 64];
   const int gidx = blockIdx.x;
   const int k = A.grp_inst[gidx];
   const InstDev I = A.inst[k];
@@ -75,25 +75,14 @@ __global__ void __launch_bounds__(GS_THREADS) k_group_stats(ScreenArgs A) {
     am = fmax(am, fabs(a));
     ams = fmax(ams, fabs(as));
   }
-  sm[0][threadIdx.x] = up; sm[1][threadIdx.x] = dn;
-  sm[2][threadIdx.x] = am; sm[3][threadIdx.x] = ams;
-  __syncthreads();
-  for (int o = GS_THREADS / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sm[0][threadIdx.x] += sm[0][threadIdx.x + o];
-      sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
-      sm[2][threadIdx.x] = fmax(sm[2][threadIdx.x], sm[2][threadIdx.x + o]);
-      sm[3][threadIdx.x] = fmax(sm[3][threadIdx.x], sm[3][threadIdx.x + o]);
-    }
-    __syncthreads();
-  }
+  gs_reduce(up, dn, am, ams, sm);
   if (threadIdx.x == 0) {
     GroupStats s;
-    s.up = sqrt(sm[0][0]);
-    s.dn = sqrt(sm[1][0]);
-    s.all = sqrt(sm[0][0] + sm[1][0]);
-    s.amax = sm[2][0];
-    s.amax_s = sm[3][0];
+    s.up = sqrt(up);
+    s.dn = sqrt(dn);
+    s.all = sqrt(up + dn);
+    s.amax = am;
+    s.amax_s = ams;
     // per-group constants of the rounding-safe upper bound
     screen_group_consts(n, s.sg, s.fa, s.fb);
     A.gstats[gidx] = s;
