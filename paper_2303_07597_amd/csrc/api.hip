@@ -105,6 +105,7 @@ struct ot_gs_handle {
   // statistics (every group at most CHUNK rows)
   bool upd_stats = false;
   int max_le = 1;                // most nonempty groups of an instance
+  bool gs_large = false;         // group-statistics workgroups of GS_LARGE threads
   int* counts_static = nullptr;  // [NBUCKET + 2]
   int* counts_dyn = nullptr;     // [NBUCKET + 2]
   long long* counters = nullptr;
@@ -266,7 +267,12 @@ static int build_work_lists(ot_gs_handle* h, hipStream_t s) {
     h->n_sc = (int)sc.size();
     h->upd_stats = h->n_sg == 0;
     h->max_le = 1;
-    for (int k = 0; k < count; ++k) h->max_le = std::max(h->max_le, h->inst[k].d.Le);
+    long long grp = 0;
+    for (int k = 0; k < count; ++k) {
+      h->max_le = std::max(h->max_le, h->inst[k].d.Le);
+      grp += h->inst[k].d.Le;
+    }
+    h->gs_large = grp > 0 && h->tot_rows > (long long)GS_SMALL * grp;
     TRY(h->alloc(&h->tiles_all, all.size()));
     TRY(h->alloc(&h->list_main, mainl.size()));
     TRY(h->alloc(&h->list_sg, sg.size()));
@@ -1163,6 +1169,16 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
 
 // Evaluation with the mode of every instance read on the device: screen
 // (bounds, extraction at refreshes, work lists), tiles, assembly, snapshot.
+// per-group statistics of every nonempty group (one workgroup each)
+static int launch_group_stats(ot_gs_handle* h, const ScreenArgs& S, hipStream_t s) {
+  if (h->gs_large)
+    hipLaunchKernelGGL(k_group_stats<GS_LARGE>, dim3((unsigned)h->tot_groups), dim3(GS_LARGE), 0, s, S);
+  else
+    hipLaunchKernelGGL(k_group_stats<GS_SMALL>, dim3((unsigned)h->tot_groups), dim3(GS_SMALL), 0, s, S);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
 static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float* ga_out,
                             float* gb_out, bool write_kappa = false, bool finalize = true,
                             bool snapshot_copy = true, bool group_stats = true,
@@ -1172,8 +1188,7 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
   ScreenArgs S = screen_args(h, use_lower);
   if (h->tot_groups > 0) {
     if (group_stats) {
-      hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(GS_THREADS), 0, s, S);
-      LAUNCHCHK();
+      TRY(launch_group_stats(h, S, s));
     }
     hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TPB)),
                        dim3(SCREEN_TILES * 64), 0, s, S);
@@ -1680,8 +1695,14 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();
   if (upd)
-    hipLaunchKernelGGL(k_lbfgs_update_gs, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_THREADS)), h->count),
-                       dim3(GS_THREADS), 0, s, A);
+  {
+    if (h->gs_large)
+      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_LARGE>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_LARGE)), h->count),
+                         dim3(GS_LARGE), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_SMALL>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_SMALL)), h->count),
+                         dim3(GS_SMALL), 0, s, A);
+  }
   else
     hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
                        dim3(256), 0, s, A);
@@ -1749,8 +1770,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   if (P.use_screen && h->upd_stats && h->tot_groups > 0) {
     // statistics of the first evaluation (later ones come from the update)
     ScreenArgs S = screen_args(h, P.use_lower);
-    hipLaunchKernelGGL(k_group_stats, dim3((unsigned)h->tot_groups), dim3(GS_THREADS), 0, s, S);
-    LAUNCHCHK();
+    TRY(launch_group_stats(h, S, s));
   }
   // upper bound on evaluations: the first one plus max_ls per iteration
   const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;

@@ -693,8 +693,9 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
 // columns each.  Block (0, 0) also resets the work-list counts of the next
 // screen pass, and each instance's group-0 block counts its next
 // evaluation, as k_group_stats does.
-__global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
-  __shared__ double sm[4][GS_THREADS / 64];
+template <int GT>
+__global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
+  __shared__ double sm[4][GT / 64];
   const int k = blockIdx.y;
   const InstDev I = A.inst[k];
   const LbState& S = A.st[k];
@@ -704,7 +705,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
   const int bx = blockIdx.x;
   if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
   if (bx >= A.max_le) {
-    const int c = (bx - A.max_le) * GS_THREADS + threadIdx.x;
+    const int c = (bx - A.max_le) * GT + threadIdx.x;
     if (c < I.nt_pad) {
       float so;
       lb_update_elem(A, I, S, I.ns + c, v0, h, snap, so);
@@ -723,7 +724,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_lbfgs_update_gs(LbArgs A) {
     am = fmax(am, fabs(a));
     ams = fmax(ams, fabs((double)as));
   }
-  gs_reduce(up, dn, am, ams, sm);
+  gs_reduce<GT>(up, dn, am, ams, sm);
   if (threadIdx.x == 0) {
     GroupStats g;
     g.up = sqrt(up);

@@ -168,9 +168,10 @@ struct alignas(16) TileRec {
 static_assert(sizeof(TileRec) == 64, "TileRec is one 64-byte record");
 
 // threads of a per-group statistics workgroup (k_group_stats and the L-BFGS
-// update that forms the same statistics): one row per thread for groups of
-// up to this many rows, and the same fixed-order reduction in both kernels
-constexpr int GS_THREADS = 1024;
+// update that forms the same statistics; both kernels of a handle use the
+// same size, hence the same fixed-order reduction): GS_LARGE for handles
+// whose groups average more than GS_SMALL rows, else GS_SMALL
+constexpr int GS_SMALL = 256, GS_LARGE = 1024;
 
 __device__ __forceinline__ double wave_max_d(double v) {
 #pragma unroll
@@ -178,11 +179,11 @@ __device__ __forceinline__ double wave_max_d(double v) {
   return v;
 }
 
-// The four statistics of a group over a GS_THREADS workgroup in a fixed
+// The four statistics of a group over a GT-thread workgroup in a fixed
 // order (wavefront trees, then the wavefronts in order); the totals are
-// valid in thread 0.  sm: [4][GS_THREADS / 64] of LDS.
-__device__ __forceinline__ void gs_reduce(double& up, double& dn, double& am, double& ams,
-                                          double (*sm)[GS_THREADS / 64]) {
+// valid in thread 0.  sm: [4][GT / 64] of LDS.
+template <int GT>
+__device__ __forceinline__ void gs_reduce(double& up, double& dn, double& am, double& ams, double (*sm)[GT / 64]) {
   up = wave_sum_dd(up);
   dn = wave_sum_dd(dn);
   am = wave_max_d(am);
@@ -197,7 +198,7 @@ __device__ __forceinline__ void gs_reduce(double& up, double& dn, double& am, do
   __syncthreads();
   if (threadIdx.x == 0) {
     up = dn = am = ams = 0.0;
-    for (int i = 0; i < GS_THREADS / 64; ++i) {
+    for (int i = 0; i < GT / 64; ++i) {
       up += sm[0][i];
       dn += sm[1][i];
       am = fmax(am, sm[2][i]);

@@ -59,8 +59,9 @@ struct ScreenArgs {
 // Per-group float64 statistics of alpha - alpha~ (and max |alpha|, |alpha~|);
 // one block per nonempty group of every instance.  Block 0 also resets the
 // work-list counts of the screen that follows.
-__global__ void __launch_bounds__(GS_THREADS) k_group_stats(ScreenArgs A) {
-  __shared__ double sm[4][GS_THREADS / 64];
+template <int GT>
+__global__ void __launch_bounds__(GT) k_group_stats(ScreenArgs A) {
+  __shared__ double sm[4][GT / 64];
   const int gidx = blockIdx.x;
   const int k = A.grp_inst[gidx];
   const InstDev I = A.inst[k];
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(GS_THREADS) k_group_stats(ScreenArgs A) {
     am = fmax(am, fabs(a));
     ams = fmax(ams, fabs(as));
   }
-  gs_reduce(up, dn, am, ams, sm);
+  gs_reduce<GT>(up, dn, am, ams, sm);
   if (threadIdx.x == 0) {
     GroupStats s;
     s.up = sqrt(up);
