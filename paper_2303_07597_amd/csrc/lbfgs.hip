@@ -112,10 +112,9 @@ __device__ __forceinline__ float lb_gt(const LbArgs& A, const InstDev& I, int e)
 // grid (maxb, count, 1 + hist), one wavefront per block, LB_PER_THREAD
 // elements per lane.  blockIdx.z = 0 forms the five base dots, z = 1 + i the
 // three dots of history slot i, so every block issues all its loads at once.
-// Each lane writes its partials into an LDS row; lane j then adds column j
-// over the 64 rows in order: one float64 partial per block and dot.
+// Each lane adds its elements' products, fixed-order wavefront reductions
+// (maximum for dot 4) give one float64 partial per block and dot.
 __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
-  __shared__ double rows[64][6];
   const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
   const int lane = threadIdx.x;
   // the instance, its vector offset and its state are read together
@@ -152,6 +151,9 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
       dv[q] = ok ? A.Dv[v0 + e] : 0.f;   // d (for d.y_i)
     }
   }
+  // per-lane partials, then fixed-order wavefront reductions (the totals in
+  // every lane); lane j < nd writes dot j's partial of this block
+  double t = 0.0;
   if (z == 0) {
     double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
     float gm = 0.f;
@@ -163,11 +165,12 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
       a3 += (double)v2[q] * v2[q];
       gm = fmaxf(gm, fabsf(gt[q]));
     }
-    rows[lane][0] = a0;
-    rows[lane][1] = a1;
-    rows[lane][2] = a2;
-    rows[lane][3] = a3;
-    rows[lane][4] = (double)gm;
+    a0 = wave_sum_dd(a0);
+    a1 = wave_sum_dd(a1);
+    a2 = wave_sum_dd(a2);
+    a3 = wave_sum_dd(a3);
+    const double g4 = wave_max_d((double)gm);
+    t = lane == 0 ? a0 : lane == 1 ? a1 : lane == 2 ? a2 : lane == 3 ? a3 : g4;
   } else {
     double s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
@@ -176,21 +179,13 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
       s1 += (double)gt[q] * v2[q];
       s2 += (double)dv[q] * v2[q];
     }
-    rows[lane][0] = s0;
-    rows[lane][1] = s1;
-    rows[lane][2] = s2;
+    s0 = wave_sum_dd(s0);
+    s1 = wave_sum_dd(s1);
+    s2 = wave_sum_dd(s2);
+    t = lane == 0 ? s0 : lane == 1 ? s1 : s2;
   }
-  __syncthreads();
   const int nd = z == 0 ? 5 : 3;
-  if (lane < nd) {
-    double t = 0.0;
-    if (z == 0 && lane == 4) {
-      for (int r = 0; r < 64; ++r) t = fmax(t, rows[r][lane]);
-    } else {
-      for (int r = 0; r < 64; ++r) t += rows[r][lane];
-    }
-    out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
-  }
+  if (lane < nd) out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
 }
 
 __device__ double lb_cubic(double t0, double f0, double d0, double t1, double f1, double d1) {
