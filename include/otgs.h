@@ -183,6 +183,25 @@ int ot_gs_solve(ot_gs_handle *h, const ot_gs_options *opts, float *alpha_io,
 int ot_gs_plan(ot_gs_handle *h, const float *alpha, const float *beta, float *T,
                void *stream);
 
+/* The same plan in compressed sparse row form (its entries are exact zeros
+ * outside the active (group, target) blocks and where alpha_i + beta_j <
+ * c_ij), in two calls at the same (alpha, beta).  Rows are the caller's
+ * source rows stacked over the instances (sum n_src); column indices are the
+ * caller's target index within the instance.
+ * Count (col_idx NULL): row_ptr [sum n_src + 1] (device, int64,
+ * caller-allocated) receives the exclusive prefix of the rows' nonzero
+ * counts and *nnz (host) their total.  Fill (col_idx, val non-NULL):
+ * col_idx [nnz] (device int32) and val [nnz] (device float32,
+ * caller-allocated) receive row i's entries at row_ptr[i] .. row_ptr[i+1] - 1,
+ * in the library's internal column order (targets grouped by nearest source
+ * class; deterministic, not sorted by index); values bit-identical to
+ * ot_gs_plan's.  Allocates temporary device memory (4-12 bytes per row and
+ * 32-target column block) and synchronises the stream.
+ * Errors: as ot_gs_dual_grad; OT_GS_EINVAL for a missing nnz (count) or
+ * val (fill); OT_GS_ENOMEM. */
+int ot_gs_plan_csr(ot_gs_handle *h, const float *alpha, const float *beta, long long *row_ptr,
+                   int *col_idx, float *val, long long *nnz, void *stream);
+
 /* The scaled cost the evaluations use (Sec. 2.1; for COST_ONTHEFLY the
  * values its matrix-core tiles produce, bit for bit), written to C_out in
  * the layout of ot_gs_plan: instance k at offset sum_{k'<k} n_src n_tgt,

@@ -1380,6 +1380,26 @@ static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
 
 // ------------------------------------------------------------ C ABI
 
+// one pass of the sparse plan over every tile (count or fill)
+template <int MODE>
+static int csr_pass(ot_gs_handle* h, const CsrSink& K, hipStream_t s) {
+  const int n = (int)h->tot_tiles;
+  if (n == 0) return OT_GS_OK;
+  if (h->onthefly) {
+    GradArgs A = grad_args(h);
+    A.list = h->tiles_all;
+    hipLaunchKernelGGL(k_otf_emit<MODE>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n, (const int*)h->perm_row,
+                       (const int*)h->perm_col, (const long long*)h->t_off, (float*)nullptr, K);
+  } else {
+    hipLaunchKernelGGL(k_plan_csr<MODE>, dim3((unsigned)std::min(n, 8 * h->n_cu)), dim3(256), 0, s, h->d_inst,
+                       (const TileDesc*)h->tiles_all, n, (const int*)h->perm_row, (const int*)h->perm_col,
+                       (const int*)h->g_start, (const int*)h->g_size, (const float*)h->C, (const float*)h->alpha,
+                       (const float*)h->beta, (const float*)h->kappa, K);
+  }
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
 extern "C" {
 
 int ot_gs_create(const ot_gs_problem* probs, int count, ot_gs_handle** out, void* stream) {
@@ -1413,8 +1433,8 @@ int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T,
     A.list = h->tiles_all;
     const int n = (int)h->tot_tiles;
     if (n > 0) {
-      hipLaunchKernelGGL(k_otf_emit<1>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n,
-                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, T);
+      hipLaunchKernelGGL(k_otf_emit<PLAN_DENSE>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n,
+                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, T, CsrSink{});
       LAUNCHCHK();
     }
     return OT_GS_OK;
@@ -1423,6 +1443,67 @@ int ot_gs_plan(ot_gs_handle* h, const float* alpha, const float* beta, float* T,
   hipLaunchKernelGGL(k_plan_dense, grid, dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->row_grp,
                      h->g_start, h->g_size, h->C, h->alpha, h->beta, h->kappa, h->t_off, T);
   LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+int ot_gs_plan_csr(ot_gs_handle* h, const float* alpha, const float* beta, long long* row_ptr, int* col_idx,
+                   float* val, long long* nnz, void* stream) {
+  if (!h || !alpha || !beta || !row_ptr) return fail(OT_GS_EINVAL, "plan_csr: NULL argument");
+  if (col_idx ? !val : !nnz) return fail(OT_GS_EINVAL, "plan_csr: count needs nnz, fill needs col_idx and val");
+  hipStream_t s = (hipStream_t)stream;
+  TRY(gather(h, alpha, beta, s));
+  TRY(evaluate(h, OT_GS_DENSE, nullptr, nullptr, s, true));
+  long long cstride = 1;
+  for (int k = 0; k < h->count; ++k) cstride = std::max<long long>(cstride, h->inst[k].d.njb);
+  const long long rows = h->tot_rows;
+  // temporary device memory of this call: segment counts, then row totals
+  // (count) or segment offsets (fill)
+  std::vector<void*> tmp;
+  struct Free {
+    std::vector<void*>& v;
+    ~Free() {
+      for (void* p : v) (void)hipFree(p);
+    }
+  } free_tmp{tmp};
+  auto al = [&](void** p, size_t bytes) -> int {
+    const hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return fail(OT_GS_ENOMEM, "plan_csr: hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    tmp.push_back(*p);
+    return OT_GS_OK;
+  };
+  int* cnt = nullptr;
+  TRY(al((void**)&cnt, sizeof(int) * (size_t)rows * cstride));
+  CsrSink K{cnt, nullptr, cstride, nullptr, nullptr};
+  TRY(csr_pass<CSR_COUNT>(h, K, s));
+  const dim3 rgrid((unsigned)std::min<long long>(ceil_div(h->max_ns, 256), 1024), h->count);
+  if (!col_idx) {
+    long long* tot = nullptr;
+    TRY(al((void**)&tot, sizeof(long long) * (size_t)rows));
+    hipLaunchKernelGGL(k_csr_rowsum, rgrid, dim3(256), 0, s, h->d_inst, (const int*)cnt, cstride, tot);
+    LAUNCHCHK();
+    std::vector<long long> ht((size_t)rows), rp((size_t)rows + 1);
+    HIPCHK(hipMemcpyAsync(ht.data(), tot, sizeof(long long) * (size_t)rows, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rp[0] = 0;
+    for (long long i = 0; i < rows; ++i) rp[(size_t)i + 1] = rp[(size_t)i] + ht[(size_t)i];
+    HIPCHK(hipMemcpyAsync(row_ptr, rp.data(), sizeof(long long) * ((size_t)rows + 1), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *nnz = rp[(size_t)rows];
+    return OT_GS_OK;
+  }
+  long long* seg = nullptr;
+  TRY(al((void**)&seg, sizeof(long long) * (size_t)rows * cstride));
+  HIPCHK(hipMemsetAsync(h->err, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_csr_segoff, rgrid, dim3(256), 0, s, h->d_inst, (const int*)cnt, cstride,
+                     (const long long*)row_ptr, seg, h->err);
+  LAUNCHCHK();
+  K.seg = seg;
+  K.col = col_idx;
+  K.val = val;
+  TRY(csr_pass<CSR_FILL>(h, K, s));
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
+  if (herr & 16) return fail(OT_GS_EINVAL, "plan_csr: row counts differ from row_ptr (a point other than the count call's)");
   return OT_GS_OK;
 }
 
@@ -1435,7 +1516,8 @@ int ot_gs_cost(ot_gs_handle* h, float* C_out, void* stream) {
     const int n = (int)h->tot_tiles;
     if (n > 0) {
       hipLaunchKernelGGL(k_otf_emit<0>, dim3(grid_for(h, n)), dim3(BLOCK), 0, s, A, n,
-                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, C_out);
+                         (const int*)h->perm_row, (const int*)h->perm_col, (const long long*)h->t_off, C_out,
+                         CsrSink{});
       LAUNCHCHK();
     }
     return OT_GS_OK;

@@ -963,6 +963,116 @@ __global__ void __launch_bounds__(256) k_plan_dense(const InstDev* __restrict__ 
 }
 
 
+// Plan recovery in compressed sparse row form, per (row, 32-target column
+// block) segment: CSR_COUNT writes the number of nonzero entries of row i in
+// column block jb to cnt[i * cstride + jb] (i the caller row, stacked over
+// the instances); CSR_FILL writes entry (i, j) at seg[i * cstride + jb] plus
+// its rank among the row's nonzero entries of the block (internal column
+// order), as the caller's column j and the value.
+enum PlanMode { PLAN_DENSE = 1, CSR_COUNT = 2, CSR_FILL = 3 };
+
+struct CsrSink {
+  int* cnt;             // CSR_COUNT: [rows][cstride]
+  const long long* seg; // CSR_FILL: [rows][cstride] segment offsets
+  long long cstride;
+  int* col;
+  float* val;
+};
+
+// One entry per lane of a 64-lane group whose half h (lanes 32 h ..
+// 32 h + 31, column c) shares one row: the half's nonzero pattern by ballot.
+template <int MODE>
+__device__ __forceinline__ void csr_emit(const CsrSink& K, bool ok, int grow, int jb, int c, int h, int dcol,
+                                         float v) {
+  const unsigned long long b = __ballot(ok && v > 0.f);
+  const unsigned m = (unsigned)(h ? (b >> 32) : b);
+  if (MODE == CSR_COUNT) {
+    if (c == 0 && ok) K.cnt[(size_t)grow * K.cstride + jb] = __popc(m);
+  } else {
+    if (ok && v > 0.f) {
+      const long long sg = K.seg[(size_t)grow * K.cstride + jb];
+      if (sg >= 0) {   // rows whose count disagrees with the caller's row_ptr are skipped
+        const long long pos = sg + __popc(m & ((1u << c) - 1u));
+        K.col[pos] = dcol;
+        K.val[pos] = v;
+      }
+    }
+  }
+}
+
+// Materialized cost: one wavefront per two rows of a (group, column block)
+// tile at a time (lane = 32 h + c), every tile of the handle.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_plan_csr(const InstDev* __restrict__ inst, const TileDesc* __restrict__ tiles,
+                                                  int ntiles, const int* __restrict__ perm_row,
+                                                  const int* __restrict__ perm_col, const int* __restrict__ g_start,
+                                                  const int* __restrict__ g_size, const float* __restrict__ C,
+                                                  const float* __restrict__ alpha, const float* __restrict__ beta,
+                                                  const float* __restrict__ kappa, CsrSink K) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int h = lane >> 5, c = lane & (TJ - 1);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const TileDesc d = tiles[t];
+    const InstDev I = inst[d.inst];
+    const int gs = g_start[I.grp_off + d.grp], gn = g_size[I.grp_off + d.grp];
+    const int col = d.jb * TJ + c;
+    const bool colok = col < I.nt;
+    const float bj = colok ? beta[I.col_off + col] : 0.f;
+    const float kap = colok ? kappa[(size_t)I.pair_off + (size_t)d.grp * I.nt_pad + col] : 0.f;
+    const int dcol = colok ? perm_col[I.col_off + col] : 0;
+    for (int r0 = 2 * w; r0 < gn; r0 += 2 * nw) {
+      const int r = r0 + h;
+      const bool ok = r < gn && colok;
+      float v = 0.f;
+      int grow = 0;
+      if (ok) {
+        const float f = (alpha[I.row_off + gs + r] + bj) - C[c_index(I, gs, gn, gs + r, col)];
+        v = kap * fmaxf(f, 0.f);
+        grow = I.row_off + perm_row[I.row_off + gs + r];
+      }
+      csr_emit<MODE>(K, ok, grow, d.jb, c, h, dcol, v);
+    }
+  }
+}
+
+// Row totals of the segment counts (CSR_COUNT output), caller rows of
+// instance blockIdx.y
+__global__ void __launch_bounds__(256) k_csr_rowsum(const InstDev* __restrict__ inst, const int* __restrict__ cnt,
+                                                    long long cstride, long long* __restrict__ tot) {
+  const InstDev I = inst[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < I.ns; i += gridDim.x * blockDim.x) {
+    const int* ci = cnt + (size_t)(I.row_off + i) * cstride;
+    long long t = 0;
+    for (int jb = 0; jb < I.njb; ++jb) t += ci[jb];
+    tot[I.row_off + i] = t;
+  }
+}
+
+// Segment offsets from the caller's row pointers: seg[i][jb] = row_ptr[i]
+// plus the counts of the row's earlier column blocks.  A row whose total
+// differs from row_ptr[i + 1] - row_ptr[i] (a point other than the count
+// call's) gets -1 everywhere (nothing is written for it) and sets bit 16 of
+// err.
+__global__ void __launch_bounds__(256) k_csr_segoff(const InstDev* __restrict__ inst, const int* __restrict__ cnt,
+                                                    long long cstride, const long long* __restrict__ row_ptr,
+                                                    long long* __restrict__ seg, int* __restrict__ err) {
+  const InstDev I = inst[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < I.ns; i += gridDim.x * blockDim.x) {
+    const size_t base = (size_t)(I.row_off + i) * cstride;
+    const long long r0 = row_ptr[I.row_off + i], r1 = row_ptr[I.row_off + i + 1];
+    long long o = r0;
+    for (int jb = 0; jb < I.njb; ++jb) {
+      seg[base + jb] = o;
+      o += cnt[base + jb];
+    }
+    if (o != r1) {
+      for (int jb = 0; jb < I.njb; ++jb) seg[base + jb] = -1;
+      atomicOr(err, 16);
+    }
+  }
+}
+
 // The scaled internal cost in the caller's order (materialized pool).
 __global__ void __launch_bounds__(256) k_cost_dump(const InstDev* __restrict__ inst,
                                                    const int* __restrict__ perm_row,
@@ -1291,7 +1401,7 @@ template <int MODE>
 __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int* __restrict__ perm_row,
                                                     const int* __restrict__ perm_col,
                                                     const long long* __restrict__ t_off,
-                                                    float* __restrict__ out) {
+                                                    float* __restrict__ out, CsrSink K) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int h = lane >> 5, c = lane & (TJ - 1);
   const int w = threadIdx.x >> 6;
@@ -1321,7 +1431,11 @@ __global__ void __launch_bounds__(BLOCK) k_otf_emit(GradArgs A, int n, const int
         const int prow = __float_as_int(otf_row_value(__int_as_float(pv), q, h));
         const float C = otf_cost(otf_row_value(xv, q, h), ynj, acc[q], I.cscale);
         const float v = MODE ? kap * fmaxf((otf_row_value(av, q, h) + bj) - C, 0.f) : C;
-        if (i0 + rr0 + 4 * h < gn && colok) o[(size_t)prow * I.nt + dcol] = v;
+        const bool ok = i0 + rr0 + 4 * h < gn && colok;
+        if (MODE >= CSR_COUNT)
+          csr_emit<(MODE >= CSR_COUNT ? MODE : CSR_COUNT)>(K, ok, I.row_off + prow, d.jb, c, h, dcol, v);
+        else if (ok)
+          o[(size_t)prow * I.nt + dcol] = v;
       }
     }
   }

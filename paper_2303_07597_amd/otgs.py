@@ -83,6 +83,7 @@ def _load():
     lib.ot_gs_default_options.argtypes = [ct.POINTER(ot_gs_options)]
     lib.ot_gs_default_options.restype = None
     lib.ot_gs_plan.argtypes = [vp, vp, vp, vp, vp]
+    lib.ot_gs_plan_csr.argtypes = [vp, vp, vp, vp, vp, vp, ct.POINTER(ct.c_longlong), vp]
     lib.ot_gs_cost.argtypes = [vp, vp, vp]
     lib.ot_gs_rho_to_mu.argtypes = [d, d, ct.POINTER(d), ct.POINTER(d)]
     lib.ot_gs_get_stats.argtypes = [vp, ct.POINTER(ot_gs_stats), i, vp]
@@ -303,6 +304,20 @@ class Handle:
 
     def plan(self, alpha, beta, T, stream=None):
         _check(lib().ot_gs_plan(self.h, _ptr(alpha), _ptr(beta), _ptr(T), _stream(stream)))
+
+    def plan_csr(self, alpha, beta, stream=None):
+        """The plan in CSR form: (row_ptr int64 [sum n_src + 1], col_idx int32
+        [nnz], val float32 [nnz]) on the device (ot_gs_plan_csr's two calls)."""
+        dev = alpha.device
+        row_ptr = torch.empty(sum(self.n_src) + 1, dtype=torch.int64, device=dev)
+        nnz = ct.c_longlong()
+        _check(lib().ot_gs_plan_csr(self.h, _ptr(alpha), _ptr(beta), _ptr(row_ptr), None, None, ct.byref(nnz),
+                                    _stream(stream)))
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(nnz.value, 1), dtype=torch.float32, device=dev)
+        _check(lib().ot_gs_plan_csr(self.h, _ptr(alpha), _ptr(beta), _ptr(row_ptr), _ptr(col), _ptr(val), None,
+                                    _stream(stream)))
+        return row_ptr, col[:nnz.value], val[:nnz.value]
 
     def cost(self, C_out, stream=None):
         _check(lib().ot_gs_cost(self.h, _ptr(C_out), _stream(stream)))

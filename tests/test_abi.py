@@ -19,7 +19,8 @@ def declared_symbols():
 
 def test_header_declares_the_hot_path():
     syms = declared_symbols()
-    for name in ("ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_plan"):
+    for name in ("ot_gs_create", "ot_gs_destroy", "ot_gs_dual_grad", "ot_gs_solve", "ot_gs_plan",
+                 "ot_gs_plan_csr"):
         assert name in syms
 
 

@@ -194,6 +194,87 @@ def test_plan_matches_oracle():
     assert np.array_equal(T.cpu().numpy() > 0, Tref > 0)
 
 
+def csr_blocks(row_ptr, col, val, ns, nt):
+    """Dense per-instance blocks from the CSR plan (rows stacked, local
+    columns), checking its structure on the way."""
+    rp, c, v = row_ptr.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy()
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == c.size == v.size
+    out, r0 = [], 0
+    for n, m in zip(ns, nt):
+        T = np.zeros((n, m), np.float32)
+        for i in range(n):
+            cols = c[rp[r0 + i]:rp[r0 + i + 1]]
+            assert np.all((cols >= 0) & (cols < m)) and np.unique(cols).size == cols.size
+            T[i, cols] = v[rp[r0 + i]:rp[r0 + i + 1]]
+        assert np.all(v[rp[r0]:rp[r0 + n]] > 0)
+        out.append(T)
+        r0 += n
+    return out
+
+
+@pytest.mark.parametrize("seed,sizes,nt", [(40, [50, 0, 70, 30], 90), (42, [2300, 300, 5], 130)])
+def test_plan_csr_equals_dense_plan(seed, sizes, nt):
+    """The sparse plan holds exactly the nonzero entries of the dense plan,
+    bit for bit (an empty label, a split group of 2300 rows, a ragged column
+    tail), and matches the oracle's plan."""
+    inst = cases.ragged(seed, sum(sizes), nt, sizes)
+    C32, P = cases.with_cost(inst)
+    h = make_handle(C32, P)
+    r = oracle.solve(P, max_iter=30)
+    a32, b32 = r["alpha"].astype(np.float32), r["beta"].astype(np.float32)
+    T = torch.empty((P.ns, P.nt), dtype=torch.float32, device="cuda")
+    h.plan(_dev(a32), _dev(b32), T)
+    rp, col, val = h.plan_csr(_dev(a32), _dev(b32))
+    torch.cuda.synchronize()
+    Td = T.cpu().numpy()
+    (Ts,) = csr_blocks(rp, col, val, [P.ns], [P.nt])
+    np.testing.assert_array_equal(Ts, Td)
+    assert col.numel() == int(np.count_nonzero(Td))
+    Tref = oracle.plan(P, a32.astype(np.float64), b32.astype(np.float64))
+    np.testing.assert_allclose(Ts, Tref, rtol=2e-5, atol=1e-7)
+    # a fill at another point than the count is refused (nothing written
+    # outside the caller's arrays)
+    import ctypes as ct
+    O = _otgs()
+    nnz = ct.c_longlong()
+    rp2 = torch.empty(P.ns + 1, dtype=torch.int64, device="cuda")
+    al, be = _dev(a32), _dev(b32)
+    assert O.lib().ot_gs_plan_csr(h.h, al.data_ptr(), be.data_ptr(), rp2.data_ptr(), None, None,
+                                  ct.byref(nnz), None) == 0
+    c2 = torch.full((max(nnz.value, 1) + 64,), -7, dtype=torch.int32, device="cuda")
+    v2 = torch.full((max(nnz.value, 1) + 64,), -7.0, dtype=torch.float32, device="cuda")
+    al2 = _dev((a32 + 0.05).astype(np.float32))
+    rc = O.lib().ot_gs_plan_csr(h.h, al2.data_ptr(), be.data_ptr(), rp2.data_ptr(), c2.data_ptr(),
+                                v2.data_ptr(), None, None)
+    assert rc == O.OT_GS_EINVAL
+    assert torch.all(c2[nnz.value:] == -7) and torch.all(v2[nnz.value:] == -7.0)
+
+
+def test_plan_csr_batched():
+    O = _otgs()
+    insts = [cases.ragged(70 + i, n, m, s) for i, (n, m, s) in
+             enumerate([(40, 70, [10, 30]), (600, 33, [580, 20]), (9, 130, [3, 3, 3])])]
+    probs, Ps, pts = [], [], []
+    for i, inst in enumerate(insts):
+        C32, P = cases.with_cost(inst)
+        probs.append(dict(labels=_dev(P.labels), n_groups=P.L, gamma=P.gamma, mu=P.mu, cost=_dev(C32),
+                          cost_scale=1.0, cost_mode=O.OT_GS_COST_GIVEN))
+        Ps.append(P)
+        pts.append(cases.dual_point(P, 80 + i))
+    h = O.Handle(probs)
+    al = _dev(np.concatenate([p[0] for p in pts]))
+    be = _dev(np.concatenate([p[1] for p in pts]))
+    T = torch.empty(sum(P.ns * P.nt for P in Ps), dtype=torch.float32, device="cuda")
+    h.plan(al, be, T)
+    rp, col, val = h.plan_csr(al, be)
+    torch.cuda.synchronize()
+    blocks = csr_blocks(rp, col, val, [P.ns for P in Ps], [P.nt for P in Ps])
+    Tn, off = T.cpu().numpy(), 0
+    for P, B in zip(Ps, blocks):
+        np.testing.assert_array_equal(B, Tn[off:off + P.ns * P.nt].reshape(P.ns, P.nt))
+        off += P.ns * P.nt
+
+
 def test_argument_errors():
     O = _otgs()
     inst = cases.ragged(50, 20, 10, [10, 10])

@@ -120,6 +120,28 @@ def test_integer_features_gradient_parity(seed, sizes, nt, d):
     assert np.all(np.abs(gb - ob) <= rb)
 
 
+def test_integer_features_plan_csr_equals_dense_plan():
+    """The sparse plan from the matrix-core tiles holds exactly the nonzero
+    entries of the dense plan (a 1300-row group evaluated in chunks, an empty
+    label, a ragged target tail)."""
+    from tests.test_gpu_dual_grad import csr_blocks
+    seed, sizes, nt, d = INT_CASES[0]
+    inst = int_instance(seed, sizes, nt, d, gamma=0.2, mu=0.3)
+    scale = 2.0 ** -10
+    h = otf_handle(inst, scale)
+    C = oracle.cost_sqeuclid(inst["xs"], inst["xt"]) * scale
+    P = oracle.Problem(C, inst["labels"], inst["n_groups"], inst["gamma"], inst["mu"])
+    a32, b32 = cases.dual_point(P, seed)
+    T = torch.empty((P.ns, P.nt), dtype=torch.float32, device="cuda")
+    h.plan(_dev(a32), _dev(b32), T)
+    rp, col, val = h.plan_csr(_dev(a32), _dev(b32))
+    torch.cuda.synchronize()
+    (Ts,) = csr_blocks(rp, col, val, [P.ns], [P.nt])
+    Td = T.cpu().numpy()
+    np.testing.assert_array_equal(Ts, Td)
+    assert col.numel() == int(np.count_nonzero(Td)) > 0
+
+
 def real_instance(seed=31, ns=3000, nt=1000, d=256, L=12):
     inst = synth.zipf_blobs(seed=seed, n_src=ns, n_tgt=nt, d=d, n_groups=L, gamma=0.05, mu=0.5)
     return inst
