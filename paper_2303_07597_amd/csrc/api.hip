@@ -1218,7 +1218,8 @@ static int evaluate(ot_gs_handle* h, int mode, float* ga_out, float* gb_out, hip
     LAUNCHCHK();
   }
   if (mode != OT_GS_DENSE) {
-    TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa, true, true, true,
+    // (the snapshot copy acts only on instances evaluated at a snapshot)
+    TRY(evaluate_dynamic(h, s, 1, ga_out, gb_out, write_kappa, true, mode == OT_GS_SNAPSHOT, true,
                          mode == OT_GS_SNAPSHOT, obj_out));
     if (mode == OT_GS_SNAPSHOT) h->has_snapshot = true;
     return OT_GS_OK;
