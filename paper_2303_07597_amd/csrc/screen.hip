@@ -123,6 +123,11 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
   const bool tile_ok = t < A.n_tiles_all;
   TileDesc d{0, 0, 0, 0};
   if (tile_ok) d = A.tiles_all[t];
+  // the tile's 64-byte record, 16 bytes per lane on lanes 0..3 of the half,
+  // fetched now so that the list write below waits on no further load
+  int4 rq{0, 0, 0, 0};
+  const bool rec_lane = A.rec_all != nullptr && tile_ok && c < 4;
+  if (rec_lane) rq = reinterpret_cast<const int4*>(A.rec_all + t)[c];
   int mode = EM_SKIP, tile_off = 0, njb = 0;
   bool valid = false, inN = false, checked = false, compute = false;
   if (tile_ok) {
@@ -151,14 +156,19 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
         compute = true;
       } else if (mode == EM_DENSE) {
         compute = true;
-      } else if (A.inN[pr] == PAIR_IN_N) {
-        inN = true;
-        compute = true;
       } else {
-        checked = true;
-        const double ub = screen_upper(A.zsnap[pr], b, bs, Sp->up, Sp->amax, Sp->amax_s, sg, Sp->fa,
-                                       Sp->fb, (double)cmax);
-        compute = !(ub <= thr);
+        // flag and snapshot norm loaded together (one round trip)
+        const uint8_t f = A.inN[pr];
+        const float zs = A.zsnap[pr];
+        if (f == PAIR_IN_N) {
+          inN = true;
+          compute = true;
+        } else {
+          checked = true;
+          const double ub = screen_upper(zs, b, bs, Sp->up, Sp->amax, Sp->amax_s, sg, Sp->fa, Sp->fb,
+                                         (double)cmax);
+          compute = !(ub <= thr);
+        }
       }
     }
   }
@@ -249,18 +259,19 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
   }
   __syncthreads();
   // list entries in tile order within the block
-  if (c == 0 && on) {
-    if (d.aux >= 0) {
-      // the bucket's list offset (unrolled select: a kernel-argument array
-      // indexed at run time would be copied to private memory)
-      int moff = 0;
+  if (on && d.aux >= 0 && (c == 0 || rec_lane)) {
+    // the bucket's list offset (unrolled select: a kernel-argument array
+    // indexed at run time would be copied to private memory)
+    int moff = 0;
 #pragma unroll
-      for (int q = 0; q < NBUCKET; ++q)
-        if (q == d.aux) moff = A.main_off[q];
-      const int pm = s_base[d.aux] + s_cnt[slot][4];
-      A.list_main[moff + pm] = d;
-      if (A.rec_all) A.rec_dyn[moff + pm] = A.rec_all[t];
-    } else {
+    for (int q = 0; q < NBUCKET; ++q)
+      if (q == d.aux) moff = A.main_off[q];
+    const int pm = s_base[d.aux] + s_cnt[slot][4];
+    if (c == 0) A.list_main[moff + pm] = d;
+    if (rec_lane) reinterpret_cast<int4*>(A.rec_dyn + moff + pm)[c] = rq;
+  }
+  if (c == 0 && on) {
+    if (d.aux < 0) {
       const int ps = s_base[NBUCKET] + s_cnt[slot][5], pc = s_base[NBUCKET + 1] + s_cnt[slot][6];
       TileDesc e = d;
       e.aux = 0;
