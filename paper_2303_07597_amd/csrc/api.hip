@@ -1190,8 +1190,14 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
     if (group_stats) {
       TRY(launch_group_stats(h, S, s));
     }
-    hipLaunchKernelGGL(k_screen_pairs, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TPB)),
-                       dim3(SCREEN_TILES * 64), 0, s, S);
+    // two passes per block once one pass per block would take several
+    // rounds of resident blocks
+    if (ceil_div(h->tot_tiles, SCREEN_TPB) > SCREEN_WIDE_BLOCKS)
+      hipLaunchKernelGGL(k_screen_pairs<2>, dim3((unsigned)ceil_div(h->tot_tiles, 2 * SCREEN_TPB)),
+                         dim3(SCREEN_TILES * 64), 0, s, S);
+    else
+      hipLaunchKernelGGL(k_screen_pairs<1>, dim3((unsigned)ceil_div(h->tot_tiles, SCREEN_TPB)),
+                         dim3(SCREEN_TILES * 64), 0, s, S);
     LAUNCHCHK();
   }
   TRY(tend(h, KT_SCREEN, s, e0));

@@ -97,128 +97,179 @@ __global__ void __launch_bounds__(GT) k_group_stats(ScreenArgs A) {
   }
 }
 
-constexpr int SCREEN_TILES = 16;   // group tiles (wavefronts) per screen block
-
-
-constexpr int SCREEN_TPB = 2 * SCREEN_TILES;   // group tiles per screen block
+constexpr int SCREEN_TILES = 16;   // wavefronts per screen block
+constexpr int SCREEN_TPB = 2 * SCREEN_TILES;   // group tiles per pass of a screen block
 static_assert(SCREEN_TPB <= WAVE && NBUCKET + 2 <= WAVE, "the block tally uses one lane per slot");
+constexpr int SCREEN_WIDE_BLOCKS = 1024;  // single-pass grids above this many blocks take two passes
 
-// One half wavefront per group tile (SCREEN_TPB per block: only 32 lanes of
-// a tile have a column), one lane per target column.  SCREEN: classify
-// every pair (in N / bound tested / skipped), mark the tile when any pair
-// must be evaluated.  SNAPSHOT: rebuild N from the lower bound, then
-// evaluate densely.  DENSE: every tile.  SKIP: nothing.  Active tiles are
-// appended to the work lists; counters and list positions are aggregated
-// per block so each block issues one atomic per quantity.
+// One half wavefront per group tile (SCREEN_TPB tiles per pass, TPH passes
+// per block: only 32 lanes of a tile have a column), one lane per target
+// column.  SCREEN: classify every pair (in N / bound tested / skipped), mark
+// the tile when any pair must be evaluated.  SNAPSHOT: rebuild N from the
+// lower bound, then evaluate densely.  DENSE: every tile.  SKIP: nothing.
+// Active tiles are appended to the work lists; counters and list positions
+// are aggregated per block so each block issues one atomic per quantity.
+// More passes per block amortise the block's fixed latency (descriptor
+// fetch, list atomics, barriers, list writes) over more tiles and put fewer
+// atomics on the shared list counts; a single pass keeps small grids wide.
+template <int TPH>
 __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A) {
-  __shared__ int s_cnt[SCREEN_TPB][8];   // valid, inN, checked, unskipped, main, split,
-                                         // chunks of an active split tile, tile counted
-  __shared__ int s_bkt[SCREEN_TPB];
+  constexpr int NE = SCREEN_TPB * TPH;        // tiles of the block; entry i * SCREEN_TPB + slot
+  constexpr int NP = (NE + WAVE - 1) / WAVE;  // tally passes of wavefront 0
+  __shared__ int s_cnt[NE][8];   // valid, inN, checked, unskipped, main, split,
+                                 // chunks of an active split tile, tile counted
+  __shared__ int s_bkt[NE];
   __shared__ int s_base[NBUCKET + 2];
+  __shared__ int4 s_rec[TPH > 1 ? NE : 1][4];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
   const int half = lane >> 5, c = lane & (TJ - 1);
-  const int slot = 2 * wv + half;   // the tile's slot in the block
-  const int t = blockIdx.x * SCREEN_TPB + slot;
-  const bool tile_ok = t < A.n_tiles_all;
-  TileDesc d{0, 0, 0, 0};
-  if (tile_ok) d = A.tiles_all[t];
-  // the tile's 64-byte record, 16 bytes per lane on lanes 0..3 of the half,
-  // fetched now so that the list write below waits on no further load
-  int4 rq{0, 0, 0, 0};
-  const bool rec_lane = A.rec_all != nullptr && tile_ok && c < 4;
-  if (rec_lane) rq = reinterpret_cast<const int4*>(A.rec_all + t)[c];
-  int mode = EM_SKIP, tile_off = 0, njb = 0;
-  bool valid = false, inN = false, checked = false, compute = false;
-  if (tile_ok) {
-    const InstDev* Ip = A.inst + d.inst;
-    const int grp_off = Ip->grp_off, nt = Ip->nt, pair_off = Ip->pair_off;
-    const int nt_pad = Ip->nt_pad, col_off = Ip->col_off;
-    const float ithr = Ip->thr, cmax = Ip->cmax;
-    tile_off = Ip->tile_off;
-    njb = Ip->njb;
-    mode = A.inst_mode[d.inst];
-    const int gidx = grp_off + d.grp;
-    const int col = d.jb * TJ + c;
-    valid = col < nt && mode != EM_SKIP;
-    const size_t pr = (size_t)pair_off + (size_t)d.grp * nt_pad + col;
-    if (valid) {
-      const GroupStats* Sp = A.gstats + gidx;
-      const double b = A.beta[col_off + col], bs = A.beta_s[col_off + col];
-      const double sg = Sp->sg;
-      const double thr = (double)ithr;
-      if (mode == EM_SNAPSHOT) {
-        // Algorithm 1: rebuild N from the lower bound against the old snapshot
-        uint8_t f = PAIR_SKIP;
-        if (A.use_lower && screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, Sp->all, Sp->dn, sg) > thr)
-          f = PAIR_IN_N;
-        A.inN[pr] = f;
-        compute = true;
-      } else if (mode == EM_DENSE) {
-        compute = true;
-      } else {
-        // flag and snapshot norm loaded together (one round trip)
-        const uint8_t f = A.inN[pr];
-        const float zs = A.zsnap[pr];
-        if (f == PAIR_IN_N) {
-          inN = true;
+  const int slot = 2 * wv + half;   // the tile's slot in a pass
+  const int tb = blockIdx.x * NE + slot;
+  // descriptors of every pass, and each tile's 64-byte record (16 bytes per
+  // lane on lanes 0..3 of the half), fetched first so that neither the
+  // passes nor the list write below wait on them
+  TileDesc dd[TPH];
+  int4 rq[TPH];
+  const bool rec_lane = A.rec_all != nullptr && c < 4;
+#pragma unroll
+  for (int i = 0; i < TPH; ++i) {
+    const int t = tb + i * SCREEN_TPB;
+    dd[i] = TileDesc{0, 0, 0, 0};
+    rq[i] = int4{0, 0, 0, 0};
+    if (t < A.n_tiles_all) {
+      dd[i] = A.tiles_all[t];
+      if (rec_lane) rq[i] = reinterpret_cast<const int4*>(A.rec_all + t)[c];
+    }
+  }
+  // with several passes the records wait in LDS (registers stay free)
+  if (TPH > 1 && rec_lane) {
+#pragma unroll
+    for (int i = 0; i < TPH; ++i) s_rec[i * SCREEN_TPB + slot][c] = rq[i];
+  }
+  bool onv[TPH];
+  const int sh = 32 * half;
+  auto halfcount = [&](bool x) { return __popcll((__ballot(x) >> sh) & 0xffffffffull); };
+#pragma unroll
+  for (int i = 0; i < TPH; ++i) {
+    const int t = tb + i * SCREEN_TPB;
+    const bool tile_ok = t < A.n_tiles_all;
+    const TileDesc d = dd[i];
+    int mode = EM_SKIP, tile_off = 0, njb = 0;
+    bool valid = false, inN = false, checked = false, compute = false;
+    if (tile_ok) {
+      const InstDev* Ip = A.inst + d.inst;
+      const int grp_off = Ip->grp_off, nt = Ip->nt, pair_off = Ip->pair_off;
+      const int nt_pad = Ip->nt_pad, col_off = Ip->col_off;
+      const float ithr = Ip->thr, cmax = Ip->cmax;
+      tile_off = Ip->tile_off;
+      njb = Ip->njb;
+      mode = A.inst_mode[d.inst];
+      const int gidx = grp_off + d.grp;
+      const int col = d.jb * TJ + c;
+      valid = col < nt && mode != EM_SKIP;
+      const size_t pr = (size_t)pair_off + (size_t)d.grp * nt_pad + col;
+      if (valid) {
+        const GroupStats* Sp = A.gstats + gidx;
+        const double b = A.beta[col_off + col], bs = A.beta_s[col_off + col];
+        const double sg = Sp->sg;
+        const double thr = (double)ithr;
+        if (mode == EM_SNAPSHOT) {
+          // Algorithm 1: rebuild N from the lower bound against the old snapshot
+          uint8_t f = PAIR_SKIP;
+          if (A.use_lower && screen_lower(A.zsnap[pr], A.osnap[pr], b, bs, Sp->all, Sp->dn, sg) > thr)
+            f = PAIR_IN_N;
+          A.inN[pr] = f;
+          compute = true;
+        } else if (mode == EM_DENSE) {
           compute = true;
         } else {
-          checked = true;
-          const double ub = screen_upper(zs, b, bs, Sp->up, Sp->amax, Sp->amax_s, sg, Sp->fa, Sp->fb,
-                                         (double)cmax);
-          compute = !(ub <= thr);
+          // flag and snapshot norm loaded together (one round trip)
+          const uint8_t f = A.inN[pr];
+          const float zs = A.zsnap[pr];
+          if (f == PAIR_IN_N) {
+            inN = true;
+            compute = true;
+          } else {
+            checked = true;
+            const double ub = screen_upper(zs, b, bs, Sp->up, Sp->amax, Sp->amax_s, sg, Sp->fa, Sp->fb,
+                                           (double)cmax);
+            compute = !(ub <= thr);
+          }
         }
       }
     }
-  }
-  // per-half tallies
-  const int sh = 32 * half;
-  auto halfcount = [&](bool x) { return __popcll((__ballot(x) >> sh) & 0xffffffffull); };
-  const int c_valid = halfcount(valid), c_in = halfcount(inN), c_chk = halfcount(checked);
-  const int c_uns = halfcount(checked && compute);
-  const bool on = tile_ok && halfcount(compute) != 0;
-  if (c == 0) {
-    if (tile_ok) A.tile_on[(size_t)tile_off + (size_t)d.grp * njb + d.jb] = on ? 1 : 0;
-    s_cnt[slot][0] = c_valid;
-    s_cnt[slot][1] = c_in;
-    s_cnt[slot][2] = c_chk;
-    s_cnt[slot][3] = c_uns;
-    s_cnt[slot][4] = (on && d.aux >= 0) ? 1 : 0;
-    s_cnt[slot][5] = (on && d.aux < 0) ? 1 : 0;
-    s_cnt[slot][6] = (on && d.aux < 0) ? -d.aux : 0;
-    s_cnt[slot][7] = (tile_ok && mode != EM_SKIP) ? 1 : 0;
-    s_bkt[slot] = d.aux >= 0 ? d.aux : 0;
+    // per-half tallies
+    const int c_valid = halfcount(valid), c_in = halfcount(inN), c_chk = halfcount(checked);
+    const int c_uns = halfcount(checked && compute);
+    const bool on = tile_ok && halfcount(compute) != 0;
+    onv[i] = on;
+    if (c == 0) {
+      if (tile_ok) A.tile_on[(size_t)tile_off + (size_t)d.grp * njb + d.jb] = on ? 1 : 0;
+      int* sc = s_cnt[i * SCREEN_TPB + slot];
+      sc[0] = c_valid;
+      sc[1] = c_in;
+      sc[2] = c_chk;
+      sc[3] = c_uns;
+      sc[4] = (on && d.aux >= 0) ? 1 : 0;
+      sc[5] = (on && d.aux < 0) ? 1 : 0;
+      sc[6] = (on && d.aux < 0) ? -d.aux : 0;
+      sc[7] = (tile_ok && mode != EM_SKIP) ? 1 : 0;
+      s_bkt[i * SCREEN_TPB + slot] = d.aux >= 0 ? d.aux : 0;
+    }
   }
   __syncthreads();
-  // Block tally by wavefront 0, lane l standing for slot l: per-bucket
-  // counts and each slot's rank by ballots, split offsets by wavefront
-  // sums, one atomic per quantity (issued by different lanes together)
+  // Block tally by wavefront 0, lane l standing for entries l, l + 64, ...:
+  // per-bucket counts and each entry's rank by ballots, split offsets by
+  // wavefront sums, one atomic per quantity (issued by different lanes
+  // together)
   if (wv == 0) {
-    const bool has = lane < SCREEN_TPB;
-    const int m4 = has ? s_cnt[lane][4] : 0, m5 = has ? s_cnt[lane][5] : 0;
-    const int m6 = has ? s_cnt[lane][6] : 0, bk = has ? s_bkt[lane] : 0;
     const unsigned long long below = (1ull << lane) - 1ull;
-    int rank = 0, nb_mine = 0;   // lane q < NBUCKET: tiles of bucket q in the block
+    int cntq[NBUCKET];   // wavefront-uniform running count per bucket
 #pragma unroll
-    for (int q = 0; q < NBUCKET; ++q) {
-      const unsigned long long bq = __ballot(m4 && bk == q);
-      if (bk == q) rank = __popcll(bq & below);
-      if (lane == q) nb_mine = __popcll(bq);
-    }
-    // exclusive prefixes of split tiles and chunks over the slots
-    int ps = m5, pc = m6;
+    for (int q = 0; q < NBUCKET; ++q) cntq[q] = 0;
+    int nsg = 0, nsc = 0, nt_ = 0, non = 0;
+    long long tq[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const int ys = __shfl_up(ps, o), yc = __shfl_up(pc, o);
-      if (lane >= o) {
-        ps += ys;
-        pc += yc;
+    for (int p = 0; p < NP; ++p) {
+      const int e = p * WAVE + lane;
+      const bool has = e < NE;
+      const int m4 = has ? s_cnt[e][4] : 0, m5 = has ? s_cnt[e][5] : 0;
+      const int m6 = has ? s_cnt[e][6] : 0, bk = has ? s_bkt[e] : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] += has ? s_cnt[e][q] : 0;
+      nt_ += has ? s_cnt[e][7] : 0;
+      non += m4 + m5;
+      int rank = 0;
+#pragma unroll
+      for (int q = 0; q < NBUCKET; ++q) {
+        const unsigned long long bq = __ballot(m4 && bk == q);
+        if (bk == q) rank = cntq[q] + __popcll(bq & below);
+        cntq[q] += __popcll(bq);
       }
+      // exclusive prefixes of split tiles and chunks over the entries
+      int ps = m5, pc = m6;
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const int ys = __shfl_up(ps, o), yc = __shfl_up(pc, o);
+        if (lane >= o) {
+          ps += ys;
+          pc += yc;
+        }
+      }
+      const int ts = __shfl(ps, WAVE - 1), tc = __shfl(pc, WAVE - 1);
+      if (has) {
+        s_cnt[e][4] = rank;            // reused: position within the block's bucket
+        s_cnt[e][5] = nsg + ps - m5;   // split group position within the block
+        s_cnt[e][6] = nsc + pc - m6;   // split chunk position within the block
+      }
+      nsg += ts;
+      nsc += tc;
     }
-    const int nsg = __shfl(ps, WAVE - 1), nsc = __shfl(pc, WAVE - 1);
-    ps -= m5;
-    pc -= m6;
+    int nb_mine = 0;   // lane q < NBUCKET: tiles of bucket q in the block
+#pragma unroll
+    for (int q = 0; q < NBUCKET; ++q)
+      if (lane == q) nb_mine = cntq[q];
     // list bases: lane q < NBUCKET for bucket q, NBUCKET split groups,
     // NBUCKET + 1 split chunks
     int base = 0;
@@ -226,24 +277,12 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     if (lane == NBUCKET && nsg) base = atomicAdd(&A.counts[NBUCKET], nsg);
     if (lane == NBUCKET + 1 && nsc) base = atomicAdd(&A.counts[NBUCKET + 1], nsc);
     if (lane < NBUCKET + 2) s_base[lane] = base;
-    if (has) {
-      s_cnt[lane][4] = rank;   // reused: position within the block's bucket
-      s_cnt[lane][5] = ps;     // split group position within the block
-      s_cnt[lane][6] = pc;     // split chunk position within the block
-    }
     // counters: every block owns a slot (evaluations are ordered on the
     // stream, so a plain update suffices); slots are summed on request
-    long long tq[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      long long v = has ? s_cnt[lane][q] : 0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      tq[q] = v;
-    }
-    int nt_ = has ? s_cnt[lane][7] : 0, non = m4 + m5;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] += __shfl_xor(tq[q], o);
       nt_ += __shfl_xor(nt_, o);
       non += __shfl_xor(non, o);
     }
@@ -258,27 +297,32 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
     }
   }
   __syncthreads();
-  // list entries in tile order within the block
-  if (on && d.aux >= 0 && (c == 0 || rec_lane)) {
-    // the bucket's list offset (unrolled select: a kernel-argument array
-    // indexed at run time would be copied to private memory)
-    int moff = 0;
+  // list entries in entry order within the block
 #pragma unroll
-    for (int q = 0; q < NBUCKET; ++q)
-      if (q == d.aux) moff = A.main_off[q];
-    const int pm = s_base[d.aux] + s_cnt[slot][4];
-    if (c == 0) A.list_main[moff + pm] = d;
-    if (rec_lane) reinterpret_cast<int4*>(A.rec_dyn + moff + pm)[c] = rq;
-  }
-  if (c == 0 && on) {
-    if (d.aux < 0) {
-      const int ps = s_base[NBUCKET] + s_cnt[slot][5], pc = s_base[NBUCKET + 1] + s_cnt[slot][6];
-      TileDesc e = d;
-      e.aux = 0;
-      A.list_sg[ps] = e;
+  for (int i = 0; i < TPH; ++i) {
+    const TileDesc d = dd[i];
+    const int e = i * SCREEN_TPB + slot;
+    if (!onv[i]) continue;
+    if (d.aux >= 0) {
+      if (c == 0 || rec_lane) {
+        // the bucket's list offset (unrolled select: a kernel-argument array
+        // indexed at run time would be copied to private memory)
+        int moff = 0;
+#pragma unroll
+        for (int q = 0; q < NBUCKET; ++q)
+          if (q == d.aux) moff = A.main_off[q];
+        const int pm = s_base[d.aux] + s_cnt[e][4];
+        if (c == 0) A.list_main[moff + pm] = d;
+        if (rec_lane) reinterpret_cast<int4*>(A.rec_dyn + moff + pm)[c] = TPH > 1 ? s_rec[e][c] : rq[0];
+      }
+    } else if (c == 0) {
+      const int ps = s_base[NBUCKET] + s_cnt[e][5], pc = s_base[NBUCKET + 1] + s_cnt[e][6];
+      TileDesc f = d;
+      f.aux = 0;
+      A.list_sg[ps] = f;
       for (int q = 0; q < -d.aux; ++q) {
-        e.aux = q;
-        A.list_sc[pc + q] = e;
+        f.aux = q;
+        A.list_sc[pc + q] = f;
       }
     }
   }
