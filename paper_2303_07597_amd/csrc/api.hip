@@ -1190,9 +1190,13 @@ static int evaluate_dynamic(ot_gs_handle* h, hipStream_t s, int use_lower, float
     if (group_stats) {
       TRY(launch_group_stats(h, S, s));
     }
-    // two passes per block once one pass per block would take several
-    // rounds of resident blocks
-    if (ceil_div(h->tot_tiles, SCREEN_TPB) > SCREEN_WIDE_BLOCKS)
+    // two or four passes per block once one pass per block would take
+    // several rounds of resident blocks
+    const long long nb1 = ceil_div(h->tot_tiles, SCREEN_TPB);
+    if (nb1 > 2 * SCREEN_WIDE_BLOCKS)
+      hipLaunchKernelGGL(k_screen_pairs<4>, dim3((unsigned)ceil_div(h->tot_tiles, 4 * SCREEN_TPB)),
+                         dim3(SCREEN_TILES * 64), 0, s, S);
+    else if (nb1 > SCREEN_WIDE_BLOCKS)
       hipLaunchKernelGGL(k_screen_pairs<2>, dim3((unsigned)ceil_div(h->tot_tiles, 2 * SCREEN_TPB)),
                          dim3(SCREEN_TILES * 64), 0, s, S);
     else

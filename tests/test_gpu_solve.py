@@ -61,9 +61,10 @@ def test_solve_small_matches_oracle_optimum():
     assert np.all(np.diff(t) >= -1e-12 * abs(t[-1]))
 
 
-# (2600, 2): 1300-row whole groups; (4400, 2): split groups; (4000, 2000):
-# 44000 group tiles, where the screen takes two passes of tiles per block
-@pytest.mark.parametrize("n_src,n_groups", [(800, 5), (2600, 2), (4400, 2), (4000, 2000)])
+# (2600, 2): 1300-row whole groups; (4400, 2): split groups; (4000, 2000)
+# and (8000, 4000): 44000 and 88000 group tiles, where the screen takes two
+# and four passes of tiles per block
+@pytest.mark.parametrize("n_src,n_groups", [(800, 5), (2600, 2), (4400, 2), (4000, 2000), (8000, 4000)])
 def test_screened_trajectory_is_bitwise_dense(n_src, n_groups):
     inst = synth.blobs(seed=12, n_src=n_src, n_tgt=700, d=8, n_groups=n_groups, gamma=0.1, mu=0.3)
     C32, P = cases.with_cost(inst)
