@@ -1783,7 +1783,13 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
-  hipLaunchKernelGGL(k_lbfgs_dots, dim3(h->sol.maxb, h->count, 1 + h->sol.hist), dim3(LB_BLOCK), 0, s, A);
+  // batches with long vectors: LB_SEQ_SPLIT wavefronts per vector block
+  // loop over the history slots (g~ and d read LB_SEQ_SPLIT times instead of
+  // once per slot); otherwise one wavefront per (block, slot)
+  if (h->count > 1 && h->sol.vtot >= LB_SEQ_MIN_VTOT)
+    hipLaunchKernelGGL(k_lbfgs_dots_seq, dim3(h->sol.maxb, h->count, LB_SEQ_SPLIT), dim3(LB_BLOCK), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_lbfgs_dots, dim3(h->sol.maxb, h->count, 1 + h->sol.hist), dim3(LB_BLOCK), 0, s, A);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();

@@ -25,6 +25,10 @@ constexpr int HMAX = 32;
 constexpr int LB_BLOCK = 64;
 constexpr int LB_PER_THREAD = 8;
 constexpr int LB_VB = LB_BLOCK * LB_PER_THREAD;   // vector elements per dots block
+// batched handles with at least this many vector elements in all form their
+// dots with k_lbfgs_dots_seq
+constexpr long long LB_SEQ_MIN_VTOT = 32768;
+constexpr int LB_SEQ_SPLIT = 2;   // wavefronts sharing the history slots of a vector block
 
 enum LbStatus { LB_RUNNING = 0, LB_CONVERGED = 1, LB_LSFAIL = 2, LB_MAXITER = 3 };
 
@@ -109,6 +113,45 @@ __device__ __forceinline__ float lb_gt(const LbArgs& A, const InstDev& I, int e)
   return e < I.ns ? -A.ga[I.row_off + e] : -A.gb[I.col_off + (e - I.ns)];
 }
 
+// Per-lane partials, then fixed-order wavefront reductions (the totals in
+// every lane).  Base dots of a vector block: g~.d, g~.g~, g~.G, d.d and
+// max |g~| (lane j holds dot j, lanes >= 4 the maximum).
+__device__ __forceinline__ double lb_base_dots(const float* gt, const float* G, const float* d, int lane) {
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  float gm = 0.f;
+#pragma unroll
+  for (int q = 0; q < LB_PER_THREAD; ++q) {
+    a0 += (double)gt[q] * d[q];
+    a1 += (double)gt[q] * gt[q];
+    a2 += (double)gt[q] * G[q];
+    a3 += (double)d[q] * d[q];
+    gm = fmaxf(gm, fabsf(gt[q]));
+  }
+  a0 = wave_sum_dd(a0);
+  a1 = wave_sum_dd(a1);
+  a2 = wave_sum_dd(a2);
+  a3 = wave_sum_dd(a3);
+  const double g4 = wave_max_d((double)gm);
+  return lane == 0 ? a0 : lane == 1 ? a1 : lane == 2 ? a2 : lane == 3 ? a3 : g4;
+}
+
+// Dots of history slot i over a vector block: g~.s_i, g~.y_i, d.y_i (lane j
+// holds dot j, lanes >= 2 the last).
+__device__ __forceinline__ double lb_slot_dots(const float* gt, const float* s_, const float* y_,
+                                               const float* d, int lane) {
+  double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+  for (int q = 0; q < LB_PER_THREAD; ++q) {
+    s0 += (double)gt[q] * s_[q];
+    s1 += (double)gt[q] * y_[q];
+    s2 += (double)d[q] * y_[q];
+  }
+  s0 = wave_sum_dd(s0);
+  s1 = wave_sum_dd(s1);
+  s2 = wave_sum_dd(s2);
+  return lane == 0 ? s0 : lane == 1 ? s1 : s2;
+}
+
 // grid (maxb, count, 1 + hist), one wavefront per block, LB_PER_THREAD
 // elements per lane.  blockIdx.z = 0 forms the five base dots, z = 1 + i the
 // three dots of history slot i, so every block issues all its loads at once.
@@ -151,41 +194,73 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
       dv[q] = ok ? A.Dv[v0 + e] : 0.f;   // d (for d.y_i)
     }
   }
-  // per-lane partials, then fixed-order wavefront reductions (the totals in
-  // every lane); lane j < nd writes dot j's partial of this block
-  double t = 0.0;
-  if (z == 0) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    float gm = 0.f;
-#pragma unroll
-    for (int q = 0; q < LB_PER_THREAD; ++q) {
-      a0 += (double)gt[q] * v2[q];
-      a1 += (double)gt[q] * gt[q];
-      a2 += (double)gt[q] * v1[q];
-      a3 += (double)v2[q] * v2[q];
-      gm = fmaxf(gm, fabsf(gt[q]));
-    }
-    a0 = wave_sum_dd(a0);
-    a1 = wave_sum_dd(a1);
-    a2 = wave_sum_dd(a2);
-    a3 = wave_sum_dd(a3);
-    const double g4 = wave_max_d((double)gm);
-    t = lane == 0 ? a0 : lane == 1 ? a1 : lane == 2 ? a2 : lane == 3 ? a3 : g4;
-  } else {
-    double s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-    for (int q = 0; q < LB_PER_THREAD; ++q) {
-      s0 += (double)gt[q] * v1[q];
-      s1 += (double)gt[q] * v2[q];
-      s2 += (double)dv[q] * v2[q];
-    }
-    s0 = wave_sum_dd(s0);
-    s1 = wave_sum_dd(s1);
-    s2 = wave_sum_dd(s2);
-    t = lane == 0 ? s0 : lane == 1 ? s1 : s2;
-  }
+  // lane j < nd writes dot j's partial of this block
+  const double t = z == 0 ? lb_base_dots(gt, v1, v2, lane) : lb_slot_dots(gt, v1, v2, dv, lane);
   const int nd = z == 0 ? 5 : 3;
   if (lane < nd) out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
+}
+
+// Batches of many instances: grid (maxb, count, LB_SEQ_SPLIT), wavefront z
+// of an (instance, vector block) forms the three dots of each history slot
+// of its share in turn (the next slot's s, y loads in flight while the
+// current slot's dots are formed), wavefront 0 also the five base dots.  The
+// per-slot grid of k_lbfgs_dots reads g~ and d once per slot; over a batch
+// that traffic bounds the pass.  Same per-lane sums and reductions, so the
+// same bits.
+__global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots_seq(LbArgs A) {
+  const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
+  const int per = (A.P.hist + LB_SEQ_SPLIT - 1) / LB_SEQ_SPLIT;
+  const int sl0 = z * per, sl1 = min(A.P.hist, sl0 + per);   // history slots of this wavefront
+  const int lane = threadIdx.x;
+  const InstDev I = A.inst[k];
+  const long long v0 = A.voff[k];
+  const LbState& S = A.st[k];
+  const int st_status = S.status, st_phase = S.phase, st_count = S.count;
+  const int n = I.ns + I.nt_pad;
+  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
+  if (b * LB_VB >= n) return;
+  const bool run = st_status == LB_RUNNING;
+  const int cnt = (run && st_phase != 0) ? st_count : 0;
+  const int sc1 = min(cnt, sl1);   // slots [sl0, sc1) hold pairs, [max(sl0, cnt), sl1) are zeros
+  double* out = A.part + (size_t)k * A.ndot * A.maxb + b;
+  float gt[LB_PER_THREAD], g[LB_PER_THREAD], dv[LB_PER_THREAD], sc[LB_PER_THREAD], yc[LB_PER_THREAD];
+  auto load_slot = [&](int slot, float* s_, float* y_) {
+#pragma unroll
+    for (int q = 0; q < LB_PER_THREAD; ++q) {
+      const int e = b * LB_VB + q * LB_BLOCK + lane;
+      const bool ok = e < n && run;
+      s_[q] = ok ? A.S[(size_t)slot * A.vtot + v0 + e] : 0.f;
+      y_[q] = ok ? A.Y[(size_t)slot * A.vtot + v0 + e] : 0.f;
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < LB_PER_THREAD; ++q) {
+    const int e = b * LB_VB + q * LB_BLOCK + lane;
+    const bool ok = e < n && run;
+    gt[q] = ok ? lb_gt(A, I, e) : 0.f;
+    g[q] = (ok && z == 0) ? A.G[v0 + e] : 0.f;
+    dv[q] = ok ? A.Dv[v0 + e] : 0.f;
+  }
+  if (sl0 < sc1) load_slot(sl0, sc, yc);
+  if (z == 0) {
+    const double t0 = lb_base_dots(gt, g, dv, lane);
+    if (lane < 5) out[(size_t)lane * A.maxb] = t0;
+  }
+  for (int slot = sl0; slot < sc1; ++slot) {
+    float sn[LB_PER_THREAD], yn[LB_PER_THREAD];
+    if (slot + 1 < sc1) load_slot(slot + 1, sn, yn);
+    const double t = lb_slot_dots(gt, sc, yc, dv, lane);
+    if (lane < 3) out[(size_t)(5 + 3 * slot + lane) * A.maxb] = t;
+    if (slot + 1 < sc1) {
+#pragma unroll
+      for (int q = 0; q < LB_PER_THREAD; ++q) {
+        sc[q] = sn[q];
+        yc[q] = yn[q];
+      }
+    }
+  }
+  for (int slot = max(sl0, cnt); slot < sl1; ++slot)
+    if (lane < 3) out[(size_t)(5 + 3 * slot + lane) * A.maxb] = 0.0;
 }
 
 __device__ double lb_cubic(double t0, double f0, double d0, double t1, double f1, double d1) {

@@ -107,6 +107,36 @@ def test_batched_solve_equals_single_solves():
         ob += P.nt
 
 
+def test_batched_solve_with_long_vectors_equals_single_solves():
+    """Batches whose vectors total at least 32768 elements form the L-BFGS
+    dots with one wavefront per vector block over all history slots, single
+    solves with one per (block, slot): the trajectories agree bit for bit."""
+    O = _O()
+    shapes = [(1700, 1500), (1400, 1900), (2000, 1300), (1600, 1600), (1800, 1700), (1500, 2000),
+              (1900, 1400), (1300, 2100), (1650, 1550), (1750, 1450), (1550, 1800)]
+    assert sum(n + m for n, m in shapes) >= 32768 + 32 * len(shapes)
+    probs, keep = [], {}
+    for i, (n, m) in enumerate(shapes):
+        L = 3 + i % 5
+        sizes = [n // L] * (L - 1) + [n - (n // L) * (L - 1)]
+        inst = cases.ragged(90 + i, n, m, sizes, gamma=0.2 + 0.05 * i, mu=0.1 + 0.03 * i)
+        C32, P = cases.with_cost(inst)
+        probs.append(dict(labels=_dev(P.labels), n_groups=P.L, gamma=P.gamma, mu=P.mu, cost=_dev(C32),
+                          cost_scale=1.0, cost_mode=O.OT_GS_COST_GIVEN))
+        if i in (0, 5, 10):
+            keep[i] = P
+    hb = O.Handle(probs)
+    ab, bb, infob, trb, _ = run(hb, 60, use_screen=1)
+    oa = np.concatenate([[0], np.cumsum([n for n, _ in shapes])])
+    ob = np.concatenate([[0], np.cumsum([m for _, m in shapes])])
+    for i, P in keep.items():
+        a, b, info, tr, _ = run(O.Handle([probs[i]]), 60, use_screen=1)
+        np.testing.assert_array_equal(tr[0], trb[i])
+        np.testing.assert_array_equal(a, ab[oa[i]:oa[i + 1]])
+        np.testing.assert_array_equal(b, bb[ob[i]:ob[i + 1]])
+        assert info[0]["evals"] == infob[i]["evals"]
+
+
 def test_user_start_at_the_optimum_stays_there():
     inst = cases.ragged(70, 150, 120, [50, 100], gamma=0.3, mu=0.2)
     C32, P = cases.with_cost(inst)
