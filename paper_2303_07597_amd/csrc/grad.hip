@@ -587,13 +587,23 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
     const int n = A.n_static >= 0 ? A.n_static : *A.count;
     const int mode0 = A.inst_mode[0];
     if (A.single_inst && mode0 == EM_SKIP) return;
-    for (int t0 = blockIdx.x * K; t0 < n; t0 += gridDim.x * K) {
+    // K >= 8 (groups of at most 64 rows, rounds of small tiles): the next
+    // round's record is fetched while the current round runs
+    constexpr bool PF = K >= 8;
+    const int step = gridDim.x * K;
+    TileRec rn = {};
+    if (PF && blockIdx.x * K + team < n) rn = A.rec[blockIdx.x * K + team];
+    for (int t0 = blockIdx.x * K; t0 < n; t0 += step) {
       const int t = t0 + team;
       bool act = t < n;
       TileRec r = {};
       int m = mode0;
+      if (PF) {
+        r = rn;
+        if (t + step < n) rn = A.rec[t + step];
+      }
       if (act) {
-        r = A.rec[t];
+        if (!PF) r = A.rec[t];
         if (!A.single_inst) m = A.inst_mode[r.inst];
         act = m != EM_SKIP;
       }
