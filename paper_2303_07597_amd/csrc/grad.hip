@@ -587,9 +587,10 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_mixed(GradArgs A) {
     const int n = A.n_static >= 0 ? A.n_static : *A.count;
     const int mode0 = A.inst_mode[0];
     if (A.single_inst && mode0 == EM_SKIP) return;
-    // K >= 8 (groups of at most 64 rows, rounds of small tiles): the next
-    // round's record is fetched while the current round runs
-    constexpr bool PF = K >= 8;
+    // K >= 4 (groups of at most 128 rows, rounds of small tiles): the next
+    // round's record is fetched while the current round runs (with K = 2
+    // the extra registers would spill)
+    constexpr bool PF = K >= 4;
     const int step = gridDim.x * K;
     TileRec rn = {};
     if (PF && blockIdx.x * K + team < n) rn = A.rec[blockIdx.x * K + team];
