@@ -969,6 +969,7 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   R.a_uniform = h->a_uniform;
   R.b_uniform = h->b_uniform;
   R.err = h->err;
+  R.inst_mode = h->inst_mode;
   R.done = h->asm_done;
   return R;
 }

@@ -698,6 +698,7 @@ struct ReduceArgs {
   unsigned int* done;       // finalize: assembly blocks finished, per instance (reset by the last)
   double* obj_out;          // finalize: caller's copy of D (may be NULL)
   int finalize;             // 1: the last assembly block of an instance forms D
+  const int* inst_mode;     // EvalMode per instance
 };
 
 constexpr int ASM_BLOCK = 256;
@@ -776,6 +777,10 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
 __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   __shared__ double red[ASM_BLOCK / 64];
   const int k = blockIdx.y;
+  // inside a batched solve, an instance whose solve has ended (mode SKIP)
+  // has no tiles evaluated and nothing reads its gradient or D: its blocks
+  // leave at once (calls that finalize D never see SKIP)
+  if (!A.finalize && A.inst_mode[k] == EM_SKIP) return;
   const InstDev I = A.inst[k];
   // per-instance layout of the partials (rows, then columns), so that an
   // instance's objective does not depend on the other instances of a batch
