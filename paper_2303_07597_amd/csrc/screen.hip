@@ -286,7 +286,9 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
       nt_ += __shfl_xor(nt_, o);
       non += __shfl_xor(non, o);
     }
-    if (lane == 0) {
+    // (nothing to add, e.g. every tile of an instance whose solve has ended:
+    // no read-modify-write)
+    if (lane == 0 && (tq[0] | tq[1] | tq[2] | tq[3] | (long long)nt_ | (long long)non) != 0) {
       long long* C = A.block_counters + (size_t)blockIdx.x * CNT_NUM;
       C[CNT_PAIRS_TOTAL] += tq[0];
       C[CNT_PAIRS_N] += tq[1];
