@@ -1766,6 +1766,7 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.g_size = h->g_size;
   A.counts = h->counts_dyn;
   A.max_le = h->max_le;
+  A.batched = h->count > 1;
   return A;
 }
 

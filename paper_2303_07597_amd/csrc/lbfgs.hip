@@ -101,7 +101,16 @@ struct LbArgs {
   const int* g_size;
   int* counts;              // work-list counts of the next screen pass
   int max_le;               // most groups of an instance
+  int batched;              // more than one instance: finished ones skip their update
 };
+
+// An instance whose solve has ended and whose last control step accepted no
+// point has a zero step and no new direction: its update would rewrite the
+// same values (and form group statistics no screen reads).  Batches skip it;
+// a single instance does not wait for its state before its first loads.
+__device__ __forceinline__ bool lb_update_idle(const LbArgs& A, const LbState& S) {
+  return A.batched && S.status != LB_RUNNING && !S.accept;
+}
 
 __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }
 
@@ -748,6 +757,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const long long v0 = A.voff[k];
   const int h = A.P.hist;
   const bool snap = S.mode_eval == EM_SNAPSHOT;
+  if (lb_update_idle(A, S)) return;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     float so;
     lb_update_elem(A, I, S, e, v0, h, snap, so);
@@ -774,6 +784,7 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   const bool snap = S.mode_eval == EM_SNAPSHOT;
   const int bx = blockIdx.x;
   if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
+  if (lb_update_idle(A, S)) return;
   if (bx >= A.max_le) {
     const int c = (bx - A.max_le) * GT + threadIdx.x;
     if (c < I.nt_pad) {
