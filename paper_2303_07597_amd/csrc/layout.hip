@@ -89,8 +89,17 @@ __global__ void k_cost_max(const float* const* __restrict__ costs, const long lo
 }
 
 // Squared Euclidean cost from features in the caller's order (materialised
-// provider): c_ij = sum_k (x_ik - y_jk)^2, float32, 16x16 threads per 64x64
-// block with both feature tiles staged in LDS.
+// provider): c_ij = sum_k (x_ik - y_jk)^2 in float32, 16x16 threads per 64x64
+// block with both feature tiles staged in LDS.  The sum is compensated, so
+// the stored value is within about one rounding of the exact cost of the
+// float32 features (plain float32 accumulation over d terms errs by up to
+// d + 2 roundings): each difference t = x - y is split exactly into
+// t + t_lo (TwoSum), each square into t*t + p_lo (fma), and the running sum
+// carries its own rounding errors (TwoSum) in a second word, the
+// compensated dot product of Ogita, Rump and Oishi (SIAM J. Sci. Comput.,
+// 2005).  The cross term 2 t t_lo is added to the second word; t_lo^2 is
+// below the final rounding.  One-time setup work; the kernel is not on the
+// evaluation path.
 __global__ void __launch_bounds__(256) k_cost_features(const float* __restrict__ xs,
                                                        const float* __restrict__ xt, int ns,
                                                        int nt, int d, float* __restrict__ C) {
@@ -99,7 +108,7 @@ __global__ void __launch_bounds__(256) k_cost_features(const float* __restrict__
   __shared__ float sy[KB][TB + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int i0 = blockIdx.y * TB, j0 = blockIdx.x * TB;
-  float acc[4][4] = {};
+  float acc[4][4] = {}, cmp[4][4] = {};
   for (int k0 = 0; k0 < d; k0 += KB) {
     for (int e = threadIdx.x; e < TB * KB; e += 256) {
       const int rr = e / KB, kk = e % KB;
@@ -119,8 +128,18 @@ __global__ void __launch_bounds__(256) k_cost_features(const float* __restrict__
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float t = xv[u] - yv[v];
-          acc[u][v] = fmaf(t, t, acc[u][v]);
+          const float x = xv[u], y = yv[v];
+          const float t = x - y;                           // TwoSum(x, -y)
+          const float tv = t - x;
+          const float t_lo = (x - (t - tv)) + (-y - tv);
+          const float p = t * t;                           // TwoProduct by fma
+          const float p_lo = fmaf(t, t, -p);
+          const float s0 = acc[u][v];
+          const float s1 = s0 + p;                         // TwoSum(s0, p)
+          const float sv = s1 - s0;
+          const float e = (s0 - (s1 - sv)) + (p - sv);
+          acc[u][v] = s1;
+          cmp[u][v] += e + fmaf(2.f * t, t_lo, p_lo);
         }
     }
     __syncthreads();
@@ -130,7 +149,7 @@ __global__ void __launch_bounds__(256) k_cost_features(const float* __restrict__
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
-      if (gi < ns && gj < nt) C[(size_t)gi * nt + gj] = acc[u][v];
+      if (gi < ns && gj < nt) C[(size_t)gi * nt + gj] = acc[u][v] + cmp[u][v];
     }
 }
 

@@ -106,10 +106,13 @@ struct LbArgs {
 
 // An instance whose solve has ended and whose last control step accepted no
 // point has a zero step and no new direction: its update would rewrite the
-// same values (and form group statistics no screen reads).  Batches skip it;
-// a single instance does not wait for its state before its first loads.
+// same values (and form group statistics no screen reads).  Batches skip it,
+// unless the evaluation just done was a snapshot: its z~ and o~ were written
+// at the trial point, so that point must still become alpha~, beta~ (a later
+// screened evaluation on the handle pairs them).  A single instance does not
+// wait for its state before its first loads.
 __device__ __forceinline__ bool lb_update_idle(const LbArgs& A, const LbState& S) {
-  return A.batched && S.status != LB_RUNNING && !S.accept;
+  return A.batched && S.status != LB_RUNNING && !S.accept && S.mode_eval != EM_SNAPSHOT;
 }
 
 __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }

@@ -348,6 +348,94 @@ def test_algorithm2_equals_the_dense_gradient():
     assert c["s_u"] <= c["s_n"]
 
 
+# --------------------------------------------------------------- set N (Eq. 8)
+
+def test_extraction_is_sound():
+    """Lemma 5: every block put in N by Eq. 8 has z > mu gamma at the point of
+    extraction (its gradient is nonzero).  Snapshots near the point make N
+    large; the check would fail for an N holding every block, since many
+    blocks there have z <= mu gamma."""
+    P = rand_problem(45, 60, 50, 4, gamma=0.2, mu=0.4)
+    rng = np.random.default_rng(45)
+    a = 0.4 + 0.3 * rng.standard_normal(P.ns)
+    b = 0.3 * rng.standard_normal(P.nt)
+    Z, _, _ = oracle.group_norms(P, a, b)
+    thr = P.mu * P.gamma
+    assert 0 < np.count_nonzero(Z > thr) < Z.size
+    sizes = []
+    for eps in (0.0, 1e-4, 1e-3, 1e-2, 5e-2):
+        S = oracle.ScreenState(P, a + eps * rng.standard_normal(P.ns), b + eps * rng.standard_normal(P.nt))
+        S.extract(a, b)
+        N = S.inN.astype(bool)
+        assert np.all(Z[N] > thr)
+        sizes.append(int(N.sum()))
+    # close snapshots extract most active blocks, far ones fewer
+    assert sizes[0] > 0 and sizes[0] >= sizes[-1]
+
+
+def test_extraction_is_exact_for_single_signed_blocks_at_the_snapshot():
+    """Corollary 1: at the snapshot (no change in alpha, beta) the lower
+    bound equals z for a block whose f has one sign, so N is exactly
+    {z > mu gamma} there.  One-row groups make every block single-signed;
+    one block sits exactly at z = mu gamma (0.125, exact in binary) and must
+    stay out of N (Eq. 8 is strict)."""
+    ns, nt = 6, 5
+    labels = np.arange(ns, dtype=np.int32)
+    C = np.tile(np.linspace(0.0, 0.5, nt), (ns, 1))
+    P = oracle.Problem(C, labels, ns, 0.5, 0.25)
+    thr = P.mu * P.gamma
+    assert thr == 0.125
+    a = np.array([0.125, 0.3, 0.1, 0.7, 0.2, 0.0])
+    b = np.zeros(nt)
+    Z, O, K = oracle.group_norms(P, a, b)
+    assert Z[0, 0] == thr
+    S = oracle.ScreenState(P, a, b)
+    S.extract(a, b)
+    np.testing.assert_array_equal(S.inN.astype(bool), Z > thr)
+    assert not S.inN[0, 0]
+
+
+def test_extraction_against_a_far_snapshot_is_empty():
+    """Eq. 7 subtracts ||alpha - alpha~|| restricted to the group from
+    k~ = ||f~||; once that change exceeds every k~, no lower bound is
+    positive and N is empty, although many blocks have z > mu gamma at the
+    point itself.  (Bounds taken against the point itself instead of the
+    snapshot would put those blocks in N.)"""
+    P = rand_problem(46, 40, 30, 3, gamma=0.2, mu=0.3)
+    rng = np.random.default_rng(46)
+    a = 0.5 + 0.2 * rng.standard_normal(P.ns)
+    b = 0.2 * rng.standard_normal(P.nt)
+    Z, _, _ = oracle.group_norms(P, a, b)
+    assert np.count_nonzero(Z > P.mu * P.gamma) > 10
+    S = oracle.ScreenState(P, a + 10.0, b)
+    S.extract(a, b)
+    assert not S.inN.any()
+    # at the point itself as snapshot, the same blocks are extracted
+    S0 = oracle.ScreenState(P, a, b)
+    S0.extract(a, b)
+    assert S0.inN.any()
+
+
+def test_first_refresh_extracts_against_the_zero_snapshot():
+    """Algorithm 1 builds N from the bounds of the previous snapshot before
+    refreshing it.  The first refresh (after r iterations) therefore uses the
+    zero snapshot, where f = -C <= 0 gives k~ = o~ and a lower bound <= 0:
+    its N is empty, and no block is evaluated because of N before the second
+    refresh, although extracting against the refreshed snapshot itself would
+    have filled N.  Later refreshes do use N."""
+    inst = synth.paper_synthetic(10, g=10)
+    C, _ = oracle.cost_normalized(inst["xs"], inst["xt"])
+    P = oracle.Problem(C, inst["labels"], 10, *oracle.rho_form(1.0, 0.8))
+    r10 = oracle.solve(P, max_iter=10, r=10, use_screen=True)
+    S = oracle.ScreenState(P, r10["alpha"], r10["beta"])
+    S.extract(r10["alpha"], r10["beta"])
+    assert S.inN.any()
+    r1 = oracle.solve(P, max_iter=19, r=10, use_screen=True)
+    assert r1["iters"] == 19 and r1["s_r"] == 1 and r1["s_i"] == 0
+    r3 = oracle.solve(P, max_iter=100, r=10, use_screen=True)
+    assert r3["s_r"] == 10 and r3["s_i"] > 0
+
+
 def test_screened_solve_follows_the_dense_trajectory():
     """Theorem 2: Algorithm 1 reaches the same objective as the original
     method; here every iterate agrees, and gradients were skipped."""
