@@ -51,6 +51,8 @@ extern "C" {
 #define OT_GS_EDEVICE        -3   /* a HIP runtime call failed                        */
 #define OT_GS_ENUMERIC       -4   /* NaN or Inf met in an input or the objective      */
 #define OT_GS_ENOMEM         -5   /* device allocation failed                         */
+#define OT_GS_EVERIFY        -6   /* a verified screened evaluation differed from the
+                                     dense one at the same point (Lemma 2 violated)   */
 #define OT_GS_NOT_CONVERGED   1   /* solve stopped at max_iter                        */
 #define OT_GS_LINESEARCH      2   /* solve stopped: line search found no step         */
 
@@ -63,6 +65,13 @@ extern "C" {
                                (alpha~, beta~, z~_lj, o~_lj) of Defs. 1-2 at this
                                point; the set N is first rebuilt from the lower bound
                                of Eq. 7 against the previous snapshot (Algorithm 1)   */
+/* flags OR-ed into the mode of ot_gs_dual_grad (both make the call synchronous) */
+#define OT_GS_CHECK    0x100  /* report NaN or Inf in this call's alpha, beta or in the
+                                 objective as OT_GS_ENUMERIC                          */
+#define OT_GS_VERIFY   0x200  /* with SCREENED or SNAPSHOT: evaluate densely at the same
+                                 point as well and require bit-identical gradients and
+                                 objective (every skipped block is zero, Lemma 2);
+                                 OT_GS_EVERIFY otherwise.  Implies OT_GS_CHECK        */
 
 /* cost providers */
 #define OT_GS_COST_GIVEN       0  /* caller passes C [n_src x n_tgt] row-major        */
@@ -92,8 +101,11 @@ typedef struct {
                               ONTHEFLY: of the unscaled float32 cost above)        */
     const float *a;        /* [n_src] source marginal, NULL = 1/n_src              */
     const float *b;        /* [n_tgt] target marginal, NULL = 1/n_tgt              */
-    float gamma;           /* > 0                                                   */
-    float mu;              /* >= 0                                                  */
+    double gamma;          /* > 0; the kernels use float32 gamma in the soft
+                              threshold and the threshold fl32(mu * gamma) (the
+                              product formed in double, rounded once); the
+                              objective uses gamma in double                     */
+    double mu;             /* >= 0                                                  */
 } ot_gs_problem;
 
 /* Screening and timing counters, cumulative since create / last reset.
@@ -116,9 +128,12 @@ typedef struct {
  * the cost in that layout (or the features for COST_ONTHEFLY), marginals.
  * Synchronises `stream` before returning.  Errors: OT_GS_EINVAL for
  * n_src/n_tgt < 1, n_groups < 1 or > 16384, gamma <= 0, mu < 0, a label
- * outside [0, n_groups), missing cost or features for the chosen mode;
- * OT_GS_ENUMERIC if the cost or the scale is not finite or max C is 0 with
- * cost_scale == 0; OT_GS_ENOMEM, OT_GS_EDEVICE. */
+ * outside [0, n_groups), missing cost or features for the chosen mode, a
+ * negative marginal entry, or marginals whose masses differ by more than
+ * 1e-6 max(1, sum a, sum b) (no plan with those row and column sums
+ * exists; uniform marginals have mass 1); OT_GS_ENUMERIC if the cost, the
+ * scale or a marginal is not finite or max C is 0 with cost_scale == 0;
+ * OT_GS_ENOMEM, OT_GS_EDEVICE. */
 int ot_gs_create(const ot_gs_problem *probs /* host [count] */, int count,
                  ot_gs_handle **out /* host */, void *stream);
 
@@ -131,10 +146,16 @@ void ot_gs_destroy(ot_gs_handle *h);
  * T = [grad psi(alpha + beta_j 1 - c_j)]_j (Eq. 5), for every instance.
  * alpha [sum n_src], beta [sum n_tgt] in; grad_alpha, grad_beta out (same
  * shapes, may be NULL); obj out [count] float64 (device, may be NULL).
- * mode: OT_GS_DENSE, OT_GS_SCREENED or OT_GS_SNAPSHOT.  SCREENED results are
- * bit-identical to DENSE at the same point (Theorem 2); SCREENED before any
- * SNAPSHOT uses the zero snapshot (valid for alpha~ = beta~ = 0 since C >= 0).
- * Errors: OT_GS_EINVAL (NULL alpha/beta, bad mode), OT_GS_EDEVICE. */
+ * mode: OT_GS_DENSE, OT_GS_SCREENED or OT_GS_SNAPSHOT, optionally OR-ed with
+ * OT_GS_CHECK or OT_GS_VERIFY.  SCREENED results are bit-identical to DENSE
+ * at the same point (Theorem 2); SCREENED before any SNAPSHOT uses the zero
+ * snapshot (valid for alpha~ = beta~ = 0 since C >= 0).  Without flags the
+ * call is asynchronous; a NaN or Inf in alpha or beta then raises a sticky
+ * flag that ot_gs_check reports.  With a flag the call synchronises the
+ * stream and reports for its own inputs.  Errors: OT_GS_EINVAL (NULL
+ * alpha/beta, bad mode or flag), OT_GS_ENUMERIC, OT_GS_EVERIFY (flags
+ * only), OT_GS_ENOMEM (the first flagged call allocates two sets of
+ * outputs on the handle), OT_GS_EDEVICE. */
 int ot_gs_dual_grad(ot_gs_handle *h, const float *alpha, const float *beta,
                     float *grad_alpha, float *grad_beta, double *obj, int mode,
                     void *stream);
@@ -157,6 +178,13 @@ typedef struct {
     int use_graph;        /* 1 (default): record the launches of 16 solver steps
                              into a HIP graph once per call and replay it; same
                              results as 0 (direct launches)                          */
+    int verify;           /* 1: every screened evaluation of the solve is repeated
+                             densely at the same point (static tile lists, no
+                             screen) and the two must agree bit for bit (Lemma 2:
+                             skipped blocks are zero); the solve then returns
+                             OT_GS_EVERIFY if any evaluation differed.  Direct
+                             launches, about twice the evaluation cost; the
+                             trajectory is the unverified one.  Default 0.      */
 } ot_gs_options;
 
 /* Fills `o` with the defaults listed above. */
@@ -173,7 +201,10 @@ typedef struct {
  * when use_screen = 1).  alpha_io [sum n_src], beta_io [sum n_tgt]: start
  * point if init_user, final point on return.  info: host [count] or NULL.
  * Synchronises the stream before returning.  Returns OT_GS_OK or the worst
- * per-instance status (OT_GS_NOT_CONVERGED, OT_GS_LINESEARCH), or an error. */
+ * per-instance status (OT_GS_NOT_CONVERGED, OT_GS_LINESEARCH), or an error:
+ * OT_GS_ENUMERIC when the start point holds a NaN or Inf or an instance's
+ * objective is not finite there, OT_GS_EVERIFY (opts.verify) when a screened
+ * evaluation differed from the dense one. */
 int ot_gs_solve(ot_gs_handle *h, const ot_gs_options *opts, float *alpha_io,
                 float *beta_io, ot_gs_info *info, void *stream);
 
@@ -211,6 +242,25 @@ int ot_gs_plan_csr(ot_gs_handle *h, const float *alpha, const float *beta, long 
 int ot_gs_cost(ot_gs_handle *h, float *C_out, void *stream);
 
 /* ------------------------------------------------------------ utilities */
+
+/* Synchronises `stream` and reports (OT_GS_ENUMERIC) whether a NaN or Inf
+ * dual value reached an evaluation since the last check; clears the flag. */
+int ot_gs_check(ot_gs_handle *h, void *stream);
+
+/* The screening state of Algorithm 1 as the last evaluation left it, in the
+ * caller's layout: alpha_s [sum n_src], beta_s [sum n_tgt] the snapshot
+ * point (caller order); z_snap, o_snap (float32) and in_N (uint8, 1 = in
+ * the set N of Eq. 8) per (label, target) pair, instance k as a row-major
+ * [n_groups x n_tgt] block (row = label, column = caller's target index)
+ * at offset sum_{k'<k} n_groups n_tgt.  z_snap and o_snap are ||[f]_+|| and
+ * ||[f]_-|| of Defs. 1-2 at the snapshot point as the gradient kernel
+ * computed them; N is the set built at the last SNAPSHOT evaluation (or
+ * refresh of a solve) from Eq. 7 against the snapshot before it.  Pairs of
+ * empty labels read 0.  Any output may be NULL; all are device arrays owned
+ * by the caller.  For tests and inspection.  Errors: OT_GS_EINVAL,
+ * OT_GS_EDEVICE. */
+int ot_gs_screen_state(ot_gs_handle *h, float *alpha_s, float *beta_s, float *z_snap,
+                       float *o_snap, uint8_t *in_N, void *stream);
 
 /* rho parameterisation of the experiments (Sec. 5.2):
  * gamma (1-rho)/2 ||t||^2 + gamma rho sum ||t_[l]||  ==  Eq. 3 with

@@ -48,7 +48,7 @@ static inline long long ceil_div(long long a, long long b) { return (a + b - 1) 
 struct InstHost {
   InstDev d;
   int cost_mode;
-  std::vector<int> g_size, g_start, g_chunk0, g_xblk;
+  std::vector<int> g_size, g_start, g_chunk0, g_xblk, g_label;
   int n_chunk_rows;
 };
 
@@ -87,6 +87,18 @@ struct ot_gs_handle {
   int otf_dpmax = 16;   // largest padded feature count of the instances
   float *Xp = nullptr, *Yp = nullptr, *xn = nullptr, *yn = nullptr;
   int* g_xblk = nullptr;
+  int* g_label = nullptr;          // label of each nonempty group
+  long long* lab_pair_off = nullptr;   // [count] offsets of the caller-layout pair arrays
+  long long tot_lab_pairs = 0;     // sum of n_groups * n_tgt
+  // verification buffers (allocated by the first verified evaluation)
+  struct Verify {
+    float *ga = nullptr, *gb = nullptr;
+    double* obj = nullptr;
+    long long* cnt = nullptr;
+    int* modes = nullptr;
+    unsigned long long* diff = nullptr;
+    double* objp = nullptr;   // assembly partials of D (verified solves)
+  } ver;
   float *a_int = nullptr, *b_int = nullptr;
   int *a_uniform = nullptr, *b_uniform = nullptr;
   float *alpha = nullptr, *beta = nullptr, *ga = nullptr, *gb = nullptr;
@@ -197,6 +209,49 @@ static int tend(ot_gs_handle* h, int which, hipStream_t s, hipEvent_t ev0) {
 static int sync_err(ot_gs_handle* h, hipStream_t s, int* out) {
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipMemcpy(out, h->err, sizeof(int), hipMemcpyDeviceToHost));
+  return OT_GS_OK;
+}
+
+// error flag bits raised by kernels after set-up
+constexpr int ERR_NONFINITE = 8;   // a NaN or Inf dual value met by the gather
+
+static int clear_err(ot_gs_handle* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, h->err, 1LL, 0);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
+// buffers of checked and verified evaluations: two sets of caller-order
+// gradients and objectives, saved counters and modes, a difference count
+static int ensure_verify(ot_gs_handle* h) {
+  auto& V = h->ver;
+  if (V.ga) return OT_GS_OK;
+  TRY(h->alloc(&V.ga, 2 * h->tot_rows));
+  TRY(h->alloc(&V.gb, 2 * h->tot_cols_pad));
+  TRY(h->alloc(&V.obj, 2 * (size_t)h->count));
+  TRY(h->alloc(&V.cnt, CNT_NUM));
+  TRY(h->alloc(&V.modes, h->count));
+  TRY(h->alloc(&V.diff, 1));
+  TRY(h->alloc(&V.objp, (size_t)h->count * h->n_asm));
+  return OT_GS_OK;
+}
+
+// Synchronised report of a checked evaluation: ENUMERIC for a NaN or Inf
+// input or objective, EVERIFY when the verified screened and dense
+// evaluations differ.  Clears the error flags it reports.
+static int check_report(ot_gs_handle* h, hipStream_t s, bool verify) {
+  int herr = 0;
+  std::vector<double> D(h->count);
+  unsigned long long diff = 0;
+  HIPCHK(hipMemcpyAsync(D.data(), h->ver.obj, sizeof(double) * h->count, hipMemcpyDeviceToHost, s));
+  if (verify) HIPCHK(hipMemcpyAsync(&diff, h->ver.diff, sizeof diff, hipMemcpyDeviceToHost, s));
+  TRY(sync_err(h, s, &herr));
+  TRY(clear_err(h, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr & ERR_NONFINITE) return fail(OT_GS_ENUMERIC, "dual_grad: alpha or beta holds a NaN or Inf");
+  for (int k = 0; k < h->count; ++k)
+    if (!std::isfinite(D[k])) return fail(OT_GS_ENUMERIC, "dual_grad: the objective of instance %d is not finite", k);
+  if (diff) return fail(OT_GS_EVERIFY, "dual_grad: %llu screened results differ from the dense ones", diff);
   return OT_GS_OK;
 }
 
@@ -441,8 +496,10 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     if (p.n_groups < 1 || p.n_groups > MAX_GROUPS)
       return fail(OT_GS_EINVAL, "instance %d: n_groups must lie in [1, %d]", k, MAX_GROUPS);
     if (!p.labels) return fail(OT_GS_EINVAL, "instance %d: labels is NULL", k);
-    if (!(p.gamma > 0.f) || !std::isfinite(p.gamma)) return fail(OT_GS_EINVAL, "instance %d: gamma must be > 0", k);
-    if (!(p.mu >= 0.f) || !std::isfinite(p.mu)) return fail(OT_GS_EINVAL, "instance %d: mu must be >= 0", k);
+    if (!(p.gamma > 0.0) || !std::isfinite(p.gamma) || !((float)p.gamma > 0.f) || !std::isfinite((float)p.gamma))
+      return fail(OT_GS_EINVAL, "instance %d: gamma must be > 0 (and a normal float32)", k);
+    if (!(p.mu >= 0.0) || !std::isfinite(p.mu) || !std::isfinite((float)(p.mu * p.gamma)))
+      return fail(OT_GS_EINVAL, "instance %d: mu must be >= 0 with mu gamma finite in float32", k);
     if (!std::isfinite(p.cost_scale) || p.cost_scale < 0.f)
       return fail(OT_GS_ENUMERIC, "instance %d: cost_scale must be finite and >= 0", k);
     if (p.cost_mode == OT_GS_COST_GIVEN) {
@@ -491,9 +548,10 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     d.row_off = (int)h->tot_rows;
     d.scol_off = (int)h->tot_cols;
     d.col_off = (int)h->tot_cols_pad;
-    d.gamma = p.gamma;
-    d.mu = p.mu;
-    d.thr = (float)((double)p.mu * (double)p.gamma);
+    d.gamma = (float)p.gamma;
+    d.mu = (float)p.mu;
+    d.thr = (float)(p.mu * p.gamma);
+    d.gamma64 = p.gamma;
     if (otf) {
       d.onthefly = 1;
       d.dim = p.dim;
@@ -548,6 +606,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       if (c > 0) {
         ih.g_start.push_back(acc);
         ih.g_size.push_back(c);
+        ih.g_label.push_back(l);
         ++ge;
       }
       acc += c;
@@ -600,9 +659,13 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       return fail(OT_GS_EINVAL, "total pair count exceeds the 32-bit index range");
   }
   {
-    std::vector<int> gs, gn, gc, gi, gx;
+    std::vector<int> gs, gn, gc, gi, gx, gl;
+    std::vector<long long> lpo(count);
     for (int k = 0; k < count; ++k) {
       const InstHost& ih = h->inst[k];
+      lpo[k] = h->tot_lab_pairs;
+      h->tot_lab_pairs += (long long)ih.d.L * ih.d.nt;
+      gl.insert(gl.end(), ih.g_label.begin(), ih.g_label.end());
       gx.insert(gx.end(), ih.g_xblk.begin(), ih.g_xblk.end());
       gs.insert(gs.end(), ih.g_start.begin(), ih.g_start.end());
       gn.insert(gn.end(), ih.g_size.begin(), ih.g_size.end());
@@ -613,6 +676,10 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     TRY(h->alloc(&h->g_size, gs.size()));
     TRY(h->alloc(&h->g_chunk0, gs.size()));
     TRY(h->alloc(&h->grp_inst, gs.size()));
+    TRY(h->alloc(&h->g_label, gs.size()));
+    TRY(h->alloc(&h->lab_pair_off, count));
+    HIPCHK(hipMemcpyAsync(h->g_label, gl.data(), sizeof(int) * gl.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->lab_pair_off, lpo.data(), sizeof(long long) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->g_start, gs.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->g_size, gn.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->g_chunk0, gc.data(), sizeof(int) * gs.size(), hipMemcpyHostToDevice, s));
@@ -791,7 +858,30 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
 
   }
 
-  // ---- marginals
+  // ---- marginals: given ones must be finite, nonnegative and carry the same
+  // total mass (a plan with row sums a and column sums b exists only then);
+  // uniform ones have mass 1
+  for (int k = 0; k < count; ++k) {
+    double mass[2] = {1.0, 1.0};
+    const float* m[2] = {probs[k].a, probs[k].b};
+    const int len[2] = {probs[k].n_src, probs[k].n_tgt};
+    for (int q = 0; q < 2; ++q) {
+      if (!m[q]) continue;
+      std::vector<float> hm((size_t)len[q]);
+      HIPCHK(hipMemcpyAsync(hm.data(), m[q], sizeof(float) * len[q], hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double acc = 0.0;
+      for (float v : hm) {
+        if (!std::isfinite(v)) return fail(OT_GS_ENUMERIC, "instance %d: marginal %c has a NaN or Inf", k, "ab"[q]);
+        if (v < 0.f) return fail(OT_GS_EINVAL, "instance %d: marginal %c has a negative entry", k, "ab"[q]);
+        acc += v;
+      }
+      mass[q] = acc;
+    }
+    if (!(std::fabs(mass[0] - mass[1]) <= 1e-6 * std::max(1.0, std::max(mass[0], mass[1]))))
+      return fail(OT_GS_EINVAL, "instance %d: marginals differ in mass (sum a = %.9g, sum b = %.9g)", k, mass[0],
+                  mass[1]);
+  }
   TRY(h->alloc(&h->a_int, h->tot_rows));
   TRY(h->alloc(&h->b_int, h->tot_cols_pad));
   TRY(h->alloc(&h->a_uniform, count));
@@ -1427,11 +1517,81 @@ void ot_gs_destroy(ot_gs_handle* h) { delete h; }
 int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, float* grad_alpha,
                     float* grad_beta, double* obj, int mode, void* stream) {
   if (!h || !alpha || !beta) return fail(OT_GS_EINVAL, "dual_grad: NULL argument");
-  if (mode != OT_GS_DENSE && mode != OT_GS_SCREENED && mode != OT_GS_SNAPSHOT)
-    return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", mode);
+  const int base = mode & 0xff, flags = mode & ~0xff;
+  if (base != OT_GS_DENSE && base != OT_GS_SCREENED && base != OT_GS_SNAPSHOT)
+    return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", base);
+  if (flags & ~(OT_GS_CHECK | OT_GS_VERIFY)) return fail(OT_GS_EINVAL, "dual_grad: unknown mode flags 0x%x", flags);
   hipStream_t s = (hipStream_t)stream;
-  TRY(gather(h, alpha, beta, s, mode));
-  TRY(evaluate(h, mode, grad_alpha, grad_beta, s, false, true, obj));
+  if (!flags) {
+    TRY(gather(h, alpha, beta, s, base));
+    TRY(evaluate(h, base, grad_alpha, grad_beta, s, false, true, obj));
+    return OT_GS_OK;
+  }
+  // checked call: this call's inputs only, then a synchronised report
+  TRY(clear_err(h, s));
+  TRY(gather(h, alpha, beta, s, base));
+  if (!(flags & OT_GS_VERIFY) || base == OT_GS_DENSE) {
+    TRY(ensure_verify(h));
+    TRY(evaluate(h, base, grad_alpha, grad_beta, s, false, true, h->ver.obj));
+    if (obj) HIPCHK(hipMemcpyAsync(obj, h->ver.obj, sizeof(double) * h->count, hipMemcpyDeviceToDevice, s));
+    return check_report(h, s, false);
+  }
+  // verified call: the screened evaluation, then a dense one at the same
+  // point (its counts taken back), compared bit for bit
+  TRY(ensure_verify(h));
+  auto& V = h->ver;
+  float* ga2 = V.ga + h->tot_rows;
+  float* gb2 = V.gb + h->tot_cols;
+  double* o2 = V.obj + h->count;
+  TRY(evaluate(h, base, V.ga, V.gb, s, false, true, V.obj));
+  HIPCHK(hipMemcpyAsync(V.cnt, h->counters, sizeof(long long) * CNT_NUM, hipMemcpyDeviceToDevice, s));
+  TRY(evaluate(h, OT_GS_DENSE, ga2, gb2, s, false, false, o2));
+  HIPCHK(hipMemcpyAsync(h->counters, V.cnt, sizeof(long long) * CNT_NUM, hipMemcpyDeviceToDevice, s));
+  const long long maxn = std::max<long long>(std::max<long long>(h->max_ns, h->max_ntp), 1);
+  hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, V.diff, 1LL, 0ull);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_bits_differ, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 256), h->count), dim3(256),
+                     0, s, h->d_inst, (const int*)nullptr, 1, V.ga, ga2, V.gb, gb2, V.obj, o2, 1LL, V.diff);
+  LAUNCHCHK();
+  if (grad_alpha)
+    HIPCHK(hipMemcpyAsync(grad_alpha, V.ga, sizeof(float) * h->tot_rows, hipMemcpyDeviceToDevice, s));
+  if (grad_beta)
+    HIPCHK(hipMemcpyAsync(grad_beta, V.gb, sizeof(float) * h->tot_cols, hipMemcpyDeviceToDevice, s));
+  if (obj) HIPCHK(hipMemcpyAsync(obj, V.obj, sizeof(double) * h->count, hipMemcpyDeviceToDevice, s));
+  return check_report(h, s, true);
+}
+
+int ot_gs_check(ot_gs_handle* h, void* stream) {
+  if (!h) return fail(OT_GS_EINVAL, "check: NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
+  TRY(clear_err(h, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr & ERR_NONFINITE) return fail(OT_GS_ENUMERIC, "a NaN or Inf dual value was passed since the last check");
+  return OT_GS_OK;
+}
+
+int ot_gs_screen_state(ot_gs_handle* h, float* alpha_s, float* beta_s, float* z_snap, float* o_snap,
+                       uint8_t* in_N, void* stream) {
+  if (!h) return fail(OT_GS_EINVAL, "screen_state: NULL handle");
+  hipStream_t s = (hipStream_t)stream;
+  const long long np = h->tot_lab_pairs;
+  const unsigned fb = (unsigned)std::min<long long>(std::max<long long>(ceil_div(np, 256), 1), 4096);
+  if (z_snap) hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, z_snap, np, 0.f);
+  if (o_snap) hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, o_snap, np, 0.f);
+  if (in_N) hipLaunchKernelGGL(k_fill<uint8_t>, dim3(fb), dim3(256), 0, s, in_N, np, (uint8_t)0);
+  LAUNCHCHK();
+  long long maxp = 1;
+  for (int k = 0; k < h->count; ++k)
+    maxp = std::max<long long>(maxp, std::max<long long>((long long)h->inst[k].d.Le * h->inst[k].d.nt,
+                                                         h->inst[k].d.ns + h->inst[k].d.nt));
+  hipLaunchKernelGGL(k_export_screen, dim3((unsigned)std::min<long long>(ceil_div(maxp, 256), 1024), h->count),
+                     dim3(256), 0, s, h->d_inst, (const int*)h->perm_row, (const int*)h->perm_col,
+                     (const int*)h->g_label, (const long long*)h->lab_pair_off, (const float*)h->alpha_s,
+                     (const float*)h->beta_s, (const float*)h->zsnap, (const float*)h->osnap,
+                     (const uint8_t*)h->inN, alpha_s, beta_s, z_snap, o_snap, in_N);
+  LAUNCHCHK();
   return OT_GS_OK;
 }
 
@@ -1682,6 +1842,7 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->obj_trace = nullptr;
   o->time_trace = nullptr;
   o->use_graph = 1;
+  o->verify = 0;
 }
 
 }  // extern "C"
@@ -1772,7 +1933,7 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
 
 // One function evaluation of every live instance and one step of its solver.
 static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_screen,
-                       int init_user, hipStream_t s) {
+                       int init_user, hipStream_t s, bool verify = false) {
   // the control kernel finalises D and the update kernel records snapshots;
   // unscreened solves run every tile of the live instances from the static
   // lists, with no screen pass
@@ -1782,6 +1943,26 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
     TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, false, !upd, true));
   else
     TRY(run_tiles_and_reduce(h, false, nullptr, nullptr, s, false, false, false, nullptr));
+  if (verify && use_screen) {
+    // Lemma 2 checked at every evaluation: the live instances evaluated
+    // again densely at the same trial point must give the same bits; the
+    // modes go back before the control kernel reads them
+    auto& V = h->ver;
+    HIPCHK(hipMemcpyAsync(V.ga, h->ga, sizeof(float) * h->tot_rows, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(V.gb, h->gb, sizeof(float) * h->tot_cols_pad, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(V.objp, h->obj_part, sizeof(double) * h->count * h->n_asm, hipMemcpyDeviceToDevice, s));
+    const unsigned mb = (unsigned)std::min<long long>(ceil_div(h->count, 256), 64);
+    hipLaunchKernelGGL(k_verify_modes, dim3(mb), dim3(256), 0, s, h->inst_mode, V.modes, h->count, 0);
+    LAUNCHCHK();
+    TRY(run_tiles_and_reduce(h, false, nullptr, nullptr, s, false, false, false, nullptr));
+    const long long maxn = std::max<long long>(h->max_ns, h->max_ntp);
+    hipLaunchKernelGGL(k_bits_differ, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 256), h->count),
+                       dim3(256), 0, s, h->d_inst, (const int*)V.modes, 0, V.ga, (const float*)h->ga, V.gb,
+                       (const float*)h->gb, V.objp, (const double*)h->obj_part, (long long)h->n_asm, V.diff);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_verify_modes, dim3(mb), dim3(256), 0, s, h->inst_mode, V.modes, h->count, 1);
+    LAUNCHCHK();
+  }
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
@@ -1861,6 +2042,13 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   P.obj_trace = o.obj_trace;
   P.time_trace = o.time_trace;
   LbArgs A = lb_args(h, P);
+  const bool verify = o.verify && P.use_screen;
+  if (verify) {
+    TRY(ensure_verify(h));
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, h->ver.diff, 1LL, 0ull);
+    LAUNCHCHK();
+  }
+  TRY(clear_err(h, s));
   if (o.init_user) TRY(gather(h, alpha_io, beta_io, s));
   const long long maxv = h->max_ns + h->max_ntp;
   hipLaunchKernelGGL(k_lbfgs_init, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
@@ -1880,7 +2068,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   // (every argument is a device pointer or a constant of this solve); not
   // while kernel timing records events
   hipGraphExec_t exec = nullptr;
-  if (o.use_graph && !h->timing.on) TRY(capture_steps(h, A, P, o.init_user, check_every, &exec));
+  if (o.use_graph && !h->timing.on && !verify) TRY(capture_steps(h, A, P, o.init_user, check_every, &exec));
   struct ExecFree {
     hipGraphExec_t& e;
     ~ExecFree() {
@@ -1892,7 +2080,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
       HIPCHK(hipGraphLaunch(exec, s));
       step += check_every;
     } else {
-      TRY(solver_step(h, A, P.use_lower, P.use_screen, o.init_user, s));
+      TRY(solver_step(h, A, P.use_lower, P.use_screen, o.init_user, s, verify));
       ++step;
       if (step % check_every != 0 && step != max_steps) continue;
     }
@@ -1909,7 +2097,10 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   LAUNCHCHK();
   std::vector<LbState> hs(h->count);
   HIPCHK(hipMemcpyAsync(hs.data(), h->sol.st, sizeof(LbState) * h->count, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  unsigned long long diff = 0;
+  if (verify) HIPCHK(hipMemcpyAsync(&diff, h->ver.diff, sizeof diff, hipMemcpyDeviceToHost, s));
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
   int worst = OT_GS_OK;
   for (int k = 0; k < h->count; ++k) {
     int st = OT_GS_NOT_CONVERGED;
@@ -1924,5 +2115,12 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
       info[k].gnorm_inf = hs[k].gmax;
     }
   }
+  if (herr & ERR_NONFINITE) {
+    TRY(clear_err(h, s));
+    return fail(OT_GS_ENUMERIC, "solve: the starting point holds a NaN or Inf");
+  }
+  for (int k = 0; k < h->count; ++k)
+    if (!std::isfinite(hs[k].f)) return fail(OT_GS_ENUMERIC, "solve: the objective of instance %d is not finite", k);
+  if (diff) return fail(OT_GS_EVERIFY, "solve: %llu screened results differed from dense ones", diff);
   return worst;
 }

@@ -166,7 +166,7 @@ static int ws_features(const ot_gs_problem* probs, int count, const float* scale
     if (!p.x_src || !p.x_tgt || !p.labels) return fail(OT_GS_EINVAL, "features: instance %d lacks features", k);
     if (p.n_src < 1 || p.n_tgt < 1 || p.n_groups < 1 || p.n_groups > MAX_GROUPS)
       return fail(OT_GS_EINVAL, "features: instance %d has bad sizes", k);
-    if (!(scales[k] > 0.f) || !(p.gamma > 0.f) || !(p.mu >= 0.f))
+    if (!(scales[k] > 0.f) || !(p.gamma > 0.0) || !(p.mu >= 0.0))
       return fail(OT_GS_EINVAL, "features: instance %d needs scale > 0, gamma > 0, mu >= 0", k);
     tot_n += p.n_src;
     tot_m += p.n_tgt;
@@ -188,8 +188,8 @@ static int ws_features(const ot_gs_problem* probs, int count, const float* scale
     D.cent_off = tot_c;
     D.cls_off = tot_L;
     D.scale = scales[k];
-    D.lg = std::log(p.gamma);
-    D.lm = std::log(std::max(p.mu, 1e-8f));
+    D.lg = (float)std::log(p.gamma);
+    D.lm = (float)std::log(std::max(p.mu, 1e-8));
     sr += p.n_src;
     tr += p.n_tgt;
     tot_c += (long long)p.n_groups * d;

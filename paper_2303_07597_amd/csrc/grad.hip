@@ -838,7 +838,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       if (A.gb_out && cok) A.gb_out[I.scol_off + pm_c] = gval;
       if (cok) {
         const double bv = b_uni ? 1.0 / (double)I.nt : (double)b_c;
-        part = bv * (double)be_c - e2 * (0.5 / (double)I.gamma);
+        part = bv * (double)be_c - e2 * (0.5 / I.gamma64);
       }
     }
   }
@@ -926,7 +926,7 @@ __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict_
     bad |= !isfinite(v);
     be_int[I.col_off + c] = v;
   }
-  if (bad) atomicOr(err, 8);
+  if (bad) atomicOr(err, 8);   // a NaN or Inf dual value (reported by checked calls)
 }
 
 __global__ void k_prologue(int* inst_mode, int count, int mode, long long* counters,

@@ -440,6 +440,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   }
   const size_t tr = (size_t)k * (P.max_iter + 1);
   if (!isfinite(D) || !isfinite(GtGt)) {
+    if (S.phase == 0) S.f = ft;   // the starting point itself: reported as not finite
     S.status = LB_LSFAIL;
     if (l0) A.inst_mode[k] = EM_SKIP;
     S.t_next = 0.0;

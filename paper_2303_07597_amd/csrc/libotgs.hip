@@ -4,6 +4,7 @@
 #include "grad.hip"
 #include "screen.hip"
 #include "lbfgs.hip"
+#include "inspect.hip"
 #include "api.hip"
 #include "mlp.hip"
 #include "api_ws.hip"

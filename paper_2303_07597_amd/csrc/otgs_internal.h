@@ -55,6 +55,7 @@ struct InstDev {
   int onthefly, dim, dp, pad1;   // dp: dims padded to a multiple of 16
   long long x_off, y_off;        // packed feature pools (floats)
   float cscale, pad2;            // C = max(cscale (|x|^2 + |y|^2 - 2 x.y), 0)
+  double gamma64;                // gamma as given (the objective's 1 / (2 gamma))
 };
 
 // A segment of keys for the stable counting sort: n keys in [0, K) at

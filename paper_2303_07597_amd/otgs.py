@@ -22,12 +22,15 @@ OT_GS_ESHAPE = -2
 OT_GS_EDEVICE = -3
 OT_GS_ENUMERIC = -4
 OT_GS_ENOMEM = -5
+OT_GS_EVERIFY = -6
 OT_GS_NOT_CONVERGED = 1
 OT_GS_LINESEARCH = 2
 
 OT_GS_DENSE = 0
 OT_GS_SCREENED = 1
 OT_GS_SNAPSHOT = 2
+OT_GS_CHECK = 0x100
+OT_GS_VERIFY = 0x200
 
 OT_GS_COST_GIVEN = 0
 OT_GS_COST_MATERIALIZE = 1
@@ -41,7 +44,7 @@ class ot_gs_problem(ct.Structure):
     _fields_ = [("n_src", ct.c_int), ("n_tgt", ct.c_int), ("dim", ct.c_int), ("n_groups", ct.c_int),
                 ("labels", ct.c_void_p), ("cost_mode", ct.c_int), ("cost", ct.c_void_p),
                 ("x_src", ct.c_void_p), ("x_tgt", ct.c_void_p), ("cost_scale", ct.c_float),
-                ("a", ct.c_void_p), ("b", ct.c_void_p), ("gamma", ct.c_float), ("mu", ct.c_float)]
+                ("a", ct.c_void_p), ("b", ct.c_void_p), ("gamma", ct.c_double), ("mu", ct.c_double)]
 
 
 class ot_gs_stats(ct.Structure):
@@ -58,7 +61,7 @@ class ot_gs_options(ct.Structure):
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
                 ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
                 ("gtol", ct.c_double), ("obj_trace", ct.c_void_p), ("time_trace", ct.c_void_p),
-                ("use_graph", ct.c_int)]
+                ("use_graph", ct.c_int), ("verify", ct.c_int)]
 
 
 class ot_gs_info(ct.Structure):
@@ -106,6 +109,8 @@ def _load():
     lib.ot_gs_autotune.argtypes = [vp, i, vp]
     lib.ot_gs_tile_config.argtypes = [vp, i, i, i]
     lib.ot_gs_get_tile_config.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
+    lib.ot_gs_check.argtypes = [vp, vp]
+    lib.ot_gs_screen_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
     return lib
@@ -319,6 +324,23 @@ class Handle:
                                     _stream(stream)))
         return row_ptr, col[:nnz.value], val[:nnz.value]
 
+    def check(self, stream=None):
+        _check(lib().ot_gs_check(self.h, _stream(stream)))
+
+    def screen_state(self, n_groups, stream=None):
+        """(alpha_s, beta_s, z_snap, o_snap, in_N): the snapshot point in the
+        caller's order and per-(label, target) snapshot norms and set-N flags,
+        instance blocks of n_groups[k] x n_tgt[k] concatenated."""
+        dev = torch.device("cuda")
+        npairs = sum(L * m for L, m in zip(n_groups, self.n_tgt))
+        a = torch.empty(sum(self.n_src), dtype=torch.float32, device=dev)
+        b = torch.empty(sum(self.n_tgt), dtype=torch.float32, device=dev)
+        z = torch.empty(max(npairs, 1), dtype=torch.float32, device=dev)
+        o = torch.empty_like(z)
+        n = torch.empty(max(npairs, 1), dtype=torch.uint8, device=dev)
+        _check(lib().ot_gs_screen_state(self.h, _ptr(a), _ptr(b), _ptr(z), _ptr(o), _ptr(n), _stream(stream)))
+        return a, b, z[:npairs], o[:npairs], n[:npairs]
+
     def cost(self, C_out, stream=None):
         _check(lib().ot_gs_cost(self.h, _ptr(C_out), _stream(stream)))
 
@@ -377,5 +399,6 @@ EXPORTED = [
     "ot_gs_mlp_create", "ot_gs_mlp_destroy", "ot_gs_mlp_n_params", "ot_gs_mlp_set_params",
     "ot_gs_mlp_get_params", "ot_gs_mlp_forward", "ot_gs_mlp_loss_grad", "ot_gs_mlp_train",
     "ot_gs_features", "ot_gs_cost_scale", "ot_gs_warm_start",
-    "ot_gs_autotune", "ot_gs_tile_config", "ot_gs_get_tile_config",
+    "ot_gs_autotune", "ot_gs_tile_config", "ot_gs_get_tile_config", "ot_gs_check", "ot_gs_screen_state",
+    "ot_gs_plan_csr",
 ]
