@@ -233,6 +233,22 @@ int ot_gs_plan(ot_gs_handle *h, const float *alpha, const float *beta, float *T,
 int ot_gs_plan_csr(ot_gs_handle *h, const float *alpha, const float *beta, long long *row_ptr,
                    int *col_idx, float *val, long long *nnz, void *stream);
 
+/* ot_gs_plan_csr for callers that cannot allocate device memory (code
+ * that must not call hipMalloc, tight serving loops): the same two calls,
+ * arguments, results (bit for bit) and errors, with the call's scratch
+ * (segment counts and offsets, 12 bytes per row and 32-target column block
+ * for a fill call, 4 per block plus 8 per row for a count) taken from one
+ * fixed device array of OT_GS_STATIC_SCRATCH_BYTES that each GPU holds from
+ * the first call until the process ends; no device memory is allocated or
+ * freed.  Calls on one GPU share that array, so calls that overlap in time
+ * on one GPU (other streams, other host threads) race and must not be
+ * issued; each call rewrites everything of it that it reads.  Sizes beyond
+ * the array are refused with OT_GS_EINVAL before any work is enqueued.
+ * Synchronises the stream. */
+#define OT_GS_STATIC_SCRATCH_BYTES (64u << 20)
+int ot_gs_plan_csr_static(ot_gs_handle *h, const float *alpha, const float *beta, long long *row_ptr,
+                          int *col_idx, float *val, long long *nnz, void *stream);
+
 /* The scaled cost the evaluations use (Sec. 2.1; for COST_ONTHEFLY the
  * values its matrix-core tiles produce, bit for bit), written to C_out in
  * the layout of ot_gs_plan: instance k at offset sum_{k'<k} n_src n_tgt,

@@ -6,5 +6,6 @@
 #include "lbfgs.hip"
 #include "inspect.hip"
 #include "api.hip"
+#include "plan_static.hip"
 #include "mlp.hip"
 #include "api_ws.hip"
