@@ -57,7 +57,7 @@ class _State(ct.Structure):
 class _Opts(ct.Structure):
     _fields_ = [("max_iter", ct.c_int), ("hist", ct.c_int), ("r", ct.c_int),
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
-                ("c1", ct.c_double), ("c2", ct.c_double), ("gtol", ct.c_double)]
+                ("c1", ct.c_double), ("c2", ct.c_double), ("gtol", ct.c_double), ("nthreads", ct.c_int)]
 
 
 class _Info(ct.Structure):
@@ -71,7 +71,7 @@ def build(force: bool = False) -> str:
     """Compile the C oracle into ``oracle/liborc.so`` (gcc, -O3, no fast-math)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         tmp = _SO + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-fPIC", "-shared", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O3", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp",
                                "-std=c99", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
@@ -84,6 +84,7 @@ def lib():
         _lib = ct.CDLL(_SO)
         P = ct.POINTER(_Problem)
         _lib.orc_dual_grad.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib.orc_dual_grad_par.argtypes = [P, _dp, _dp, _dp, _dp, _dp, ct.c_int]
         _lib.orc_primal.argtypes = [P, _dp]
         _lib.orc_primal.restype = ct.c_double
         _lib.orc_group_norms.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
@@ -138,6 +139,17 @@ def dual_grad(P: Problem, alpha, beta, want_plan=False):
     rc = lib().orc_dual_grad(P.ref, _ptr(al), _ptr(be), _ptr(ga), _ptr(gb), ct.byref(D), _ptr(T))
     assert rc == 0, rc
     return (ga, gb, D.value, T) if want_plan else (ga, gb, D.value)
+
+
+def dual_grad_par(P: Problem, alpha, beta, nthreads=0):
+    """dual_grad's values (bit for bit) from OpenMP threads over the target
+    columns; nthreads 0 = the OpenMP default."""
+    al, be = _d(alpha), _d(beta)
+    ga, gb = np.empty(P.ns), np.empty(P.nt)
+    D = ct.c_double()
+    rc = lib().orc_dual_grad_par(P.ref, _ptr(al), _ptr(be), _ptr(ga), _ptr(gb), ct.byref(D), int(nthreads))
+    assert rc == 0, rc
+    return ga, gb, D.value
 
 
 def dual_obj(P: Problem, alpha, beta):
@@ -211,7 +223,7 @@ def gradpsi(P: Problem, S: ScreenState, alpha, beta):
 
 
 def solve(P: Problem, max_iter=200, hist=10, r=10, use_screen=False, use_lower=True,
-          max_ls=40, c1=1e-4, c2=0.9, gtol=0.0, alpha0=None, beta0=None):
+          max_ls=40, c1=1e-4, c2=0.9, gtol=0.0, alpha0=None, beta0=None, nthreads=0):
     """L-BFGS ascent on the dual from (alpha0, beta0) (zeros by default).
 
     Returns dict(alpha, beta, obj, trace, iters, evals, status, gnorm_inf,
@@ -219,7 +231,7 @@ def solve(P: Problem, max_iter=200, hist=10, r=10, use_screen=False, use_lower=T
     al = _d(np.zeros(P.ns) if alpha0 is None else alpha0).copy()
     be = _d(np.zeros(P.nt) if beta0 is None else beta0).copy()
     opts = _Opts(int(max_iter), int(hist), int(r), int(bool(use_screen)), int(bool(use_lower)),
-                 int(max_ls), float(c1), float(c2), float(gtol))
+                 int(max_ls), float(c1), float(c2), float(gtol), int(nthreads))
     info = _Info()
     trace = np.full(max_iter + 1, np.nan)
     rc = lib().orc_solve(P.ref, ct.byref(opts), _ptr(al), _ptr(be), ct.byref(info), _ptr(trace))

@@ -17,6 +17,9 @@
  * Functions and the passages they follow:
  *   orc_cost_sqeuclid  - c_ij = ||x_i - y_j||^2            (Sec. 2.1)
  *   orc_dual_grad      - D(alpha, beta) of the smooth relaxed dual (Eq. 4)
+ *   orc_dual_grad_par  - the same values, bit for bit, computed by OpenMP
+ *                        threads over target columns (used to time the
+ *                        definition on every host core)
  *                        and its gradient; per column j and group l the
  *                        block of grad psi is the group soft-threshold of
  *                        [f]_+ / gamma (Eq. 5, rewritten with z_lj as in
@@ -34,6 +37,7 @@
  *                        screening off it is the original dense method.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -162,6 +166,74 @@ int orc_dual_grad(const orc_problem *P, const double *alpha, const double *beta,
         for (int i = 0; i < P->ns; ++i) grad_a[i] = P->a[i] - rowacc[i];
     if (obj) *obj = dual_linear(P, alpha, beta) - kval(&psi_tot);
     free(rowacc);
+    groups_free(&G);
+    return 0;
+}
+
+/* orc_dual_grad with the columns shared among `nthreads` OpenMP threads (0:
+ * the runtime's default).  Pass 1 takes the columns: every block's norm,
+ * soft-threshold factor kappa, column sum and psi (the same arithmetic as
+ * group_block); pass 2 takes the rows: each row adds its entries of T over
+ * the columns in ascending order, the order orc_dual_grad adds them in, so
+ * the results are identical. */
+int orc_dual_grad_par(const orc_problem *P, const double *alpha, const double *beta,
+                      double *grad_a, double *grad_b, double *obj, int nthreads) {
+    groups_t G;
+    int rc = groups_build(P, &G);
+    if (rc) { groups_free(&G); return rc; }
+    const double thr = P->mu * P->gamma;
+    const int nt = P->nt, L = P->L;
+    double *kap = (double *)calloc((size_t)L * nt + 1, sizeof(double));
+    double *col = (double *)calloc((size_t)nt + 1, sizeof(double));
+    double *psi = (double *)calloc((size_t)nt + 1, sizeof(double));
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < nt; ++j) {
+        double cj = 0.0, pj = 0.0;
+        for (int l = 0; l < L; ++l) {
+            double z2 = 0.0;
+            for (int q = G.off[l]; q < G.off[l + 1]; ++q) {
+                int i = G.rows[q];
+                double f = alpha[i] + beta[j] - P->C[(size_t)i * nt + j];
+                double p = f > 0.0 ? f : 0.0;
+                z2 += p * p;
+            }
+            double z = sqrt(z2);
+            if (!(z > thr)) continue;
+            double kappa = (z - thr) / (P->gamma * z);
+            double cl = 0.0;
+            for (int q = G.off[l]; q < G.off[l + 1]; ++q) {
+                int i = G.rows[q];
+                double f = alpha[i] + beta[j] - P->C[(size_t)i * nt + j];
+                cl += f > 0.0 ? kappa * f : 0.0;
+            }
+            cj += cl;
+            pj += (z - thr) * (z - thr) / (2.0 * P->gamma);
+            kap[(size_t)l * nt + j] = kappa;
+        }
+        col[j] = cj;
+        psi[j] = pj;
+    }
+    if (grad_a) {
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < P->ns; ++i) {
+            const double *kl = kap + (size_t)P->labels[i] * nt;
+            double r = 0.0;
+            for (int j = 0; j < nt; ++j) {
+                if (!(kl[j] > 0.0)) continue;
+                double f = alpha[i] + beta[j] - P->C[(size_t)i * nt + j];
+                r += f > 0.0 ? kl[j] * f : 0.0;
+            }
+            grad_a[i] = P->a[i] - r;
+        }
+    }
+    ksum_t psi_tot = {0, 0};
+    for (int j = 0; j < nt; ++j) {
+        if (grad_b) grad_b[j] = P->b[j] - col[j];
+        kadd(&psi_tot, psi[j]);
+    }
+    if (obj) *obj = dual_linear(P, alpha, beta) - kval(&psi_tot);
+    free(kap); free(col); free(psi);
     groups_free(&G);
     return 0;
 }
@@ -377,6 +449,8 @@ typedef struct {
     int max_ls;         /* evaluations per line search */
     double c1, c2;      /* strong-Wolfe constants */
     double gtol;        /* stop when ||grad||_inf <= gtol */
+    int nthreads;       /* dense evaluations by orc_dual_grad_par with this many
+                           threads (same values); 0: orc_dual_grad */
 } orc_solve_opts;
 
 typedef struct {
@@ -391,6 +465,7 @@ typedef struct {
     int use_screen;
     int evals;
     double *ga, *gb;
+    int nthreads;
 } evaluator_t;
 
 /* F = -D, G = -grad D, x = [alpha; beta] */
@@ -400,6 +475,8 @@ static double eval_fg(evaluator_t *E, const double *x, double *g) {
     E->evals++;
     if (E->use_screen)
         orc_gradpsi(P, E->S, x, x + P->ns, E->ga, E->gb, &D);
+    else if (E->nthreads > 0)
+        orc_dual_grad_par(P, x, x + P->ns, E->ga, E->gb, &D, E->nthreads);
     else
         orc_dual_grad(P, x, x + P->ns, E->ga, E->gb, &D, NULL);
     for (int i = 0; i < P->ns; ++i) g[i] = -E->ga[i];
@@ -449,7 +526,7 @@ int orc_solve(const orc_problem *P, const orc_solve_opts *o, double *alpha, doub
     S.inN = (unsigned char *)calloc(LN, 1);
     evaluator_t E = {P, &S, o->use_screen, 0,
                      (double *)malloc(sizeof(double) * (size_t)P->ns),
-                     (double *)malloc(sizeof(double) * (size_t)P->nt)};
+                     (double *)malloc(sizeof(double) * (size_t)P->nt), o->nthreads};
     double *x = (double *)malloc(sizeof(double) * n);
     double *g = (double *)malloc(sizeof(double) * n);
     double *d = (double *)malloc(sizeof(double) * n);

@@ -506,3 +506,22 @@ def test_cost_matches_scipy_cdist():
     xs, xt = rng.standard_normal((13, 5)), rng.standard_normal((9, 5))
     np.testing.assert_allclose(oracle.cost_sqeuclid(xs, xt), cdist(xs, xt, "sqeuclidean"),
                                rtol=1e-13, atol=1e-13)
+
+
+def test_parallel_definition_equals_the_serial_one():
+    """orc_dual_grad_par is the same definition with the columns shared among
+    threads: every value equal bit for bit, whatever the thread count (an
+    empty label, uneven groups), and the solve that uses it follows the same
+    trajectory."""
+    P = rand_problem(47, 300, 211, 5, gamma=0.2, mu=0.3, sizes=[100, 0, 150, 7, 43])
+    rng = np.random.default_rng(47)
+    a = 0.4 + 0.3 * rng.standard_normal(P.ns)
+    b = 0.3 * rng.standard_normal(P.nt)
+    ref = oracle.dual_grad(P, a, b)
+    for nt in (1, 2, 3, 8):
+        got = oracle.dual_grad_par(P, a, b, nthreads=nt)
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y)
+    r1 = oracle.solve(P, max_iter=60)
+    r2 = oracle.solve(P, max_iter=60, nthreads=4)
+    assert np.array_equal(r1["trace"], r2["trace"]) and np.array_equal(r1["alpha"], r2["alpha"])
