@@ -136,7 +136,7 @@ struct ot_gs_handle {
     int hist = 0, maxb = 0, ndot = 0;
     long long vtot = 0;
     long long* voff = nullptr;
-    float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr;
+    float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr, *W = nullptr;
     LbState* st = nullptr;
     double* gram = nullptr;
     double* part = nullptr;
@@ -1875,6 +1875,7 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   };
   TRY(al((void**)&V.voff, sizeof(long long) * h->count));
   TRY(al((void**)&V.X, sizeof(float) * acc));
+  TRY(al((void**)&V.W, sizeof(float) * acc));
   TRY(al((void**)&V.G, sizeof(float) * acc));
   TRY(al((void**)&V.Dv, sizeof(float) * acc));
   TRY(al((void**)&V.S, sizeof(float) * acc * hist));
@@ -1888,6 +1889,13 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   HIPCHK(hipMemsetAsync(V.st, 0, sizeof(LbState) * h->count, s));
   HIPCHK(hipMemsetAsync(V.S, 0, sizeof(float) * acc * hist, s));
   HIPCHK(hipMemsetAsync(V.Y, 0, sizeof(float) * acc * hist, s));
+  {
+    const long long maxv = h->max_ns + h->max_ntp;
+    hipLaunchKernelGGL(k_lbfgs_weights, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                       dim3(256), 0, s, h->d_inst, (const long long*)V.voff, (const float*)h->a_int,
+                       (const float*)h->b_int, (const int*)h->a_uniform, (const int*)h->b_uniform, V.W);
+    LAUNCHCHK();
+  }
   return OT_GS_OK;
 }
 
@@ -1928,6 +1936,7 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.counts = h->counts_dyn;
   A.max_le = h->max_le;
   A.batched = h->count > 1;
+  A.W = V.W;
   return A;
 }
 

@@ -17,6 +17,13 @@
 //            in Algorithm 1);
 //   update - the vector work: accept the trial point, push (s, y), form the
 //            new direction and the next trial point.
+// The iteration runs on scaled variables x = (alpha_i / w_i, beta_j / w_j)
+// with w_i = 1 / sqrt(M a_i), w_j = 1 / sqrt(M b_j), M = (n_src + n_tgt) / 2
+// (a diagonal preconditioner: the dual's curvature along alpha_i and beta_j
+// scales with the marginals a_i and b_j, so with n_src != n_tgt the two
+// blocks differ by the size ratio; for n_src = n_tgt and uniform marginals
+// every w is 1).  Evaluations see the actual point w x; the gradient with
+// respect to x is w times the gradient of D.
 #include "otgs_internal.h"
 
 namespace otgs {
@@ -102,6 +109,7 @@ struct LbArgs {
   int* counts;              // work-list counts of the next screen pass
   int max_le;               // most groups of an instance
   int batched;              // more than one instance: finished ones skip their update
+  const float* W;           // [vtot] variable scales w (actual = w * scaled)
 };
 
 // An instance whose solve has ended and whose last control step accepted no
@@ -120,24 +128,24 @@ __device__ __forceinline__ int lb_ndot(int hist) { return 5 + 3 * hist; }
 // dot slots: 0 Gt.d, 1 Gt.Gt, 2 Gt.G, 3 d.d, 4 max|Gt| (as a double),
 // 5 + 3i: Gt.s_i, 6 + 3i: Gt.y_i, 7 + 3i: d.y_i
 
-// element e of instance k: trial gradient of F (= -grad D)
+// element e of instance k: trial gradient of F (= -grad D) in the actual
+// variables (lb_gt) and in the scaled ones (times w)
 __device__ __forceinline__ float lb_gt(const LbArgs& A, const InstDev& I, int e) {
   return e < I.ns ? -A.ga[I.row_off + e] : -A.gb[I.col_off + (e - I.ns)];
 }
 
 // Per-lane partials, then fixed-order wavefront reductions (the totals in
-// every lane).  Base dots of a vector block: g~.d, g~.g~, g~.G, d.d and
-// max |g~| (lane j holds dot j, lanes >= 4 the maximum).
-__device__ __forceinline__ double lb_base_dots(const float* gt, const float* G, const float* d, int lane) {
+// every lane).  Base dots of a vector block: g~.d, g~.g~, g~.G, d.d (scaled
+// variables) and the lane's max |grad D| gm in the actual ones (lane j
+// holds dot j, lanes >= 4 the maximum).
+__device__ __forceinline__ double lb_base_dots(const float* gt, const float* G, const float* d, int lane, float gm) {
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  float gm = 0.f;
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
     a0 += (double)gt[q] * d[q];
     a1 += (double)gt[q] * gt[q];
     a2 += (double)gt[q] * G[q];
     a3 += (double)d[q] * d[q];
-    gm = fmaxf(gm, fabsf(gt[q]));
   }
   a0 = wave_sum_dd(a0);
   a1 = wave_sum_dd(a1);
@@ -191,11 +199,14 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   }
   // an instance whose solve has ended loads nothing (its dots are zeros)
   float gt[LB_PER_THREAD], v1[LB_PER_THREAD], v2[LB_PER_THREAD], dv[LB_PER_THREAD];
+  float gm = 0.f;
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
     const int e = b * LB_VB + q * LB_BLOCK + lane;
     const bool ok = e < n && run;
-    gt[q] = ok ? lb_gt(A, I, e) : 0.f;
+    const float g0 = ok ? lb_gt(A, I, e) : 0.f;
+    gm = fmaxf(gm, fabsf(g0));
+    gt[q] = ok ? g0 * A.W[v0 + e] : 0.f;
     if (z == 0) {
       v1[q] = ok ? A.G[v0 + e] : 0.f;    // G
       v2[q] = ok ? A.Dv[v0 + e] : 0.f;   // d
@@ -207,7 +218,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
     }
   }
   // lane j < nd writes dot j's partial of this block
-  const double t = z == 0 ? lb_base_dots(gt, v1, v2, lane) : lb_slot_dots(gt, v1, v2, dv, lane);
+  const double t = z == 0 ? lb_base_dots(gt, v1, v2, lane, gm) : lb_slot_dots(gt, v1, v2, dv, lane);
   const int nd = z == 0 ? 5 : 3;
   if (lane < nd) out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
 }
@@ -245,17 +256,20 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots_seq(LbArgs A) {
       y_[q] = ok ? A.Y[(size_t)slot * A.vtot + v0 + e] : 0.f;
     }
   };
+  float gm = 0.f;
 #pragma unroll
   for (int q = 0; q < LB_PER_THREAD; ++q) {
     const int e = b * LB_VB + q * LB_BLOCK + lane;
     const bool ok = e < n && run;
-    gt[q] = ok ? lb_gt(A, I, e) : 0.f;
+    const float g0 = ok ? lb_gt(A, I, e) : 0.f;
+    gm = fmaxf(gm, fabsf(g0));
+    gt[q] = ok ? g0 * A.W[v0 + e] : 0.f;
     g[q] = (ok && z == 0) ? A.G[v0 + e] : 0.f;
     dv[q] = ok ? A.Dv[v0 + e] : 0.f;
   }
   if (sl0 < sc1) load_slot(sl0, sc, yc);
   if (z == 0) {
-    const double t0 = lb_base_dots(gt, g, dv, lane);
+    const double t0 = lb_base_dots(gt, g, dv, lane, gm);
     if (lane < 5) out[(size_t)lane * A.maxb] = t0;
   }
   for (int slot = sl0; slot < sc1; ++slot) {
@@ -724,10 +738,12 @@ __device__ __forceinline__ float lb_update_elem(const LbArgs& A, const InstDev& 
   const float told = *tp;
   if (snap) *sp = told;   // the point just evaluated densely becomes the snapshot
   snap_out = snap ? told : *sp;
+  const float w = A.W[v0 + e];
   float x = A.X[v0 + e];
   if (S.accept) {
-    const float gt = lb_gt(A, I, e);
-    x = told;
+    const float gt = lb_gt(A, I, e) * w;
+    // the accepted trial point, formed again exactly as when it was evaluated
+    x = x + (float)S.t_acc * A.Dv[v0 + e];
     if (S.push) {
       A.S[(size_t)S.slot * A.vtot + v0 + e] = (float)S.t_acc * A.Dv[v0 + e];
       A.Y[(size_t)S.slot * A.vtot + v0 + e] = gt - A.G[v0 + e];
@@ -747,7 +763,7 @@ __device__ __forceinline__ float lb_update_elem(const LbArgs& A, const InstDev& 
     }
     A.Dv[v0 + e] = (float)d;
   }
-  const float xn = x + (float)S.t_next * A.Dv[v0 + e];
+  const float xn = w * (x + (float)S.t_next * A.Dv[v0 + e]);
   *tp = xn;
   return xn;
 }
@@ -827,14 +843,38 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   }
 }
 
+// Variable scales of the iteration (see the top of this file): w = 1 /
+// sqrt(M m_e) for the marginal m_e of element e, M = (n_src + n_tgt) / 2,
+// formed in float64 and rounded once; exactly 1 for uniform marginals with
+// n_src = n_tgt; 1 on padding columns and where a marginal is 0.
+__global__ void __launch_bounds__(256) k_lbfgs_weights(const InstDev* __restrict__ inst,
+                                                       const long long* __restrict__ voff,
+                                                       const float* __restrict__ a_int,
+                                                       const float* __restrict__ b_int,
+                                                       const int* __restrict__ a_uniform,
+                                                       const int* __restrict__ b_uniform, float* __restrict__ W) {
+  const int k = blockIdx.y;
+  const InstDev I = inst[k];
+  const long long v0 = voff[k];
+  const double M = 0.5 * ((double)I.ns + (double)I.nt);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.ns + I.nt_pad; e += gridDim.x * blockDim.x) {
+    double m;
+    if (e < I.ns) m = a_uniform[k] ? 1.0 / I.ns : (double)a_int[I.row_off + e];
+    else if (e - I.ns < I.nt) m = b_uniform[k] ? 1.0 / I.nt : (double)b_int[I.col_off + (e - I.ns)];
+    else m = 0.0;
+    W[v0 + e] = m > 0.0 ? (float)(1.0 / sqrt(M * m)) : 1.0f;
+  }
+}
+
 // X -> trial arrays (alpha, beta), for the export at the end of a solve
 __global__ void __launch_bounds__(256) k_lbfgs_export(LbArgs A) {
   const int k = blockIdx.y;
   const InstDev I = A.inst[k];
   const long long v0 = A.voff[k];
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.ns + I.nt_pad; e += gridDim.x * blockDim.x) {
-    if (e < I.ns) A.alpha[I.row_off + e] = A.X[v0 + e];
-    else A.beta[I.col_off + (e - I.ns)] = A.X[v0 + e];
+    const float x = A.W[v0 + e] * A.X[v0 + e];
+    if (e < I.ns) A.alpha[I.row_off + e] = x;
+    else A.beta[I.col_off + (e - I.ns)] = x;
   }
 }
 
@@ -870,7 +910,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     if (!init_user) *tp = 0.f;
     const bool pad = e >= I.ns && (e - I.ns) >= I.nt;
     if (pad) *tp = 0.f;
-    A.X[v0 + e] = *tp;
+    A.X[v0 + e] = *tp / A.W[v0 + e];
     A.G[v0 + e] = 0.f;
     A.Dv[v0 + e] = 0.f;
     if (e < I.ns) alpha_s[I.row_off + e] = 0.f;

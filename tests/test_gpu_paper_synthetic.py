@@ -1,0 +1,50 @@
+"""The paper's synthetic experiments on the device (Sec. 5.1 set, Sec. 5.2
+(gamma, rho) grid): several grid points as one batched handle, solved
+densely ("origin") and with Algorithms 1-2 ("ours", with and without the
+set N): the three follow the same trajectory bit for bit (Theorem 2), and
+the final objectives match the FP64 oracle's optimum."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_dual_grad import _dev
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _O():
+    import paper_2303_07597_amd.otgs as O
+    return O
+
+
+@pytest.mark.parametrize("n_classes,g", [(10, 10), (80, 10), (10, 80)])
+def test_grid_points_origin_equals_ours(n_classes, g):
+    O = _O()
+    grid = [(1e3, 0.8), (1.0, 0.2), (1.0, 0.8), (1e-2, 0.4)]
+    insts, Ps = [], []
+    for gam, rho in grid:
+        g_, m_ = oracle.rho_form(gam, rho)
+        inst = synth.paper_synthetic(n_classes, g=g, gamma=g_, mu=m_)
+        insts.append(inst)
+        C, _ = oracle.cost_normalized(inst["xs"], inst["xt"])
+        Ps.append(oracle.Problem(C, inst["labels"], n_classes, g_, m_))
+    h = O.Handle([dict(labels=_dev(i["labels"]), n_groups=n_classes, gamma=i["gamma"], mu=i["mu"],
+                       x_src=_dev(i["xs"]), x_tgt=_dev(i["xt"]), cost_mode=O.OT_GS_COST_MATERIALIZE,
+                       cost_scale=0.0) for i in insts])
+    K = 1500
+    runs = []
+    for scr, low in ((0, 1), (1, 1), (1, 0)):
+        tr = torch.full((len(grid) * (K + 1),), float("nan"), dtype=torch.float64, device="cuda")
+        a, b, info, _ = h.solve(max_iter=K, use_screen=scr, use_lower=low, obj_trace=tr)
+        torch.cuda.synchronize()
+        runs.append((a.cpu().numpy(), tr.cpu().numpy(), info))
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r[0], runs[0][0])
+        np.testing.assert_array_equal(r[1], runs[0][1])
+    for P, inf in zip(Ps, runs[0][2]):
+        ref = oracle.solve(P, max_iter=20000, gtol=1e-12)
+        gap = (ref["obj"] - inf["obj"]) / abs(ref["obj"])
+        assert abs(gap) <= 1e-5, (P.gamma, P.mu, inf, ref["obj"])
