@@ -160,6 +160,14 @@ def plan(P: Problem, alpha, beta):
     return dual_grad(P, alpha, beta, want_plan=True)[3]
 
 
+def transport(P: Problem, alpha, beta, X):
+    """Barycentric mapping of the source samples X [n_src, d] onto the
+    targets with the plan at (alpha, beta): diag(1/b) T^T X, the paper's
+    n T^T X_S for uniform b (Sec. 2.1).  T from plan(); a library matmul."""
+    T = plan(P, alpha, beta)
+    return (T.T @ _d(X)) / P.b[:, None]
+
+
 def primal(P: Problem, T):
     return lib().orc_primal(P.ref, _ptr(_d(T)))
 

@@ -525,3 +525,59 @@ def test_parallel_definition_equals_the_serial_one():
     r1 = oracle.solve(P, max_iter=60)
     r2 = oracle.solve(P, max_iter=60, nthreads=4)
     assert np.array_equal(r1["trace"], r2["trace"]) and np.array_equal(r1["alpha"], r2["alpha"])
+
+
+# --------------------------------------------------------------- barycentric mapping (Sec. 2.1)
+
+def test_mapping_with_a_single_source_is_that_source():
+    """n_src = 1: every plan column is b_j (the only feasible plan, reached at
+    the optimum), so every target is mapped onto the one source point."""
+    rng = np.random.default_rng(48)
+    C = rng.uniform(0.1, 1.0, (1, 7))
+    P = oracle.Problem(C, np.zeros(1, np.int32), 1, 0.4, 0.3)
+    r = oracle.solve(P, max_iter=500, gtol=1e-13)
+    X = rng.standard_normal((1, 3))
+    Y = oracle.transport(P, r["alpha"], r["beta"], X)
+    np.testing.assert_allclose(Y, np.repeat(X, 7, axis=0), rtol=1e-9, atol=1e-12)
+
+
+def test_mapping_is_affine_and_a_barycentre_at_the_optimum():
+    """y(X + v) - y(X) = v (sum_i T_ij) / b_j exactly (linear in X); at the
+    optimum the column sums equal b (marginal satisfaction), so a shift of
+    every source moves every target image by the same vector, and each y_j
+    lies in the box spanned by the sources."""
+    P = rand_problem(49, 30, 20, 3, gamma=0.3, mu=0.2)
+    rng = np.random.default_rng(49)
+    r = oracle.solve(P, max_iter=3000, gtol=1e-12)
+    X = rng.standard_normal((P.ns, 4))
+    v = rng.standard_normal(4)
+    Y = oracle.transport(P, r["alpha"], r["beta"], X)
+    Y2 = oracle.transport(P, r["alpha"], r["beta"], X + v)
+    T = oracle.plan(P, r["alpha"], r["beta"])
+    np.testing.assert_allclose(Y2 - Y, np.outer(T.sum(0) / P.b, v), rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(T.sum(0), P.b, atol=1e-9)
+    np.testing.assert_allclose(Y2 - Y, np.tile(v, (P.nt, 1)), atol=1e-6)
+    assert np.all(Y >= X.min(0) - 1e-6) and np.all(Y <= X.max(0) + 1e-6)
+
+
+# --------------------------------------------------------------- sanitizers
+
+def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """Every oracle entry point on small problems (an empty label, a single
+    source row, a single target) in a standalone driver built with
+    -fsanitize=address,undefined: no memory error, leak or undefined
+    arithmetic, and the driver's own invariants hold."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = os.path.join(HERE, os.pardir, "oracle")
+    exe = str(tmp_path / "orc_sanitized")
+    subprocess.check_call([gcc, "-O1", "-g", "-std=c99", "-fopenmp", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-o", exe,
+                           os.path.join(src, "sanitize_driver.c"), os.path.join(src, "otgs_oracle.c"), "-lm"])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.count(" ok") == 4, r.stdout
