@@ -139,6 +139,24 @@ int ot_gs_create(const ot_gs_problem *probs /* host [count] */, int count,
 
 void ot_gs_destroy(ot_gs_handle *h);
 
+/* A handle that keeps all its device memory in a caller-owned workspace:
+ * ot_gs_workspace_size gives the bytes (it builds the handle once to count
+ * them, allocating and freeing device memory, and synchronises `stream`);
+ * ot_gs_create_ws builds the same handle in `workspace` (device,
+ * caller-owned, kept alive until ot_gs_destroy; any alignment) and reserves
+ * everything later calls need: the solver's vectors for histories up to
+ * max_hist (1..32), the buffers of checked evaluations, the re-centring copy
+ * of a materialised cost and the scratch of ot_gs_plan_csr.  Afterwards
+ * ot_gs_dual_grad, ot_gs_solve (hist <= max_hist), ot_gs_plan, ot_gs_plan_csr,
+ * ot_gs_transport and ot_gs_screen_state allocate no device memory (the
+ * warm-start entry points still do).  Same results, bit for bit, as a handle
+ * from ot_gs_create.  Errors: as ot_gs_create; OT_GS_ENOMEM when the
+ * workspace is smaller than ot_gs_workspace_size's answer. */
+int ot_gs_workspace_size(const ot_gs_problem *probs /* host [count] */, int count, int max_hist,
+                         size_t *bytes /* host */, void *stream);
+int ot_gs_create_ws(const ot_gs_problem *probs /* host [count] */, int count, int max_hist, void *workspace,
+                    size_t ws_bytes, ot_gs_handle **out /* host */, void *stream);
+
 /* ------------------------------------------------------------ hot path */
 
 /* One evaluation of the dual objective (Eq. 4) and its gradient (the ascent
@@ -185,6 +203,23 @@ typedef struct {
                              OT_GS_EVERIFY if any evaluation differed.  Direct
                              launches, about twice the evaluation cost; the
                              trajectory is the unverified one.  Default 0.      */
+    int recenter;         /* 1 (default; materialised costs only): when a line search
+                             finds no step because the float32 iterate cannot move
+                             finely enough, the instance is re-centred there: the
+                             evaluations go on with the point split as a float64
+                             reference plus a small float32 part, on the reduced
+                             cost fl32(c_ij - ref_i - ref_j) (a working copy of the
+                             cost, allocated by the first such solve) and D plus
+                             a.ref_alpha + b.ref_beta; at most 8 times per
+                             instance, each after a gain.  0: stop there (status
+                             OT_GS_LINESEARCH).  A re-centred solve leaves the
+                             handle with the zero snapshot.                      */
+    int fused_step;       /* 1 (default): instances with at most 8192 dual variables
+                             (n_src + n_tgt rounded up to 32) run the dot products,
+                             control step and update of a solver step in one
+                             workgroup (hist <= 12); 0: three kernels for every
+                             instance.  The same iterates up to the order of the
+                             float64 dot sums.                                   */
 } ot_gs_options;
 
 /* Fills `o` with the defaults listed above. */
@@ -248,6 +283,18 @@ int ot_gs_plan_csr(ot_gs_handle *h, const float *alpha, const float *beta, long 
 #define OT_GS_STATIC_SCRATCH_BYTES (64u << 20)
 int ot_gs_plan_csr_static(ot_gs_handle *h, const float *alpha, const float *beta, long long *row_ptr,
                           int *col_idx, float *val, long long *nnz, void *stream);
+
+/* Barycentric mapping of the source samples onto the targets with the plan
+ * at (alpha, beta) (Sec. 2.1, where the source matrix is transported as
+ * n T^T X_S): y_j = (1 / b_j) sum_i T_ij x_i, i.e. n_tgt T^T X_S for uniform
+ * b (at a solution every y_j is then a convex combination of source
+ * samples).  x_src: device [sum n_src x dim] row-major, caller order (the
+ * instances' source rows stacked); y_out: device [sum n_tgt x dim].
+ * 1 <= dim <= 256.  Deterministic (fixed summation order).  Materialised or
+ * given costs only.  Errors: OT_GS_EINVAL (NULL, dim, on-the-fly handle),
+ * OT_GS_EDEVICE. */
+int ot_gs_transport(ot_gs_handle *h, const float *alpha, const float *beta, const float *x_src, int dim,
+                    float *y_out, void *stream);
 
 /* The scaled cost the evaluations use (Sec. 2.1; for COST_ONTHEFLY the
  * values its matrix-core tiles produce, bit for bit), written to C_out in

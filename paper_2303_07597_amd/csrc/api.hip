@@ -82,6 +82,15 @@ struct ot_gs_handle {
   int *perm_row = nullptr, *row_grp = nullptr, *perm_col = nullptr;
   int *g_start = nullptr, *g_size = nullptr, *g_chunk0 = nullptr, *grp_inst = nullptr;
   float* C = nullptr;
+  // the pool the evaluations read and the cost bound of the screen margins:
+  // C and InstDev cmax, or during a re-centred solve the reduced pool Cw and
+  // its per-instance bounds cmax_w
+  const float* C_eval = nullptr;
+  const float* cmax_eval = nullptr;
+  float* Cw = nullptr;
+  float* cmax_w = nullptr;
+  long long c_pool = 0;   // floats of the pool, padding rows included
+  char* csr_scratch = nullptr;   // plan_csr's scratch, reserved in a workspace
   // on-the-fly cost: packed features and squared norms, per-group block offsets
   bool onthefly = false;
   int otf_dpmax = 16;   // largest padded feature count of the instances
@@ -133,19 +142,23 @@ struct ot_gs_handle {
   unsigned int* asm_done = nullptr;   // [count] assembly blocks finished (finalising evaluations)
   // solver buffers (allocated by the first solve)
   struct Solver {
-    int hist = 0, maxb = 0, ndot = 0;
+    int hist = 0, maxb = 0, ndot = 0, cap_hist = 0;
+    int n_small = 0;   // instances whose whole step runs in one workgroup
     long long vtot = 0;
     long long* voff = nullptr;
     float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr, *W = nullptr;
     LbState* st = nullptr;
     double* gram = nullptr;
     double* part = nullptr;
-    int* n_active = nullptr;
-    int* h_active = nullptr;  // pinned host
+    int* n_active = nullptr;  // [2]: instances still running (or waiting), re-centrings asked for
+    int* h_active = nullptr;  // pinned host [2]
+    double* xref = nullptr;   // re-centring reference, actual variables
+    double* obj_const = nullptr;
     std::vector<void*> mem;
   } sol;
   Timing timing;
   bool has_snapshot = false;
+  bool step1 = true;   // solver steps of small instances in one workgroup (ot_gs_solve option)
   hipStream_t cap_stream = nullptr;   // stream that records solver steps into a graph
   // tile configuration (autotuned or set): per bucket of the tile lists the
   // team-shape variant (on-the-fly) and the grid multiplier (workgroups per
@@ -153,18 +166,58 @@ struct ot_gs_handle {
   int tile_var[NBUCKET + 1] = {};
   int tile_gm[NBUCKET + 1] = {};   // set to 2 at create
 
-  template <class T>
-  int alloc(T** p, size_t n) {
-    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) return fail(OT_GS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    allocs.push_back(q);
-    *p = (T*)q;
+  // Device memory.  Without a caller workspace every buffer is a hipMalloc;
+  // with one (ot_gs_create_ws) buffers are carved from it: those kept by the
+  // handle from the bottom, set-up temporaries from the top (released at the
+  // end of create).  The ledger counts the aligned bytes either way, which is
+  // what ot_gs_workspace_size reports.
+  char* ws_base = nullptr;
+  size_t ws_size = 0, ws_lo = 0, ws_hi = 0;
+  size_t led_persist = 0, led_temp = 0, led_temp_peak = 0;
+  static size_t aligned(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+  int dev_alloc(void** p, size_t bytes, bool temp) {
+    const size_t a = aligned(bytes);
+    if (temp) {
+      led_temp += a;
+      led_temp_peak = std::max(led_temp_peak, led_temp);
+    } else {
+      led_persist += a;
+    }
+    if (ws_base) {
+      if (ws_hi - ws_lo < a)
+        return fail(OT_GS_ENOMEM, "the workspace (%zu bytes) is too small; ot_gs_workspace_size gives the size",
+                    ws_size);
+      if (temp) {
+        ws_hi -= a;
+        *p = ws_base + ws_hi;
+      } else {
+        *p = ws_base + ws_lo;
+        ws_lo += a;
+      }
+      return OT_GS_OK;
+    }
+    const hipError_t e = hipMalloc(p, a);
+    if (e != hipSuccess) return fail(OT_GS_ENOMEM, "hipMalloc(%zu) failed: %s", a, hipGetErrorString(e));
+    if (!temp) allocs.push_back(*p);
     return OT_GS_OK;
   }
+  template <class T>
+  int alloc(T** p, size_t n) {
+    return dev_alloc((void**)p, std::max<size_t>(n, 1) * sizeof(T), false);
+  }
+  template <class T>
+  int alloc_temp(T** p, size_t n) {
+    return dev_alloc((void**)p, std::max<size_t>(n, 1) * sizeof(T), true);
+  }
+  // set-up temporaries (LIFO): in a workspace the top region comes back
+  void free_temp(void* p, size_t bytes) {
+    led_temp -= aligned(bytes);
+    if (ws_base) ws_hi += aligned(bytes);
+    else (void)hipFree(p);
+  }
   void free_solver() {
-    for (void* p : sol.mem) (void)hipFree(p);
+    if (!ws_base)
+      for (void* p : sol.mem) (void)hipFree(p);
     if (sol.h_active) (void)hipHostFree(sol.h_active);
     sol = Solver();
   }
@@ -399,7 +452,7 @@ static void cache_apply(ot_gs_handle* h);
 // the largest unscaled cost (normalisation) and each column's least cost per
 // group (nearest-class key), then the scale and max C of every instance.
 static int setup_onthefly(ot_gs_handle* h, const ot_gs_problem* probs, int* colkey,
-                          std::vector<float*>& temps, hipStream_t s) {
+                          std::vector<std::pair<float*, size_t>>& temps, hipStream_t s) {
   const int count = h->count;
   TRY(h->alloc(&h->Xp, h->tot_x));
   TRY(h->alloc(&h->xn, h->tot_rows));
@@ -407,12 +460,12 @@ static int setup_onthefly(ot_gs_handle* h, const ot_gs_problem* probs, int* colk
   TRY(h->alloc(&h->yn, h->tot_cols_pad));
   HIPCHK(hipMemsetAsync(h->Xp, 0, sizeof(float) * std::max<long long>(h->tot_x, 1), s));
   float *ynat = nullptr, *ynnat = nullptr, *colmin = nullptr;
-  HIPCHK(hipMalloc(&ynat, sizeof(float) * std::max<long long>(h->tot_y, 1)));
-  temps.push_back(ynat);
-  HIPCHK(hipMalloc(&ynnat, sizeof(float) * h->tot_cols_pad));
-  temps.push_back(ynnat);
-  HIPCHK(hipMalloc(&colmin, sizeof(float) * std::max<long long>(h->tot_pairs, 1)));
-  temps.push_back(colmin);
+  TRY(h->alloc_temp(&ynat, std::max<long long>(h->tot_y, 1)));
+  temps.push_back({ynat, sizeof(float) * std::max<long long>(h->tot_y, 1)});
+  TRY(h->alloc_temp(&ynnat, h->tot_cols_pad));
+  temps.push_back({ynnat, sizeof(float) * h->tot_cols_pad});
+  TRY(h->alloc_temp(&colmin, std::max<long long>(h->tot_pairs, 1)));
+  temps.push_back({colmin, sizeof(float) * std::max<long long>(h->tot_pairs, 1)});
   TRY(h->alloc(&h->d_inst, count));
   std::vector<InstDev> hd(count);
   for (int k = 0; k < count; ++k) hd[k] = h->inst[k].d;
@@ -488,7 +541,8 @@ static int setup_onthefly(ot_gs_handle* h, const ot_gs_problem* probs, int* colk
   return OT_GS_OK;
 }
 
-static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out, hipStream_t s) {
+static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out, hipStream_t s,
+                       void* ws = nullptr, size_t ws_bytes = 0) {
   if (!probs || !out || count < 1) return fail(OT_GS_EINVAL, "create: bad arguments");
   for (int k = 0; k < count; ++k) {
     const ot_gs_problem& p = probs[k];
@@ -522,6 +576,14 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   auto* h = new ot_gs_handle();
   for (int b = 0; b <= NBUCKET; ++b) h->tile_gm[b] = 2;   // workgroups per resident slot
   std::unique_ptr<ot_gs_handle> guard(h);
+  if (ws) {
+    const uintptr_t p0 = (uintptr_t)ws, p1 = (p0 + 255) & ~(uintptr_t)255;
+    if (ws_bytes < (p1 - p0) + 256) return fail(OT_GS_ENOMEM, "create: workspace too small");
+    h->ws_base = (char*)p1;
+    h->ws_size = ws_bytes - (p1 - p0);
+    h->ws_lo = 0;
+    h->ws_hi = h->ws_size;
+  }
   h->onthefly = otf;
   h->count = count;
   h->inst.resize(count);
@@ -696,13 +758,14 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
   // on-the-fly cost; both give the scale, max C and the column clustering key
   int* colkey = nullptr;
   TRY(h->alloc(&colkey, h->tot_cols));
-  std::vector<float*> temps;
+  std::vector<std::pair<float*, size_t>> temps;
   struct TempFree {
-    std::vector<float*>& v;
+    ot_gs_handle* h;
+    std::vector<std::pair<float*, size_t>>& v;
     ~TempFree() {
-      for (float* p : v) (void)hipFree(p);
+      for (size_t i = v.size(); i-- > 0;) h->free_temp(v[i].first, v[i].second);
     }
-  } tfree{temps};
+  } tfree{h, temps};
   const float** d_costs = nullptr;
   float* d_scale = nullptr;
   if (!otf) {
@@ -714,8 +777,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
         hcost[k] = p.cost;
       } else {
         float* tmp = nullptr;
-        HIPCHK(hipMalloc(&tmp, sizeof(float) * (size_t)p.n_src * p.n_tgt));
-        temps.push_back(tmp);
+        TRY(h->alloc_temp(&tmp, (size_t)p.n_src * p.n_tgt));
+        temps.push_back({tmp, sizeof(float) * (size_t)p.n_src * p.n_tgt});
         dim3 grid((unsigned)ceil_div(p.n_tgt, 64), (unsigned)ceil_div(p.n_src, 64));
         hipLaunchKernelGGL(k_cost_features, grid, dim3(256), 0, s, p.x_src, p.x_tgt, p.n_src, p.n_tgt,
                            p.dim, tmp);
@@ -841,7 +904,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       long long maxntp = 64;
       for (int k = 0; k < count; ++k) maxntp = std::max<long long>(maxntp, h->inst[k].d.nt_pad);
       const long long pad = (long long)CHUNK * maxntp;
-      TRY(h->alloc(&h->C, h->tot_c + pad));
+      h->c_pool = h->tot_c + pad;
+      TRY(h->alloc(&h->C, h->c_pool));
       HIPCHK(hipMemsetAsync(h->C + h->tot_c, 0, sizeof(float) * pad, s));
     }
     {
@@ -975,7 +1039,7 @@ static GradArgs grad_args(ot_gs_handle* h) {
   A.g_start = h->g_start;
   A.g_size = h->g_size;
   A.g_chunk0 = h->g_chunk0;
-  A.C = h->C;
+  A.C = h->C_eval ? h->C_eval : h->C;
   A.g_xblk = h->g_xblk;
   A.Xp = h->Xp;
   A.Yp = h->Yp;
@@ -1025,6 +1089,7 @@ static ScreenArgs screen_args(ot_gs_handle* h, int use_lower) {
   S.block_counters = h->block_counters;
   S.inst_mode = h->inst_mode;
   S.use_lower = use_lower;
+  S.cmax_w = h->cmax_eval;
   return S;
 }
 
@@ -1252,6 +1317,9 @@ static int run_tiles_and_reduce(ot_gs_handle* h, bool dynamic, float* ga_out, fl
   // finalising: the last assembly block of each instance forms D
   R.finalize = finalize ? 1 : 0;
   R.obj_out = obj_out;
+  // inside a solver step (the only non-finalising evaluations) the control
+  // step counts the live instances afresh
+  R.zero_first = finalize ? nullptr : h->sol.n_active;
   hipLaunchKernelGGL(k_assemble, dim3(h->n_asm, h->count), dim3(ASM_BLOCK), 0, s, R);
   LAUNCHCHK();
   TRY(tend(h, KT_REDUCE, s, e0));
@@ -1502,7 +1570,60 @@ static int csr_pass(ot_gs_handle* h, const CsrSink& K, hipStream_t s) {
   return OT_GS_OK;
 }
 
+static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s);
+
+// Everything a handle can later need on the device, allocated now: the
+// solver buffers for up to max_hist pairs, the checked-evaluation buffers,
+// the re-centring copy of a materialised cost and plan_csr's scratch.
+static int reserve_all(ot_gs_handle* h, int max_hist, hipStream_t s) {
+  TRY(ensure_solver(h, max_hist, s));
+  TRY(ensure_verify(h));
+  if (!h->onthefly) {
+    TRY(h->alloc(&h->Cw, h->c_pool));
+    TRY(h->alloc(&h->cmax_w, h->count));
+  }
+  long long cstride = 1;
+  for (int k = 0; k < h->count; ++k) cstride = std::max<long long>(cstride, h->inst[k].d.njb);
+  const size_t rows = (size_t)h->tot_rows;
+  const size_t bytes = ot_gs_handle::aligned(sizeof(int) * rows * cstride) +
+                       ot_gs_handle::aligned(sizeof(long long) * rows * cstride);
+  TRY(h->alloc(&h->csr_scratch, bytes));
+  HIPCHK(hipStreamSynchronize(s));
+  return OT_GS_OK;
+}
+
 extern "C" {
+
+int ot_gs_workspace_size(const ot_gs_problem* probs, int count, int max_hist, size_t* bytes, void* stream) {
+  if (!bytes || max_hist < 1 || max_hist > HMAX)
+    return fail(OT_GS_EINVAL, "workspace_size: bytes NULL or max_hist outside [1, %d]", HMAX);
+  ot_gs_handle* h = nullptr;
+  try {
+    TRY(create_impl(probs, count, &h, (hipStream_t)stream));
+  } catch (...) {
+    return fail(OT_GS_ENOMEM, "workspace_size: host allocation failed");
+  }
+  std::unique_ptr<ot_gs_handle> guard(h);
+  TRY(reserve_all(h, max_hist, (hipStream_t)stream));
+  *bytes = h->led_persist + h->led_temp_peak + 256;
+  return OT_GS_OK;
+}
+
+int ot_gs_create_ws(const ot_gs_problem* probs, int count, int max_hist, void* workspace, size_t ws_bytes,
+                    ot_gs_handle** out, void* stream) {
+  if (!workspace || !out || max_hist < 1 || max_hist > HMAX)
+    return fail(OT_GS_EINVAL, "create_ws: NULL workspace or out, or max_hist outside [1, %d]", HMAX);
+  ot_gs_handle* h = nullptr;
+  try {
+    TRY(create_impl(probs, count, &h, (hipStream_t)stream, workspace, ws_bytes));
+  } catch (...) {
+    return fail(OT_GS_ENOMEM, "create_ws: host allocation failed");
+  }
+  std::unique_ptr<ot_gs_handle> guard(h);
+  TRY(reserve_all(h, max_hist, (hipStream_t)stream));
+  *out = guard.release();
+  return OT_GS_OK;
+}
 
 int ot_gs_create(const ot_gs_problem* probs, int count, ot_gs_handle** out, void* stream) {
   try {
@@ -1637,7 +1758,13 @@ int ot_gs_plan_csr(ot_gs_handle* h, const float* alpha, const float* beta, long 
       for (void* p : v) (void)hipFree(p);
     }
   } free_tmp{tmp};
+  size_t used = 0;   // of the workspace's reserved scratch
   auto al = [&](void** p, size_t bytes) -> int {
+    if (h->csr_scratch) {
+      *p = h->csr_scratch + used;
+      used += ot_gs_handle::aligned(bytes);
+      return OT_GS_OK;
+    }
     const hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
     if (e != hipSuccess) return fail(OT_GS_ENOMEM, "plan_csr: hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     tmp.push_back(*p);
@@ -1843,15 +1970,32 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->time_trace = nullptr;
   o->use_graph = 1;
   o->verify = 0;
+  o->recenter = 1;
+  o->fused_step = 1;
 }
 
 }  // extern "C"
 
 // ------------------------------------------------------------ solver
 
+// Solver buffers for a history of `hist` pairs.  Without a workspace they are
+// allocated by the first solve (again when the history grows); in a
+// workspace they were reserved at create for the largest history the
+// caller named, and a solve with a shorter history uses a prefix of them.
 static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   auto& V = h->sol;
   if (V.hist == hist && V.X) return OT_GS_OK;
+  if (V.X && h->ws_base) {
+    if (hist > V.cap_hist)
+      return fail(OT_GS_EINVAL, "solve: hist %d above the %d the workspace was sized for", hist, V.cap_hist);
+    HIPCHK(hipStreamSynchronize(s));
+    V.hist = hist;
+    V.ndot = 5 + 3 * hist;
+    HIPCHK(hipMemsetAsync(V.st, 0, sizeof(LbState) * h->count, s));
+    HIPCHK(hipMemsetAsync(V.S, 0, sizeof(float) * V.vtot * hist, s));
+    HIPCHK(hipMemsetAsync(V.Y, 0, sizeof(float) * V.vtot * hist, s));
+    return OT_GS_OK;
+  }
   HIPCHK(hipStreamSynchronize(s));
   h->free_solver();
   std::vector<long long> voff(h->count);
@@ -1867,7 +2011,10 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   V.vtot = acc;
   V.maxb = maxb;
   V.ndot = 5 + 3 * hist;
+  V.cap_hist = hist;
   auto al = [&](void** p, size_t bytes) -> int {
+    if (h->ws_base) return h->dev_alloc(p, bytes, false);
+    h->led_persist += ot_gs_handle::aligned(bytes);
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
     if (e != hipSuccess) return fail(OT_GS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     V.mem.push_back(*p);
@@ -1883,8 +2030,11 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   TRY(al((void**)&V.st, sizeof(LbState) * h->count));
   TRY(al((void**)&V.gram, sizeof(double) * 2 * hist * hist * h->count));
   TRY(al((void**)&V.part, sizeof(double) * (size_t)h->count * maxb * V.ndot));
-  TRY(al((void**)&V.n_active, sizeof(int)));
-  HIPCHK(hipHostMalloc((void**)&V.h_active, sizeof(int), hipHostMallocDefault));
+  TRY(al((void**)&V.n_active, 2 * sizeof(int)));
+  TRY(al((void**)&V.xref, sizeof(double) * acc));
+  TRY(al((void**)&V.obj_const, sizeof(double) * h->count));
+  HIPCHK(hipHostMalloc((void**)&V.h_active, 2 * sizeof(int), hipHostMallocDefault));
+  HIPCHK(hipMemsetAsync(V.n_active, 0, 2 * sizeof(int), s));
   HIPCHK(hipMemcpyAsync(V.voff, voff.data(), sizeof(long long) * h->count, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(V.st, 0, sizeof(LbState) * h->count, s));
   HIPCHK(hipMemsetAsync(V.S, 0, sizeof(float) * acc * hist, s));
@@ -1937,6 +2087,15 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.max_le = h->max_le;
   A.batched = h->count > 1;
   A.W = V.W;
+  A.n_recenter = V.n_active + 1;
+  A.step1_max = (P.hist <= STEP1_HMAX && h->step1) ? STEP1_MAX : 0;
+  V.n_small = 0;
+  for (int k = 0; k < h->count; ++k)
+    if (A.step1_max && h->inst[k].d.ns + h->inst[k].d.nt_pad <= A.step1_max) ++V.n_small;
+  if (P.recenter) {
+    A.xref = V.xref;
+    A.obj_const = V.obj_const;
+  }
   return A;
 }
 
@@ -1975,6 +2134,18 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
+  // instances with short vectors: the whole step in one workgroup each
+  if (A.step1_max && h->sol.n_small > 0) {
+    if (upd)
+      hipLaunchKernelGGL(k_lbfgs_step1<true>, dim3(h->count), dim3(STEP1_THREADS), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_lbfgs_step1<false>, dim3(h->count), dim3(STEP1_THREADS), 0, s, A);
+    LAUNCHCHK();
+    if (h->sol.n_small == h->count) {
+      TRY(tend(h, KT_LBFGS, s, e0));
+      return OT_GS_OK;
+    }
+  }
   // batches with long vectors: LB_SEQ_SPLIT wavefronts per vector block
   // loop over the history slots (g~ and d read LB_SEQ_SPLIT times instead of
   // once per slot); otherwise one wavefront per (block, slot)
@@ -2050,6 +2221,31 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   P.gtol = o.gtol;
   P.obj_trace = o.obj_trace;
   P.time_trace = o.time_trace;
+  P.recenter = (o.recenter && !h->onthefly) ? 1 : 0;
+  h->step1 = o.fused_step != 0;
+  if (P.recenter) {
+    // the evaluations of this solve read a working copy of the pool, which
+    // re-centrings rewrite; its cost bounds start as max C
+    if (!h->Cw) {
+      TRY(h->alloc(&h->Cw, h->c_pool));
+      TRY(h->alloc(&h->cmax_w, h->count));
+    }
+    HIPCHK(hipMemcpyAsync(h->Cw, h->C, sizeof(float) * h->c_pool, hipMemcpyDeviceToDevice, s));
+    std::vector<float> cm(h->count);
+    for (int k = 0; k < h->count; ++k) cm[k] = h->inst[k].d.cmax;
+    HIPCHK(hipMemcpyAsync(h->cmax_w, cm.data(), sizeof(float) * h->count, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->C_eval = h->Cw;
+    h->cmax_eval = h->cmax_w;
+  }
+  struct EvalPoolReset {
+    ot_gs_handle* h;
+    ~EvalPoolReset() {
+      h->C_eval = nullptr;
+      h->cmax_eval = nullptr;
+    }
+  } pool_reset{h};
+  bool recentered = false;
   LbArgs A = lb_args(h, P);
   const bool verify = o.verify && P.use_screen;
   if (verify) {
@@ -2093,9 +2289,28 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
       ++step;
       if (step % check_every != 0 && step != max_steps) continue;
     }
-    HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (*h->sol.h_active == 0) break;
+    if (h->sol.h_active[1] > 0) {
+      // instances whose searches ran out of float32 resolution: re-centre
+      // them at their points and let them go on
+      recentered = true;
+      hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, s, h->sol.n_active + 1, 1LL, 0);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_recenter_vec, dim3(h->count), dim3(1024), 0, s, A, (const float*)h->a_int,
+                         (const float*)h->b_int, (const int*)h->a_uniform, (const int*)h->b_uniform, h->zsnap,
+                         h->osnap, h->inN, h->cmax_w);
+      LAUNCHCHK();
+      const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8), (unsigned)std::min(h->max_ns, 4096),
+                    h->count);
+      hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A, (const float*)h->C, h->Cw, (const int*)h->row_grp,
+                         (const int*)h->g_start, (const int*)h->g_size, h->cmax_w);
+      LAUNCHCHK();
+      hipLaunchKernelGGL(k_recenter_resume, dim3((unsigned)ceil_div(h->count, 256)), dim3(256), 0, s, A, h->count);
+      LAUNCHCHK();
+      continue;
+    }
+    if (h->sol.h_active[0] == 0) break;
   }
   // final points: X of every instance, back in the caller's order
   hipLaunchKernelGGL(k_lbfgs_export, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
@@ -2104,6 +2319,17 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   hipLaunchKernelGGL(k_scatter_duals, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 1024), h->count),
                      dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->alpha, h->beta, alpha_io, beta_io);
   LAUNCHCHK();
+  if (recentered) {
+    // the snapshot and N refer to re-centred points and the reduced cost:
+    // back to the zero snapshot, exact for the handle's own cost (C >= 0)
+    const unsigned fb = (unsigned)std::min<long long>(ceil_div(std::max(h->tot_pairs, h->tot_cols_pad), 256), 4096);
+    hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, h->zsnap, h->tot_pairs, 0.f);
+    hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, h->osnap, h->tot_pairs, 0.f);
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3(fb), dim3(256), 0, s, h->inN, h->tot_pairs, (uint8_t)0);
+    hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, h->alpha_s, h->tot_rows, 0.f);
+    hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, s, h->beta_s, h->tot_cols_pad, 0.f);
+    LAUNCHCHK();
+  }
   std::vector<LbState> hs(h->count);
   HIPCHK(hipMemcpyAsync(hs.data(), h->sol.st, sizeof(LbState) * h->count, hipMemcpyDeviceToHost, s));
   unsigned long long diff = 0;

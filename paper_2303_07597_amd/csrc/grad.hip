@@ -2,19 +2,21 @@
 // assemble grad_alpha = a - T 1, grad_beta = b - T^T 1 and the objective of
 // the smooth relaxed dual (Eq. 4).
 //
-// Gradient tile (group l, 64 target columns j, one column per lane): every
-// lane streams the cost column segment of all rows of the group, forms
+// Gradient tile (group l, TJ = 32 target columns j): lane 32 h + c takes
+// column c and the rows of parity h, streams the tile's cost (one
+// contiguous [rows x 32] block of the tile-major pool), forms
 // f = (alpha_i + beta_j) - c_ij and p = max(f, 0) in registers, accumulates
-// z^2 = sum p^2 and s1 = sum p; the 16 wavefronts combine their partial
-// sums through LDS in a fixed order; then
+// z^2 = sum p^2 and s1 = sum p; the two parities and the 16 wavefronts
+// combine their partial sums through LDS in a fixed order; then
 //     kappa = (z - mu gamma) / (gamma z)   if z > mu gamma, else 0
 // is the group soft threshold of Eq. 5 (T_ij = kappa p_ij), the column sum of
 // the block is kappa s1, the block's share of psi is (z - mu gamma)^2/(2 gamma)
 // and the row sums sum_j kappa_j p_ij are wavefront reductions over lanes.
-// Groups up to 512 rows keep p in registers (R rows per lane, R in
-// {1,...,32}); larger groups are cut in chunks of 512 rows: one pass writes
-// per-chunk column sums, a combine step forms kappa, a second pass re-reads
-// the chunk and forms the row sums.
+// Whole groups of up to WHOLE_MAX = 2048 rows keep p in registers (R loads
+// per lane, row buckets R = 2, 4, 8, ..., 64; small groups run as teams of
+// 2, 4 or 8 wavefronts per tile); larger groups are cut in CHUNK = 1024-row
+// chunks: one pass writes per-chunk column sums, a combine step forms kappa,
+// a second pass re-reads the chunk and forms the row sums.
 // Every reduction has a fixed order and there are no floating-point atomics,
 // so a tile gives bit-identical results whichever mode requested it; skipped
 // tiles contribute exact zeros, hence screened == dense bit for bit.
@@ -699,6 +701,7 @@ struct ReduceArgs {
   double* obj_out;          // finalize: caller's copy of D (may be NULL)
   int finalize;             // 1: the last assembly block of an instance forms D
   const int* inst_mode;     // EvalMode per instance
+  int* zero_first;          // solver steps: the step's count of live instances, zeroed here (may be NULL)
 };
 
 constexpr int ASM_BLOCK = 256;
@@ -777,6 +780,7 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
 __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   __shared__ double red[ASM_BLOCK / 64];
   const int k = blockIdx.y;
+  if (A.zero_first && blockIdx.x == 0 && k == 0 && threadIdx.x == 0) *A.zero_first = 0;
   // inside a batched solve, an instance whose solve has ended (mode SKIP)
   // has no tiles evaluated and nothing reads its gradient or D: its blocks
   // leave at once (calls that finalize D never see SKIP)

@@ -37,10 +37,12 @@ constexpr int LB_VB = LB_BLOCK * LB_PER_THREAD;   // vector elements per dots bl
 constexpr long long LB_SEQ_MIN_VTOT = 32768;
 constexpr int LB_SEQ_SPLIT = 2;   // wavefronts sharing the history slots of a vector block
 
-enum LbStatus { LB_RUNNING = 0, LB_CONVERGED = 1, LB_LSFAIL = 2, LB_MAXITER = 3 };
+enum LbStatus { LB_RUNNING = 0, LB_CONVERGED = 1, LB_LSFAIL = 2, LB_MAXITER = 3, LB_RECENTER = 4 };
+constexpr int RECENTER_MAX = 8;   // re-centrings per instance and solve
 
 struct LbParams {
   int hist, max_iter, max_ls, refresh, use_screen, use_lower;
+  int recenter;           // re-centre instead of stopping on a failed search
   double c1, c2, gtol;
   double* obj_trace;      // [count * (max_iter + 1)] or NULL
   long long* time_trace;  // [count * (max_iter + 1)] or NULL
@@ -51,7 +53,8 @@ struct LbState {
   int count, head;            // history ring
   int accept, push, slot, newdir;
   int since_refresh, mode_eval;   // mode_eval: mode of the evaluation just done
-  int force, pad2;                // force: accept the next evaluation (best step of a failed search)
+  int force, n_rec;               // force: accept the next evaluation (best step of a failed search);
+                                  // n_rec: re-centrings so far
   double f, gtd0, gmax;
   double t, t_prev, f_prev, dp_prev;
   double t_lo, f_lo, dp_lo, t_hi, f_hi, dp_hi;
@@ -60,6 +63,8 @@ struct LbState {
   double SG[HMAX], YG[HMAX], rho[HMAX];
   double cs[HMAX], cy[HMAX];
   double f_restart;   // objective when the memory was last dropped after a failed search
+  double f_rec;       // objective at the last re-centring
+  double h0;          // s.y / y.y of the newest pair accepted into the memory (0: none yet)
 };
 // The Gram matrices s_i.y_j and y_i.y_j of an instance live next to the state
 // as [2][hist][hist] float64 (row-major, stride hist); the control kernel
@@ -110,6 +115,16 @@ struct LbArgs {
   int max_le;               // most groups of an instance
   int batched;              // more than one instance: finished ones skip their update
   const float* W;           // [vtot] variable scales w (actual = w * scaled)
+  // re-centred solves (see k_recenter_vec): the evaluations see the point
+  // relative to a reference xref (actual variables, float64) through the
+  // reduced cost c_ij - xref_i - xref_j; D adds obj_const = a.xref_a + b.xref_b
+  double* xref;             // [vtot] or NULL
+  double* obj_const;        // [count]
+  int* n_recenter;          // instances waiting for a re-centring
+  // instances with at most step1_max vector elements run the whole step in
+  // one workgroup (k_lbfgs_step1); the three-kernel path skips them.  0: no
+  // instance does
+  int step1_max;
 };
 
 // An instance whose solve has ended and whose last control step accepted no
@@ -186,8 +201,8 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   const LbState& S = A.st[k];
   const int st_status = S.status, st_phase = S.phase, st_count = S.count;
   const int n = I.ns + I.nt_pad;
-  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
   if (b * LB_VB >= n) return;           // beyond this instance: ctrl reads no such partial
+  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
   const bool run = st_status == LB_RUNNING;
   const int cnt = (run && st_phase != 0) ? st_count : 0;
   const int slot = z - 1;
@@ -240,8 +255,8 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots_seq(LbArgs A) {
   const LbState& S = A.st[k];
   const int st_status = S.status, st_phase = S.phase, st_count = S.count;
   const int n = I.ns + I.nt_pad;
-  if (b == 0 && k == 0 && z == 0 && lane == 0) *A.n_active = 0;
   if (b * LB_VB >= n) return;
+  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
   const bool run = st_status == LB_RUNNING;
   const int cnt = (run && st_phase != 0) ? st_count : 0;
   const int sc1 = min(cnt, sl1);   // slots [sl0, sc1) hold pairs, [max(sl0, cnt), sl1) are zeros
@@ -406,10 +421,15 @@ __device__ double lb_steepest(LbState& S, const LbParams& P) {
   return -S.GG;
 }
 
-// start a line search along the direction whose slope is gtd
+// start a line search along the direction whose slope is gtd.  Without a
+// memory the first trial step is 1 / ||G|| at the start of a solve; after
+// the memory was dropped (a restart, a re-centring) it is the curvature
+// scale s.y / y.y of the last pair, which near the optimum is orders of
+// magnitude below 1 / ||G|| (a search from there could not shrink far
+// enough within its trials).
 __device__ void lb_start_search(LbState& S, double gtd) {
   S.gtd0 = gtd;
-  S.t = (S.count == 0) ? 1.0 / sqrt(S.GG) : 1.0;
+  S.t = (S.count != 0) ? 1.0 : (S.h0 > 0.0 ? S.h0 : 1.0 / sqrt(S.GG));
   S.t_prev = 0.0;
   S.f_prev = S.f;
   S.dp_prev = gtd;
@@ -435,7 +455,10 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   S.mode_eval = A.inst_mode[k];
   __builtin_amdgcn_wave_barrier();
   if (S.status != LB_RUNNING) {
-    if (l0) A.inst_mode[k] = EM_SKIP;
+    if (l0) {
+      A.inst_mode[k] = EM_SKIP;
+      if (S.status == LB_RECENTER) atomicAdd(A.n_active, 1);   // resumes after the re-centring
+    }
     S.t_next = 0.0;
     return;
   }
@@ -460,7 +483,8 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
     S.t_next = 0.0;
     return;
   }
-  if (S.phase == 0) {  // first evaluation, at the starting point
+  if (S.phase == 0 || S.phase == 2) {  // first evaluation, at the starting point (2: after a re-centring)
+    const bool restart = S.phase == 2;
     S.phase = 1;
     S.f = ft;
     S.accept = 1;
@@ -469,11 +493,11 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
     S.gmax = dots[4];
     S.count = 0;
     S.head = 0;
-    if (P.obj_trace && l0) P.obj_trace[tr] = D;
-    if (P.time_trace && l0) P.time_trace[tr] = wall_clock64();
+    if (P.obj_trace && l0 && !restart) P.obj_trace[tr] = D;
+    if (P.time_trace && l0 && !restart) P.time_trace[tr] = wall_clock64();
     if (S.gmax <= P.gtol) {
       S.status = LB_CONVERGED;
-    } else if (P.max_iter <= 0) {
+    } else if (S.iter >= P.max_iter) {
       S.status = LB_MAXITER;
     }
     if (S.status != LB_RUNNING) {
@@ -486,6 +510,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
       A.inst_mode[k] = P.use_screen ? EM_SCREEN : EM_DENSE;
       atomicAdd(A.n_active, 1);
     }
+    S.since_refresh = 0;
     return;
   }
   // strong-Wolfe line search on phi(t) = F(X + t d)
@@ -546,6 +571,21 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
         if (l0) atomicAdd(A.n_active, 1);
         return;
       }
+      if (P.recenter && S.n_rec < RECENTER_MAX && S.f_rec - S.f > 1e-12 * fabs(S.f)) {
+        // the search ran out of float32 resolution around the point: ask
+        // for a re-centring there (the host launches it between steps) and
+        // continue from it with a fresh memory
+        S.f_rec = S.f;
+        S.n_rec++;
+        S.status = LB_RECENTER;
+        if (l0) {
+          A.inst_mode[k] = EM_SKIP;
+          atomicAdd(A.n_active, 1);
+          atomicAdd(A.n_recenter, 1);
+        }
+        S.t_next = 0.0;
+        return;
+      }
       S.status = LB_LSFAIL;
       if (l0) A.inst_mode[k] = EM_SKIP;
       S.t_next = 0.0;
@@ -586,6 +626,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
     G.sy(sl, sl) = sy;
     G.yy(sl, sl) = yy;
     S.rho[sl] = 1.0 / sy;
+    S.h0 = sy / yy;
     if (lane == sl) {
       SGn = t * Gtd;
       YGn = GtGt - GtG;
@@ -629,6 +670,7 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   __shared__ double gram_s[2 * HMAX * HMAX];
   const int k = blockIdx.x;
   const int h = A.P.hist;
+  if (A.step1_max && A.inst[k].ns + A.inst[k].nt_pad <= A.step1_max) return;   // k_lbfgs_step1's
   double* gram_g = A.gram + (size_t)k * 2 * h * h;
   // Every load of the step is issued at once, before any is used: the
   // state, the Gram matrices, the first PD block partials of the lane's dot
@@ -715,7 +757,7 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   for (int u = 0; u < PO; ++u)
     if (u * 64 + lane < nob) os += po[u];
   for (int i = PO * 64 + lane; i < nob; i += 64) os += osrc[i];
-  const double Dobj = wave_sum_dd(os);
+  const double Dobj = wave_sum_dd(os) + (A.obj_const ? A.obj_const[k] : 0.0);
   __syncthreads();
   if (threadIdx.x == 0) A.obj_out[k] = Dobj;
   lb_ctrl_logic(A, k, S, G, dots, Dobj);
@@ -777,6 +819,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const long long v0 = A.voff[k];
   const int h = A.P.hist;
   const bool snap = S.mode_eval == EM_SNAPSHOT;
+  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
   if (lb_update_idle(A, S)) return;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     float so;
@@ -804,6 +847,7 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   const bool snap = S.mode_eval == EM_SNAPSHOT;
   const int bx = blockIdx.x;
   if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
+  if (A.step1_max && I.ns + I.nt_pad <= A.step1_max) return;   // k_lbfgs_step1's
   if (lb_update_idle(A, S)) return;
   if (bx >= A.max_le) {
     const int c = (bx - A.max_le) * GT + threadIdx.x;
@@ -843,6 +887,173 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   }
 }
 
+// ------------------------------------------------------------ one-workgroup step
+// An instance with at most STEP1_MAX vector elements (and a history of at
+// most STEP1_HMAX pairs) runs its whole solver step in one workgroup, which
+// needs no device-wide ordering between its parts: every dot product (each
+// thread its elements, fixed-order wavefront trees, then the wavefronts in
+// order), the control step on wavefront 0 (the state and Gram matrices in
+// LDS), the vector update, and - in screened solves whose groups have at
+// most CHUNK rows - the next evaluation's per-group statistics (wavefront
+// w takes groups w, w + 8, ..., from the new point and snapshot kept in
+// LDS).  One launch for a batch of instances replaces the dots, control and
+// update kernels (three launches, each a chain of dependent memory round
+// trips).  The dot sums run in another order than the three-kernel path's,
+// so the two paths differ in the last bits; a given instance always takes
+// the same one.
+constexpr int STEP1_THREADS = 512;
+constexpr int STEP1_MAX = 8192;
+constexpr int STEP1_PER = STEP1_MAX / STEP1_THREADS;
+constexpr int STEP1_HMAX = 12;
+
+template <bool GS>
+__global__ void __launch_bounds__(STEP1_THREADS) k_lbfgs_step1(LbArgs A) {
+  constexpr int NW = STEP1_THREADS / 64;
+  constexpr int ND = 5 + 3 * STEP1_HMAX;
+  __shared__ double red[NW][ND];
+  __shared__ double dots[5 + 3 * HMAX];
+  __shared__ LbState S;
+  __shared__ double gram_s[2 * STEP1_HMAX * STEP1_HMAX];
+  __shared__ float a_new[GS ? STEP1_MAX : 1];
+  __shared__ float a_snap[GS ? STEP1_MAX : 1];
+  const int k = blockIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const InstDev I = A.inst[k];
+  const int n = I.ns + I.nt_pad;
+  if (GS && k == 0 && t < NBUCKET + 2) A.counts[t] = 0;
+  if (n > A.step1_max) return;   // the three-kernel path's
+  const long long v0 = A.voff[k];
+  const int h = A.P.hist;
+  {
+    // ---- dot products of the trial gradient (scaled variables)
+    const LbState& Sg = A.st[k];
+    const bool run = Sg.status == LB_RUNNING;
+    const int cnt = (run && Sg.phase != 0) ? Sg.count : 0;
+    double acc[ND - 1];
+#pragma unroll
+    for (int j = 0; j < ND - 1; ++j) acc[j] = 0.0;
+    float gm = 0.f;
+    if (run) {
+      for (int m = 0; m < STEP1_PER; ++m) {
+        const int e = t + m * STEP1_THREADS;
+        if (e >= n) break;
+        const float g0 = lb_gt(A, I, e);
+        gm = fmaxf(gm, fabsf(g0));
+        const double gt = (double)(g0 * A.W[v0 + e]);
+        const double Gv = (double)A.G[v0 + e], dv = (double)A.Dv[v0 + e];
+        acc[0] += gt * dv;
+        acc[1] += gt * gt;
+        acc[2] += gt * Gv;
+        acc[3] += dv * dv;
+#pragma unroll
+        for (int i = 0; i < STEP1_HMAX; ++i) {
+          if (i < cnt) {
+            const double sv = (double)A.S[(size_t)i * A.vtot + v0 + e];
+            const double yv = (double)A.Y[(size_t)i * A.vtot + v0 + e];
+            acc[4 + 3 * i] += gt * sv;
+            acc[5 + 3 * i] += gt * yv;
+            acc[6 + 3 * i] += dv * yv;
+          }
+        }
+      }
+    }
+    // slot j of red: dots 0..3, max |grad D| (4), then 5 + 3 i ... as the
+    // three-kernel path numbers them
+#pragma unroll
+    for (int j = 0; j < ND - 1; ++j) {
+      if (j < 4 + 3 * cnt) {
+        const double v = wave_sum_dd(acc[j]);
+        if (lane == 0) red[wv][j < 4 ? j : j + 1] = v;
+      }
+    }
+    const double g4 = wave_max_d((double)gm);
+    if (lane == 0) red[wv][4] = g4;
+    __syncthreads();
+    if (t < 5 + 3 * h) {
+      double v = 0.0;
+      if (t < 5 + 3 * cnt) {
+        for (int w = 0; w < NW; ++w) v = t == 4 ? fmax(v, red[w][t]) : v + red[w][t];
+      }
+      dots[t] = v;
+    }
+  }
+  // ---- control step on wavefront 0 (state and Gram matrices copied to LDS
+  // by every thread first)
+  {
+    constexpr int NV = (int)(sizeof(LbState) / 16);
+    const int4* src = (const int4*)&A.st[k];
+    int4* dst = (int4*)&S;
+    for (int i = t; i < NV; i += STEP1_THREADS) dst[i] = src[i];
+    const double* gram_g = A.gram + (size_t)k * 2 * h * h;
+    for (int q = t; q < 2 * h * h; q += STEP1_THREADS) gram_s[q] = gram_g[q];
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const int nob = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
+    const double* osrc = A.obj_part + (size_t)k * A.obj_stride;
+    double os = 0.0;
+    for (int i = lane; i < nob; i += 64) os += osrc[i];
+    const double Dobj = wave_sum_dd(os) + (A.obj_const ? A.obj_const[k] : 0.0);
+    if (lane == 0) A.obj_out[k] = Dobj;
+    LbGram G{gram_s, gram_s + h * h, h};
+    lb_ctrl_logic(A, k, S, G, dots, Dobj);
+    __builtin_amdgcn_wave_barrier();
+    double* gram_g = A.gram + (size_t)k * 2 * h * h;
+    for (int q = lane; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
+    constexpr int NV = (int)(sizeof(LbState) / 16);
+    const int4* src = (const int4*)&S;
+    int4* dst = (int4*)&A.st[k];
+    for (int i = lane; i < NV; i += 64) dst[i] = src[i];
+  }
+  __syncthreads();
+  // ---- vector update (and the group statistics)
+  if (lb_update_idle(A, S)) return;
+  const bool snap = S.mode_eval == EM_SNAPSHOT;
+  for (int m = 0; m < STEP1_PER; ++m) {
+    const int e = t + m * STEP1_THREADS;
+    if (e >= n) break;
+    float so;
+    const float xa = lb_update_elem(A, I, S, e, v0, h, snap, so);
+    if (GS && e < I.ns) {
+      a_new[e] = xa;
+      a_snap[e] = so;
+    }
+  }
+  if (!GS) return;
+  __syncthreads();
+  for (int ge = wv; ge < I.Le; ge += NW) {
+    const int gidx = I.grp_off + ge;
+    const int r0 = A.g_start[gidx], gn = A.g_size[gidx];
+    double up = 0, dn = 0, am = 0, ams = 0;
+    for (int q = lane; q < gn; q += 64) {
+      const double a = a_new[r0 + q], as = a_snap[r0 + q];
+      const double d = a - as;
+      if (d > 0) up += d * d; else dn += d * d;
+      am = fmax(am, fabs(a));
+      ams = fmax(ams, fabs(as));
+    }
+    up = wave_sum_dd(up);
+    dn = wave_sum_dd(dn);
+    am = wave_max_d(am);
+    ams = wave_max_d(ams);
+    if (lane == 0) {
+      GroupStats g;
+      g.up = sqrt(up);
+      g.dn = sqrt(dn);
+      g.all = sqrt(up + dn);
+      g.amax = am;
+      g.amax_s = ams;
+      screen_group_consts(gn, g.sg, g.fa, g.fb);
+      A.gstats[gidx] = g;
+      if (ge == 0) {
+        const int md = A.inst_mode[k];
+        if (md != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
+        if (md == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
+      }
+    }
+  }
+}
+
 // Variable scales of the iteration (see the top of this file): w = 1 /
 // sqrt(M m_e) for the marginal m_e of element e, M = (n_src + n_tgt) / 2,
 // formed in float64 and rounded once; exactly 1 for uniform marginals with
@@ -872,7 +1083,8 @@ __global__ void __launch_bounds__(256) k_lbfgs_export(LbArgs A) {
   const InstDev I = A.inst[k];
   const long long v0 = A.voff[k];
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < I.ns + I.nt_pad; e += gridDim.x * blockDim.x) {
-    const float x = A.W[v0 + e] * A.X[v0 + e];
+    const float xw = A.W[v0 + e] * A.X[v0 + e];
+    const float x = A.xref ? (float)(A.xref[v0 + e] + (double)xw) : xw;
     if (e < I.ns) A.alpha[I.row_off + e] = x;
     else A.beta[I.col_off + (e - I.ns)] = x;
   }
@@ -896,6 +1108,10 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     S.accept = S.push = S.newdir = 0;
     S.force = 0;
     S.f_restart = INFINITY;
+    S.f_rec = INFINITY;
+    S.n_rec = 0;
+    S.h0 = 0.0;
+    if (A.obj_const) A.obj_const[k] = 0.0;
     S.since_refresh = 0;
     S.t_next = 0.0;
     S.GG = 0.0;
@@ -908,6 +1124,7 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     float* tp = e < I.ns ? &A.alpha[I.row_off + e] : &A.beta[I.col_off + (e - I.ns)];
     if (!init_user) *tp = 0.f;
+    if (A.xref) A.xref[v0 + e] = 0.0;
     const bool pad = e >= I.ns && (e - I.ns) >= I.nt;
     if (pad) *tp = 0.f;
     A.X[v0 + e] = *tp / A.W[v0 + e];
@@ -922,6 +1139,113 @@ __global__ void __launch_bounds__(256) k_lbfgs_init(LbArgs A, int init_user, flo
     zsnap[I.pair_off + q] = 0.f;
     osnap[I.pair_off + q] = 0.f;
     inN[I.pair_off + q] = 0;
+  }
+}
+
+// Re-centring (materialised cost).  A float32 iterate moves on a grid of
+// spacing ulp(alpha) ~ 6e-8 |alpha|, while near the optimum the dual's
+// remaining increase can need finer moves than that: the line search then
+// finds no step although D* is not reached.  The point is therefore split as
+// xref + current (xref in float64): the evaluations see the current part and
+// the reduced cost c'_ij = fl32(c_ij - xref_i - xref_j) (psi depends on
+// alpha_i + beta_j - c_ij only, so it is the same function, up to one
+// rounding of c'), and D adds a.xref_alpha + b.xref_beta.  The current part is
+// small, so its float32 grid is fine.  Runs between solver steps, for the
+// instances whose control step asked for it (status LB_RECENTER).
+//
+// Vector part, one workgroup per instance: xref += w x, x = 0, the trial
+// point and snapshot point zero, the snapshot norms and N cleared (N = {}
+// until the next refresh; the first evaluation takes a new snapshot), the
+// objective constant advanced by the marginals' dot with the move (fixed
+// order), and the state restarted (phase 2: a fresh memory at this point).
+__global__ void __launch_bounds__(1024) k_recenter_vec(LbArgs A, const float* __restrict__ a_int,
+                                                       const float* __restrict__ b_int,
+                                                       const int* __restrict__ a_uniform,
+                                                       const int* __restrict__ b_uniform, float* zsnap,
+                                                       float* osnap, uint8_t* inN, float* cmax_w) {
+  __shared__ double red[16];
+  const int k = blockIdx.x;
+  LbState& S = A.st[k];
+  if (S.status != LB_RECENTER) return;
+  const InstDev I = A.inst[k];
+  const long long v0 = A.voff[k];
+  double part = 0.0;
+  for (int e = threadIdx.x; e < I.ns + I.nt_pad; e += blockDim.x) {
+    const float d = A.W[v0 + e] * A.X[v0 + e];   // the accepted point as evaluated
+    A.xref[v0 + e] += (double)d;
+    A.X[v0 + e] = 0.f;
+    A.Dv[v0 + e] = 0.f;
+    double m = 0.0;
+    if (e < I.ns) {
+      m = a_uniform[k] ? 1.0 / I.ns : (double)a_int[I.row_off + e];
+      A.alpha[I.row_off + e] = 0.f;
+      A.alpha_s[I.row_off + e] = 0.f;
+    } else {
+      const int c = e - I.ns;
+      m = c < I.nt ? (b_uniform[k] ? 1.0 / I.nt : (double)b_int[I.col_off + c]) : 0.0;
+      A.beta[I.col_off + c] = 0.f;
+      A.beta_s[I.col_off + c] = 0.f;
+    }
+    part += m * (double)d;
+  }
+  const long long np = (long long)I.Le * I.nt_pad;
+  for (long long q = threadIdx.x; q < np; q += blockDim.x) {
+    zsnap[I.pair_off + q] = 0.f;
+    osnap[I.pair_off + q] = 0.f;
+    inN[I.pair_off + q] = 0;
+  }
+  part = wave_sum_dd(part);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    A.obj_const[k] += t;
+    cmax_w[k] = 0.f;
+    S.phase = 2;
+    S.count = S.head = 0;
+    S.nls = S.zoom = 0;
+    S.accept = S.push = S.newdir = S.force = 0;
+    S.since_refresh = 0;
+    S.t_next = 0.0;
+    A.inst_mode[k] = A.P.use_screen ? EM_SNAPSHOT : EM_DENSE;
+  }
+}
+
+// Cost part, grid (column blocks, rows, count): c' = fl32(c - xref_i -
+// xref_j) from the original pool for the instances just re-centred (phase 2
+// and still waiting), and their largest |c'| (the rounding margin of the
+// screen's upper bound takes it in place of max C).  The last launch of a
+// re-centring also sets them running.
+__global__ void __launch_bounds__(256) k_recenter_cost(LbArgs A, const float* __restrict__ C, float* __restrict__ Cw,
+                                                       const int* __restrict__ row_grp, const int* __restrict__ g_start,
+                                                       const int* __restrict__ g_size, float* cmax_w) {
+  const int k = blockIdx.z;
+  const LbState& S = A.st[k];
+  if (S.status != LB_RECENTER || S.phase != 2) return;
+  const InstDev I = A.inst[k];
+  const long long v0 = A.voff[k];
+  float mx = 0.f;
+  for (int r = blockIdx.y; r < I.ns; r += gridDim.y) {
+    const int g = row_grp[I.row_off + r];
+    const int gs = g_start[I.grp_off + g], gn = g_size[I.grp_off + g];
+    const double xr = A.xref[v0 + r];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt; c += gridDim.x * blockDim.x) {
+      const size_t q = c_index(I, gs, gn, r, c);
+      const float v = (float)((double)C[q] - xr - A.xref[v0 + I.ns + c]);
+      Cw[q] = v;
+      mx = fmaxf(mx, fabsf(v));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) atomicMax((unsigned int*)&cmax_w[k], __float_as_uint(mx));
+}
+
+// Re-centred instances resume (after the cost kernel).
+__global__ void k_recenter_resume(LbArgs A, int count) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
+    LbState& S = A.st[k];
+    if (S.status == LB_RECENTER && S.phase == 2) S.status = LB_RUNNING;
   }
 }
 

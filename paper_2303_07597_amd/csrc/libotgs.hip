@@ -7,5 +7,6 @@
 #include "inspect.hip"
 #include "api.hip"
 #include "plan_static.hip"
+#include "transport.hip"
 #include "mlp.hip"
 #include "api_ws.hip"

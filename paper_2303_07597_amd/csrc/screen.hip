@@ -54,6 +54,7 @@ struct ScreenArgs {
   long long* block_counters; // [screen blocks][CNT_NUM]
   const int* inst_mode;      // EvalMode per instance
   int use_lower;             // build N at snapshot refreshes
+  const float* cmax_w;       // per instance max |c| of a re-centred cost (NULL: InstDev cmax)
 };
 
 // Per-group float64 statistics of alpha - alpha~ (and max |alpha|, |alpha~|);
@@ -161,7 +162,7 @@ __global__ void __launch_bounds__(SCREEN_TILES * 64) k_screen_pairs(ScreenArgs A
       const InstDev* Ip = A.inst + d.inst;
       const int grp_off = Ip->grp_off, nt = Ip->nt, pair_off = Ip->pair_off;
       const int nt_pad = Ip->nt_pad, col_off = Ip->col_off;
-      const float ithr = Ip->thr, cmax = Ip->cmax;
+      const float ithr = Ip->thr, cmax = A.cmax_w ? A.cmax_w[d.inst] : Ip->cmax;
       tile_off = Ip->tile_off;
       njb = Ip->njb;
       mode = A.inst_mode[d.inst];

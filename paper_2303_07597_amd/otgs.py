@@ -61,7 +61,7 @@ class ot_gs_options(ct.Structure):
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
                 ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
                 ("gtol", ct.c_double), ("obj_trace", ct.c_void_p), ("time_trace", ct.c_void_p),
-                ("use_graph", ct.c_int), ("verify", ct.c_int)]
+                ("use_graph", ct.c_int), ("verify", ct.c_int), ("recenter", ct.c_int), ("fused_step", ct.c_int)]
 
 
 class ot_gs_info(ct.Structure):
@@ -110,6 +110,9 @@ def _load():
     lib.ot_gs_tile_config.argtypes = [vp, i, i, i]
     lib.ot_gs_get_tile_config.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.ot_gs_check.argtypes = [vp, vp]
+    lib.ot_gs_workspace_size.argtypes = [ct.POINTER(ot_gs_problem), i, i, ct.POINTER(ct.c_size_t), vp]
+    lib.ot_gs_create_ws.argtypes = [ct.POINTER(ot_gs_problem), i, i, vp, ct.c_size_t, ct.POINTER(vp), vp]
+    lib.ot_gs_transport.argtypes = [vp, vp, vp, vp, i, vp, vp]
     lib.ot_gs_screen_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
@@ -184,6 +187,14 @@ def problem_array(problems):
     return arr, n_src, n_tgt
 
 
+def workspace_size(problems, max_hist=10, stream=None):
+    """Device bytes a handle of these problems needs in a caller workspace."""
+    arr, _, _ = problem_array(problems)
+    nb = ct.c_size_t()
+    _check(lib().ot_gs_workspace_size(arr, len(problems), int(max_hist), ct.byref(nb), _stream(stream)))
+    return nb.value
+
+
 def features(problems, scales, F, stream=None):
     """Warm-start features of the problems into F (float32 cuda
     [sum n_src + sum n_tgt, dim + 8]); scales: per-instance cost scales."""
@@ -245,13 +256,21 @@ class Handle:
     [n_src, n_tgt]) or x_src / x_tgt (float32 cuda) with cost_mode; optional
     a, b, cost_scale.  Tensors are referenced only during creation."""
 
-    def __init__(self, problems, stream=None):
+    def __init__(self, problems, stream=None, workspace=None, max_hist=10):
+        """workspace: None (the library allocates), or a cuda uint8 tensor of
+        at least workspace_size(problems, max_hist) bytes that the handle
+        keeps its device memory in (the tensor must outlive the handle)."""
         if isinstance(problems, dict):
             problems = [problems]
         arr, self.n_src, self.n_tgt = problem_array(problems)
         n = len(problems)
         h = ct.c_void_p()
-        _check(lib().ot_gs_create(arr, n, ct.byref(h), _stream(stream)))
+        if workspace is None:
+            _check(lib().ot_gs_create(arr, n, ct.byref(h), _stream(stream)))
+        else:
+            _check(lib().ot_gs_create_ws(arr, n, int(max_hist), _ptr(workspace), workspace.numel(), ct.byref(h),
+                                         _stream(stream)))
+        self.workspace = workspace
         self.h = h
         self.count = n
 
@@ -341,6 +360,14 @@ class Handle:
         _check(lib().ot_gs_screen_state(self.h, _ptr(a), _ptr(b), _ptr(z), _ptr(o), _ptr(n), _stream(stream)))
         return a, b, z[:npairs], o[:npairs], n[:npairs]
 
+    def transport(self, alpha, beta, x_src, stream=None):
+        """Barycentric mapping y_j = (1/b_j) sum_i T_ij x_i of the source
+        features x_src (cuda [sum n_src, dim]) onto the targets."""
+        y = torch.empty((sum(self.n_tgt), x_src.shape[1]), dtype=torch.float32, device=x_src.device)
+        _check(lib().ot_gs_transport(self.h, _ptr(alpha), _ptr(beta), _ptr(x_src), int(x_src.shape[1]), _ptr(y),
+                                     _stream(stream)))
+        return y
+
     def cost(self, C_out, stream=None):
         _check(lib().ot_gs_cost(self.h, _ptr(C_out), _stream(stream)))
 
@@ -400,5 +427,6 @@ EXPORTED = [
     "ot_gs_mlp_get_params", "ot_gs_mlp_forward", "ot_gs_mlp_loss_grad", "ot_gs_mlp_train",
     "ot_gs_features", "ot_gs_cost_scale", "ot_gs_warm_start",
     "ot_gs_autotune", "ot_gs_tile_config", "ot_gs_get_tile_config", "ot_gs_check", "ot_gs_screen_state",
+    "ot_gs_transport", "ot_gs_workspace_size", "ot_gs_create_ws",
     "ot_gs_plan_csr",
 ]

@@ -34,7 +34,7 @@ def test_grid_points_origin_equals_ours(n_classes, g):
     h = O.Handle([dict(labels=_dev(i["labels"]), n_groups=n_classes, gamma=i["gamma"], mu=i["mu"],
                        x_src=_dev(i["xs"]), x_tgt=_dev(i["xt"]), cost_mode=O.OT_GS_COST_MATERIALIZE,
                        cost_scale=0.0) for i in insts])
-    K = 1500
+    K = 8000
     runs = []
     for scr, low in ((0, 1), (1, 1), (1, 0)):
         tr = torch.full((len(grid) * (K + 1),), float("nan"), dtype=torch.float64, device="cuda")
