@@ -211,15 +211,12 @@ typedef struct {
                              cost fl32(c_ij - ref_i - ref_j) (a working copy of the
                              cost, allocated by the first such solve) and D plus
                              a.ref_alpha + b.ref_beta; at most 8 times per
-                             instance, each after a gain.  0: stop there (status
+                             instance, the second and later ones only after a
+                             gain of D above 1e-9 |D| since the previous one
+                             (below that the solve has reached the float32
+                             floor).  0: stop there (status
                              OT_GS_LINESEARCH).  A re-centred solve leaves the
                              handle with the zero snapshot.                      */
-    int fused_step;       /* 1 (default): instances with at most 8192 dual variables
-                             (n_src + n_tgt rounded up to 32) run the dot products,
-                             control step and update of a solver step in one
-                             workgroup (hist <= 12); 0: three kernels for every
-                             instance.  The same iterates up to the order of the
-                             float64 dot sums.                                   */
 } ot_gs_options;
 
 /* Fills `o` with the defaults listed above. */

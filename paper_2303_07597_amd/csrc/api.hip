@@ -110,6 +110,7 @@ struct ot_gs_handle {
   } ver;
   float *a_int = nullptr, *b_int = nullptr;
   int *a_uniform = nullptr, *b_uniform = nullptr;
+  std::vector<int> w_unit_h;   // per instance: every variable scale is 1 (uniform a, b and n_src = n_tgt)
   float *alpha = nullptr, *beta = nullptr, *ga = nullptr, *gb = nullptr;
   float *alpha_s = nullptr, *beta_s = nullptr, *zsnap = nullptr, *osnap = nullptr;
   float *rowpart = nullptr, *colsum = nullptr, *part = nullptr, *kappa = nullptr;
@@ -143,10 +144,10 @@ struct ot_gs_handle {
   // solver buffers (allocated by the first solve)
   struct Solver {
     int hist = 0, maxb = 0, ndot = 0, cap_hist = 0;
-    int n_small = 0;   // instances whose whole step runs in one workgroup
     long long vtot = 0;
     long long* voff = nullptr;
     float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr, *W = nullptr;
+    int* w_unit = nullptr;   // [count]: every scale of the instance is 1 (loads of W skipped)
     LbState* st = nullptr;
     double* gram = nullptr;
     double* part = nullptr;
@@ -158,7 +159,6 @@ struct ot_gs_handle {
   } sol;
   Timing timing;
   bool has_snapshot = false;
-  bool step1 = true;   // solver steps of small instances in one workgroup (ot_gs_solve option)
   hipStream_t cap_stream = nullptr;   // stream that records solver steps into a graph
   // tile configuration (autotuned or set): per bucket of the tile lists the
   // team-shape variant (on-the-fly) and the grid multiplier (workgroups per
@@ -963,6 +963,7 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
       hb[k] = probs[k].b;
       ua[k] = probs[k].a == nullptr;
       ub[k] = probs[k].b == nullptr;
+      h->w_unit_h.push_back(ua[k] && ub[k] && h->inst[k].d.ns == h->inst[k].d.nt);
       maxn = std::max(maxn, std::max(h->inst[k].d.ns, h->inst[k].d.nt_pad));
     }
     HIPCHK(hipMemcpyAsync(da, ha.data(), sizeof(void*) * count, hipMemcpyHostToDevice, s));
@@ -1971,7 +1972,6 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->use_graph = 1;
   o->verify = 0;
   o->recenter = 1;
-  o->fused_step = 1;
 }
 
 }  // extern "C"
@@ -2023,6 +2023,7 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   TRY(al((void**)&V.voff, sizeof(long long) * h->count));
   TRY(al((void**)&V.X, sizeof(float) * acc));
   TRY(al((void**)&V.W, sizeof(float) * acc));
+  TRY(al((void**)&V.w_unit, sizeof(int) * h->count));
   TRY(al((void**)&V.G, sizeof(float) * acc));
   TRY(al((void**)&V.Dv, sizeof(float) * acc));
   TRY(al((void**)&V.S, sizeof(float) * acc * hist));
@@ -2036,6 +2037,7 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   HIPCHK(hipHostMalloc((void**)&V.h_active, 2 * sizeof(int), hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(V.n_active, 0, 2 * sizeof(int), s));
   HIPCHK(hipMemcpyAsync(V.voff, voff.data(), sizeof(long long) * h->count, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(V.w_unit, h->w_unit_h.data(), sizeof(int) * h->count, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(V.st, 0, sizeof(LbState) * h->count, s));
   HIPCHK(hipMemsetAsync(V.S, 0, sizeof(float) * acc * hist, s));
   HIPCHK(hipMemsetAsync(V.Y, 0, sizeof(float) * acc * hist, s));
@@ -2087,11 +2089,8 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.max_le = h->max_le;
   A.batched = h->count > 1;
   A.W = V.W;
+  A.w_unit = V.w_unit;
   A.n_recenter = V.n_active + 1;
-  A.step1_max = (P.hist <= STEP1_HMAX && h->step1) ? STEP1_MAX : 0;
-  V.n_small = 0;
-  for (int k = 0; k < h->count; ++k)
-    if (A.step1_max && h->inst[k].d.ns + h->inst[k].d.nt_pad <= A.step1_max) ++V.n_small;
   if (P.recenter) {
     A.xref = V.xref;
     A.obj_const = V.obj_const;
@@ -2134,18 +2133,6 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
   const long long maxv = h->max_ns + h->max_ntp;
-  // instances with short vectors: the whole step in one workgroup each
-  if (A.step1_max && h->sol.n_small > 0) {
-    if (upd)
-      hipLaunchKernelGGL(k_lbfgs_step1<true>, dim3(h->count), dim3(STEP1_THREADS), 0, s, A);
-    else
-      hipLaunchKernelGGL(k_lbfgs_step1<false>, dim3(h->count), dim3(STEP1_THREADS), 0, s, A);
-    LAUNCHCHK();
-    if (h->sol.n_small == h->count) {
-      TRY(tend(h, KT_LBFGS, s, e0));
-      return OT_GS_OK;
-    }
-  }
   // batches with long vectors: LB_SEQ_SPLIT wavefronts per vector block
   // loop over the history slots (g~ and d read LB_SEQ_SPLIT times instead of
   // once per slot); otherwise one wavefront per (block, slot)
@@ -2222,7 +2209,6 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   P.obj_trace = o.obj_trace;
   P.time_trace = o.time_trace;
   P.recenter = (o.recenter && !h->onthefly) ? 1 : 0;
-  h->step1 = o.fused_step != 0;
   if (P.recenter) {
     // the evaluations of this solve read a working copy of the pool, which
     // re-centrings rewrite; its cost bounds start as max C

@@ -115,16 +115,13 @@ struct LbArgs {
   int max_le;               // most groups of an instance
   int batched;              // more than one instance: finished ones skip their update
   const float* W;           // [vtot] variable scales w (actual = w * scaled)
+  const int* w_unit;        // [count] 1: every scale of the instance is 1 (W is not read)
   // re-centred solves (see k_recenter_vec): the evaluations see the point
   // relative to a reference xref (actual variables, float64) through the
   // reduced cost c_ij - xref_i - xref_j; D adds obj_const = a.xref_a + b.xref_b
   double* xref;             // [vtot] or NULL
   double* obj_const;        // [count]
   int* n_recenter;          // instances waiting for a re-centring
-  // instances with at most step1_max vector elements run the whole step in
-  // one workgroup (k_lbfgs_step1); the three-kernel path skips them.  0: no
-  // instance does
-  int step1_max;
 };
 
 // An instance whose solve has ended and whose last control step accepted no
@@ -202,7 +199,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   const int st_status = S.status, st_phase = S.phase, st_count = S.count;
   const int n = I.ns + I.nt_pad;
   if (b * LB_VB >= n) return;           // beyond this instance: ctrl reads no such partial
-  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
+  const bool wu = A.w_unit[k] != 0;
   const bool run = st_status == LB_RUNNING;
   const int cnt = (run && st_phase != 0) ? st_count : 0;
   const int slot = z - 1;
@@ -221,7 +218,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
     const bool ok = e < n && run;
     const float g0 = ok ? lb_gt(A, I, e) : 0.f;
     gm = fmaxf(gm, fabsf(g0));
-    gt[q] = ok ? g0 * A.W[v0 + e] : 0.f;
+    gt[q] = ok ? (wu ? g0 : g0 * A.W[v0 + e]) : 0.f;
     if (z == 0) {
       v1[q] = ok ? A.G[v0 + e] : 0.f;    // G
       v2[q] = ok ? A.Dv[v0 + e] : 0.f;   // d
@@ -256,7 +253,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots_seq(LbArgs A) {
   const int st_status = S.status, st_phase = S.phase, st_count = S.count;
   const int n = I.ns + I.nt_pad;
   if (b * LB_VB >= n) return;
-  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
+  const bool wu = A.w_unit[k] != 0;
   const bool run = st_status == LB_RUNNING;
   const int cnt = (run && st_phase != 0) ? st_count : 0;
   const int sc1 = min(cnt, sl1);   // slots [sl0, sc1) hold pairs, [max(sl0, cnt), sl1) are zeros
@@ -278,7 +275,7 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots_seq(LbArgs A) {
     const bool ok = e < n && run;
     const float g0 = ok ? lb_gt(A, I, e) : 0.f;
     gm = fmaxf(gm, fabsf(g0));
-    gt[q] = ok ? g0 * A.W[v0 + e] : 0.f;
+    gt[q] = ok ? (wu ? g0 : g0 * A.W[v0 + e]) : 0.f;
     g[q] = (ok && z == 0) ? A.G[v0 + e] : 0.f;
     dv[q] = ok ? A.Dv[v0 + e] : 0.f;
   }
@@ -571,10 +568,11 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
         if (l0) atomicAdd(A.n_active, 1);
         return;
       }
-      if (P.recenter && S.n_rec < RECENTER_MAX && S.f_rec - S.f > 1e-12 * fabs(S.f)) {
+      if (P.recenter && S.n_rec < RECENTER_MAX && S.f_rec - S.f > 1e-9 * fabs(S.f)) {
         // the search ran out of float32 resolution around the point: ask
         // for a re-centring there (the host launches it between steps) and
-        // continue from it with a fresh memory
+        // continue from it with a fresh memory; a later one only after the
+        // objective has gained more than its rounding floor since the last
         S.f_rec = S.f;
         S.n_rec++;
         S.status = LB_RECENTER;
@@ -670,7 +668,6 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   __shared__ double gram_s[2 * HMAX * HMAX];
   const int k = blockIdx.x;
   const int h = A.P.hist;
-  if (A.step1_max && A.inst[k].ns + A.inst[k].nt_pad <= A.step1_max) return;   // k_lbfgs_step1's
   double* gram_g = A.gram + (size_t)k * 2 * h * h;
   // Every load of the step is issued at once, before any is used: the
   // state, the Gram matrices, the first PD block partials of the lane's dot
@@ -774,13 +771,13 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
 // trial point; returns the new trial value and, in snap_out, alpha~ after
 // this step
 __device__ __forceinline__ float lb_update_elem(const LbArgs& A, const InstDev& I, const LbState& S, int e,
-                                                long long v0, int h, bool snap, float& snap_out) {
+                                                long long v0, int h, bool snap, bool wu, float& snap_out) {
   float* tp = e < I.ns ? &A.alpha[I.row_off + e] : &A.beta[I.col_off + (e - I.ns)];
   float* sp = e < I.ns ? &A.alpha_s[I.row_off + e] : &A.beta_s[I.col_off + (e - I.ns)];
   const float told = *tp;
   if (snap) *sp = told;   // the point just evaluated densely becomes the snapshot
   snap_out = snap ? told : *sp;
-  const float w = A.W[v0 + e];
+  const float w = wu ? 1.f : A.W[v0 + e];
   float x = A.X[v0 + e];
   if (S.accept) {
     const float gt = lb_gt(A, I, e) * w;
@@ -819,11 +816,11 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const long long v0 = A.voff[k];
   const int h = A.P.hist;
   const bool snap = S.mode_eval == EM_SNAPSHOT;
-  if (A.step1_max && n <= A.step1_max) return;   // k_lbfgs_step1's
+  const bool wu = A.w_unit[k] != 0;
   if (lb_update_idle(A, S)) return;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
     float so;
-    lb_update_elem(A, I, S, e, v0, h, snap, so);
+    lb_update_elem(A, I, S, e, v0, h, snap, wu, so);
   }
 }
 
@@ -845,15 +842,15 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   const long long v0 = A.voff[k];
   const int h = A.P.hist;
   const bool snap = S.mode_eval == EM_SNAPSHOT;
+  const bool wu = A.w_unit[k] != 0;
   const int bx = blockIdx.x;
   if (bx == 0 && k == 0 && threadIdx.x < NBUCKET + 2) A.counts[threadIdx.x] = 0;
-  if (A.step1_max && I.ns + I.nt_pad <= A.step1_max) return;   // k_lbfgs_step1's
   if (lb_update_idle(A, S)) return;
   if (bx >= A.max_le) {
     const int c = (bx - A.max_le) * GT + threadIdx.x;
     if (c < I.nt_pad) {
       float so;
-      lb_update_elem(A, I, S, I.ns + c, v0, h, snap, so);
+      lb_update_elem(A, I, S, I.ns + c, v0, h, snap, wu, so);
     }
     return;
   }
@@ -863,7 +860,7 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
   double up = 0, dn = 0, am = 0, ams = 0;
   for (int q = threadIdx.x; q < n; q += blockDim.x) {
     float as;
-    const double a = lb_update_elem(A, I, S, r0 + q, v0, h, snap, as);
+    const double a = lb_update_elem(A, I, S, r0 + q, v0, h, snap, wu, as);
     const double d = a - (double)as;
     if (d > 0) up += d * d; else dn += d * d;
     am = fmax(am, fabs(a));
@@ -883,173 +880,6 @@ __global__ void __launch_bounds__(GT) k_lbfgs_update_gs(LbArgs A) {
       const int m = A.inst_mode[k];
       if (m != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
       if (m == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
-    }
-  }
-}
-
-// ------------------------------------------------------------ one-workgroup step
-// An instance with at most STEP1_MAX vector elements (and a history of at
-// most STEP1_HMAX pairs) runs its whole solver step in one workgroup, which
-// needs no device-wide ordering between its parts: every dot product (each
-// thread its elements, fixed-order wavefront trees, then the wavefronts in
-// order), the control step on wavefront 0 (the state and Gram matrices in
-// LDS), the vector update, and - in screened solves whose groups have at
-// most CHUNK rows - the next evaluation's per-group statistics (wavefront
-// w takes groups w, w + 8, ..., from the new point and snapshot kept in
-// LDS).  One launch for a batch of instances replaces the dots, control and
-// update kernels (three launches, each a chain of dependent memory round
-// trips).  The dot sums run in another order than the three-kernel path's,
-// so the two paths differ in the last bits; a given instance always takes
-// the same one.
-constexpr int STEP1_THREADS = 512;
-constexpr int STEP1_MAX = 8192;
-constexpr int STEP1_PER = STEP1_MAX / STEP1_THREADS;
-constexpr int STEP1_HMAX = 12;
-
-template <bool GS>
-__global__ void __launch_bounds__(STEP1_THREADS) k_lbfgs_step1(LbArgs A) {
-  constexpr int NW = STEP1_THREADS / 64;
-  constexpr int ND = 5 + 3 * STEP1_HMAX;
-  __shared__ double red[NW][ND];
-  __shared__ double dots[5 + 3 * HMAX];
-  __shared__ LbState S;
-  __shared__ double gram_s[2 * STEP1_HMAX * STEP1_HMAX];
-  __shared__ float a_new[GS ? STEP1_MAX : 1];
-  __shared__ float a_snap[GS ? STEP1_MAX : 1];
-  const int k = blockIdx.x;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const InstDev I = A.inst[k];
-  const int n = I.ns + I.nt_pad;
-  if (GS && k == 0 && t < NBUCKET + 2) A.counts[t] = 0;
-  if (n > A.step1_max) return;   // the three-kernel path's
-  const long long v0 = A.voff[k];
-  const int h = A.P.hist;
-  {
-    // ---- dot products of the trial gradient (scaled variables)
-    const LbState& Sg = A.st[k];
-    const bool run = Sg.status == LB_RUNNING;
-    const int cnt = (run && Sg.phase != 0) ? Sg.count : 0;
-    double acc[ND - 1];
-#pragma unroll
-    for (int j = 0; j < ND - 1; ++j) acc[j] = 0.0;
-    float gm = 0.f;
-    if (run) {
-      for (int m = 0; m < STEP1_PER; ++m) {
-        const int e = t + m * STEP1_THREADS;
-        if (e >= n) break;
-        const float g0 = lb_gt(A, I, e);
-        gm = fmaxf(gm, fabsf(g0));
-        const double gt = (double)(g0 * A.W[v0 + e]);
-        const double Gv = (double)A.G[v0 + e], dv = (double)A.Dv[v0 + e];
-        acc[0] += gt * dv;
-        acc[1] += gt * gt;
-        acc[2] += gt * Gv;
-        acc[3] += dv * dv;
-#pragma unroll
-        for (int i = 0; i < STEP1_HMAX; ++i) {
-          if (i < cnt) {
-            const double sv = (double)A.S[(size_t)i * A.vtot + v0 + e];
-            const double yv = (double)A.Y[(size_t)i * A.vtot + v0 + e];
-            acc[4 + 3 * i] += gt * sv;
-            acc[5 + 3 * i] += gt * yv;
-            acc[6 + 3 * i] += dv * yv;
-          }
-        }
-      }
-    }
-    // slot j of red: dots 0..3, max |grad D| (4), then 5 + 3 i ... as the
-    // three-kernel path numbers them
-#pragma unroll
-    for (int j = 0; j < ND - 1; ++j) {
-      if (j < 4 + 3 * cnt) {
-        const double v = wave_sum_dd(acc[j]);
-        if (lane == 0) red[wv][j < 4 ? j : j + 1] = v;
-      }
-    }
-    const double g4 = wave_max_d((double)gm);
-    if (lane == 0) red[wv][4] = g4;
-    __syncthreads();
-    if (t < 5 + 3 * h) {
-      double v = 0.0;
-      if (t < 5 + 3 * cnt) {
-        for (int w = 0; w < NW; ++w) v = t == 4 ? fmax(v, red[w][t]) : v + red[w][t];
-      }
-      dots[t] = v;
-    }
-  }
-  // ---- control step on wavefront 0 (state and Gram matrices copied to LDS
-  // by every thread first)
-  {
-    constexpr int NV = (int)(sizeof(LbState) / 16);
-    const int4* src = (const int4*)&A.st[k];
-    int4* dst = (int4*)&S;
-    for (int i = t; i < NV; i += STEP1_THREADS) dst[i] = src[i];
-    const double* gram_g = A.gram + (size_t)k * 2 * h * h;
-    for (int q = t; q < 2 * h * h; q += STEP1_THREADS) gram_s[q] = gram_g[q];
-  }
-  __syncthreads();
-  if (wv == 0) {
-    const int nob = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
-    const double* osrc = A.obj_part + (size_t)k * A.obj_stride;
-    double os = 0.0;
-    for (int i = lane; i < nob; i += 64) os += osrc[i];
-    const double Dobj = wave_sum_dd(os) + (A.obj_const ? A.obj_const[k] : 0.0);
-    if (lane == 0) A.obj_out[k] = Dobj;
-    LbGram G{gram_s, gram_s + h * h, h};
-    lb_ctrl_logic(A, k, S, G, dots, Dobj);
-    __builtin_amdgcn_wave_barrier();
-    double* gram_g = A.gram + (size_t)k * 2 * h * h;
-    for (int q = lane; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
-    constexpr int NV = (int)(sizeof(LbState) / 16);
-    const int4* src = (const int4*)&S;
-    int4* dst = (int4*)&A.st[k];
-    for (int i = lane; i < NV; i += 64) dst[i] = src[i];
-  }
-  __syncthreads();
-  // ---- vector update (and the group statistics)
-  if (lb_update_idle(A, S)) return;
-  const bool snap = S.mode_eval == EM_SNAPSHOT;
-  for (int m = 0; m < STEP1_PER; ++m) {
-    const int e = t + m * STEP1_THREADS;
-    if (e >= n) break;
-    float so;
-    const float xa = lb_update_elem(A, I, S, e, v0, h, snap, so);
-    if (GS && e < I.ns) {
-      a_new[e] = xa;
-      a_snap[e] = so;
-    }
-  }
-  if (!GS) return;
-  __syncthreads();
-  for (int ge = wv; ge < I.Le; ge += NW) {
-    const int gidx = I.grp_off + ge;
-    const int r0 = A.g_start[gidx], gn = A.g_size[gidx];
-    double up = 0, dn = 0, am = 0, ams = 0;
-    for (int q = lane; q < gn; q += 64) {
-      const double a = a_new[r0 + q], as = a_snap[r0 + q];
-      const double d = a - as;
-      if (d > 0) up += d * d; else dn += d * d;
-      am = fmax(am, fabs(a));
-      ams = fmax(ams, fabs(as));
-    }
-    up = wave_sum_dd(up);
-    dn = wave_sum_dd(dn);
-    am = wave_max_d(am);
-    ams = wave_max_d(ams);
-    if (lane == 0) {
-      GroupStats g;
-      g.up = sqrt(up);
-      g.dn = sqrt(dn);
-      g.all = sqrt(up + dn);
-      g.amax = am;
-      g.amax_s = ams;
-      screen_group_consts(gn, g.sg, g.fa, g.fb);
-      A.gstats[gidx] = g;
-      if (ge == 0) {
-        const int md = A.inst_mode[k];
-        if (md != EM_SKIP) atomicAdd((unsigned long long*)&A.counters[CNT_EVALS], 1ull);
-        if (md == EM_SNAPSHOT) atomicAdd((unsigned long long*)&A.counters[CNT_REFRESH], 1ull);
-      }
     }
   }
 }

@@ -49,33 +49,77 @@ struct GemmArgs {
   const float* Zin;    // EPI_GELU_GRAD: C = (A B) GELU'(Zin)
 };
 
-// 64 x 64 output tile per workgroup of four wavefronts (32 x 32 each).
+// 64 x 64 output tile per workgroup of four wavefronts (32 x 32 each), K
+// in steps of 32 staged through LDS.  Each step the 256 threads load the
+// 64 x 32 slices of A and B along whichever index is contiguous in memory
+// (so the loads coalesce for plain and transposed operands alike), round
+// them to bfloat16 and store them in the matrix-core operand layout (k
+// contiguous per row of A and per column of B, rows padded against bank
+// conflicts); each wavefront then reads 16-byte fragments and issues two
+// v_mfma_f32_32x32x16_bf16.  The MFMA sequence over k is the same as a
+// direct 16-step loop, so the results do not depend on the staging.
+constexpr int GK = 32;          // K per LDS step
+constexpr int GLD = GK + 8;     // padded row length (bf16) of an LDS tile
+
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = blockIdx.y * 64 + 32 * (w >> 1), j0 = blockIdx.x * 64 + 32 * (w & 1);
+  __shared__ short As[64 * GLD];
+  __shared__ short Bs[64 * GLD];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
+  const int i0 = 32 * (w >> 1), j0 = 32 * (w & 1);   // the wavefront's sub-tile in the block
   const int ka = blockIdx.z * g.kchunk, kb = min(ka + g.kchunk, g.K);
-  const int r = i0 + (lane & 31), c = j0 + (lane & 31), ko = 8 * (lane >> 5);
-  const bool rok = r < g.M, cok = c < g.N;
-  const float* Ar = g.A + (long long)(rok ? r : 0) * g.a_rs;
-  const float* Bc = g.B + (long long)(cok ? c : 0) * g.b_cs;
+  const bool a_krow = g.a_cs == 1;   // A(i, k): k contiguous
+  const bool b_kcol = g.b_rs == 1;   // B(k, j): k contiguous
   floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int k = ka; k < kb; k += 16) {
-    shortx8 av, bv;
+  for (int k0 = ka; k0 < kb; k0 += GK) {
+    // ---- stage A[bi .. bi+63][k0 .. k0+31] and B[k0 ..][bj .. bj+63]
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kk = k + ko + t;
-      const bool kok = kk < kb;
-      av[t] = bf16_bits((rok && kok) ? Ar[(long long)kk * g.a_cs] : 0.f);
-      bv[t] = bf16_bits((cok && kok) ? Bc[(long long)kk * g.b_rs] : 0.f);
+    for (int u = 0; u < 8; ++u) {
+      // A: each load instruction covers 32 consecutive k of 8 rows, or 64
+      // consecutive rows of one k, whichever runs along memory
+      int ra, kaa;
+      if (a_krow) {
+        ra = (t >> 5) + 8 * u;
+        kaa = t & 31;
+      } else {
+        ra = t & 63;
+        kaa = (t >> 6) + 4 * u;
+      }
+      const int gr = bi + ra, gk = k0 + kaa;
+      const float va = (gr < g.M && gk < kb) ? g.A[(long long)gr * g.a_rs + (long long)gk * g.a_cs] : 0.f;
+      As[ra * GLD + kaa] = bf16_bits(va);
+      int cb, kbb;
+      if (b_kcol) {
+        cb = (t >> 5) + 8 * u;
+        kbb = t & 31;
+      } else {
+        cb = t & 63;
+        kbb = (t >> 6) + 4 * u;
+      }
+      const int gc = bj + cb, gk2 = k0 + kbb;
+      const float vb = (gc < g.N && gk2 < kb) ? g.B[(long long)gk2 * g.b_rs + (long long)gc * g.b_cs] : 0.f;
+      Bs[cb * GLD + kbb] = bf16_bits(vb);
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                  __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+    __syncthreads();
+    // ---- two 16-deep products from LDS fragments (lane: row / column
+    // lane & 31, k offset 8 (lane >> 5))
+#pragma unroll
+    for (int h = 0; h < GK / 16; ++h) {
+      const int ko = 16 * h + 8 * (lane >> 5);
+      const shortx8 av = *reinterpret_cast<const shortx8*>(&As[(i0 + (lane & 31)) * GLD + ko]);
+      const shortx8 bv = *reinterpret_cast<const shortx8*>(&Bs[(j0 + (lane & 31)) * GLD + ko]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                    __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+    }
+    __syncthreads();
   }
+  const int c = bj + j0 + (lane & 31);
+  const bool cok = c < g.N;
   float* C = g.C + (EPI == EPI_STORE ? (long long)blockIdx.z * g.part_stride : 0);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int row = i0 + 8 * (q / 4) + 4 * (lane >> 5) + (q % 4);
+    const int row = bi + i0 + 8 * (q / 4) + 4 * (lane >> 5) + (q % 4);
     if (row >= g.M || !cok) continue;
     const long long e = (long long)row * g.ldc + c;
     if (EPI == EPI_STORE) {

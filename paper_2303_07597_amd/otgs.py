@@ -61,7 +61,7 @@ class ot_gs_options(ct.Structure):
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
                 ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
                 ("gtol", ct.c_double), ("obj_trace", ct.c_void_p), ("time_trace", ct.c_void_p),
-                ("use_graph", ct.c_int), ("verify", ct.c_int), ("recenter", ct.c_int), ("fused_step", ct.c_int)]
+                ("use_graph", ct.c_int), ("verify", ct.c_int), ("recenter", ct.c_int)]
 
 
 class ot_gs_info(ct.Structure):
