@@ -60,6 +60,11 @@ class _Opts(ct.Structure):
                 ("c1", ct.c_double), ("c2", ct.c_double), ("gtol", ct.c_double), ("nthreads", ct.c_int)]
 
 
+class _AgdOpts(ct.Structure):
+    _fields_ = [("max_iter", ct.c_int), ("r", ct.c_int), ("use_screen", ct.c_int), ("use_lower", ct.c_int),
+                ("max_bt", ct.c_int), ("gtol", ct.c_double), ("shrink", ct.c_double), ("momentum", ct.c_int)]
+
+
 class _Info(ct.Structure):
     _fields_ = [("iters", ct.c_int), ("evals", ct.c_int), ("status", ct.c_int),
                 ("obj", ct.c_double), ("gnorm_inf", ct.c_double),
@@ -94,6 +99,7 @@ def lib():
         _lib.orc_extract.argtypes = [P, ct.POINTER(_State), _dp, _dp]
         _lib.orc_snapshot.argtypes = [P, ct.POINTER(_State), _dp, _dp]
         _lib.orc_solve.argtypes = [P, ct.POINTER(_Opts), _dp, _dp, ct.POINTER(_Info), _dp]
+        _lib.orc_agd_solve.argtypes = [P, ct.POINTER(_AgdOpts), _dp, _dp, ct.POINTER(_Info), _dp]
         _lib.orc_cost_sqeuclid.argtypes = [ct.c_int, ct.c_int, ct.c_int, _dp, _dp, _dp]
     return _lib
 
@@ -243,6 +249,27 @@ def solve(P: Problem, max_iter=200, hist=10, r=10, use_screen=False, use_lower=T
     info = _Info()
     trace = np.full(max_iter + 1, np.nan)
     rc = lib().orc_solve(P.ref, ct.byref(opts), _ptr(al), _ptr(be), ct.byref(info), _ptr(trace))
+    assert rc == 0
+    n = info.iters + 1
+    return dict(alpha=al, beta=be, obj=info.obj, trace=trace[:n], iters=info.iters,
+                evals=info.evals, status=info.status, gnorm_inf=info.gnorm_inf,
+                s_i=info.s_i, s_n=info.s_n, s_u=info.s_u, s_r=info.s_r)
+
+
+def agd_solve(P: Problem, max_iter=2000, r=10, use_screen=False, use_lower=True, max_bt=60, gtol=0.0,
+              shrink=0.8, alpha0=None, beta0=None, momentum=True):
+    """Accelerated gradient ascent on the dual (momentum with backtracking
+    and function-value restart, in marginal-scaled variables) from (alpha0,
+    beta0), zeros by default; with use_screen, Algorithm 1's snapshots and
+    set N around it.  Returns the dict of ``solve``; ``trace[k]`` is D after
+    k accepted steps."""
+    al = _d(np.zeros(P.ns) if alpha0 is None else alpha0).copy()
+    be = _d(np.zeros(P.nt) if beta0 is None else beta0).copy()
+    opts = _AgdOpts(int(max_iter), int(r), int(bool(use_screen)), int(bool(use_lower)), int(max_bt),
+                    float(gtol), float(shrink), int(bool(momentum)))
+    info = _Info()
+    trace = np.full(max_iter + 1, np.nan)
+    rc = lib().orc_agd_solve(P.ref, ct.byref(opts), _ptr(al), _ptr(be), ct.byref(info), _ptr(trace))
     assert rc == 0
     n = info.iters + 1
     return dict(alpha=al, beta=be, obj=info.obj, trace=trace[:n], iters=info.iters,

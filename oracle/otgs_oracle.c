@@ -35,6 +35,15 @@
  *   orc_solve          - Algorithm 1 driving limited-memory BFGS (Liu and
  *                        Nocedal) with a strong-Wolfe line search; with
  *                        screening off it is the original dense method.
+ *   orc_agd_solve      - Algorithm 1 driving another first-order solver
+ *                        (the screening's solver-independence, Theorem 1
+ *                        and its remark in Sec. 3.4): accelerated gradient
+ *                        ascent (Nesterov's momentum in the FISTA form of
+ *                        Beck and Teboulle) with backtracking on the
+ *                        step and the function-value restart of
+ *                        O'Donoghue and Candes, in variables scaled by the
+ *                        marginals.  The paper fixes no such solver; its
+ *                        steps are stated with the function.
  */
 #include <math.h>
 #include <omp.h>
@@ -642,5 +651,148 @@ int orc_solve(const orc_problem *P, const orc_solve_opts *o, double *alpha, doub
     free(S.alpha_s); free(S.beta_s); free(S.Zs); free(S.Os); free(S.Ks); free(S.inN);
     free(E.ga); free(E.gb); free(x); free(g); free(d); free(xt); free(gt); free(q);
     free(sk); free(yk); free(rho); free(al);
+    return 0;
+}
+
+/* ------------------------------- accelerated gradient ascent (maximises D) */
+
+typedef struct {
+    int max_iter;       /* accepted steps */
+    int r;              /* snapshot / N refresh period (Algorithm 1) */
+    int use_screen, use_lower;
+    int max_bt;         /* step halvings per iteration before giving up */
+    double gtol;        /* stop when ||grad D||_inf <= gtol at an accepted point */
+    double shrink;      /* L <- shrink L after every accepted step, in (0, 1] */
+    int momentum;       /* 0: no extrapolation (plain gradient ascent with the
+                           same step rule), for comparison */
+} orc_agd_opts;
+
+/* The method, in the variables u with x = w * u (x = [alpha; beta]),
+ * w_e = 1 / sqrt(M m_e) for the marginal m_e of entry e (1 where it is 0)
+ * and M = (n_src + n_tgt) / 2; q(u) = w * grad D(w * u) is the gradient in u.
+ *   u_0 = x_0 / w, D_0 = D(x_0), L = ||q(u_0)||_2, v = u_0, t = 1.
+ *   each iteration, with q_v = q(v) and D_v = D(w v):
+ *     trial u+ = v + q_v / L; while D(w u+) < D_v + ||q_v||^2 / (2 L):
+ *       L <- 2 L and a new trial (at most max_bt times, else stop: status 2);
+ *     if D(w u+) < D_k and v is not u_k: restart (t = 1, v = u_k) and
+ *       take the trial again from there;
+ *     else accept: u_{k+1} = u+, t' = (1 + sqrt(1 + 4 t^2)) / 2,
+ *       v = u_{k+1} + ((t - 1) / t') (u_{k+1} - u_k), t = t', L <- shrink L.
+ * Accepted objectives never decrease: a trial from u_k itself gains at
+ * least ||q||^2 / (2 L) >= 0.  With screening, every r accepted steps N is
+ * rebuilt and the snapshot refreshed at the accepted point, as Algorithm 1
+ * does for any solver. */
+int orc_agd_solve(const orc_problem *P, const orc_agd_opts *o, double *alpha, double *beta,
+                  orc_solve_info *info, double *obj_trace /* [max_iter+1] or NULL */) {
+    const int ns = P->ns, n = P->ns + P->nt;
+    size_t LN = (size_t)P->L * P->nt;
+    orc_screen_state S;
+    memset(&S, 0, sizeof S);
+    S.alpha_s = (double *)calloc((size_t)P->ns, sizeof(double));
+    S.beta_s = (double *)calloc((size_t)P->nt, sizeof(double));
+    S.Zs = (double *)calloc(LN, sizeof(double));
+    S.Os = (double *)calloc(LN, sizeof(double));
+    S.Ks = (double *)calloc(LN, sizeof(double));
+    S.inN = (unsigned char *)calloc(LN, 1);
+    evaluator_t E = {P, &S, o->use_screen, 0,
+                     (double *)malloc(sizeof(double) * (size_t)P->ns),
+                     (double *)malloc(sizeof(double) * (size_t)P->nt), 0};
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *u = (double *)malloc(sizeof(double) * n);      /* accepted point u_k */
+    double *uprev = (double *)malloc(sizeof(double) * n);
+    double *v = (double *)malloc(sizeof(double) * n);      /* extrapolated point */
+    double *ut = (double *)malloc(sizeof(double) * n);     /* trial point */
+    double *x = (double *)malloc(sizeof(double) * n);      /* w * (a point in u) */
+    double *g = (double *)malloc(sizeof(double) * n);      /* -grad D at x */
+    double *qk = (double *)malloc(sizeof(double) * n);     /* q at u_k */
+    double *qv = (double *)malloc(sizeof(double) * n);     /* q at v */
+    double *qt = (double *)malloc(sizeof(double) * n);     /* q at the trial */
+    const double M = 0.5 * ((double)P->ns + (double)P->nt);
+    for (int e = 0; e < n; ++e) {
+        double m = e < ns ? P->a[e] : P->b[e - ns];
+        w[e] = m > 0.0 ? 1.0 / sqrt(M * m) : 1.0;
+    }
+    for (int i = 0; i < ns; ++i) u[i] = alpha[i] / w[i];
+    for (int j = 0; j < P->nt; ++j) u[ns + j] = beta[j] / w[ns + j];
+    if (o->use_screen) orc_snapshot(P, &S, alpha, beta), S.s_r = 0;
+    /* value and q at a point given in u */
+#define AGD_EVAL(pt, qout, Dout)                                  \
+    do {                                                          \
+        for (int e = 0; e < n; ++e) x[e] = w[e] * (pt)[e];        \
+        (Dout) = -eval_fg(&E, x, g);                              \
+        for (int e = 0; e < n; ++e) (qout)[e] = -w[e] * g[e];     \
+    } while (0)
+    double Dk, Dv, Dt = 0.0;
+    AGD_EVAL(u, qk, Dk);
+    if (obj_trace) obj_trace[0] = Dk;
+    double L = sqrt(vdot(qk, qk, n));
+    memcpy(v, u, sizeof(double) * n);
+    memcpy(qv, qk, sizeof(double) * n);
+    Dv = Dk;
+    int at_k = 1;        /* v is u_k */
+    double t = 1.0;
+    int it = 0, status = 0;
+    while (it < o->max_iter) {
+        double ginf = 0.0;
+        for (int e = 0; e < n; ++e) ginf = fmax(ginf, fabs(qk[e] / w[e]));
+        if (ginf <= o->gtol) { status = 1; break; }
+        const double qq = vdot(qv, qv, n);
+        int bt = 0, ok = 0;
+        for (;;) {
+            for (int e = 0; e < n; ++e) ut[e] = v[e] + qv[e] / L;
+            AGD_EVAL(ut, qt, Dt);
+            if (Dt >= Dv + qq / (2.0 * L)) { ok = 1; break; }
+            if (++bt > o->max_bt) break;
+            L *= 2.0;
+        }
+        if (!ok) { status = 2; break; }
+        if (Dt < Dk && !at_k) {
+            /* function-value restart: drop the momentum, step from u_k */
+            t = 1.0;
+            memcpy(v, u, sizeof(double) * n);
+            memcpy(qv, qk, sizeof(double) * n);
+            Dv = Dk;
+            at_k = 1;
+            continue;
+        }
+        memcpy(uprev, u, sizeof(double) * n);
+        memcpy(u, ut, sizeof(double) * n);
+        memcpy(qk, qt, sizeof(double) * n);
+        Dk = Dt;
+        ++it;
+        if (obj_trace) obj_trace[it] = Dk;
+        const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+        const double mom = o->momentum ? (t - 1.0) / tn : 0.0;
+        t = tn;
+        L *= o->shrink;
+        if (o->use_screen && it % o->r == 0) {
+            for (int e = 0; e < n; ++e) x[e] = w[e] * u[e];
+            if (o->use_lower) orc_extract(P, &S, x, x + ns);
+            orc_snapshot(P, &S, x, x + ns);
+        }
+        if (mom == 0.0) {
+            memcpy(v, u, sizeof(double) * n);
+            memcpy(qv, qk, sizeof(double) * n);
+            Dv = Dk;
+            at_k = 1;
+        } else {
+            for (int e = 0; e < n; ++e) v[e] = u[e] + mom * (u[e] - uprev[e]);
+            AGD_EVAL(v, qv, Dv);
+            at_k = 0;
+        }
+    }
+#undef AGD_EVAL
+    for (int i = 0; i < ns; ++i) alpha[i] = w[i] * u[i];
+    for (int j = 0; j < P->nt; ++j) beta[j] = w[ns + j] * u[ns + j];
+    if (info) {
+        double ginf = 0.0;
+        for (int e = 0; e < n; ++e) ginf = fmax(ginf, fabs(qk[e] / w[e]));
+        info->iters = it; info->evals = E.evals; info->status = status;
+        info->obj = Dk; info->gnorm_inf = ginf;
+        info->s_i = S.s_i; info->s_n = S.s_n; info->s_u = S.s_u; info->s_r = S.s_r;
+    }
+    free(S.alpha_s); free(S.beta_s); free(S.Zs); free(S.Os); free(S.Ks); free(S.inN);
+    free(E.ga); free(E.gb); free(w); free(u); free(uprev); free(v); free(ut); free(x); free(g);
+    free(qk); free(qv); free(qt);
     return 0;
 }

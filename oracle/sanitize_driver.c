@@ -32,6 +32,11 @@ typedef struct {
     int nthreads;
 } orc_solve_opts;
 typedef struct {
+    int max_iter, r, use_screen, use_lower, max_bt;
+    double gtol, shrink;
+    int momentum;
+} orc_agd_opts;
+typedef struct {
     int iters, evals, status;
     double obj, gnorm_inf;
     long long s_i, s_n, s_u, s_r;
@@ -50,6 +55,7 @@ int orc_gradpsi(const orc_problem *, orc_screen_state *, const double *, const d
 int orc_extract(const orc_problem *, orc_screen_state *, const double *, const double *);
 int orc_snapshot(const orc_problem *, orc_screen_state *, const double *, const double *);
 int orc_solve(const orc_problem *, const orc_solve_opts *, double *, double *, orc_solve_info *, double *);
+int orc_agd_solve(const orc_problem *, const orc_agd_opts *, double *, double *, orc_solve_info *, double *);
 void orc_cost_sqeuclid(int, int, int, const double *, const double *, double *);
 
 static unsigned long long rng_state = 88172645463325252ull;
@@ -88,6 +94,17 @@ static int run_case(int ns, int nt, int L, int d, double gamma, double mu, int e
     double *trace = malloc(sizeof(double) * (o.max_iter + 1));
     int bad = 0;
     bad |= orc_solve(&P, &o, al, be, &inf, trace) != 0;
+    {
+        /* accelerated ascent, screened: reaches the L-BFGS value, monotone */
+        orc_agd_opts oa = {300, 10, 1, 1, 60, 0.0, 0.8, 1};
+        orc_solve_info ia;
+        double *a2 = calloc(ns, sizeof(double)), *b2 = calloc(nt, sizeof(double));
+        double *tr2 = malloc(sizeof(double) * (oa.max_iter + 1));
+        bad |= orc_agd_solve(&P, &oa, a2, b2, &ia, tr2) != 0;
+        for (int k = 0; k < ia.iters; ++k) bad |= tr2[k + 1] < tr2[k];
+        bad |= ia.obj > inf.obj + 1e-9 * (1 + fabs(inf.obj));
+        free(a2); free(b2); free(tr2);
+    }
     double D, D2;
     bad |= orc_dual_grad(&P, al, be, ga, gb, &D, T) != 0;
     bad |= orc_dual_grad_par(&P, al, be, ga2, gb2, &D2, 2) != 0;
