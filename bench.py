@@ -57,6 +57,9 @@ def parse():
                     help="batched workload: omit the one-after-another reference solves (no speedup)")
     ap.add_argument("--skip-warmstart", action="store_true", help="omit the learned warm-start workload")
     ap.add_argument("--skip-paper", action="store_true", help="omit the paper's synthetic experiments")
+    ap.add_argument("--skip-agd", action="store_true", help="omit the accelerated-ascent solver workload")
+    ap.add_argument("--agd-n", type=int, nargs="*", default=[4096, 16384], help="accelerated ascent: n_src = n_tgt")
+    ap.add_argument("--agd-iters", type=int, default=4000, help="accelerated ascent: iteration limit")
     ap.add_argument("--paper-iters", type=int, default=2000, help="paper synthetic: L-BFGS iteration limit")
     ap.add_argument("--paper-classes", type=int, nargs="*", default=[10, 20, 40, 80, 160, 320, 640, 1280])
     ap.add_argument("--ws-train", type=int, default=20000, help="training instances (cold solves)")
@@ -335,7 +338,7 @@ def bench_hbm(args, torch, synth, O):
         dense()
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
-    tiles_us = h.profile_tiles(reps)
+    tiles_us = h.profile_tiles(reps, alpha=a_pt, beta=b_pt)
     alg = algorithmic_bytes(n, n, 10)
     achieved = alg / (tiles_us * 1e-6) / 1e9
     h.close()
@@ -357,6 +360,45 @@ def bench_hbm(args, torch, synth, O):
                tile_config=tiles_cfg)
     if not args.skip_solve and not args.skip_mu_sweep:
         out["mu_sweep"] = bench_mu_sweep(args, torch, synth, O, n=n)
+    return out
+
+
+def bench_agd(args, torch, synth, O, fix):
+    """The second solver (accelerated gradient ascent, OT_GS_SOLVER_AGD) under
+    the same screening: blobs n x n (d = 64, 10 classes, gamma = 0.1) at
+    mu = 0.1 and 1, dense and screened.  Time to 1e-6 relative objective
+    against the FP64 optimum where the fixtures hold it (else the best of
+    the two runs), whether the two trajectories agree bit for bit, and the
+    share of tiles the screened solve computed."""
+    out = {}
+    for n in args.agd_n:
+        for mu in (0.1, 1.0):
+            inst = synth.blobs(seed=2, n_src=n, n_tgt=n, d=64, n_groups=10, gamma=0.1, mu=mu)
+            h = O.Handle(_problems([inst], torch, O))
+            K = args.agd_iters
+            res = {}
+            for name, scr in (("dense", 0), ("screened", 1)):
+                h.stats(reset=True)
+                _, _, inf, tr, tt, wall = _solve_traced(h, 1, K, torch, use_screen=scr, solver=O.OT_GS_SOLVER_AGD,
+                                                       max_ls=60)
+                res[name] = (inf[0], tr, tt, wall, h.stats(reset=True))
+            h.close()
+            key = (f"blobs{n}_mu{mu:g}", 2)
+            anchored = key in fix
+            dstar = np.array([fix[key] if anchored else max(np.nanmax(res["dense"][1][0]),
+                                                             np.nanmax(res["screened"][1][0]))])
+            row = dict(d_star=float(dstar[0]), d_star_from="FP64 oracle" if anchored else "best of the two runs",
+                       same_trajectory=bool(np.array_equal(res["dense"][1], res["screened"][1], equal_nan=True)))
+            for name in ("dense", "screened"):
+                inf, tr, tt, wall, st = res[name]
+                its, ts = _trace_hits(tr, tt, dstar)
+                row[name] = dict(iters_to_1e6=its[0], time_to_1e6_s=ts[0], iters=inf["iters"], evals=inf["evals"],
+                                 wall_s=wall, status=inf["status"],
+                                 final_rel_gap=float((dstar[0] - inf["obj"]) / abs(dstar[0])),
+                                 tiles_computed_frac=st["tiles_computed"] / max(st["tiles_total"], 1))
+            td, ts_ = row["dense"]["time_to_1e6_s"], row["screened"]["time_to_1e6_s"]
+            row["speedup_time_to_1e6"] = (td / ts_) if (td and ts_) else None
+            out[f"n={n} mu={mu:g}"] = row
     return out
 
 
@@ -676,7 +718,7 @@ def main():
     # per-launch duration of the gradient-tile kernel: HIP events around
     # `steps` back-to-back launches on the stream the kernel runs on
     h.dual_grad(a_pt, b_pt, ga, gb, obj, mode=O.OT_GS_DENSE)
-    grad_us = h.profile_tiles(args.steps)
+    grad_us = h.profile_tiles(args.steps, alpha=a_pt, beta=b_pt)
     grad_avg_s = grad_us * 1e-6
     alg_bytes = algorithmic_bytes(ns, nt, L)
     achieved = alg_bytes / grad_avg_s / 1e9
@@ -767,6 +809,10 @@ def main():
     if not args.skip_hbm:
         hbm = bench_hbm(args, torch, synth, O)
         log(f"HBM-scale workload: {hbm['ms_per_eval']:.3f} ms per dense evaluation")
+    agd = None
+    if not args.skip_solve and not args.skip_agd:
+        agd = bench_agd(args, torch, synth, O, fix)
+        log("accelerated-ascent solves done")
     otf = None
     if not args.skip_onthefly:
         otf = bench_onthefly(args, torch, synth, O)
@@ -812,6 +858,7 @@ def main():
         solves=solves,
         mu_sweep=sweep,
         hbm_scale=hbm,
+        second_solver=agd,
         onthefly=otf,
         batched=batched,
         warm_start=warm,

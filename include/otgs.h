@@ -212,12 +212,73 @@ typedef struct {
                              cost, allocated by the first such solve) and D plus
                              a.ref_alpha + b.ref_beta; at most 8 times per
                              instance, the second and later ones only after a
-                             gain of D above 1e-9 |D| since the previous one
-                             (below that the solve has reached the float32
+                             gain of D above recenter_tol |D| since the previous
+                             one (below that the solve has reached the float32
                              floor).  0: stop there (status
                              OT_GS_LINESEARCH).  A re-centred solve leaves the
                              handle with the zero snapshot.                      */
+    int solver;           /* OT_GS_SOLVER_LBFGS (default) or OT_GS_SOLVER_AGD: the
+                             same evaluations (and screening) driven by another
+                             method, see below                                   */
+    long long *stats_trace; /* optional DEVICE [count * (max_iter + 1) * 8]: the
+                             handle's ot_gs_stats counters (in that struct's order)
+                             as instance k's control step saw them at each accepted
+                             iteration, including the evaluation that was accepted;
+                             differences between iterations give the evaluations,
+                             the Theorem 1 counters (s_i, s_n, s_u, s_r) and the
+                             skipped tiles of each iteration.  The counters are
+                             per handle: exact per instance for a one-instance
+                             handle, the whole batch's otherwise                */
+    double *gnorm_trace;  /* optional DEVICE [count * (max_iter + 1)]: ||grad D||_inf
+                             at each accepted iteration                          */
+    int resume;           /* 1: go on from the L-BFGS state on the handle (the last
+                             L-BFGS solve on it, or ot_gs_solver_load) instead of
+                             starting afresh: instances that stopped at the
+                             iteration limit continue up to this call's max_iter
+                             (counted from the original start; traces are indexed
+                             the same way), with the same iterates, bit for bit,
+                             as one uninterrupted solve with the same options.
+                             alpha_io / beta_io receive the result; init_user is
+                             ignored; hist must equal the state's; a state with a
+                             re-centred instance needs recenter = 1.  The first
+                             evaluation is a snapshot (dense).  L-BFGS only.     */
+    double recenter_tol;  /* relative gain of D since the last re-centring that
+                             allows another one (default 1e-10)                 */
 } ot_gs_options;
+
+/* Solvers.  The screening changes how an evaluation is computed, never its
+ * result (Lemma 2), so any solver built on D and its gradient can use it
+ * (Theorem 1 and the remark after it, Sec. 3.4).
+ *   OT_GS_SOLVER_LBFGS: the paper's solver (Sec. 2.3), the options above.
+ *   OT_GS_SOLVER_AGD:   accelerated gradient ascent (Nesterov momentum in the
+ *     FISTA form, backtracking on the step, function-value restart) in the
+ *     marginal-scaled variables; max_iter counts accepted steps, max_ls is
+ *     the number of step halvings per trial before the solve stops with
+ *     OT_GS_LINESEARCH, refresh / use_screen / use_lower / gtol / traces /
+ *     use_graph / init_user as for L-BFGS; hist, c1, c2 and recenter are not
+ *     used and verify must be 0.  Accepted objectives never decrease. */
+#define OT_GS_SOLVER_LBFGS 0
+#define OT_GS_SOLVER_AGD   1
+
+/* Solver checkpoint.  The L-BFGS state a solve leaves on the handle - per
+ * instance the iterate, gradient, direction, the (s, y) history and its Gram
+ * matrices, the line-search state, the iteration count, the re-centring
+ * reference and the pending trial point - as one host byte string, and back
+ * into a handle built from the same problems (ot_gs_solve with resume then
+ * continues it).  The screening snapshot is not part of it: a resumed solve
+ * takes a fresh one (Lemma 2: the snapshot changes which blocks are skipped,
+ * never the values).
+ *   ot_gs_solver_state_size: bytes of the state (host out); OT_GS_EINVAL if
+ *     the handle holds no L-BFGS state (no finished L-BFGS solve).
+ *   ot_gs_solver_save: writes the state into the caller's HOST buffer of
+ *     `bytes` bytes (at least the size above); synchronises `stream`.
+ *   ot_gs_solver_load: reads a saved state into a handle with the same
+ *     instance shapes (n_src, n_tgt, groups, gamma, mu of every instance;
+ *     checked, OT_GS_EINVAL on any mismatch or a truncated buffer); allocates
+ *     the solver buffers if the handle has none yet; synchronises `stream`. */
+int ot_gs_solver_state_size(ot_gs_handle *h, size_t *bytes);
+int ot_gs_solver_save(ot_gs_handle *h, void *host_buf, size_t bytes, void *stream);
+int ot_gs_solver_load(ot_gs_handle *h, const void *host_buf, size_t bytes, void *stream);
 
 /* Fills `o` with the defaults listed above. */
 void ot_gs_default_options(ot_gs_options *o);
@@ -340,11 +401,14 @@ int ot_gs_kernel_timing(ot_gs_handle *h, int enable);
 int ot_gs_kernel_time(ot_gs_handle *h, int which, double *ms, long long *launches);
 
 /* Launch-by-launch cost of the dense gradient tiles (Eq. 5 per (group, 32
- * target) tile) at the handle's current evaluation point: `repeats`
- * back-to-back launches of the tile kernels between two HIP events on
- * `stream`; writes the mean microseconds per launch (host out).  Leaves the
- * row and column partials of a dense evaluation; synchronises `stream`. */
-int ot_gs_profile_tiles(ot_gs_handle *h, int repeats, double *us_per_launch, void *stream);
+ * target) tile): `repeats` back-to-back launches of the tile kernels between
+ * two HIP events on `stream`; writes the mean microseconds per launch (host
+ * out).  With `alpha` and `beta` (device, caller order, as for
+ * ot_gs_dual_grad) the tiles read them as a dense ot_gs_dual_grad call does;
+ * with NULL they read the handle's current evaluation point.  Leaves the row
+ * and column partials of a dense evaluation; synchronises `stream`. */
+int ot_gs_profile_tiles(ot_gs_handle *h, const float *alpha, const float *beta, int repeats,
+                        double *us_per_launch, void *stream);
 
 /* Tile configuration.  The gradient tiles are launched per bucket of the
  * work lists (groups of similar size; buckets 0..12, bucket 13 holds the

@@ -80,6 +80,8 @@ struct ot_gs_handle {
   // device arrays
   InstDev* d_inst = nullptr;
   int *perm_row = nullptr, *row_grp = nullptr, *perm_col = nullptr;
+  int *row_map = nullptr, *col_map = nullptr;   // caller-order index of each internal row / column
+  int* mode_dense = nullptr;                     // [count] EM_DENSE (dense evaluations of caller-order duals)
   int *g_start = nullptr, *g_size = nullptr, *g_chunk0 = nullptr, *grp_inst = nullptr;
   float* C = nullptr;
   // the pool the evaluations read and the cost bound of the screen margins:
@@ -149,12 +151,17 @@ struct ot_gs_handle {
     float *X = nullptr, *G = nullptr, *Dv = nullptr, *S = nullptr, *Y = nullptr, *W = nullptr;
     int* w_unit = nullptr;   // [count]: every scale of the instance is 1 (loads of W skipped)
     LbState* st = nullptr;
+    AgdState* agd_st = nullptr;   // accelerated-ascent solves
     double* gram = nullptr;
     double* part = nullptr;
     int* n_active = nullptr;  // [2]: instances still running (or waiting), re-centrings asked for
     int* h_active = nullptr;  // pinned host [2]
     double* xref = nullptr;   // re-centring reference, actual variables
     double* obj_const = nullptr;
+    // the buffers hold the state an L-BFGS solve left (a resumable state);
+    // the working cost copy holds that state's re-centred cost; some
+    // instance of the state was re-centred (xref != 0)
+    bool lb_valid = false, cw_valid = false, xref_used = false;
     std::vector<void*> mem;
   } sol;
   Timing timing;
@@ -975,6 +982,19 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     LAUNCHCHK();
   }
 
+  TRY(h->alloc(&h->row_map, h->tot_rows));
+  TRY(h->alloc(&h->col_map, h->tot_cols_pad));
+  TRY(h->alloc(&h->mode_dense, count));
+  HIPCHK(hipMemsetAsync(h->mode_dense, 0, sizeof(int) * count, s));   // EM_DENSE
+  {
+    int maxn = 1;
+    for (int k = 0; k < count; ++k) maxn = std::max(maxn, std::max(h->inst[k].d.ns, h->inst[k].d.nt_pad));
+    hipLaunchKernelGGL(k_build_maps, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), count),
+                       dim3(256), 0, s, h->d_inst, (const int*)h->perm_row, (const int*)h->perm_col, h->row_map,
+                       h->col_map);
+    LAUNCHCHK();
+  }
+
   // ---- evaluation state
   for (int k = 0; k < count; ++k) {
     h->max_ns = std::max(h->max_ns, h->inst[k].d.ns);
@@ -1636,6 +1656,37 @@ int ot_gs_create(const ot_gs_problem* probs, int count, ot_gs_handle** out, void
 
 void ot_gs_destroy(ot_gs_handle* h) { delete h; }
 
+// Dense evaluation of caller-order duals in two launches: the tiles read
+// alpha and beta through the caller-order maps (every instance's mode read
+// as dense), the assembly reads them through the permutations, flags
+// non-finite values and runs the evaluation prologue; the internal copies
+// of alpha and beta are not written.
+static int dense_caller_order(ot_gs_handle* h, const float* alpha, const float* beta, float* ga_out,
+                              float* gb_out, double* obj, hipStream_t s) {
+  hipEvent_t e0 = nullptr;
+  TRY(tbegin(h, KT_GRAD, s, &e0));
+  GradArgs A = grad_args(h);
+  A.alpha = alpha;
+  A.beta = beta;
+  A.row_map = h->row_map;
+  A.col_map = h->col_map;
+  A.inst_mode = h->mode_dense;
+  TRY(launch_tiles(h, A, false, false, s));
+  TRY(tend(h, KT_GRAD, s, e0));
+  TRY(tbegin(h, KT_REDUCE, s, &e0));
+  ReduceArgs R = reduce_args(h, false, ga_out, gb_out);
+  R.alpha = alpha;
+  R.beta = beta;
+  R.caller_order = 1;
+  R.pro = prologue_args(h, OT_GS_DENSE);
+  R.finalize = 1;
+  R.obj_out = obj;
+  hipLaunchKernelGGL(k_assemble, dim3(h->n_asm, h->count), dim3(ASM_BLOCK), 0, s, R);
+  LAUNCHCHK();
+  TRY(tend(h, KT_REDUCE, s, e0));
+  return OT_GS_OK;
+}
+
 int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, float* grad_alpha,
                     float* grad_beta, double* obj, int mode, void* stream) {
   if (!h || !alpha || !beta) return fail(OT_GS_EINVAL, "dual_grad: NULL argument");
@@ -1644,6 +1695,7 @@ int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, floa
     return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", base);
   if (flags & ~(OT_GS_CHECK | OT_GS_VERIFY)) return fail(OT_GS_EINVAL, "dual_grad: unknown mode flags 0x%x", flags);
   hipStream_t s = (hipStream_t)stream;
+  if (!flags && base == OT_GS_DENSE && !h->onthefly) return dense_caller_order(h, alpha, beta, grad_alpha, grad_beta, obj, s);
   if (!flags) {
     TRY(gather(h, alpha, beta, s, base));
     TRY(evaluate(h, base, grad_alpha, grad_beta, s, false, true, obj));
@@ -1862,8 +1914,11 @@ int ot_gs_get_stats(ot_gs_handle* h, ot_gs_stats* out, int reset, void* stream) 
   return OT_GS_OK;
 }
 
-int ot_gs_profile_tiles(ot_gs_handle* h, int repeats, double* us_per_launch, void* stream) {
+int ot_gs_profile_tiles(ot_gs_handle* h, const float* alpha, const float* beta, int repeats, double* us_per_launch,
+                        void* stream) {
   if (!h || repeats < 1 || !us_per_launch) return fail(OT_GS_EINVAL, "profile_tiles: bad arguments");
+  if (!alpha != !beta) return fail(OT_GS_EINVAL, "profile_tiles: alpha and beta go together");
+  if (alpha && h->onthefly) return fail(OT_GS_EINVAL, "profile_tiles: caller-order duals need a materialised cost");
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1874,6 +1929,13 @@ int ot_gs_profile_tiles(ot_gs_handle* h, int repeats, double* us_per_launch, voi
   const bool was_on = h->timing.on;
   h->timing.on = false;
   GradArgs A = grad_args(h);
+  if (alpha) {
+    A.alpha = alpha;
+    A.beta = beta;
+    A.row_map = h->row_map;
+    A.col_map = h->col_map;
+    A.inst_mode = h->mode_dense;
+  }
   HIPCHK(hipEventRecord(e0, s));
   for (int i = 0; i < repeats; ++i) TRY(launch_tiles(h, A, false, false, s));
   HIPCHK(hipEventRecord(e1, s));
@@ -1972,6 +2034,7 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->use_graph = 1;
   o->verify = 0;
   o->recenter = 1;
+  o->recenter_tol = 1e-10;
 }
 
 }  // extern "C"
@@ -1985,6 +2048,7 @@ void ot_gs_default_options(ot_gs_options* o) {
 static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   auto& V = h->sol;
   if (V.hist == hist && V.X) return OT_GS_OK;
+  V.lb_valid = V.cw_valid = V.xref_used = false;
   if (V.X && h->ws_base) {
     if (hist > V.cap_hist)
       return fail(OT_GS_EINVAL, "solve: hist %d above the %d the workspace was sized for", hist, V.cap_hist);
@@ -2029,6 +2093,7 @@ static int ensure_solver(ot_gs_handle* h, int hist, hipStream_t s) {
   TRY(al((void**)&V.S, sizeof(float) * acc * hist));
   TRY(al((void**)&V.Y, sizeof(float) * acc * hist));
   TRY(al((void**)&V.st, sizeof(LbState) * h->count));
+  TRY(al((void**)&V.agd_st, sizeof(AgdState) * h->count));
   TRY(al((void**)&V.gram, sizeof(double) * 2 * hist * hist * h->count));
   TRY(al((void**)&V.part, sizeof(double) * (size_t)h->count * maxb * V.ndot));
   TRY(al((void**)&V.n_active, 2 * sizeof(int)));
@@ -2090,12 +2155,34 @@ static LbArgs lb_args(ot_gs_handle* h, const LbParams& P) {
   A.batched = h->count > 1;
   A.W = V.W;
   A.w_unit = V.w_unit;
+  A.block_counters = h->block_counters;
+  A.n_screen_blocks = h->n_screen_blocks;
   A.n_recenter = V.n_active + 1;
   if (P.recenter) {
     A.xref = V.xref;
     A.obj_const = V.obj_const;
   }
   return A;
+}
+
+// The L-BFGS vector update of every instance (with the next evaluation's
+// group statistics when `upd`).
+static int launch_lbfgs_update(ot_gs_handle* h, const LbArgs& A, bool upd, hipStream_t s) {
+  const long long maxv = h->max_ns + h->max_ntp;
+  if (upd)
+  {
+    if (h->gs_large)
+      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_LARGE>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_LARGE)), h->count),
+                         dim3(GS_LARGE), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_SMALL>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_SMALL)), h->count),
+                         dim3(GS_SMALL), 0, s, A);
+  }
+  else
+    hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                       dim3(256), 0, s, A);
+  LAUNCHCHK();
+  return OT_GS_OK;
 }
 
 // One function evaluation of every live instance and one step of its solver.
@@ -2132,7 +2219,6 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   }
   hipEvent_t e0 = nullptr;
   TRY(tbegin(h, KT_LBFGS, s, &e0));
-  const long long maxv = h->max_ns + h->max_ntp;
   // batches with long vectors: LB_SEQ_SPLIT wavefronts per vector block
   // loop over the history slots (g~ and d read LB_SEQ_SPLIT times instead of
   // once per slot); otherwise one wavefront per (block, slot)
@@ -2143,32 +2229,19 @@ static int solver_step(ot_gs_handle* h, const LbArgs& A, int use_lower, int use_
   LAUNCHCHK();
   hipLaunchKernelGGL(k_lbfgs_ctrl, dim3(h->count), dim3(64), 0, s, A);
   LAUNCHCHK();
-  if (upd)
-  {
-    if (h->gs_large)
-      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_LARGE>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_LARGE)), h->count),
-                         dim3(GS_LARGE), 0, s, A);
-    else
-      hipLaunchKernelGGL(k_lbfgs_update_gs<GS_SMALL>, dim3((unsigned)(h->max_le + ceil_div(h->max_ntp, GS_SMALL)), h->count),
-                         dim3(GS_SMALL), 0, s, A);
-  }
-  else
-    hipLaunchKernelGGL(k_lbfgs_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
-                       dim3(256), 0, s, A);
-  LAUNCHCHK();
+  TRY(launch_lbfgs_update(h, A, upd, s));
   TRY(tend(h, KT_LBFGS, s, e0));
   return OT_GS_OK;
 }
 
-// Records `n` solver steps on the handle's capture stream into an
+// Records `n` calls of step(stream) on the handle's capture stream into an
 // executable graph.
-static int capture_steps(ot_gs_handle* h, const LbArgs& A, const LbParams& P, int init_user, int n,
-                         hipGraphExec_t* exec) {
+template <class Step>
+static int capture_n(ot_gs_handle* h, int n, hipGraphExec_t* exec, Step&& step) {
   if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = OT_GS_OK;
-  for (int i = 0; i < n && rc == OT_GS_OK; ++i)
-    rc = solver_step(h, A, P.use_lower, P.use_screen, init_user, h->cap_stream);
+  for (int i = 0; i < n && rc == OT_GS_OK; ++i) rc = step(h->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (rc != OT_GS_OK) {
@@ -2185,6 +2258,131 @@ static int capture_steps(ot_gs_handle* h, const LbArgs& A, const LbParams& P, in
   return OT_GS_OK;
 }
 
+// `n` L-BFGS solver steps into an executable graph
+static int capture_steps(ot_gs_handle* h, const LbArgs& A, const LbParams& P, int init_user, int n,
+                         hipGraphExec_t* exec) {
+  return capture_n(h, n, exec, [&](hipStream_t cs) {
+    return solver_step(h, A, P.use_lower, P.use_screen, init_user, cs);
+  });
+}
+
+// One accelerated-ascent step: the evaluation at the current point (screened
+// or dense, as for L-BFGS), then dots, control and update.
+static int agd_step(ot_gs_handle* h, const AgdArgs& G, int use_lower, int use_screen, hipStream_t s) {
+  if (use_screen)
+    TRY(evaluate_dynamic(h, s, use_lower, nullptr, nullptr, false, false, true, true, true));
+  else
+    TRY(run_tiles_and_reduce(h, false, nullptr, nullptr, s, false, false, false, nullptr));
+  hipEvent_t e0 = nullptr;
+  TRY(tbegin(h, KT_LBFGS, s, &e0));
+  const long long maxv = h->max_ns + h->max_ntp;
+  hipLaunchKernelGGL(k_agd_dots, dim3(h->sol.maxb, h->count), dim3(LB_BLOCK), 0, s, G);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_agd_ctrl, dim3(h->count), dim3(64), 0, s, G);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_agd_update, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                     dim3(256), 0, s, G);
+  LAUNCHCHK();
+  TRY(tend(h, KT_LBFGS, s, e0));
+  return OT_GS_OK;
+}
+
+// ot_gs_solve with OT_GS_SOLVER_AGD
+static int solve_agd(ot_gs_handle* h, const ot_gs_options& o, float* alpha_io, float* beta_io, ot_gs_info* info,
+                     hipStream_t s) {
+  if (o.verify) return fail(OT_GS_EINVAL, "solve: verify is for L-BFGS solves only");
+  TRY(ensure_solver(h, std::max(o.hist, 1), s));
+  LbParams P;
+  std::memset(&P, 0, sizeof P);
+  P.hist = std::max(o.hist, 1);
+  P.max_iter = o.max_iter;
+  P.max_ls = o.max_ls;
+  P.refresh = o.refresh;
+  P.use_screen = o.use_screen ? 1 : 0;
+  P.use_lower = o.use_lower ? 1 : 0;
+  P.c1 = o.c1;
+  P.c2 = o.c2;
+  P.gtol = o.gtol;
+  P.obj_trace = o.obj_trace;
+  P.time_trace = o.time_trace;
+  P.stats_trace = o.stats_trace;
+  P.gnorm_trace = o.gnorm_trace;
+  h->sol.lb_valid = h->sol.cw_valid = h->sol.xref_used = false;   // the buffers now hold this solve's vectors
+  AgdArgs G;
+  std::memset(&G, 0, sizeof G);
+  G.A = lb_args(h, P);
+  G.st = h->sol.agd_st;
+  G.max_bt = o.max_ls;
+  G.momentum = 1;
+  G.shrink = 0.8;
+  TRY(clear_err(h, s));
+  if (o.init_user) TRY(gather(h, alpha_io, beta_io, s));
+  const long long maxv = h->max_ns + h->max_ntp;
+  const dim3 vgrid((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count);
+  hipLaunchKernelGGL(k_lbfgs_init, vgrid, dim3(256), 0, s, G.A, o.init_user ? 1 : 0, h->alpha_s, h->beta_s,
+                     h->zsnap, h->osnap, h->inN, P.use_screen);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_agd_init, vgrid, dim3(256), 0, s, G);
+  LAUNCHCHK();
+  h->has_snapshot = P.use_screen != 0;
+  // at most 1 + max_ls evaluations per accepted step, plus one at v
+  const long long max_steps = 1 + (long long)o.max_iter * (o.max_ls + 2);
+  const int check_every = 16;
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph && !h->timing.on)
+    TRY(capture_n(h, check_every, &exec, [&](hipStream_t cs) { return agd_step(h, G, P.use_lower, P.use_screen, cs); }));
+  struct ExecFree {
+    hipGraphExec_t& e;
+    ~ExecFree() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } exec_free{exec};
+  for (long long step = 0; step < max_steps;) {
+    if (exec && step + check_every <= max_steps) {
+      HIPCHK(hipGraphLaunch(exec, s));
+      step += check_every;
+    } else {
+      TRY(agd_step(h, G, P.use_lower, P.use_screen, s));
+      ++step;
+      if (step % check_every != 0 && step != max_steps) continue;
+    }
+    HIPCHK(hipMemcpyAsync(h->sol.h_active, h->sol.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h->sol.h_active[0] == 0) break;
+  }
+  // final points: u_k of every instance (X), back in the caller's order
+  hipLaunchKernelGGL(k_lbfgs_export, vgrid, dim3(256), 0, s, G.A);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scatter_duals, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 1024), h->count),
+                     dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->alpha, h->beta, alpha_io, beta_io);
+  LAUNCHCHK();
+  std::vector<AgdState> hs(h->count);
+  HIPCHK(hipMemcpyAsync(hs.data(), h->sol.agd_st, sizeof(AgdState) * h->count, hipMemcpyDeviceToHost, s));
+  int herr = 0;
+  TRY(sync_err(h, s, &herr));
+  int worst = OT_GS_OK;
+  for (int k = 0; k < h->count; ++k) {
+    int st = OT_GS_NOT_CONVERGED;
+    if (hs[k].status == LB_CONVERGED) st = OT_GS_OK;
+    else if (hs[k].status == LB_LSFAIL) st = OT_GS_LINESEARCH;
+    worst = std::max(worst, st);
+    if (info) {
+      info[k].iters = hs[k].iter;
+      info[k].evals = hs[k].evals;
+      info[k].status = st;
+      info[k].obj = hs[k].Dk;
+      info[k].gnorm_inf = hs[k].gmax;
+    }
+  }
+  if (herr & ERR_NONFINITE) {
+    TRY(clear_err(h, s));
+    return fail(OT_GS_ENUMERIC, "solve: the starting point holds a NaN or Inf");
+  }
+  for (int k = 0; k < h->count; ++k)
+    if (!std::isfinite(hs[k].Dk)) return fail(OT_GS_ENUMERIC, "solve: the objective of instance %d is not finite", k);
+  return worst;
+}
+
 extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* alpha_io,
                            float* beta_io, ot_gs_info* info, void* stream) {
   if (!h || !opts || !alpha_io || !beta_io) return fail(OT_GS_EINVAL, "solve: NULL argument");
@@ -2193,7 +2391,22 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   if (o.max_iter < 0 || o.refresh < 1 || o.max_ls < 1)
     return fail(OT_GS_EINVAL, "solve: max_iter >= 0, refresh >= 1, max_ls >= 1 required");
   if (!(o.c1 > 0 && o.c1 < o.c2 && o.c2 < 1)) return fail(OT_GS_EINVAL, "solve: need 0 < c1 < c2 < 1");
+  if (o.solver != OT_GS_SOLVER_LBFGS && o.solver != OT_GS_SOLVER_AGD)
+    return fail(OT_GS_EINVAL, "solve: unknown solver %d", o.solver);
+  if (!(o.recenter_tol >= 0.0)) return fail(OT_GS_EINVAL, "solve: recenter_tol must be >= 0");
   hipStream_t s = (hipStream_t)stream;
+  const bool resume = o.resume != 0;
+  if (resume && o.solver != OT_GS_SOLVER_LBFGS) return fail(OT_GS_EINVAL, "solve: resume is for L-BFGS solves");
+  if (o.solver == OT_GS_SOLVER_AGD) return solve_agd(h, o, alpha_io, beta_io, info, s);
+  if (resume) {
+    if (!h->sol.lb_valid)
+      return fail(OT_GS_EINVAL, "solve: resume needs the state of an L-BFGS solve on the handle "
+                                "(a finished solve, or ot_gs_solver_load)");
+    if (h->sol.hist != o.hist)
+      return fail(OT_GS_EINVAL, "solve: resume needs the state's history size %d (got %d)", h->sol.hist, o.hist);
+    if (h->sol.xref_used && !(o.recenter && !h->onthefly))
+      return fail(OT_GS_EINVAL, "solve: the state was re-centred; resume it with recenter = 1");
+  }
   TRY(ensure_solver(h, o.hist, s));
   LbParams P;
   std::memset(&P, 0, sizeof P);
@@ -2208,7 +2421,10 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   P.gtol = o.gtol;
   P.obj_trace = o.obj_trace;
   P.time_trace = o.time_trace;
+  P.stats_trace = o.stats_trace;
+  P.gnorm_trace = o.gnorm_trace;
   P.recenter = (o.recenter && !h->onthefly) ? 1 : 0;
+  P.recenter_tol = o.recenter_tol;
   if (P.recenter) {
     // the evaluations of this solve read a working copy of the pool, which
     // re-centrings rewrite; its cost bounds start as max C
@@ -2216,11 +2432,26 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
       TRY(h->alloc(&h->Cw, h->c_pool));
       TRY(h->alloc(&h->cmax_w, h->count));
     }
-    HIPCHK(hipMemcpyAsync(h->Cw, h->C, sizeof(float) * h->c_pool, hipMemcpyDeviceToDevice, s));
-    std::vector<float> cm(h->count);
-    for (int k = 0; k < h->count; ++k) cm[k] = h->inst[k].d.cmax;
-    HIPCHK(hipMemcpyAsync(h->cmax_w, cm.data(), sizeof(float) * h->count, hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (!(resume && h->sol.cw_valid)) {
+      HIPCHK(hipMemcpyAsync(h->Cw, h->C, sizeof(float) * h->c_pool, hipMemcpyDeviceToDevice, s));
+      std::vector<float> cm(h->count);
+      for (int k = 0; k < h->count; ++k) cm[k] = h->inst[k].d.cmax;
+      HIPCHK(hipMemcpyAsync(h->cmax_w, cm.data(), sizeof(float) * h->count, hipMemcpyHostToDevice, s));
+      if (resume && h->sol.xref_used) {
+        // a restored state: its working cost from the reference
+        // (fl32(c - xref_i - xref_j), the re-centring's own arithmetic)
+        hipLaunchKernelGGL(k_fill<float>, dim3(1), dim3(64), 0, s, h->cmax_w, (long long)h->count, 0.f);
+        LAUNCHCHK();
+        LbParams P0 = P;
+        const LbArgs A0 = lb_args(h, P0);
+        const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8),
+                      (unsigned)std::min(h->max_ns, 4096), h->count);
+        hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A0, (const float*)h->C, h->Cw,
+                           (const int*)h->row_grp, (const int*)h->g_start, (const int*)h->g_size, h->cmax_w, 1);
+        LAUNCHCHK();
+      }
+      HIPCHK(hipStreamSynchronize(s));
+    }
     h->C_eval = h->Cw;
     h->cmax_eval = h->cmax_w;
   }
@@ -2240,18 +2471,29 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
     LAUNCHCHK();
   }
   TRY(clear_err(h, s));
-  if (o.init_user) TRY(gather(h, alpha_io, beta_io, s));
   const long long maxv = h->max_ns + h->max_ntp;
-  hipLaunchKernelGGL(k_lbfgs_init, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
-                     dim3(256), 0, s, A, o.init_user ? 1 : 0, h->alpha_s, h->beta_s, h->zsnap, h->osnap,
-                     h->inN, P.use_screen);
-  LAUNCHCHK();
-  h->has_snapshot = P.use_screen != 0;
-  if (P.use_screen && h->upd_stats && h->tot_groups > 0) {
-    // statistics of the first evaluation (later ones come from the update)
-    ScreenArgs S = screen_args(h, P.use_lower);
-    TRY(launch_group_stats(h, S, s));
+  if (resume) {
+    // go on from the state: the step the iteration limit cut short, then
+    // the update forms the trial point (and the group statistics)
+    hipLaunchKernelGGL(k_lbfgs_resume, dim3(h->count), dim3(64), 0, s, A);
+    LAUNCHCHK();
+    TRY(launch_lbfgs_update(h, A, P.use_screen && h->upd_stats, s));
+    h->has_snapshot = P.use_screen != 0;
+  } else {
+    if (o.init_user) TRY(gather(h, alpha_io, beta_io, s));
+    hipLaunchKernelGGL(k_lbfgs_init, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 256), h->count),
+                       dim3(256), 0, s, A, o.init_user ? 1 : 0, h->alpha_s, h->beta_s, h->zsnap, h->osnap,
+                       h->inN, P.use_screen);
+    LAUNCHCHK();
+    h->has_snapshot = P.use_screen != 0;
+    if (P.use_screen && h->upd_stats && h->tot_groups > 0) {
+      // statistics of the first evaluation (later ones come from the update)
+      ScreenArgs S = screen_args(h, P.use_lower);
+      TRY(launch_group_stats(h, S, s));
+    }
+    h->sol.xref_used = false;
   }
+  h->sol.lb_valid = false;   // valid again once this solve has ended
   // upper bound on evaluations: the first one plus max_ls per iteration
   const long long max_steps = 1 + (long long)o.max_iter * o.max_ls;
   const int check_every = 16;
@@ -2290,7 +2532,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
       const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8), (unsigned)std::min(h->max_ns, 4096),
                     h->count);
       hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A, (const float*)h->C, h->Cw, (const int*)h->row_grp,
-                         (const int*)h->g_start, (const int*)h->g_size, h->cmax_w);
+                         (const int*)h->g_start, (const int*)h->g_size, h->cmax_w, 0);
       LAUNCHCHK();
       hipLaunchKernelGGL(k_recenter_resume, dim3((unsigned)ceil_div(h->count, 256)), dim3(256), 0, s, A, h->count);
       LAUNCHCHK();
@@ -2305,7 +2547,8 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   hipLaunchKernelGGL(k_scatter_duals, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 1024), h->count),
                      dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, h->alpha, h->beta, alpha_io, beta_io);
   LAUNCHCHK();
-  if (recentered) {
+  h->sol.xref_used = h->sol.xref_used || recentered;
+  if (recentered || (resume && h->sol.xref_used)) {
     // the snapshot and N refer to re-centred points and the reduced cost:
     // back to the zero snapshot, exact for the handle's own cost (C >= 0)
     const unsigned fb = (unsigned)std::min<long long>(ceil_div(std::max(h->tot_pairs, h->tot_cols_pad), 256), 4096);
@@ -2318,6 +2561,8 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
   }
   std::vector<LbState> hs(h->count);
   HIPCHK(hipMemcpyAsync(hs.data(), h->sol.st, sizeof(LbState) * h->count, hipMemcpyDeviceToHost, s));
+  h->sol.lb_valid = true;
+  h->sol.cw_valid = P.recenter != 0;
   unsigned long long diff = 0;
   if (verify) HIPCHK(hipMemcpyAsync(&diff, h->ver.diff, sizeof diff, hipMemcpyDeviceToHost, s));
   int herr = 0;

@@ -33,8 +33,12 @@ struct ot_gs_mlp {
 
 namespace otgs {
 
-constexpr int WS_KCHUNK = 4096;   // rows per split-K partial of the weight gradients
-constexpr int WS_COLROWS = 1024;  // rows per partial of the column sums
+// rows per split-K partial of the weight gradients and per partial of the
+// column sums: a 4096-row batch gives 16 x 16 workgroups for a 256 x 256
+// weight gradient and 64 x (width / 256) for a column sum (one workgroup per
+// partial would leave the chip nearly idle)
+constexpr int WS_KCHUNK = 256;
+constexpr int WS_COLROWS = 64;
 
 static int ws_parts_needed(const ot_gs_mlp* M) {
   const long long nk = ceil_div(M->max_rows, WS_KCHUNK), nc = ceil_div(M->max_rows, WS_COLROWS);

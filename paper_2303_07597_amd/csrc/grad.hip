@@ -52,7 +52,19 @@ struct GradArgs {
   int single_inst;        // one instance: a kernel of the other snapshot mode has no work
   const TileRec* rec;     // whole-group materialized tiles: records of the list's entries
   int n_static;           // entries of a static list (-1: read the device count)
+  // caller-order duals (dense evaluations straight from the caller's
+  // arrays): alpha / beta index of internal row / column i is row_map[i] /
+  // col_map[i]; NULL: alpha and beta are in the internal order
+  const int* row_map;
+  const int* col_map;
 };
+
+__device__ __forceinline__ float tile_alpha(const GradArgs& A, int i) {
+  return A.alpha[A.row_map ? A.row_map[i] : i];
+}
+__device__ __forceinline__ float tile_beta(const GradArgs& A, int c) {
+  return A.beta[A.col_map ? A.col_map[c] : c];
+}
 
 // Does a tile kernel of snapshot kind `snap` take a tile of an instance in
 // mode m?  Instances whose solve has ended (EM_SKIP) are never evaluated.
@@ -188,6 +200,10 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
       for (int k = 0; k < R; ++k) p[j][k] = 0.f;
     return;
   }
+  // alpha / beta indices first (with caller-order maps these are loads, and
+  // the alpha / beta loads wait for them), then every cost load, then the
+  // alpha / beta loads: the map round trip overlaps the cost stream
+  int ia[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     // (K = 1: slots past 2 R hold -inf; j stays wavefront-uniform)
@@ -196,9 +212,11 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
     const int rwj = g.r0 + 2 * (v + WT * j);
     const int nkj = rwj < g.r1 ? min(R, (g.r1 - rwj + 2 * NW - 1) / (2 * NW)) : 0;
     const int arow = rwj + 2 * NW * k + (lane & 1);
-    av[a] = (sl < 2 * R * K && k < nkj && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
+    const bool ok = sl < 2 * R * K && k < nkj && arow < g.r1;
+    ia[a] = !ok ? -1 : (A.row_map ? A.row_map[g.a0 + arow] : g.a0 + arow);
   }
-  bj = A.beta[g.b0 + (lane & (TJ - 1))];
+  const int ib = A.col_map ? A.col_map[g.b0 + (lane & (TJ - 1))] : g.b0 + (lane & (TJ - 1));
+  __builtin_amdgcn_sched_barrier(0);
   // one descriptor at the tile's first row; every load a scalar byte offset
   const float* Ct = A.C + g.c0 + (long long)g.r0 * TJ;
   const __amdgpu_buffer_rsrc_t rsrc =
@@ -215,6 +233,10 @@ __device__ __forceinline__ void tile_loads(const GradArgs& A, const TileGeo& g, 
       p[j][k] = __uint_as_float(
           __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane * 4, base + min(k, klast) * stride_b, 0));
   }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int a = 0; a < NA; ++a) av[a] = ia[a] >= 0 ? A.alpha[ia[a]] : -INFINITY;
+  bj = A.beta[ib];
 }
 
 // red: this team's [3][NW][TJ] partials; aw: per real wavefront alpha slot;
@@ -479,8 +501,8 @@ __global__ void __launch_bounds__(BLOCK, 8) k_grad_tiles_dma(GradArgs A) {
     const int rw = 2 * w;
     const int nk = rw < g.r1 ? min(R, (g.r1 - rw + 2 * NW - 1) / (2 * NW)) : 0;
     const int arow = rw + 2 * NW * (lane >> 1) + (lane & 1);
-    av[0] = ((lane >> 1) < nk && arow < g.r1) ? A.alpha[g.a0 + arow] : -INFINITY;
-    bj = A.beta[g.b0 + (lane & (TJ - 1))];
+    av[0] = ((lane >> 1) < nk && arow < g.r1) ? tile_alpha(A, g.a0 + arow) : -INFINITY;
+    bj = tile_beta(A, g.b0 + (lane & (TJ - 1)));
     const float* Ct = A.C + g.c0;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)Ct, (short)0, 0x7fffffff, 0x00020000);
@@ -673,6 +695,28 @@ __global__ void __launch_bounds__(WAVE) k_split_combine(GradArgs A) {
 
 // ---------------------------------------------------------------- assembly
 
+// Host-directed evaluation prologue: every instance gets `mode`; for dense
+// evaluations the counters are advanced here (screened ones count in the
+// screen pass).
+struct Prologue {
+  int* inst_mode;
+  int count, mode;
+  long long* counters;
+  long long pairs_valid, tiles;
+};
+
+__device__ __forceinline__ void prologue_body(const Prologue& P) {
+  for (int k = threadIdx.x; k < P.count; k += blockDim.x) P.inst_mode[k] = P.mode;
+  if (threadIdx.x == 0 && P.mode == EM_DENSE) {
+    unsigned long long* C = (unsigned long long*)P.counters;
+    atomicAdd(&C[CNT_EVALS], (unsigned long long)P.count);
+    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)P.pairs_valid);
+    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)P.tiles);
+    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)P.tiles);
+  }
+}
+
+
 struct ReduceArgs {
   const InstDev* inst;
   const int* row_grp;
@@ -702,6 +746,12 @@ struct ReduceArgs {
   int finalize;             // 1: the last assembly block of an instance forms D
   const int* inst_mode;     // EvalMode per instance
   int* zero_first;          // solver steps: the step's count of live instances, zeroed here (may be NULL)
+  // dense evaluations straight from the caller's arrays: alpha and beta are
+  // in the caller's order (read through perm_row / perm_col and checked for
+  // NaN / Inf here), and block (0, 0) runs the evaluation prologue after
+  // the tiles (which read every mode as dense)
+  int caller_order;
+  Prologue pro;
 };
 
 constexpr int ASM_BLOCK = 256;
@@ -781,6 +831,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   __shared__ double red[ASM_BLOCK / 64];
   const int k = blockIdx.y;
   if (A.zero_first && blockIdx.x == 0 && k == 0 && threadIdx.x == 0) *A.zero_first = 0;
+  if (A.caller_order && blockIdx.x == 0 && k == 0) prologue_body(A.pro);
   // inside a batched solve, an instance whose solve has ended (mode SKIP)
   // has no tiles evaluated and nothing reads its gradient or D: its blocks
   // leave at once (calls that finalize D never see SKIP)
@@ -800,8 +851,8 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     // the row's own operands are loaded together with its partials
     const bool rok = r < I.ns;
     const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
-    const float al_r = rok ? A.alpha[I.row_off + r] : 0.f;
-    const int pm_r = (rok && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
+    const int pm_r = (rok && (A.ga_out || A.caller_order)) ? A.perm_row[I.row_off + r] : 0;
+    const float al_r = rok ? A.alpha[I.row_off + (A.caller_order ? pm_r : r)] : 0.f;
     const bool a_uni = A.a_uniform[k];
     if (rok) {
       const float* rp = A.rowpart + I.r_off + r;
@@ -815,6 +866,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     s += __shfl_xor(s, 2);
     s += __shfl_xor(s, 4);
     if (q == 0 && rok) {
+      if (A.caller_order && !isfinite(al_r)) atomicOr(A.err, 8);
       const float gval = a_r - s;
       if (A.ga_int) A.ga_int[I.row_off + r] = gval;
       if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
@@ -826,8 +878,9 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     if (c < I.nt_pad) {
       const bool cok = c < I.nt;
       const float b_c = cok ? A.b_int[I.col_off + c] : 0.f;
-      const float be_c = cok ? A.beta[I.col_off + c] : 0.f;
-      const int pm_c = (cok && A.gb_out) ? A.perm_col[I.col_off + c] : 0;
+      const int pm_c = (cok && (A.gb_out || A.caller_order)) ? A.perm_col[I.col_off + c] : 0;
+      const float be_c = cok ? (A.caller_order ? A.beta[I.scol_off + pm_c] : A.beta[I.col_off + c]) : 0.f;
+      if (A.caller_order && !isfinite(be_c)) atomicOr(A.err, 8);
       const bool b_uni = A.b_uniform[k];
       const float* cs = A.colsum + (size_t)I.pair_off + c;
       const float* ex = A.excess + (size_t)I.pair_off + c;
@@ -884,27 +937,6 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
 // (the same association wherever D is formed).
 
 
-// Host-directed evaluation prologue: every instance gets `mode`; for dense
-// evaluations the counters are advanced here (screened ones count in the
-// screen pass).
-struct Prologue {
-  int* inst_mode;
-  int count, mode;
-  long long* counters;
-  long long pairs_valid, tiles;
-};
-
-__device__ __forceinline__ void prologue_body(const Prologue& P) {
-  for (int k = threadIdx.x; k < P.count; k += blockDim.x) P.inst_mode[k] = P.mode;
-  if (threadIdx.x == 0 && P.mode == EM_DENSE) {
-    unsigned long long* C = (unsigned long long*)P.counters;
-    atomicAdd(&C[CNT_EVALS], (unsigned long long)P.count);
-    atomicAdd(&C[CNT_PAIRS_TOTAL], (unsigned long long)P.pairs_valid);
-    atomicAdd(&C[CNT_TILES_TOTAL], (unsigned long long)P.tiles);
-    atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)P.tiles);
-  }
-}
-
 // caller-order (alpha, beta) -> internal order; padding columns get 0.
 // Flags non-finite inputs.  grid.y instance.  With do_prologue, workgroup
 // (0, 0) also runs the evaluation prologue.
@@ -931,6 +963,19 @@ __global__ void __launch_bounds__(256) k_gather_duals(const InstDev* __restrict_
     be_int[I.col_off + c] = v;
   }
   if (bad) atomicOr(err, 8);   // a NaN or Inf dual value (reported by checked calls)
+}
+
+// caller-order index of every internal row and column (padding columns:
+// the instance's first target, a valid address whose value is masked)
+__global__ void __launch_bounds__(256) k_build_maps(const InstDev* __restrict__ inst,
+                                                    const int* __restrict__ perm_row,
+                                                    const int* __restrict__ perm_col, int* __restrict__ row_map,
+                                                    int* __restrict__ col_map) {
+  const InstDev I = inst[blockIdx.y];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x)
+    row_map[I.row_off + r] = I.row_off + perm_row[I.row_off + r];
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x)
+    col_map[I.col_off + c] = I.scol_off + (c < I.nt ? perm_col[I.col_off + c] : 0);
 }
 
 __global__ void k_prologue(int* inst_mode, int count, int mode, long long* counters,

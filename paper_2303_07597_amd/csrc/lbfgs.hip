@@ -44,9 +44,13 @@ struct LbParams {
   int hist, max_iter, max_ls, refresh, use_screen, use_lower;
   int recenter;           // re-centre instead of stopping on a failed search
   double c1, c2, gtol;
+  double recenter_tol;    // gain of D (relative) since the last re-centring that allows another
   double* obj_trace;      // [count * (max_iter + 1)] or NULL
   long long* time_trace;  // [count * (max_iter + 1)] or NULL
+  long long* stats_trace; // [count * (max_iter + 1)][CNT_NUM] or NULL
+  double* gnorm_trace;    // [count * (max_iter + 1)] or NULL
 };
+
 
 struct LbState {
   int status, phase, iter, evals, nls, zoom;
@@ -122,7 +126,43 @@ struct LbArgs {
   double* xref;             // [vtot] or NULL
   double* obj_const;        // [count]
   int* n_recenter;          // instances waiting for a re-centring
+  // the screen pass's per-workgroup counters (added to `counters` by
+  // ot_gs_get_stats; the statistics trace adds them the same way)
+  const long long* block_counters;
+  int n_screen_blocks;
 };
+
+// Per-iteration traces besides D and the clock.  The handle's counters as
+// ot_gs_get_stats forms them (the global array plus the screen pass's
+// per-workgroup counters), summed by the 64 lanes and read before this
+// control step adds anything; in unscreened solves its own additions for
+// the evaluation just done are added here.  Every lane gets the sums.
+__device__ __forceinline__ void lb_counter_sums(const LbArgs& A, const InstDev& I, long long (&cs)[CNT_NUM]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < CNT_NUM; ++c) cs[c] = lane == 0 ? A.counters[c] : 0;
+  for (int b = lane; b < A.n_screen_blocks; b += 64)
+#pragma unroll
+    for (int c = 0; c < CNT_NUM; ++c) cs[c] += A.block_counters[(size_t)b * CNT_NUM + c];
+#pragma unroll
+  for (int c = 0; c < CNT_NUM; ++c)
+    for (int o = 32; o > 0; o >>= 1) cs[c] += __shfl_xor(cs[c], o);
+  if (!A.P.use_screen) {
+    const long long tiles = (long long)I.Le * I.njb;
+    cs[CNT_EVALS] += 1;
+    cs[CNT_PAIRS_TOTAL] += (long long)I.Le * I.nt;
+    cs[CNT_TILES_TOTAL] += tiles;
+    cs[CNT_TILES_COMPUTED] += tiles;
+  }
+}
+
+// the statistics and gradient-norm traces at entry idx (one lane writes)
+__device__ __forceinline__ void lb_write_traces(const LbParams& P, const long long (&cs)[CNT_NUM], size_t idx,
+                                                double gmax) {
+  if (P.stats_trace)
+    for (int c = 0; c < CNT_NUM; ++c) P.stats_trace[idx * CNT_NUM + c] = cs[c];
+  if (P.gnorm_trace) P.gnorm_trace[idx] = gmax;
+}
 
 // An instance whose solve has ended and whose last control step accepted no
 // point has a zero step and no new direction: its update would rewrite the
@@ -461,6 +501,8 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   }
   const double ft = -D;
   const double Gtd = dots[0], GtGt = dots[1], GtG = dots[2], dd = dots[3];
+  long long cs[CNT_NUM];
+  if (P.stats_trace) lb_counter_sums(A, A.inst[k], cs);
   S.evals++;
   if (!P.use_screen && l0) {
     // unscreened solves evaluate every tile of the live instances without a
@@ -492,6 +534,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
     S.head = 0;
     if (P.obj_trace && l0 && !restart) P.obj_trace[tr] = D;
     if (P.time_trace && l0 && !restart) P.time_trace[tr] = wall_clock64();
+    if (l0 && !restart) lb_write_traces(P, cs, tr, S.gmax);
     if (S.gmax <= P.gtol) {
       S.status = LB_CONVERGED;
     } else if (S.iter >= P.max_iter) {
@@ -568,7 +611,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
         if (l0) atomicAdd(A.n_active, 1);
         return;
       }
-      if (P.recenter && S.n_rec < RECENTER_MAX && S.f_rec - S.f > 1e-9 * fabs(S.f)) {
+      if (P.recenter && S.n_rec < RECENTER_MAX && S.f_rec - S.f > P.recenter_tol * fabs(S.f)) {
         // the search ran out of float32 resolution around the point: ask
         // for a re-centring there (the host launches it between steps) and
         // continue from it with a fresh memory; a later one only after the
@@ -642,6 +685,7 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   S.gmax = dots[4];
   if (P.obj_trace && l0) P.obj_trace[tr + S.iter] = D;
   if (P.time_trace && l0) P.time_trace[tr + S.iter] = wall_clock64();
+  if (l0) lb_write_traces(P, cs, tr + S.iter, dots[4]);
   if (S.gmax <= P.gtol) S.status = LB_CONVERGED;
   else if (S.iter >= P.max_iter) S.status = LB_MAXITER;
   if (S.status != LB_RUNNING) {
@@ -1049,10 +1093,10 @@ __global__ void __launch_bounds__(1024) k_recenter_vec(LbArgs A, const float* __
 // re-centring also sets them running.
 __global__ void __launch_bounds__(256) k_recenter_cost(LbArgs A, const float* __restrict__ C, float* __restrict__ Cw,
                                                        const int* __restrict__ row_grp, const int* __restrict__ g_start,
-                                                       const int* __restrict__ g_size, float* cmax_w) {
+                                                       const int* __restrict__ g_size, float* cmax_w, int all) {
   const int k = blockIdx.z;
   const LbState& S = A.st[k];
-  if (S.status != LB_RECENTER || S.phase != 2) return;
+  if (!all && (S.status != LB_RECENTER || S.phase != 2)) return;
   const InstDev I = A.inst[k];
   const long long v0 = A.voff[k];
   float mx = 0.f;
@@ -1071,11 +1115,73 @@ __global__ void __launch_bounds__(256) k_recenter_cost(LbArgs A, const float* __
   if ((threadIdx.x & 63) == 0) atomicMax((unsigned int*)&cmax_w[k], __float_as_uint(mx));
 }
 
+// (all = 1: every instance, rebuilding the working cost of a solver state
+// restored from a checkpoint, whose reference is xref; an instance never
+// re-centred has xref = 0 and gets C itself)
+
 // Re-centred instances resume (after the cost kernel).
 __global__ void k_recenter_resume(LbArgs A, int count) {
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) {
     LbState& S = A.st[k];
     if (S.status == LB_RECENTER && S.phase == 2) S.status = LB_RUNNING;
+  }
+}
+
+// Continuing a solve from the state an earlier one left (ot_gs_solve with
+// resume; the state may come from a checkpoint).  One wavefront per
+// instance.  An instance that stopped at the iteration limit takes the part
+// of its last control step the limit cut short - the new direction from the
+// accepted point and the evaluation mode, exactly as after an acceptance -
+// if the new limit lets it go on.  Every live instance's next evaluation is
+// a snapshot: the snapshot on the handle need not belong to this state, and
+// a snapshot evaluation is dense, so the iterates stay the same bits
+// (Lemma 2).  The accept / push flags of the last step were already applied
+// by its update, so they are cleared: the update that follows forms only
+// the direction (if new) and the trial point, and records no snapshot.
+__global__ void __launch_bounds__(64) k_lbfgs_resume(LbArgs A) {
+  __shared__ LbState S;
+  __shared__ double gram_s[2 * HMAX * HMAX];
+  const int k = blockIdx.x, lane = threadIdx.x;
+  const int h = A.P.hist;
+  const LbParams& P = A.P;
+  constexpr int NV = (int)(sizeof(LbState) / 16);
+  {
+    const int4* src = (const int4*)&A.st[k];
+    int4* dst = (int4*)&S;
+    for (int i = lane; i < NV; i += 64) dst[i] = src[i];
+    const double* gram_g = A.gram + (size_t)k * 2 * h * h;
+    for (int q = lane; q < 2 * h * h; q += 64) gram_s[q] = gram_g[q];
+  }
+  __syncthreads();
+  const int st0 = S.status;
+  const bool cont = st0 == LB_MAXITER && S.iter < P.max_iter;
+  __syncthreads();
+  S.accept = 0;
+  S.push = 0;
+  S.newdir = 0;
+  S.mode_eval = EM_SKIP;
+  __builtin_amdgcn_wave_barrier();
+  bool live = st0 == LB_RUNNING;
+  if (cont) {
+    S.status = LB_RUNNING;
+    LbGram G{gram_s, gram_s + h * h, h};
+    lb_new_direction(S, G, P);
+    if (P.use_screen && ++S.since_refresh >= P.refresh) S.since_refresh = 0;
+    live = true;
+  } else if (!live) {
+    S.t_next = 0.0;
+  }
+  __syncthreads();
+  double* gram_g = A.gram + (size_t)k * 2 * h * h;
+  for (int q = lane; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
+  {
+    const int4* src = (const int4*)&S;
+    int4* dst = (int4*)&A.st[k];
+    for (int i = lane; i < NV; i += 64) dst[i] = src[i];
+  }
+  if (lane == 0) {
+    A.inst_mode[k] = live ? (P.use_screen ? EM_SNAPSHOT : EM_DENSE) : EM_SKIP;
+    if (live) atomicAdd(A.n_active, 1);
   }
 }
 

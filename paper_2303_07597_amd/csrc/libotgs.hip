@@ -4,8 +4,10 @@
 #include "grad.hip"
 #include "screen.hip"
 #include "lbfgs.hip"
+#include "agd.hip"
 #include "inspect.hip"
 #include "api.hip"
+#include "checkpoint.hip"
 #include "plan_static.hip"
 #include "transport.hip"
 #include "mlp.hip"

@@ -50,16 +50,19 @@ struct GemmArgs {
 };
 
 // 64 x 64 output tile per workgroup of four wavefronts (32 x 32 each), K
-// in steps of 32 staged through LDS.  Each step the 256 threads load the
-// 64 x 32 slices of A and B along whichever index is contiguous in memory
+// in stages of GK = 128 through LDS.  Each stage the 256 threads load the
+// 64 x 128 slices of A and B along whichever index is contiguous in memory
 // (so the loads coalesce for plain and transposed operands alike), round
 // them to bfloat16 and store them in the matrix-core operand layout (k
 // contiguous per row of A and per column of B, rows padded against bank
-// conflicts); each wavefront then reads 16-byte fragments and issues two
-// v_mfma_f32_32x32x16_bf16.  The MFMA sequence over k is the same as a
-// direct 16-step loop, so the results do not depend on the staging.
-constexpr int GK = 32;          // K per LDS step
-constexpr int GLD = GK + 8;     // padded row length (bf16) of an LDS tile
+// conflicts); each wavefront then reads 16-byte fragments and issues one
+// v_mfma_f32_32x32x16_bf16 per 16 k.  The next stage's global loads are in
+// flight in registers while the current stage multiplies.  The MFMA
+// sequence over k is that of a direct 16-step loop (steps past the end of
+// the chunk are not issued), so the results do not depend on the staging.
+constexpr int GK = 128;               // K per LDS stage
+constexpr int GLD = GK + 8;           // padded row length (bf16) of an LDS tile
+constexpr int GU = 64 * GK / 256;     // elements per thread and operand per stage
 
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
@@ -71,46 +74,69 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   const int ka = blockIdx.z * g.kchunk, kb = min(ka + g.kchunk, g.K);
   const bool a_krow = g.a_cs == 1;   // A(i, k): k contiguous
   const bool b_kcol = g.b_rs == 1;   // B(k, j): k contiguous
-  floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int k0 = ka; k0 < kb; k0 += GK) {
-    // ---- stage A[bi .. bi+63][k0 .. k0+31] and B[k0 ..][bj .. bj+63]
+  // element u of this thread in a stage: (row or column, k) of the tile;
+  // each load instruction covers 64 consecutive k of one row, or 64
+  // consecutive rows of one k, whichever runs along memory
+  auto a_at = [&](int u, int& r, int& k) {
+    if (a_krow) {
+      r = (t >> 7) + 2 * u;
+      k = t & 127;
+    } else {
+      r = t & 63;
+      k = (t >> 6) + 4 * u;
+    }
+  };
+  auto b_at = [&](int u, int& c, int& k) {
+    if (b_kcol) {
+      c = (t >> 7) + 2 * u;
+      k = t & 127;
+    } else {
+      c = t & 63;
+      k = (t >> 6) + 4 * u;
+    }
+  };
+  float ra[GU], rb[GU];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      // A: each load instruction covers 32 consecutive k of 8 rows, or 64
-      // consecutive rows of one k, whichever runs along memory
-      int ra, kaa;
-      if (a_krow) {
-        ra = (t >> 5) + 8 * u;
-        kaa = t & 31;
-      } else {
-        ra = t & 63;
-        kaa = (t >> 6) + 4 * u;
-      }
-      const int gr = bi + ra, gk = k0 + kaa;
-      const float va = (gr < g.M && gk < kb) ? g.A[(long long)gr * g.a_rs + (long long)gk * g.a_cs] : 0.f;
-      As[ra * GLD + kaa] = bf16_bits(va);
-      int cb, kbb;
-      if (b_kcol) {
-        cb = (t >> 5) + 8 * u;
-        kbb = t & 31;
-      } else {
-        cb = t & 63;
-        kbb = (t >> 6) + 4 * u;
-      }
-      const int gc = bj + cb, gk2 = k0 + kbb;
-      const float vb = (gc < g.N && gk2 < kb) ? g.B[(long long)gk2 * g.b_rs + (long long)gc * g.b_cs] : 0.f;
-      Bs[cb * GLD + kbb] = bf16_bits(vb);
+    for (int u = 0; u < GU; ++u) {
+      int r, k;
+      a_at(u, r, k);
+      const int gr = bi + r, gk = k0 + k;
+      ra[u] = (gr < g.M && gk < kb) ? g.A[(long long)gr * g.a_rs + (long long)gk * g.a_cs] : 0.f;
+      int c, k2;
+      b_at(u, c, k2);
+      const int gc = bj + c, gk2 = k0 + k2;
+      rb[u] = (gc < g.N && gk2 < kb) ? g.B[(long long)gk2 * g.b_rs + (long long)gc * g.b_cs] : 0.f;
+    }
+  };
+  floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (ka < kb) load(ka);
+  for (int k0 = ka; k0 < kb; k0 += GK) {
+    // ---- the staged slices into LDS as bfloat16
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      int r, k;
+      a_at(u, r, k);
+      As[r * GLD + k] = bf16_bits(ra[u]);
+      int c, k2;
+      b_at(u, c, k2);
+      Bs[c * GLD + k2] = bf16_bits(rb[u]);
     }
     __syncthreads();
-    // ---- two 16-deep products from LDS fragments (lane: row / column
+    // ---- the next stage's loads in flight during this stage's products
+    if (k0 + GK < kb) load(k0 + GK);
+    // ---- one 16-deep product per 16 k of the chunk (lane: row / column
     // lane & 31, k offset 8 (lane >> 5))
+    const int nh = (min(GK, kb - k0) + 15) / 16;
 #pragma unroll
     for (int h = 0; h < GK / 16; ++h) {
-      const int ko = 16 * h + 8 * (lane >> 5);
-      const shortx8 av = *reinterpret_cast<const shortx8*>(&As[(i0 + (lane & 31)) * GLD + ko]);
-      const shortx8 bv = *reinterpret_cast<const shortx8*>(&Bs[(j0 + (lane & 31)) * GLD + ko]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
-                                                    __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+      if (h < nh) {
+        const int ko = 16 * h + 8 * (lane >> 5);
+        const shortx8 av = *reinterpret_cast<const shortx8*>(&As[(i0 + (lane & 31)) * GLD + ko]);
+        const shortx8 bv = *reinterpret_cast<const shortx8*>(&Bs[(j0 + (lane & 31)) * GLD + ko]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av),
+                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+      }
     }
     __syncthreads();
   }

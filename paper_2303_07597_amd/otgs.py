@@ -32,6 +32,9 @@ OT_GS_SNAPSHOT = 2
 OT_GS_CHECK = 0x100
 OT_GS_VERIFY = 0x200
 
+OT_GS_SOLVER_LBFGS = 0
+OT_GS_SOLVER_AGD = 1
+
 OT_GS_COST_GIVEN = 0
 OT_GS_COST_MATERIALIZE = 1
 OT_GS_COST_ONTHEFLY = 2
@@ -61,7 +64,9 @@ class ot_gs_options(ct.Structure):
                 ("use_screen", ct.c_int), ("use_lower", ct.c_int), ("max_ls", ct.c_int),
                 ("init_user", ct.c_int), ("c1", ct.c_double), ("c2", ct.c_double),
                 ("gtol", ct.c_double), ("obj_trace", ct.c_void_p), ("time_trace", ct.c_void_p),
-                ("use_graph", ct.c_int), ("verify", ct.c_int), ("recenter", ct.c_int)]
+                ("use_graph", ct.c_int), ("verify", ct.c_int), ("recenter", ct.c_int), ("solver", ct.c_int),
+                ("stats_trace", ct.c_void_p), ("gnorm_trace", ct.c_void_p), ("resume", ct.c_int),
+                ("recenter_tol", ct.c_double)]
 
 
 class ot_gs_info(ct.Structure):
@@ -92,7 +97,7 @@ def _load():
     lib.ot_gs_get_stats.argtypes = [vp, ct.POINTER(ot_gs_stats), i, vp]
     lib.ot_gs_kernel_timing.argtypes = [vp, i]
     lib.ot_gs_kernel_time.argtypes = [vp, i, ct.POINTER(d), ct.POINTER(ct.c_longlong)]
-    lib.ot_gs_profile_tiles.argtypes = [vp, i, ct.POINTER(d), vp]
+    lib.ot_gs_profile_tiles.argtypes = [vp, vp, vp, i, ct.POINTER(d), vp]
     lib.ot_gs_layout_info.argtypes = [vp, i, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)]
     lib.ot_gs_mlp_create.argtypes = [i, i, i, ct.POINTER(vp)]
     lib.ot_gs_mlp_destroy.argtypes = [vp]
@@ -113,6 +118,9 @@ def _load():
     lib.ot_gs_workspace_size.argtypes = [ct.POINTER(ot_gs_problem), i, i, ct.POINTER(ct.c_size_t), vp]
     lib.ot_gs_create_ws.argtypes = [ct.POINTER(ot_gs_problem), i, i, vp, ct.c_size_t, ct.POINTER(vp), vp]
     lib.ot_gs_transport.argtypes = [vp, vp, vp, vp, i, vp, vp]
+    lib.ot_gs_solver_state_size.argtypes = [vp, ct.POINTER(ct.c_size_t)]
+    lib.ot_gs_solver_save.argtypes = [vp, vp, ct.c_size_t, vp]
+    lib.ot_gs_solver_load.argtypes = [vp, vp, ct.c_size_t, vp]
     lib.ot_gs_screen_state.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.ot_gs_last_error.restype = ct.c_char_p
     lib.ot_gs_version.restype = ct.c_char_p
@@ -291,7 +299,8 @@ class Handle:
         _check(lib().ot_gs_dual_grad(self.h, _ptr(alpha), _ptr(beta), _ptr(grad_alpha),
                                      _ptr(grad_beta), _ptr(obj), int(mode), _stream(stream)))
 
-    def solve(self, alpha=None, beta=None, stream=None, obj_trace=None, time_trace=None, **opts):
+    def solve(self, alpha=None, beta=None, stream=None, obj_trace=None, time_trace=None, stats_trace=None,
+              gnorm_trace=None, **opts):
         o = ot_gs_options()
         lib().ot_gs_default_options(ct.byref(o))
         for k, v in opts.items():
@@ -300,6 +309,10 @@ class Handle:
             o.obj_trace = _ptr(obj_trace).value
         if time_trace is not None:
             o.time_trace = _ptr(time_trace).value
+        if stats_trace is not None:
+            o.stats_trace = _ptr(stats_trace).value
+        if gnorm_trace is not None:
+            o.gnorm_trace = _ptr(gnorm_trace).value
         dev = torch.device("cuda")
         if alpha is None:
             alpha = torch.zeros(sum(self.n_src), dtype=torch.float32, device=dev)
@@ -368,6 +381,19 @@ class Handle:
                                      _stream(stream)))
         return y
 
+    def solver_state(self, stream=None):
+        """The handle's L-BFGS solver state as bytes (ot_gs_solver_save)."""
+        n = ct.c_size_t()
+        _check(lib().ot_gs_solver_state_size(self.h, ct.byref(n)))
+        buf = ct.create_string_buffer(n.value)
+        _check(lib().ot_gs_solver_save(self.h, buf, n.value, _stream(stream)))
+        return buf.raw
+
+    def load_solver_state(self, data, stream=None):
+        """Restore a state from solver_state() (ot_gs_solver_load)."""
+        buf = ct.create_string_buffer(bytes(data), len(data))
+        _check(lib().ot_gs_solver_load(self.h, buf, len(data), _stream(stream)))
+
     def cost(self, C_out, stream=None):
         _check(lib().ot_gs_cost(self.h, _ptr(C_out), _stream(stream)))
 
@@ -384,9 +410,11 @@ class Handle:
         _check(lib().ot_gs_kernel_time(self.h, int(which), ct.byref(ms), ct.byref(n)))
         return ms.value, n.value
 
-    def profile_tiles(self, repeats=100, stream=None):
+    def profile_tiles(self, repeats=100, alpha=None, beta=None, stream=None):
         us = ct.c_double()
-        _check(lib().ot_gs_profile_tiles(self.h, int(repeats), ct.byref(us), _stream(stream)))
+        _check(lib().ot_gs_profile_tiles(self.h, _ptr(alpha) if alpha is not None else None,
+                                         _ptr(beta) if beta is not None else None, int(repeats), ct.byref(us),
+                                         _stream(stream)))
         return us.value
 
     def cost_scale(self):
@@ -428,5 +456,6 @@ EXPORTED = [
     "ot_gs_features", "ot_gs_cost_scale", "ot_gs_warm_start",
     "ot_gs_autotune", "ot_gs_tile_config", "ot_gs_get_tile_config", "ot_gs_check", "ot_gs_screen_state",
     "ot_gs_transport", "ot_gs_workspace_size", "ot_gs_create_ws",
+    "ot_gs_solver_state_size", "ot_gs_solver_save", "ot_gs_solver_load",
     "ot_gs_plan_csr",
 ]
