@@ -243,7 +243,7 @@ typedef struct {
                              re-centred instance needs recenter = 1.  The first
                              evaluation is a snapshot (dense).  L-BFGS only.     */
     double recenter_tol;  /* relative gain of D since the last re-centring that
-                             allows another one (default 1e-10)                 */
+                             allows another one (default 1e-9)                 */
 } ot_gs_options;
 
 /* Solvers.  The screening changes how an evaluation is computed, never its

@@ -111,6 +111,9 @@ struct ot_gs_handle {
     double* objp = nullptr;   // assembly partials of D (verified solves)
   } ver;
   float *a_int = nullptr, *b_int = nullptr;
+  float *a_cal = nullptr, *b_cal = nullptr;   // the marginals in the caller's order
+  // the caller's duals of the ot_gs_dual_grad call in progress (NULL outside one)
+  const float *cal_alpha = nullptr, *cal_beta = nullptr;
   int *a_uniform = nullptr, *b_uniform = nullptr;
   std::vector<int> w_unit_h;   // per instance: every variable scale is 1 (uniform a, b and n_src = n_tgt)
   float *alpha = nullptr, *beta = nullptr, *ga = nullptr, *gb = nullptr;
@@ -954,6 +957,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
                   mass[1]);
   }
   TRY(h->alloc(&h->a_int, h->tot_rows));
+  TRY(h->alloc(&h->a_cal, h->tot_rows));
+  TRY(h->alloc(&h->b_cal, std::max<long long>(h->tot_cols, 1)));
   TRY(h->alloc(&h->b_int, h->tot_cols_pad));
   TRY(h->alloc(&h->a_uniform, count));
   TRY(h->alloc(&h->b_uniform, count));
@@ -978,7 +983,8 @@ static int create_impl(const ot_gs_problem* probs, int count, ot_gs_handle** out
     HIPCHK(hipMemcpyAsync(h->a_uniform, ua.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->b_uniform, ub.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_marginals, dim3((unsigned)std::min<long long>(ceil_div(maxn, 256), 1024), count),
-                       dim3(256), 0, s, h->d_inst, da, db, h->perm_row, h->perm_col, h->a_int, h->b_int);
+                       dim3(256), 0, s, h->d_inst, da, db, h->perm_row, h->perm_col, h->a_int, h->b_int,
+                       h->a_cal, h->b_cal);
     LAUNCHCHK();
   }
 
@@ -1132,6 +1138,10 @@ static ReduceArgs reduce_args(ot_gs_handle* h, bool dynamic, float* ga_out, floa
   R.tile_on = dynamic ? h->tile_on : nullptr;
   R.a_int = h->a_int;
   R.b_int = h->b_int;
+  R.a_cal = h->a_cal;
+  R.b_cal = h->b_cal;
+  R.alpha_cal = h->cal_alpha;
+  R.beta_cal = h->cal_beta;
   R.alpha = h->alpha;
   R.beta = h->beta;
   R.ga_int = h->ga;
@@ -1677,6 +1687,8 @@ static int dense_caller_order(ot_gs_handle* h, const float* alpha, const float* 
   ReduceArgs R = reduce_args(h, false, ga_out, gb_out);
   R.alpha = alpha;
   R.beta = beta;
+  R.alpha_cal = alpha;
+  R.beta_cal = beta;
   R.caller_order = 1;
   R.pro = prologue_args(h, OT_GS_DENSE);
   R.finalize = 1;
@@ -1696,6 +1708,13 @@ int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, floa
   if (flags & ~(OT_GS_CHECK | OT_GS_VERIFY)) return fail(OT_GS_EINVAL, "dual_grad: unknown mode flags 0x%x", flags);
   hipStream_t s = (hipStream_t)stream;
   if (!flags && base == OT_GS_DENSE && !h->onthefly) return dense_caller_order(h, alpha, beta, grad_alpha, grad_beta, obj, s);
+  // the assembly forms D from the caller's arrays, as the path above does
+  struct CallerDuals {
+    ot_gs_handle* h;
+    ~CallerDuals() { h->cal_alpha = h->cal_beta = nullptr; }
+  } caller_duals{h};
+  h->cal_alpha = alpha;
+  h->cal_beta = beta;
   if (!flags) {
     TRY(gather(h, alpha, beta, s, base));
     TRY(evaluate(h, base, grad_alpha, grad_beta, s, false, true, obj));
@@ -2034,7 +2053,7 @@ void ot_gs_default_options(ot_gs_options* o) {
   o->use_graph = 1;
   o->verify = 0;
   o->recenter = 1;
-  o->recenter_tol = 1e-10;
+  o->recenter_tol = 1e-9;
 }
 
 }  // extern "C"

@@ -68,6 +68,18 @@ static dim3 gemm_grid(const GemmArgs& g, int zparts) {
   return dim3((unsigned)ceil_div(g.N, 64), (unsigned)ceil_div(g.M, 64), (unsigned)zparts);
 }
 
+// deep stages for grids of a few hundred workgroups, shallow ones where
+// thousands of workgroups hide the latency
+template <int EPI>
+static int launch_gemm(const GemmArgs& g, dim3 grid, hipStream_t s) {
+  if ((long long)grid.x * grid.y * grid.z >= 2048)
+    hipLaunchKernelGGL((k_gemm_bf16<EPI, 32>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<EPI, 128>), grid, dim3(256), 0, s, g);
+  LAUNCHCHK();
+  return OT_GS_OK;
+}
+
 // forward of rows [0, n) of F (n <= max_rows): Z1, H1, Z2, H2, out; with y
 // also dout and the loss partials (mean over n rows)
 static int ws_forward(ot_gs_mlp* M, const float* F, int n, const float* y, float* out, hipStream_t s) {
@@ -75,12 +87,12 @@ static int ws_forward(ot_gs_mlp* M, const float* F, int n, const float* y, float
   GemmArgs g1 = gemm(n, w, din, F, din, 1, M->p + M->oW1(), w, 1, M->H1, w);
   g1.bias = M->p + M->ob1();
   g1.Z = M->Z1;
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS_GELU>, gemm_grid(g1, 1), dim3(256), 0, s, g1);
+  TRY(launch_gemm<EPI_BIAS_GELU>(g1, gemm_grid(g1, 1), s));
   LAUNCHCHK();
   GemmArgs g2 = gemm(n, w, w, M->H1, w, 1, M->p + M->oW2(), w, 1, M->H2, w);
   g2.bias = M->p + M->ob2();
   g2.Z = M->Z2;
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS_GELU>, gemm_grid(g2, 1), dim3(256), 0, s, g2);
+  TRY(launch_gemm<EPI_BIAS_GELU>(g2, gemm_grid(g2, 1), s));
   LAUNCHCHK();
   hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, (const float*)M->H2,
                      (const float*)(M->p + M->ow3()), (const float*)(M->p + M->ob3()), n, w, out, y,
@@ -107,7 +119,7 @@ static int ws_gemm_splitk(ot_gs_mlp* M, GemmArgs g, float* dst, hipStream_t s) {
   g.kchunk = WS_KCHUNK;
   g.C = M->parts;
   g.part_stride = (long long)g.M * g.ldc;
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_STORE>, gemm_grid(g, nz), dim3(256), 0, s, g);
+  TRY(launch_gemm<EPI_STORE>(g, gemm_grid(g, nz), s));
   LAUNCHCHK();
   const long long cnt = (long long)g.M * g.ldc;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)std::min<long long>(ceil_div(cnt, 256), 4096)), dim3(256), 0, s,
@@ -136,7 +148,7 @@ static int ws_loss_grad(ot_gs_mlp* M, const float* F, const float* y, int n, hip
   TRY(ws_gemm_splitk(M, gemm(w, w, n, M->H1, 1, w, M->dZ2, w, 1, nullptr, w), M->g + M->oW2(), s));
   GemmArgs gd = gemm(n, w, w, M->dZ2, w, 1, M->p + M->oW2(), 1, w, M->dZ1, w);
   gd.Zin = M->Z1;
-  hipLaunchKernelGGL(k_gemm_bf16<EPI_GELU_GRAD>, gemm_grid(gd, 1), dim3(256), 0, s, gd);
+  TRY(launch_gemm<EPI_GELU_GRAD>(gd, gemm_grid(gd, 1), s));
   LAUNCHCHK();
   // first layer: dW1 = F^T dZ1, db1
   TRY(ws_colsum(M, M->dZ1, nullptr, n, M->g + M->ob1(), s));

@@ -728,7 +728,15 @@ struct ReduceArgs {
   const uint8_t* tile_on;   // NULL: every tile was evaluated (dense)
   const float* a_int;
   const float* b_int;
-  const float* alpha;       // internal order
+  const float* a_cal;       // the marginals in the caller's order
+  const float* b_cal;
+  // the caller's alpha and beta (NULL: none): the objective's a.alpha and
+  // b.beta are then summed over caller rows and columns, so that every
+  // evaluation of ot_gs_dual_grad forms D in the same order whether its
+  // tiles read the caller's arrays or the internal copies
+  const float* alpha_cal;
+  const float* beta_cal;
+  const float* alpha;       // internal order (caller order with caller_order)
   const float* beta;
   float* ga_int;            // internal-order gradients (may be NULL)
   float* gb_int;
@@ -851,8 +859,12 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     // the row's own operands are loaded together with its partials
     const bool rok = r < I.ns;
     const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
-    const int pm_r = (rok && (A.ga_out || A.caller_order)) ? A.perm_row[I.row_off + r] : 0;
-    const float al_r = rok ? A.alpha[I.row_off + (A.caller_order ? pm_r : r)] : 0.f;
+    const int pm_r = (rok && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
+    // the row's share of a.alpha; with caller-order duals the share of
+    // caller row r (a.alpha is a sum over all rows, in any one-to-one order),
+    // so no index load precedes the alpha load
+    const float al_r = rok ? (A.alpha_cal ? A.alpha_cal : A.alpha)[I.row_off + r] : 0.f;
+    const float am_r = (rok && A.alpha_cal) ? A.a_cal[I.row_off + r] : a_r;
     const bool a_uni = A.a_uniform[k];
     if (rok) {
       const float* rp = A.rowpart + I.r_off + r;
@@ -870,7 +882,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       const float gval = a_r - s;
       if (A.ga_int) A.ga_int[I.row_off + r] = gval;
       if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
-      const double av = a_uni ? 1.0 / (double)I.ns : (double)a_r;
+      const double av = a_uni ? 1.0 / (double)I.ns : (double)am_r;
       part = av * (double)al_r;
     }
   } else {
@@ -878,8 +890,10 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     if (c < I.nt_pad) {
       const bool cok = c < I.nt;
       const float b_c = cok ? A.b_int[I.col_off + c] : 0.f;
-      const int pm_c = (cok && (A.gb_out || A.caller_order)) ? A.perm_col[I.col_off + c] : 0;
-      const float be_c = cok ? (A.caller_order ? A.beta[I.scol_off + pm_c] : A.beta[I.col_off + c]) : 0.f;
+      const int pm_c = (cok && A.gb_out) ? A.perm_col[I.col_off + c] : 0;
+      // b.beta as a.alpha above: caller column c's share with caller-order duals
+      const float be_c = cok ? (A.beta_cal ? A.beta_cal[I.scol_off + c] : A.beta[I.col_off + c]) : 0.f;
+      const float bm_c = (cok && A.beta_cal) ? A.b_cal[I.scol_off + c] : b_c;
       if (A.caller_order && !isfinite(be_c)) atomicOr(A.err, 8);
       const bool b_uni = A.b_uniform[k];
       const float* cs = A.colsum + (size_t)I.pair_off + c;
@@ -894,7 +908,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       if (A.gb_int) A.gb_int[I.col_off + c] = gval;
       if (A.gb_out && cok) A.gb_out[I.scol_off + pm_c] = gval;
       if (cok) {
-        const double bv = b_uni ? 1.0 / (double)I.nt : (double)b_c;
+        const double bv = b_uni ? 1.0 / (double)I.nt : (double)bm_c;
         part = bv * (double)be_c - e2 * (0.5 / I.gamma64);
       }
     }
@@ -911,13 +925,14 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     last = 0;
     if (A.finalize) {
       // the last block of the instance to finish forms D from the partials
-      __threadfence();
+      // (release: this block's partial is visible before its count)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       last = atomicAdd(&A.done[k], 1u) == (unsigned)(nbr + nbc - 1);
     }
   }
   __syncthreads();
   if (!last) return;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   if (threadIdx.x < 64) {
     const volatile double* parts = A.obj_part + (size_t)k * A.obj_stride;
     double t = 0.0;

@@ -201,14 +201,18 @@ __global__ void k_relayout_cost(const InstDev* __restrict__ inst, const float* c
 __global__ void k_marginals(const InstDev* __restrict__ inst, const float* const* __restrict__ a_src,
                             const float* const* __restrict__ b_src, const int* __restrict__ perm_row,
                             const int* __restrict__ perm_col, float* __restrict__ a_int,
-                            float* __restrict__ b_int) {
+                            float* __restrict__ b_int, float* __restrict__ a_cal, float* __restrict__ b_cal) {
   const InstDev I = inst[blockIdx.y];
   const float* a = a_src[blockIdx.y];
   const float* b = b_src[blockIdx.y];
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x)
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < I.ns; r += gridDim.x * blockDim.x) {
     a_int[I.row_off + r] = a ? a[perm_row[I.row_off + r]] : 1.0f / (float)I.ns;
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x)
+    a_cal[I.row_off + r] = a ? a[r] : 1.0f / (float)I.ns;
+  }
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < I.nt_pad; c += gridDim.x * blockDim.x) {
     b_int[I.col_off + c] = (c < I.nt) ? (b ? b[perm_col[I.col_off + c]] : 1.0f / (float)I.nt) : 0.f;
+    if (c < I.nt) b_cal[I.scol_off + c] = b ? b[c] : 1.0f / (float)I.nt;
+  }
 }
 
 }  // namespace otgs

@@ -50,8 +50,8 @@ struct GemmArgs {
 };
 
 // 64 x 64 output tile per workgroup of four wavefronts (32 x 32 each), K
-// in stages of GK = 128 through LDS.  Each stage the 256 threads load the
-// 64 x 128 slices of A and B along whichever index is contiguous in memory
+// in stages of GK (32 or 128) through LDS.  Each stage the 256 threads load
+// the 64 x GK slices of A and B along whichever index is contiguous in memory
 // (so the loads coalesce for plain and transposed operands alike), round
 // them to bfloat16 and store them in the matrix-core operand layout (k
 // contiguous per row of A and per column of B, rows padded against bank
@@ -60,12 +60,15 @@ struct GemmArgs {
 // flight in registers while the current stage multiplies.  The MFMA
 // sequence over k is that of a direct 16-step loop (steps past the end of
 // the chunk are not issued), so the results do not depend on the staging.
-constexpr int GK = 128;               // K per LDS stage
-constexpr int GLD = GK + 8;           // padded row length (bf16) of an LDS tile
-constexpr int GU = 64 * GK / 256;     // elements per thread and operand per stage
-
-template <int EPI>
+// GK = 128 takes a 256-deep chunk in two stages (few workgroups: the
+// split-K weight gradients, 4096-row batches); GK = 32 keeps the registers
+// and LDS of a workgroup small, for grids of thousands of workgroups where
+// occupancy hides the latency.
+template <int EPI, int GK>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  constexpr int GLD = GK + 8;           // padded row length (bf16) of an LDS tile
+  constexpr int GU = 64 * GK / 256;     // elements per thread and operand per stage
+  constexpr int RS = 256 / GK;          // rows per load instruction along k
   __shared__ short As[64 * GLD];
   __shared__ short Bs[64 * GLD];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -75,12 +78,12 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   const bool a_krow = g.a_cs == 1;   // A(i, k): k contiguous
   const bool b_kcol = g.b_rs == 1;   // B(k, j): k contiguous
   // element u of this thread in a stage: (row or column, k) of the tile;
-  // each load instruction covers 64 consecutive k of one row, or 64
-  // consecutive rows of one k, whichever runs along memory
+  // each load instruction covers min(GK, 64) consecutive k of one or more
+  // rows, or 64 consecutive rows of one k, whichever runs along memory
   auto a_at = [&](int u, int& r, int& k) {
     if (a_krow) {
-      r = (t >> 7) + 2 * u;
-      k = t & 127;
+      r = t / GK + RS * u;
+      k = t % GK;
     } else {
       r = t & 63;
       k = (t >> 6) + 4 * u;
@@ -88,8 +91,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   };
   auto b_at = [&](int u, int& c, int& k) {
     if (b_kcol) {
-      c = (t >> 7) + 2 * u;
-      k = t & 127;
+      c = t / GK + RS * u;
+      k = t % GK;
     } else {
       c = t & 63;
       k = (t >> 6) + 4 * u;
