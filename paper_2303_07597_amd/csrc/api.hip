@@ -112,6 +112,12 @@ struct ot_gs_handle {
   } ver;
   float *a_int = nullptr, *b_int = nullptr;
   float *a_cal = nullptr, *b_cal = nullptr;   // the marginals in the caller's order
+  // dense ot_gs_dual_grad of a materialised cost: 1 the tiles read the
+  // caller's duals through the index maps (no gather launch), 0 a gather
+  // then the internal order; -1 by size (the maps' index loads cost more
+  // than the gather saves once the cost pool is large); the autotuner sets it
+  // from measurement
+  int dense_direct = -1;
   // the caller's duals of the ot_gs_dual_grad call in progress (NULL outside one)
   const float *cal_alpha = nullptr, *cal_beta = nullptr;
   int *a_uniform = nullptr, *b_uniform = nullptr;
@@ -1505,8 +1511,18 @@ static void cache_apply(ot_gs_handle* h) {
 
 // time `repeats` dense launches of one bucket's tile kernel (or the split
 // passes, b = NBUCKET) under the handle's current configuration
-static int time_bucket(ot_gs_handle* h, int b, int repeats, hipStream_t s, float* ms) {
+// (cal_a, cal_b: the current point in the caller's order; the tiles then
+// read it as a dense ot_gs_dual_grad does)
+static int time_bucket(ot_gs_handle* h, int b, int repeats, hipStream_t s, float* ms, const float* cal_a = nullptr,
+                       const float* cal_b = nullptr) {
   GradArgs A = grad_args(h);
+  if (cal_a) {
+    A.alpha = cal_a;
+    A.beta = cal_b;
+    A.row_map = h->row_map;
+    A.col_map = h->col_map;
+    A.inst_mode = h->mode_dense;
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1532,6 +1548,9 @@ static int time_bucket(ot_gs_handle* h, int b, int repeats, hipStream_t s, float
   return rc;
 }
 
+static int dense_caller_order(ot_gs_handle* h, const float* alpha, const float* beta, float* ga_out,
+                              float* gb_out, double* obj, hipStream_t s);
+
 static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
   const bool was_on = h->timing.on;
   h->timing.on = false;
@@ -1540,6 +1559,75 @@ static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
                      h->counters, 0LL, 0LL);
   LAUNCHCHK();
   auto cache = cache_read();
+  // materialised handles are timed on the read path of dense
+  // ot_gs_dual_grad calls (caller-order duals through the index maps), with
+  // the current point scattered into caller order; a handle in a caller's
+  // workspace, which allocates nothing more, is timed on the internal order
+  float* cal = nullptr;
+  if (!h->onthefly && !h->ws_base) {
+    const size_t nr = (size_t)h->tot_rows, nc = (size_t)std::max<long long>(h->tot_cols, 1);
+    if (hipMalloc(&cal, sizeof(float) * (nr + nc)) == hipSuccess) {
+      const long long maxv = std::max<long long>(h->max_ns, h->max_ntp);
+      hipLaunchKernelGGL(k_scatter_duals, dim3((unsigned)std::min<long long>(ceil_div(maxv, 256), 1024), h->count),
+                         dim3(256), 0, s, h->d_inst, h->perm_row, h->perm_col, (const float*)h->alpha,
+                         (const float*)h->beta, cal, cal + nr);
+      LAUNCHCHK();
+    } else {
+      (void)hipGetLastError();
+      cal = nullptr;
+    }
+  }
+  struct CalFree {
+    float*& p;
+    ~CalFree() {
+      if (p) (void)hipFree(p);
+    }
+  } cal_free{cal};
+  const float* cal_b = cal ? cal + h->tot_rows : nullptr;
+  if (cal) {
+    // the read path of dense ot_gs_dual_grad calls: whole evaluations each
+    // way at the current point, the faster kept; the tile shapes are then
+    // tuned on that path
+    float* out = nullptr;
+    const size_t nr = (size_t)h->tot_rows, nc = (size_t)std::max<long long>(h->tot_cols, 1);
+    if (hipMalloc(&out, sizeof(float) * (nr + nc) + sizeof(double) * h->count) == hipSuccess) {
+      struct OutFree {
+        float* p;
+        ~OutFree() { (void)hipFree(p); }
+      } out_free{out};
+      double* obj = (double*)(out + nr + nc);
+      float best[2] = {INFINITY, INFINITY};
+      for (int direct = 0; direct < 2; ++direct) {
+        auto eval = [&]() -> int {
+          if (direct) return dense_caller_order(h, cal, cal_b, out, out + nr, obj, s);
+          TRY(gather(h, cal, cal_b, s, OT_GS_DENSE));
+          return evaluate(h, OT_GS_DENSE, out, out + nr, s, false, true, obj);
+        };
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        int rc = eval();
+        if (rc == OT_GS_OK) {
+          (void)hipEventRecord(e0, s);
+          for (int i = 0; i < repeats && rc == OT_GS_OK; ++i) rc = eval();
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          (void)hipEventElapsedTime(&best[direct], e0, e1);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != OT_GS_OK) {
+          h->timing.on = was_on;
+          return rc;
+        }
+      }
+      h->dense_direct = best[1] <= best[0] ? 1 : 0;
+    } else {
+      (void)hipGetLastError();
+    }
+    if (h->dense_direct == 0) cal_b = nullptr;
+  }
+  const float* cal_a = cal_b ? cal : nullptr;
   static const int gms[] = {1, 2, 4};
   for (int b = 0; b <= NBUCKET; ++b) {
     const int n = bucket_tiles(h, b);
@@ -1552,7 +1640,7 @@ static int autotune_impl(ot_gs_handle* h, int repeats, hipStream_t s) {
         h->tile_var[b] = var;
         h->tile_gm[b] = gm;
         float ms = 0.f;
-        const int rc = time_bucket(h, b, repeats, s, &ms);
+        const int rc = time_bucket(h, b, repeats, s, &ms, cal_a, cal_b);
         if (rc != OT_GS_OK) {
           h->timing.on = was_on;
           return rc;
@@ -1666,6 +1754,12 @@ int ot_gs_create(const ot_gs_problem* probs, int count, ot_gs_handle** out, void
 
 void ot_gs_destroy(ot_gs_handle* h) { delete h; }
 
+static bool use_dense_direct(const ot_gs_handle* h) {
+  if (h->onthefly) return false;
+  if (h->dense_direct >= 0) return h->dense_direct != 0;
+  return h->c_pool <= (64ll << 20);   // up to 8192^2 entries
+}
+
 // Dense evaluation of caller-order duals in two launches: the tiles read
 // alpha and beta through the caller-order maps (every instance's mode read
 // as dense), the assembly reads them through the permutations, flags
@@ -1707,7 +1801,8 @@ int ot_gs_dual_grad(ot_gs_handle* h, const float* alpha, const float* beta, floa
     return fail(OT_GS_EINVAL, "dual_grad: unknown mode %d", base);
   if (flags & ~(OT_GS_CHECK | OT_GS_VERIFY)) return fail(OT_GS_EINVAL, "dual_grad: unknown mode flags 0x%x", flags);
   hipStream_t s = (hipStream_t)stream;
-  if (!flags && base == OT_GS_DENSE && !h->onthefly) return dense_caller_order(h, alpha, beta, grad_alpha, grad_beta, obj, s);
+  if (!flags && base == OT_GS_DENSE && use_dense_direct(h))
+    return dense_caller_order(h, alpha, beta, grad_alpha, grad_beta, obj, s);
   // the assembly forms D from the caller's arrays, as the path above does
   struct CallerDuals {
     ot_gs_handle* h;
@@ -1948,12 +2043,15 @@ int ot_gs_profile_tiles(ot_gs_handle* h, const float* alpha, const float* beta, 
   const bool was_on = h->timing.on;
   h->timing.on = false;
   GradArgs A = grad_args(h);
-  if (alpha) {
+  if (alpha && use_dense_direct(h)) {
     A.alpha = alpha;
     A.beta = beta;
     A.row_map = h->row_map;
     A.col_map = h->col_map;
     A.inst_mode = h->mode_dense;
+  } else if (alpha) {
+    // the handle's dense evaluations gather first: so does this
+    TRY(gather(h, alpha, beta, s));
   }
   HIPCHK(hipEventRecord(e0, s));
   for (int i = 0; i < repeats; ++i) TRY(launch_tiles(h, A, false, false, s));
@@ -2464,7 +2562,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
         LbParams P0 = P;
         const LbArgs A0 = lb_args(h, P0);
         const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8),
-                      (unsigned)std::min(h->max_ns, 4096), h->count);
+                      (unsigned)std::min(h->max_ns, 256), h->count);
         hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A0, (const float*)h->C, h->Cw,
                            (const int*)h->row_grp, (const int*)h->g_start, (const int*)h->g_size, h->cmax_w, 1);
         LAUNCHCHK();
@@ -2548,7 +2646,7 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
                          (const float*)h->b_int, (const int*)h->a_uniform, (const int*)h->b_uniform, h->zsnap,
                          h->osnap, h->inN, h->cmax_w);
       LAUNCHCHK();
-      const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8), (unsigned)std::min(h->max_ns, 4096),
+      const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8), (unsigned)std::min(h->max_ns, 256),
                     h->count);
       hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A, (const float*)h->C, h->Cw, (const int*)h->row_grp,
                          (const int*)h->g_start, (const int*)h->g_size, h->cmax_w, 0);

@@ -35,10 +35,11 @@ namespace otgs {
 
 // rows per split-K partial of the weight gradients and per partial of the
 // column sums: a 4096-row batch gives 16 x 16 workgroups for a 256 x 256
-// weight gradient and 64 x (width / 256) for a column sum (one workgroup per
-// partial would leave the chip nearly idle)
+// weight gradient and 256 x (width / 256) for a column sum, whose partials
+// are then added 16 threads per column (one workgroup per partial of 4096
+// rows would leave the chip nearly idle)
 constexpr int WS_KCHUNK = 256;
-constexpr int WS_COLROWS = 64;
+constexpr int WS_COLROWS = 16;
 
 static int ws_parts_needed(const ot_gs_mlp* M) {
   const long long nk = ceil_div(M->max_rows, WS_KCHUNK), nc = ceil_div(M->max_rows, WS_COLROWS);
@@ -107,8 +108,8 @@ static int ws_colsum(ot_gs_mlp* M, const float* A, const float* wt, int n, float
   hipLaunchKernelGGL(k_colsum_parts, dim3((unsigned)ceil_div(M->w, 256), nc), dim3(256), 0, s, A, wt, n, M->w,
                      WS_COLROWS, M->parts);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(M->w, 256)), dim3(256), 0, s, (const float*)M->parts, nc,
-                     (long long)M->w, (long long)M->w, dst);
+  hipLaunchKernelGGL(k_sum_parts_wide, dim3((unsigned)ceil_div(M->w, 64)), dim3(1024), 0, s, (const float*)M->parts,
+                     nc, (long long)M->w, (long long)M->w, dst);
   LAUNCHCHK();
   return OT_GS_OK;
 }

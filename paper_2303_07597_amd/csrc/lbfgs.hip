@@ -1111,8 +1111,16 @@ __global__ void __launch_bounds__(256) k_recenter_cost(LbArgs A, const float* __
       mx = fmaxf(mx, fabsf(v));
     }
   }
+  // one atomic per workgroup (the maximum is order-free): a wavefront-level
+  // atomic from every wavefront of a large grid serialised on one address
+  __shared__ float wm[4];
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-  if ((threadIdx.x & 63) == 0) atomicMax((unsigned int*)&cmax_w[k], __float_as_uint(mx));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    atomicMax((unsigned int*)&cmax_w[k], __float_as_uint(m));
+  }
 }
 
 // (all = 1: every instance, rebuilding the working cost of a solver state

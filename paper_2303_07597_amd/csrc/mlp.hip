@@ -174,6 +174,26 @@ __global__ void k_sum_parts(const float* __restrict__ parts, int nparts, long lo
   }
 }
 
+// The same sums for few elements and many partials (the column sums of a
+// layer): 16 threads per element each add the partials z = j, j + 16, ...
+// in order, then the element's first thread adds the 16 sums in order.
+__global__ void __launch_bounds__(1024) k_sum_parts_wide(const float* __restrict__ parts, int nparts,
+                                                         long long stride, long long n, float* __restrict__ out) {
+  __shared__ float sm[16][64];
+  const int c = threadIdx.x & 63, j = threadIdx.x >> 6;
+  const long long e = (long long)blockIdx.x * 64 + c;
+  float s = 0.f;
+  if (e < n)
+    for (int z = j; z < nparts; z += 16) s += parts[(long long)z * stride + e];
+  sm[j][c] = s;
+  __syncthreads();
+  if (j == 0 && e < n) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += sm[q][c];
+    out[e] = t;
+  }
+}
+
 // ---------------------------------------------------------------- head and loss
 
 // out_i = sum_k r(H2[i, k]) r(w3[k]) + b3, one wavefront per row (each lane a
