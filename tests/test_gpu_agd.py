@@ -116,3 +116,24 @@ def test_options_are_checked():
     with pytest.raises(O.OTGSError) as e:
         h.solve(max_iter=5, solver=7)
     assert e.value.code == O.OT_GS_EINVAL
+
+
+
+
+def test_onthefly_cost_screened_equals_dense_and_follows_the_oracle():
+    """Cost recomputed on the matrix cores (integer features, power-of-two
+    scale: the cost is exact): screened and dense accelerated ascent follow
+    the same trajectory, and the first steps follow the oracle's."""
+    from tests.test_gpu_onthefly import int_instance, otf_handle
+    inst = int_instance(41, [300, 40, 7, 200], 250, 20, gamma=0.2, mu=0.3)
+    scale = 2.0 ** -9
+    h = otf_handle(inst, scale)
+    ad, bd, infod, trd, _ = run_agd(h, 300, use_screen=0)
+    as_, bs_, infos, trs, _ = run_agd(h, 300, use_screen=1, refresh=5)
+    np.testing.assert_array_equal(trd, trs)
+    np.testing.assert_array_equal(ad, as_)
+    np.testing.assert_array_equal(bd, bs_)
+    C = oracle.cost_sqeuclid(inst["xs"], inst["xt"]) * scale
+    P = oracle.Problem(C, inst["labels"], inst["n_groups"], inst["gamma"], inst["mu"])
+    ref = oracle.agd_solve(P, max_iter=30, max_bt=60)
+    np.testing.assert_allclose(trd[0][:31], ref["trace"][:31], rtol=2e-5, atol=1e-7)

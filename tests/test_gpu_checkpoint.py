@@ -173,3 +173,21 @@ def test_statistics_and_gradient_traces():
     # each iteration computed at most the tiles it covered
     d = np.diff(S[:it + 1], axis=0)
     assert np.all(d[:, 7] <= d[:, 6])
+
+
+def test_resume_with_the_cost_on_the_fly():
+    from tests.test_gpu_onthefly import int_instance, otf_handle
+    inst = int_instance(42, [300, 40, 7, 200], 250, 20, gamma=0.2, mu=0.3)
+    scale = 2.0 ** -9
+    K, M = 150, 60
+    a_ref, b_ref, info_ref, tr_ref = traced(otf_handle(inst, scale), K, use_screen=1)
+    h = otf_handle(inst, scale)
+    traced(h, M, use_screen=1)
+    state = h.solver_state()
+    h2 = otf_handle(inst, scale)
+    h2.load_solver_state(state)
+    a, b, info, tr = traced(h2, K, use_screen=1, resume=1)
+    np.testing.assert_array_equal(tr[0][M + 1:], tr_ref[0][M + 1:])
+    np.testing.assert_array_equal(a, a_ref)
+    np.testing.assert_array_equal(b, b_ref)
+    assert info[0] == info_ref[0]
