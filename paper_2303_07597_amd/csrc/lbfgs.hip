@@ -224,16 +224,13 @@ __device__ __forceinline__ double lb_slot_dots(const float* gt, const float* s_,
   return lane == 0 ? s0 : lane == 1 ? s1 : s2;
 }
 
-// grid (maxb, count, 1 + hist), one wavefront per block, LB_PER_THREAD
-// elements per lane.  blockIdx.z = 0 forms the five base dots, z = 1 + i the
-// three dots of history slot i, so every block issues all its loads at once.
+// One wavefront per (vector block b, slot z) of instance k, LB_PER_THREAD
+// elements per lane: z = 0 forms the five base dots, z = 1 + i the three
+// dots of history slot i, so every wavefront issues all its loads at once.
 // Each lane adds its elements' products, fixed-order wavefront reductions
-// (maximum for dot 4) give one float64 partial per block and dot.
-__global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
-  const int k = blockIdx.y, b = blockIdx.x, z = blockIdx.z;
-  const int lane = threadIdx.x;
-  // the instance, its vector offset and its state are read together
-  const InstDev I = A.inst[k];
+// (maximum for dot 4) give one float64 partial per block and dot.  Run by
+// k_lbfgs_dots (grid (maxb, count, 1 + hist)).
+__device__ __forceinline__ void lb_dots_wave(const LbArgs& A, const InstDev& I, int k, int b, int z, int lane) {
   const long long v0 = A.voff[k];
   const LbState& S = A.st[k];
   const int st_status = S.status, st_phase = S.phase, st_count = S.count;
@@ -273,6 +270,13 @@ __global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
   const double t = z == 0 ? lb_base_dots(gt, v1, v2, lane, gm) : lb_slot_dots(gt, v1, v2, dv, lane);
   const int nd = z == 0 ? 5 : 3;
   if (lane < nd) out[(size_t)((z == 0 ? 0 : 5 + 3 * slot) + lane) * A.maxb] = t;
+}
+
+__global__ void __launch_bounds__(LB_BLOCK) k_lbfgs_dots(LbArgs A) {
+  // the instance, its vector offset and its state are read together
+  const int k = blockIdx.y;
+  const InstDev I = A.inst[k];
+  lb_dots_wave(A, I, k, blockIdx.x, blockIdx.z, threadIdx.x);
 }
 
 // Batches of many instances: grid (maxb, count, LB_SEQ_SPLIT), wavefront z
@@ -705,12 +709,29 @@ __device__ void lb_ctrl_logic(const LbArgs& A, int k, LbState& S, LbGram& G, con
   }
 }
 
-// one wavefront per instance; the state lives in LDS during the step
-__global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
-  __shared__ double dots[5 + 3 * HMAX];
-  __shared__ LbState S;
-  __shared__ double gram_s[2 * HMAX * HMAX];
-  const int k = blockIdx.x;
+// LDS of one control step (one wavefront per instance; the state lives in
+// LDS during the step)
+struct LbCtrlShared {
+  double dots[5 + 3 * HMAX];
+  LbState S;
+  double gram[2 * HMAX * HMAX];
+};
+
+// LDS ordering between the lanes of the one wavefront that runs a control
+// step (a wavefront-level barrier: the step needs no other wavefront)
+__device__ __forceinline__ void lb_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The control step of instance k on one wavefront (lanes 0..63 of the
+// calling block): sums the dot and objective partials, runs the control
+// logic and writes the state and Gram matrices back.
+__device__ void lb_ctrl_wave(const LbArgs& A, int k, LbCtrlShared& sh) {
+  double* dots = sh.dots;
+  LbState& S = sh.S;
+  double* gram_s = sh.gram;
   const int h = A.P.hist;
   double* gram_g = A.gram + (size_t)k * 2 * h * h;
   // Every load of the step is issued at once, before any is used: the
@@ -722,7 +743,7 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
   constexpr int PD = 16, PO = 4;
   constexpr int NV = (int)(sizeof(LbState) / 16);
   static_assert(NV <= 2 * 64, "state copy assumes at most two int4 per lane");
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int ng = 2 * h * h;
   const double* pk = A.part + (size_t)k * A.ndot * A.maxb;
   const bool has1 = lane < A.ndot, has2 = lane + 64 < A.ndot;
@@ -799,16 +820,21 @@ __global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
     if (u * 64 + lane < nob) os += po[u];
   for (int i = PO * 64 + lane; i < nob; i += 64) os += osrc[i];
   const double Dobj = wave_sum_dd(os) + (A.obj_const ? A.obj_const[k] : 0.0);
-  __syncthreads();
-  if (threadIdx.x == 0) A.obj_out[k] = Dobj;
+  lb_wave_sync();
+  if (lane == 0) A.obj_out[k] = Dobj;
   lb_ctrl_logic(A, k, S, G, dots, Dobj);
-  __syncthreads();
-  for (int q = threadIdx.x; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
+  lb_wave_sync();
+  for (int q = lane; q < 2 * h * h; q += 64) gram_g[q] = gram_s[q];
   {
     const int4* src = (const int4*)&S;
     int4* dst = (int4*)&A.st[k];
-    for (int i = threadIdx.x; i < (int)(sizeof(LbState) / 16); i += 64) dst[i] = src[i];
+    for (int i = lane; i < (int)(sizeof(LbState) / 16); i += 64) dst[i] = src[i];
   }
+}
+
+__global__ void __launch_bounds__(64) k_lbfgs_ctrl(LbArgs A) {
+  __shared__ LbCtrlShared sh;
+  lb_ctrl_wave(A, blockIdx.x, sh);
 }
 // the vector work of one element e of instance k: record the snapshot,
 // accept the trial point, push (s, y), form the new direction and the next
@@ -851,10 +877,8 @@ __device__ __forceinline__ float lb_update_elem(const LbArgs& A, const InstDev& 
   return xn;
 }
 
-// grid (vector blocks, count); accept, push, new direction, next trial point
-__global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
-  const int k = blockIdx.y;
-  const InstDev I = A.inst[k];
+// the update of elements e0, e0 + stride, ... of instance k
+__device__ __forceinline__ void lb_update_elems(const LbArgs& A, const InstDev& I, int k, int e0, int stride) {
   const LbState& S = A.st[k];
   const int n = I.ns + I.nt_pad;
   const long long v0 = A.voff[k];
@@ -862,10 +886,17 @@ __global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
   const bool snap = S.mode_eval == EM_SNAPSHOT;
   const bool wu = A.w_unit[k] != 0;
   if (lb_update_idle(A, S)) return;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+  for (int e = e0; e < n; e += stride) {
     float so;
     lb_update_elem(A, I, S, e, v0, h, snap, wu, so);
   }
+}
+
+// grid (vector blocks, count); accept, push, new direction, next trial point
+__global__ void __launch_bounds__(256) k_lbfgs_update(LbArgs A) {
+  const int k = blockIdx.y;
+  const InstDev I = A.inst[k];
+  lb_update_elems(A, I, k, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // The same update, with the group statistics of alpha - alpha~ that the

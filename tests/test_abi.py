@@ -42,3 +42,5 @@ def test_host_only_entry_points():
     o = O.ot_gs_options()
     O.lib().ot_gs_default_options(ctypes.byref(o))
     assert (o.max_iter, o.hist, o.refresh, o.use_screen, o.max_ls) == (200, 10, 10, 1, 40)
+    # the struct's last field (its layout agrees up to its end)
+    assert o.recenter_tol == 1e-9
