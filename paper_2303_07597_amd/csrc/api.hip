@@ -1711,6 +1711,9 @@ static int reserve_all(ot_gs_handle* h, int max_hist, hipStream_t s) {
   return OT_GS_OK;
 }
 
+template <class Step>
+static int capture_n(ot_gs_handle* h, int n, hipGraphExec_t* exec, Step&& step);
+
 extern "C" {
 
 int ot_gs_workspace_size(const ot_gs_problem* probs, int count, int max_hist, size_t* bytes, void* stream) {
@@ -2053,8 +2056,18 @@ int ot_gs_profile_tiles(ot_gs_handle* h, const float* alpha, const float* beta, 
     // the handle's dense evaluations gather first: so does this
     TRY(gather(h, alpha, beta, s));
   }
+  // the launches recorded into a graph and replayed (once to warm up), so
+  // that the time between two events is the launches' own, with the short
+  // in-graph gaps between them
+  hipGraphExec_t exec = nullptr;
+  TRY(capture_n(h, repeats, &exec, [&](hipStream_t cs) { return launch_tiles(h, A, false, false, cs); }));
+  struct ExecFree {
+    hipGraphExec_t e;
+    ~ExecFree() { (void)hipGraphExecDestroy(e); }
+  } exec_free{exec};
+  HIPCHK(hipGraphLaunch(exec, s));
   HIPCHK(hipEventRecord(e0, s));
-  for (int i = 0; i < repeats; ++i) TRY(launch_tiles(h, A, false, false, s));
+  HIPCHK(hipGraphLaunch(exec, s));
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
   h->timing.on = was_on;

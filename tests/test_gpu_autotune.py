@@ -97,3 +97,22 @@ def test_autotune_caches_and_applies(tmp_path):
         assert [h2.get_tile_config(k) for k in range(O.NBUCKET + 1)] == tuned
     finally:
         del os.environ["OTGS_AUTOTUNE_CACHE"]
+
+
+@pytest.mark.parametrize("mode_name", ["OT_GS_COST_ONTHEFLY", "OT_GS_COST_MATERIALIZE"])
+def test_profile_tiles_times_and_leaves_results(mode_name):
+    """The tile-launch timer (its launches recorded into a graph and
+    replayed) returns a positive time, at the handle's own point and, for a
+    materialised cost, at caller-order duals, and later evaluations give the
+    same bits as before it ran."""
+    O = _O()
+    h = _handle(_instance(5000), getattr(O, mode_name))
+    a, b, _, _ = h.solve(max_iter=10, use_screen=0)
+    ref = _evals(h, [(a, b)], O)
+    us = [h.profile_tiles(3)]
+    if mode_name == "OT_GS_COST_MATERIALIZE":
+        us.append(h.profile_tiles(3, alpha=a, beta=b))
+    torch.cuda.synchronize()
+    assert all(np.isfinite(u) and u > 0 for u in us), us
+    for x, y in zip(_evals(h, [(a, b)], O), ref):
+        np.testing.assert_array_equal(x, y)
