@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(64) k_agd_ctrl(AgdArgs G) {
   }
   qq = __shfl(qq, 0);
   gmax = __shfl(gmax, 0);
-  const int nob = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
+  const int nob = asm_obj_parts(I);
   const double* osrc = A.obj_part + (size_t)k * A.obj_stride;
   double os = 0.0;
   for (int i = lane; i < nob; i += 64) os += osrc[i];

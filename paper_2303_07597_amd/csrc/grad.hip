@@ -1,6 +1,6 @@
-// The hot path: fused dual-gradient tiles, the fixed-order reductions that
-// assemble grad_alpha = a - T 1, grad_beta = b - T^T 1 and the objective of
-// the smooth relaxed dual (Eq. 4).
+// The hot path: fused dual-gradient tiles of the smooth relaxed dual (Eq. 4):
+// per tile the row partials of T 1, the column sums of T and the per-pair
+// group statistics (assemble.hip reduces them into the gradients and D).
 //
 // Gradient tile (group l, TJ = 32 target columns j): lane 32 h + c takes
 // column c and the rows of parity h, streams the tile's cost (one
@@ -715,241 +715,6 @@ __device__ __forceinline__ void prologue_body(const Prologue& P) {
     atomicAdd(&C[CNT_TILES_COMPUTED], (unsigned long long)P.tiles);
   }
 }
-
-
-struct ReduceArgs {
-  const InstDev* inst;
-  const int* row_grp;
-  const int* perm_row;
-  const int* perm_col;
-  const float* rowpart;
-  const float* colsum;
-  const float* excess;
-  const uint8_t* tile_on;   // NULL: every tile was evaluated (dense)
-  const float* a_int;
-  const float* b_int;
-  const float* a_cal;       // the marginals in the caller's order
-  const float* b_cal;
-  // the caller's alpha and beta (NULL: none): the objective's a.alpha and
-  // b.beta are then summed over caller rows and columns, so that every
-  // evaluation of ot_gs_dual_grad forms D in the same order whether its
-  // tiles read the caller's arrays or the internal copies
-  const float* alpha_cal;
-  const float* beta_cal;
-  const float* alpha;       // internal order (caller order with caller_order)
-  const float* beta;
-  float* ga_int;            // internal-order gradients (may be NULL)
-  float* gb_int;
-  float* ga_out;            // caller-order gradients (may be NULL)
-  float* gb_out;
-  double* obj;              // [count]
-  double* obj_part;         // [count][obj_stride] assembly partials of D
-  long long obj_stride;
-  int max_ns;               // largest n_src over the instances (grid layout)
-  const int* a_uniform;     // per instance flags
-  const int* b_uniform;
-  int* err;
-  unsigned int* done;       // finalize: assembly blocks finished, per instance (reset by the last)
-  double* obj_out;          // finalize: caller's copy of D (may be NULL)
-  int finalize;             // 1: the last assembly block of an instance forms D
-  const int* inst_mode;     // EvalMode per instance
-  int* zero_first;          // solver steps: the step's count of live instances, zeroed here (may be NULL)
-  // dense evaluations straight from the caller's arrays: alpha and beta are
-  // in the caller's order (read through perm_row / perm_col and checked for
-  // NaN / Inf here), and block (0, 0) runs the evaluation prologue after
-  // the tiles (which read every mode as dense)
-  int caller_order;
-  Prologue pro;
-};
-
-constexpr int ASM_BLOCK = 256;
-constexpr int ASM_LPR = 8;                      // lanes per row
-constexpr int ASM_ROWS = ASM_BLOCK / ASM_LPR;   // rows per assembly block
-constexpr int ASM_U = 16;                      // loads per lane in flight
-
-// Blocks of the assembly kernel per instance: row blocks, then column blocks.
-__host__ __device__ inline int asm_row_blocks(int ns) { return (ns + ASM_ROWS - 1) / ASM_ROWS; }
-__host__ __device__ inline int asm_col_blocks(int ntp) { return (ntp + ASM_BLOCK - 1) / ASM_BLOCK; }
-
-// Row sum of lane q of a row: jb = q, q + ASM_LPR, ... added in that order.
-// Each batch issues all its ASM_U loads before the first add; indices past
-// the end are clamped to the last slot (a valid address) and not added.
-// With MASK, a tile the screen skipped adds an exact zero (its slot holds
-// stale data, discarded by the select).
-template <bool MASK>
-__device__ __forceinline__ float asm_row_sum(const float* rp, int ns, int njb, const uint8_t* on, int q) {
-  float s = 0.f;
-  for (int j0 = q; j0 < njb; j0 += ASM_U * ASM_LPR) {
-    float v[ASM_U];
-    uint8_t f[ASM_U];
-#pragma unroll
-    for (int u = 0; u < ASM_U; ++u) {
-      const int jb = min(j0 + u * ASM_LPR, njb - 1);
-      v[u] = rp[(size_t)jb * ns];
-      if (MASK) f[u] = on[jb];
-    }
-#pragma unroll
-    for (int u = 0; u < ASM_U; ++u)
-      if (j0 + u * ASM_LPR < njb) s += (!MASK || f[u]) ? v[u] : 0.f;
-  }
-  return s;
-}
-
-// Column c over the groups of its instance, in group order: sum of the
-// column partials and of excess^2 (float64); batches as in asm_row_sum.
-template <bool MASK>
-__device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, int nt_pad, int Le,
-                                            const uint8_t* on, int njb, float& s, double& e2) {
-  s = 0.f;
-  e2 = 0.0;
-  for (int g0 = 0; g0 < Le; g0 += ASM_U) {
-    float cv[ASM_U], ev[ASM_U];
-    uint8_t f[ASM_U];
-#pragma unroll
-    for (int u = 0; u < ASM_U; ++u) {
-      const int g = min(g0 + u, Le - 1);
-      cv[u] = cs[(size_t)g * nt_pad];
-      ev[u] = ex[(size_t)g * nt_pad];
-      if (MASK) f[u] = on[(size_t)g * njb];
-    }
-#pragma unroll
-    for (int u = 0; u < ASM_U; ++u) {
-      if (g0 + u < Le) {
-        const bool keep = !MASK || f[u];
-        const double e = ev[u];
-        s += keep ? cv[u] : 0.f;
-        e2 += keep ? e * e : 0.0;
-      }
-    }
-  }
-}
-
-
-// Assembly, grid (max row blocks + max column blocks, count):
-//  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 lanes per row
-//                  take jb = q mod 8 in order, then a fixed xor tree), and the
-//                  block's float64 share of a.alpha;
-//  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order and
-//                  the block's share of b.beta - sum_l excess_lc^2 / (2 gamma).
-// Only evaluated tiles are summed (skipped ones are exact zeros).  Each
-// block writes one float64 partial of D; when finalising, the last block of
-// an instance to finish (or else the solver's control kernel) adds them in
-// block order.
-__global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
-  __shared__ double red[ASM_BLOCK / 64];
-  const int k = blockIdx.y;
-  if (A.zero_first && blockIdx.x == 0 && k == 0 && threadIdx.x == 0) *A.zero_first = 0;
-  if (A.caller_order && blockIdx.x == 0 && k == 0) prologue_body(A.pro);
-  // inside a batched solve, an instance whose solve has ended (mode SKIP)
-  // has no tiles evaluated and nothing reads its gradient or D: its blocks
-  // leave at once (calls that finalize D never see SKIP)
-  if (!A.finalize && A.inst_mode[k] == EM_SKIP) return;
-  const InstDev I = A.inst[k];
-  // per-instance layout of the partials (rows, then columns), so that an
-  // instance's objective does not depend on the other instances of a batch
-  const int nbr = asm_row_blocks(I.ns);
-  const int nbc = asm_col_blocks(I.nt_pad);
-  const int b = blockIdx.x;
-  if (b >= nbr + nbc) return;
-  double part = 0.0;
-  if (b < nbr) {
-    const int r = b * ASM_ROWS + threadIdx.x / ASM_LPR;
-    const int q = threadIdx.x % ASM_LPR;
-    float s = 0.f;
-    // the row's own operands are loaded together with its partials
-    const bool rok = r < I.ns;
-    const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
-    const int pm_r = (rok && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
-    // the row's share of a.alpha; with caller-order duals the share of
-    // caller row r (a.alpha is a sum over all rows, in any one-to-one order),
-    // so no index load precedes the alpha load
-    const float al_r = rok ? (A.alpha_cal ? A.alpha_cal : A.alpha)[I.row_off + r] : 0.f;
-    const float am_r = (rok && A.alpha_cal) ? A.a_cal[I.row_off + r] : a_r;
-    const bool a_uni = A.a_uniform[k];
-    if (rok) {
-      const float* rp = A.rowpart + I.r_off + r;
-      if (A.tile_on)
-        s = asm_row_sum<true>(rp, I.ns, I.njb, A.tile_on + I.tile_off + (size_t)A.row_grp[I.row_off + r] * I.njb, q);
-      else
-        s = asm_row_sum<false>(rp, I.ns, I.njb, nullptr, q);
-    }
-    // fixed-order combine of the lanes of a row (xor tree over 8 lanes)
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
-    if (q == 0 && rok) {
-      if (A.caller_order && !isfinite(al_r)) atomicOr(A.err, 8);
-      const float gval = a_r - s;
-      if (A.ga_int) A.ga_int[I.row_off + r] = gval;
-      if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
-      const double av = a_uni ? 1.0 / (double)I.ns : (double)am_r;
-      part = av * (double)al_r;
-    }
-  } else {
-    const int c = (b - nbr) * ASM_BLOCK + threadIdx.x;
-    if (c < I.nt_pad) {
-      const bool cok = c < I.nt;
-      const float b_c = cok ? A.b_int[I.col_off + c] : 0.f;
-      const int pm_c = (cok && A.gb_out) ? A.perm_col[I.col_off + c] : 0;
-      // b.beta as a.alpha above: caller column c's share with caller-order duals
-      const float be_c = cok ? (A.beta_cal ? A.beta_cal[I.scol_off + c] : A.beta[I.col_off + c]) : 0.f;
-      const float bm_c = (cok && A.beta_cal) ? A.b_cal[I.scol_off + c] : b_c;
-      if (A.caller_order && !isfinite(be_c)) atomicOr(A.err, 8);
-      const bool b_uni = A.b_uniform[k];
-      const float* cs = A.colsum + (size_t)I.pair_off + c;
-      const float* ex = A.excess + (size_t)I.pair_off + c;
-      float s;
-      double e2;
-      if (A.tile_on)
-        asm_col_sum<true>(cs, ex, I.nt_pad, I.Le, A.tile_on + I.tile_off + c / TJ, I.njb, s, e2);
-      else
-        asm_col_sum<false>(cs, ex, I.nt_pad, I.Le, nullptr, I.njb, s, e2);
-      const float gval = cok ? b_c - s : 0.f;
-      if (A.gb_int) A.gb_int[I.col_off + c] = gval;
-      if (A.gb_out && cok) A.gb_out[I.scol_off + pm_c] = gval;
-      if (cok) {
-        const double bv = b_uni ? 1.0 / (double)I.nt : (double)bm_c;
-        part = bv * (double)be_c - e2 * (0.5 / I.gamma64);
-      }
-    }
-  }
-  // fixed-order block sum
-  part = wave_sum_dd(part);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-  __syncthreads();
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < ASM_BLOCK / 64; ++w) t += red[w];
-    A.obj_part[(size_t)k * A.obj_stride + b] = t;
-    last = 0;
-    if (A.finalize) {
-      // the last block of the instance to finish forms D from the partials
-      // (release: this block's partial is visible before its count)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      last = atomicAdd(&A.done[k], 1u) == (unsigned)(nbr + nbc - 1);
-    }
-  }
-  __syncthreads();
-  if (!last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  if (threadIdx.x < 64) {
-    const volatile double* parts = A.obj_part + (size_t)k * A.obj_stride;
-    double t = 0.0;
-    for (int i = threadIdx.x; i < nbr + nbc; i += 64) t += parts[i];
-    t = wave_sum_dd(t);
-    if (threadIdx.x == 0) {
-      if (!isfinite(t)) atomicOr(A.err, 4);
-      A.obj[k] = t;
-      if (A.obj_out) A.obj_out[k] = t;
-      A.done[k] = 0;
-    }
-  }
-}
-
-// D of an instance from its assembly partials: every lane sums the
-// partials i = lane (mod 64) in order, then the fixed-order wavefront sum
-// (the same association wherever D is formed).
 
 
 // caller-order (alpha, beta) -> internal order; padding columns get 0.

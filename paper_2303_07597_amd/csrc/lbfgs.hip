@@ -813,7 +813,7 @@ __device__ void lb_ctrl_wave(const LbArgs& A, int k, LbCtrlShared& sh) {
   if (has2) dots[lane + 64] = acc2;
   // D: lane sums the partials i = lane (mod 64) in order, then the
   // fixed-order wavefront sum (as wherever D is formed)
-  const int nob = asm_row_blocks(I.ns) + asm_col_blocks(I.nt_pad);
+  const int nob = asm_obj_parts(I);
   double os = 0.0;
 #pragma unroll
   for (int u = 0; u < PO; ++u)
