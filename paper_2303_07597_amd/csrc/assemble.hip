@@ -69,14 +69,34 @@ __host__ __device__ inline int asm_obj_parts(const InstDev& I) {
 // most this many of them.
 constexpr int ASM_RPMAX = 32;
 
+// Compensated float32 sums (Knuth's TwoSum): s + c carries the sum of the
+// terms added so far with the rounding error of every addition kept in c,
+// so a gradient entry a - sum, which cancels to a small number near the
+// optimum, is formed as (a - s) - c without the sum's float32 rounding.
+struct Csum {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float v) {
+    const float t = s + v;
+    const float bv = t - s;
+    c += (s - (t - bv)) + (v - bv);
+    s = t;
+  }
+  __device__ __forceinline__ void add(const Csum& o) {
+    add(o.s);
+    c += o.c;
+  }
+  // x - (s + c)
+  __device__ __forceinline__ float from(float x) const { return (x - s) - c; }
+};
+
 // Row sum of lane q of a row: jb = q, q + ASM_LPR, ... added in that order.
 // Each batch issues all its ASM_U loads before the first add; indices past
 // the end are clamped to the last slot (a valid address) and not added.
 // With MASK, a tile the screen skipped adds an exact zero (its slot holds
 // stale data, discarded by the select).
 template <bool MASK>
-__device__ __forceinline__ float asm_row_sum(const float* rp, int ns, int njb, const uint8_t* on, int q) {
-  float s = 0.f;
+__device__ __forceinline__ Csum asm_row_sum(const float* rp, int ns, int njb, const uint8_t* on, int q) {
+  Csum s;
   for (int j0 = q; j0 < njb; j0 += ASM_U * ASM_LPR) {
     float v[ASM_U];
     uint8_t f[ASM_U];
@@ -88,7 +108,7 @@ __device__ __forceinline__ float asm_row_sum(const float* rp, int ns, int njb, c
     }
 #pragma unroll
     for (int u = 0; u < ASM_U; ++u)
-      if (j0 + u * ASM_LPR < njb) s += (!MASK || f[u]) ? v[u] : 0.f;
+      if (j0 + u * ASM_LPR < njb) s.add((!MASK || f[u]) ? v[u] : 0.f);
   }
   return s;
 }
@@ -97,8 +117,8 @@ __device__ __forceinline__ float asm_row_sum(const float* rp, int ns, int njb, c
 // column partials and of excess^2 (float64); batches as in asm_row_sum.
 template <bool MASK>
 __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, int nt_pad, int Le,
-                                            const uint8_t* on, int njb, float& s, double& e2) {
-  s = 0.f;
+                                            const uint8_t* on, int njb, Csum& s, double& e2) {
+  s = Csum();
   e2 = 0.0;
   for (int g0 = 0; g0 < Le; g0 += ASM_U) {
     float cv[ASM_U], ev[ASM_U];
@@ -115,7 +135,7 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
       if (g0 + u < Le) {
         const bool keep = !MASK || f[u];
         const double e = ev[u];
-        s += keep ? cv[u] : 0.f;
+        s.add(keep ? cv[u] : 0.f);
         e2 += keep ? e * e : 0.0;
       }
     }
@@ -125,8 +145,9 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
 
 // Assembly, grid (max row blocks + max column blocks, count):
 //  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 lanes per row
-//                  take jb = q mod 8 in order, then a fixed xor tree);
-//  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order and
+//                  take jb = q mod 8 in order, then a fixed xor tree; the sums
+//                  compensated, see Csum);
+//  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order (compensated) and
 //                  the block's share of b.beta - sum_l excess_lc^2 / (2 gamma).
 // D's float64 partials are one per row block (its rows' share of a.alpha)
 // and one per column block, and D is their sum in block order.  Only
@@ -162,7 +183,7 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   if (b < nbr) {
     const int r = b * ASM_ROWS + threadIdx.x / ASM_LPR;
     const int q = threadIdx.x % ASM_LPR;
-    float s = 0.f;
+    Csum s;
     // the row's own operands are loaded together with its partials
     const bool rok = r < I.ns;
     const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
@@ -178,11 +199,15 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
         s = asm_row_sum<false>(rp, I.ns, I.njb, nullptr, q);
     }
     // fixed-order combine of the lanes of a row (xor tree over 8 lanes)
-    s += __shfl_xor(s, 1);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 4);
+#pragma unroll
+    for (int o = 1; o < ASM_LPR; o <<= 1) {
+      Csum t;
+      t.s = __shfl_xor(s.s, o);
+      t.c = __shfl_xor(s.c, o);
+      s.add(t);
+    }
     if (q == 0 && rok) {
-      const float gval = a_r - s;
+      const float gval = s.from(a_r);
       if (A.ga_int) A.ga_int[I.row_off + r] = gval;
       if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
       if (own) {
@@ -234,13 +259,13 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       const bool b_uni = A.b_uniform[k];
       const float* cs = A.colsum + (size_t)I.pair_off + c;
       const float* ex = A.excess + (size_t)I.pair_off + c;
-      float s;
+      Csum s;
       double e2;
       if (A.tile_on)
         asm_col_sum<true>(cs, ex, I.nt_pad, I.Le, A.tile_on + I.tile_off + c / TJ, I.njb, s, e2);
       else
         asm_col_sum<false>(cs, ex, I.nt_pad, I.Le, nullptr, I.njb, s, e2);
-      const float gval = cok ? b_c - s : 0.f;
+      const float gval = cok ? s.from(b_c) : 0.f;
       if (A.gb_int) A.gb_int[I.col_off + c] = gval;
       if (A.gb_out && cok) A.gb_out[I.scol_off + pm_c] = gval;
       if (cok) {
