@@ -149,6 +149,25 @@ def cpu_baseline(inst, alpha, beta, dstar, budget_s=6.0):
     rel = (dstar - r["trace"]) / abs(dstar) if dstar else None
     hit = int(np.nonzero(rel <= 1e-6)[0][0]) if rel is not None and np.any(rel <= 1e-6) else None
     ttt = t_solve * hit / max(r["iters"], 1) if hit is not None else None
+
+    def cpu_ttt(inst_k, ds, max_iter):
+        """Time to 1e-6 of the FP64 D* (every core): the solve's time up to the first iteration
+        within 1e-6, by the share of its iterations."""
+        Ck, _ = oracle.cost_normalized(inst_k["xs"], inst_k["xt"])
+        Pk = oracle.Problem(Ck, inst_k["labels"], inst_k["n_groups"], inst_k["gamma"], inst_k["mu"])
+        t0 = time.perf_counter()
+        rk = oracle.solve(Pk, max_iter=max_iter, nthreads=ncpu)
+        tk = time.perf_counter() - t0
+        relk = (ds - rk["trace"]) / abs(ds)
+        hk = np.nonzero(relk <= 1e-6)[0]
+        return (tk * int(hk[0]) / max(rk["iters"], 1) if hk.size else None), (int(hk[0]) if hk.size else None)
+    fix = load_dstar()
+    t_cfg1, i_cfg1 = cpu_ttt(synth.gaussian4_2d(), fix[("cfg1", 1)], 3000)
+    # a sample of the batched generator (instances 0..3 of the 256), each with its fixture
+    sample = []
+    for kk in range(4):
+        tk, ik = cpu_ttt(synth.instance_from_generator((4, kk)), fix[("batch", kk)], 3000)
+        sample.append(dict(k=kk, seconds=tk, iters=ik))
     # Algorithms 1-2 ("ours") against the dense method ("origin"), one core
     ps = synth.paper_synthetic(40, g=10)
     Cs, _ = oracle.cost_normalized(ps["xs"], ps["xt"])
@@ -165,6 +184,13 @@ def cpu_baseline(inst, alpha, beta, dstar, budget_s=6.0):
                                sample=f"{nall} evaluations, OpenMP over target columns, {eall:.1f} s"),
                 time_to_1e6=dict(seconds=ttt, iters=hit, cores=ncpu, solve_s=t_solve, solve_iters=r["iters"],
                                  d_star="FP64 oracle fixture"),
+                time_to_1e6_cfg1=dict(workload="4 Gaussians in 2-D, 200 x 200, gamma=1, mu=0.1", seconds=t_cfg1,
+                                      iters=i_cfg1, cores=ncpu),
+                time_to_1e6_batch_sample=dict(workload="instances 0-3 of the 256-instance batched workload, "
+                                                       "one after another", cores=ncpu,
+                                              seconds_sum=sum(x["seconds"] or 0.0 for x in sample),
+                                              all_reached=all(x["seconds"] is not None for x in sample),
+                                              instances=sample),
                 paper_synthetic_ours_vs_origin=dict(
                     workload="paper synthetic |L|=40, g=10, d=2, gamma=0.1, rho=0.8 (gamma'=0.02, mu'=4), "
                              "1000 L-BFGS iterations, one core",
