@@ -312,9 +312,11 @@ def bench_mu_sweep(args, torch, synth, O, n=4096, fix=None):
                            cost_mode=O.OT_GS_COST_MATERIALIZE, cost_scale=0.0)])
         K = 10000   # mu = 1 needs about 4000 iterations to 1e-6
         res = {}
+        st_tr = torch.zeros((K + 1) * 8, dtype=torch.int64, device=dev)
         for name, scr in (("dense", 0), ("screened", 1)):
             h.stats(reset=True)
-            _, _, inf, tr, tt, wall = _solve_traced(h, 1, K, torch, use_screen=scr)
+            kw = dict(stats_trace=st_tr) if scr else {}
+            _, _, inf, tr, tt, wall = _solve_traced(h, 1, K, torch, use_screen=scr, **kw)
             st = h.stats(reset=True)
             res[name] = (inf[0], tr, tt, wall, st)
         key = (f"blobs{n}_mu{mu:g}", 2)
@@ -333,6 +335,19 @@ def bench_mu_sweep(args, torch, synth, O, n=4096, fix=None):
                     st["pairs_total"], 1)
         td, ts_ = row["dense"]["time_to_1e6_s"], row["screened"]["time_to_1e6_s"]
         row["speedup_time_to_1e6"] = (td / ts_) if (td and ts_) else None
+        # per-iteration skipping of the screened solve (the handle's counters at every accepted
+        # iteration): share of pairs skipped and of tiles computed between consecutive iterations,
+        # at 20 iterations spread over the solve
+        S = st_tr.cpu().numpy().reshape(K + 1, 8)[:res["screened"][0]["iters"] + 1].astype(np.float64)
+        dS = np.diff(S, axis=0)
+        curve = []
+        for it in np.unique(np.linspace(1, len(dS), 20).astype(int)):
+            d = dS[it - 1]
+            curve.append([int(it), float(1 - (d[4] + d[2]) / max(d[1], 1)), float(d[7] / max(d[6], 1)), int(d[5])])
+        # (refreshes: snapshot evaluations in the step, dense by construction; the pair counts
+        # are those of the screen pass)
+        row["screened"]["per_iteration"] = dict(columns=["iteration", "pairs_skipped_frac", "tiles_computed_frac",
+                                                         "refreshes"], rows=curve)
         out[f"mu={mu:g}"] = row
         h.close()
     return out
