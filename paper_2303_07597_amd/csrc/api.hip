@@ -2659,8 +2659,12 @@ extern "C" int ot_gs_solve(ot_gs_handle* h, const ot_gs_options* opts, float* al
                          (const float*)h->b_int, (const int*)h->a_uniform, (const int*)h->b_uniform, h->zsnap,
                          h->osnap, h->inN, h->cmax_w);
       LAUNCHCHK();
-      const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8), (unsigned)std::min(h->max_ns, 256),
-                    h->count);
+      // (batches: fewer row workgroups per instance; the instances not being
+      // re-centred leave at once, and a grid of 2048 workgroups per instance
+      // over 256 instances costs more to dispatch than the re-centred
+      // instance's cost takes to rewrite)
+      const dim3 cg((unsigned)std::min<long long>(ceil_div(h->max_ntp, 256), 8),
+                    (unsigned)std::min(h->max_ns, std::max(16, 256 / h->count)), h->count);
       hipLaunchKernelGGL(k_recenter_cost, cg, dim3(256), 0, s, A, (const float*)h->C, h->Cw, (const int*)h->row_grp,
                          (const int*)h->g_start, (const int*)h->g_size, h->cmax_w, 0);
       LAUNCHCHK();
