@@ -89,7 +89,7 @@ struct Csum {
   __device__ __forceinline__ float from(float x) const { return (x - s) - c; }
 };
 
-// Row sum of lane q of a row: jb = q, q + ASM_LPR, ... added in that order.
+// Row sum of slot q of a row: jb = q, q + ASM_LPR, ... added in that order.
 // Each batch issues all its ASM_U loads before the first add; indices past
 // the end are clamped to the last slot (a valid address) and not added.
 // With MASK, a tile the screen skipped adds an exact zero (its slot holds
@@ -144,9 +144,9 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
 
 
 // Assembly, grid (max row blocks + max column blocks, count):
-//  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 lanes per row
-//                  take jb = q mod 8 in order, then a fixed xor tree; the sums
-//                  compensated, see Csum);
+//  row block b:    grad_alpha_r = a_r - sum_jb rowpart[jb][r] (8 slots per row
+//                  take jb = q mod 8 in order, then a fixed pairwise tree; the
+//                  sums compensated, see Csum);
 //  column block b: grad_beta_c = b_c - sum_l colsum[l][c] in group order (compensated) and
 //                  the block's share of b.beta - sum_l excess_lc^2 / (2 gamma).
 // D's float64 partials are one per row block (its rows' share of a.alpha)
@@ -162,6 +162,7 @@ __device__ __forceinline__ void asm_col_sum(const float* cs, const float* ex, in
 __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   __shared__ double red[ASM_BLOCK / 64];
   __shared__ double rpart[ASM_RPMAX];
+  __shared__ float lds_s[ASM_LPR][ASM_ROWS], lds_c[ASM_LPR][ASM_ROWS];
   const int k = blockIdx.y;
   if (A.zero_first && blockIdx.x == 0 && k == 0 && threadIdx.x == 0) *A.zero_first = 0;
   if (A.caller_order && blockIdx.x == 0 && k == 0) prologue_body(A.pro);
@@ -181,16 +182,19 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
   const bool a_uni = A.a_uniform[k];
   double part = 0.0;
   if (b < nbr) {
-    const int r = b * ASM_ROWS + threadIdx.x / ASM_LPR;
-    const int q = threadIdx.x % ASM_LPR;
-    Csum s;
-    // the row's own operands are loaded together with its partials
+    // thread t takes row t mod 32 and slot q = t / 32, so that one load
+    // instruction of a wavefront reads two runs of 32 consecutive partials
+    const int r = b * ASM_ROWS + threadIdx.x % ASM_ROWS;
+    const int q = threadIdx.x / ASM_ROWS;
     const bool rok = r < I.ns;
-    const float a_r = rok ? A.a_int[I.row_off + r] : 0.f;
-    const int pm_r = (rok && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
-    const bool own = !cols_publish && rok;   // this block forms its share of a.alpha
+    const bool lead = q == 0 && rok;         // slot 0 forms the row's results
+    // the row's own operands are loaded together with its partials
+    const float a_r = lead ? A.a_int[I.row_off + r] : 0.f;
+    const int pm_r = (lead && A.ga_out) ? A.perm_row[I.row_off + r] : 0;
+    const bool own = !cols_publish && lead;  // this block forms its share of a.alpha
     const float al_r = own ? (A.alpha_cal ? A.alpha_cal : A.alpha)[I.row_off + r] : 0.f;
     const float am_r = (own && A.alpha_cal) ? A.a_cal[I.row_off + r] : a_r;
+    Csum s;
     if (rok) {
       const float* rp = A.rowpart + I.r_off + r;
       if (A.tile_on)
@@ -198,22 +202,43 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
       else
         s = asm_row_sum<false>(rp, I.ns, I.njb, nullptr, q);
     }
-    // fixed-order combine of the lanes of a row (xor tree over 8 lanes)
+    lds_s[q][threadIdx.x % ASM_ROWS] = s.s;
+    lds_c[q][threadIdx.x % ASM_ROWS] = s.c;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      if (q == 0) {
+        // fixed-order combine of the slots of a row: pairs (0,1), (2,3),
+        // (4,5), (6,7), then pairs of pairs, each added lower slot first
+        Csum p[ASM_LPR];
 #pragma unroll
-    for (int o = 1; o < ASM_LPR; o <<= 1) {
-      Csum t;
-      t.s = __shfl_xor(s.s, o);
-      t.c = __shfl_xor(s.c, o);
-      s.add(t);
-    }
-    if (q == 0 && rok) {
-      const float gval = s.from(a_r);
-      if (A.ga_int) A.ga_int[I.row_off + r] = gval;
-      if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
-      if (own) {
-        if (A.caller_order && !isfinite(al_r)) atomicOr(A.err, 8);
-        const double av = a_uni ? 1.0 / (double)I.ns : (double)am_r;
-        part = av * (double)al_r;
+        for (int i = 0; i < ASM_LPR; ++i) {
+          p[i].s = lds_s[i][threadIdx.x];
+          p[i].c = lds_c[i][threadIdx.x];
+        }
+#pragma unroll
+        for (int o = 1; o < ASM_LPR; o <<= 1)
+#pragma unroll
+          for (int i = 0; i < ASM_LPR; i += 2 * o) p[i].add(p[i + o]);
+        if (rok) {
+          const float gval = p[0].from(a_r);
+          if (A.ga_int) A.ga_int[I.row_off + r] = gval;
+          if (A.ga_out) A.ga_out[I.row_off + pm_r] = gval;
+          if (own) {
+            if (A.caller_order && !isfinite(al_r)) atomicOr(A.err, 8);
+            const double av = a_uni ? 1.0 / (double)I.ns : (double)am_r;
+            part = av * (double)al_r;
+          }
+        }
+      }
+      if (!cols_publish) {
+        // the block's share of a.alpha, added as the column blocks add it
+        // for a row block when they publish its partial
+        double v = part + 0.0;
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        const double g1 = __shfl_down(v, 8), g2 = __shfl_down(v, 16), g3 = __shfl_down(v, 24);
+        part = threadIdx.x == 0 ? (((0.0 + v) + g1) + g2) + g3 : 0.0;
       }
     }
     if (cols_publish) return;
@@ -221,13 +246,12 @@ __global__ void __launch_bounds__(ASM_BLOCK) k_assemble(ReduceArgs A) {
     const int cb = b - nbr;
     if (cols_publish) {
       // the partials of the row blocks assigned to this block, 32 threads
-      // (one row each) per row block: the same sums in the same order as in
-      // the row block itself, whose rows sit one per 8 lanes (a value plus
-      // +0.0, then the fixed wavefront tree: pairs, then pairs of pairs, of
-      // each wavefront's 8 rows), and the four wavefront totals added in
-      // order.  With caller-order duals the share of caller rows (a.alpha is
-      // a sum over all rows in any one-to-one order, so no index load
-      // precedes the alpha loads).
+      // (one row each) per row block: the same sums in the same order as a
+      // row block forms its own (a value plus +0.0, pairs, pairs of pairs
+      // and the tree of eight rows, then the four totals added in order).
+      // With caller-order duals the share of caller rows (a.alpha is a sum
+      // over all rows in any one-to-one order, so no index load precedes
+      // the alpha loads).
       const int nrb = (nbr - cb + nbc - 1) / nbc;   // row blocks cb, cb + nbc, ... below nbr
       const float* al = (A.alpha_cal ? A.alpha_cal : A.alpha) + I.row_off;
       const float* am = (A.alpha_cal ? A.a_cal : A.a_int) + I.row_off;
