@@ -564,9 +564,9 @@ def test_mapping_is_affine_and_a_barycentre_at_the_optimum():
 
 def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     """Every oracle entry point on small problems (an empty label, a single
-    source row, a single target) in a standalone driver built with
+    source row, a single target) in a standalone C test program built with
     -fsanitize=address,undefined: no memory error, leak or undefined
-    arithmetic, and the driver's own invariants hold."""
+    arithmetic, and the program's own invariants hold."""
     import shutil
     import subprocess
     gcc = shutil.which("gcc")
